@@ -1,0 +1,267 @@
+"""Plain FP64 bootstrap multigrid (BMG) eigensolver for A u = lambda M u.
+
+TEST INFRASTRUCTURE: the reference the HIP path is compared with.  Slow on
+purpose: SciPy sparse products and dense LAPACK calls, no blocking or fusion.
+
+What is computed (paper Sec. 4, Alg. 2 and Alg. 3, with Remark 3.2):
+
+ 1. Coarse eigensolve on level 0 (Alg. 2 step 1): all eigenpairs of
+    (A_0, M_0).  The n_c coarse eigenvectors nearest the shift sigma are
+    prolongated to the finest level L: W_c = P_{0->L} Phi_c.  Together with
+    the block of test vectors they span the enriched space V_H + X_h
+    (Alg. 2 step 4), evaluated exactly on the finest level (Galerkin reading
+    of the enriched pencil, which makes the Ritz step an exact Rayleigh-Ritz
+    on span[W_c, U]).
+ 2. Test vectors: an N_L x m Gaussian block (see rng.py), followed by a first
+    Rayleigh-Ritz step.
+ 3. Each cycle relaxes the fine source problem of eq. (pb-f-aux-mat) starting
+    from the current approximation (Remark 3.2: a smoother started from the
+    previous approximation replaces the solve).  In defect form this is the
+    correction U' = U - B_sigma (A U - M U Theta), where B_sigma is one
+    V(nu1, nu2) cycle for the rediscretised operators A_l - sigma M_l on
+    levels L down to l_c, with P^T as restriction and P as prolongation
+    (Sec. 3), smoothing by multicolour symmetric Gauss-Seidel (Sec. 5.3,
+    method 4; Remark 4.2) or weighted Jacobi.
+ 4. M-orthonormalisation of Z = [W_c, U'] (Alg. 2 step 3, "orthogonalize with
+    respect to b_h") by SVQB, then the Ritz eigenproblem of the enriched
+    pencil (eq. pb-c-aux-mat) shifted by sigma; the m Ritz pairs nearest sigma
+    are kept (Alg. 2 step 2 choice of the index set Lambda, Remark 4.1).
+ 5. Stop when every returned pair carries a residual certificate: with
+    rho_i = 2 ||r_i||_{D^-1} (D the lumped mass, 1/4 D <= M <= D elementwise
+    for P1 so rho_i >= ||r_i||_{M^-1}) and delta_i the distance from theta_i
+    to the nearest Ritz value outside its cluster, require
+    rho_i^2 / delta_i <= 0.1 tol max(|theta_i|, 1)   (Kato-Temple)  and
+    rho_i / delta_i <= angle_tol                      (Davis-Kahan).
+
+Readings where the paper is silent (the library states the same readings in
+its own words): n_c = min(N_0, 32); l_c is the coarsest level with
+N_l >= 8 n_W(sigma), n_W(sigma) = |Gamma_h| sigma / (4 pi) (Weyl count); at
+l_c = 0 the coarse operator is inverted on its spectrum with the modes within
+1e-2 max(1, |sigma|) of sigma dropped, otherwise 8 smoothing sweeps are used;
+Ritz values whose relative gap is below 1e-2 form one cluster.
+"""
+import math
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import fem, mesh, transfer, colour, rng
+
+
+class LevelOps:
+    """Matrices and transfer data of one level of the hierarchy."""
+
+    def __init__(self, lv, P=None):
+        self.xyz = lv.xyz
+        self.tri = lv.tri
+        self.parents = lv.parents
+        self.A, self.M = fem.assemble(lv.xyz, lv.tri)
+        self.D = fem.lumped_mass(self.M)
+        self.P = P  # prolongation from the previous level to this one
+        self.colours = colour.greedy_colouring(self.A)
+        self.n = self.A.shape[0]
+        self.area = float(fem.triangle_areas(lv.xyz, lv.tri).sum())
+
+
+def build_levels(kind, n_refine, axes=(1.0, 1.0, 1.0)):
+    """Hierarchy with matrices on every level (Sec. 3 refinement; Sec. 2 assembly)."""
+    lvls = mesh.hierarchy(kind, n_refine, axes=axes)
+    out = []
+    for l, lv in enumerate(lvls):
+        P = None if l == 0 else transfer.prolongation(len(lvls[l - 1].xyz), lv.parents)
+        out.append(LevelOps(lv, P))
+    return out
+
+
+def nearest_indices(values, target, count):
+    """Indices of the `count` values nearest target; ties by value, then index."""
+    v = np.asarray(values)
+    order = np.lexsort((np.arange(len(v)), v, np.abs(v - target)))
+    return order[:count]
+
+
+def coarsest_level(levels, sigma):
+    """l_c: the coarsest level with N_l >= 8 n_W(sigma) (Weyl count)."""
+    n_w = levels[-1].area * max(sigma, 0.0) / (4.0 * math.pi)
+    for l, lv in enumerate(levels):
+        if lv.n >= 8.0 * n_w:
+            return l
+    return len(levels) - 1
+
+
+class Smoother:
+    """Gauss-Seidel (multicolour, symmetric) or weighted Jacobi on A_l - sigma M_l."""
+
+    def __init__(self, lv, sigma, kind, omega):
+        self.S = (lv.A - sigma * lv.M).tocsr()
+        self.d = self.S.diagonal()
+        self.kind = kind
+        self.omega = omega
+        nc = int(lv.colours.max()) + 1
+        self.rows = [np.flatnonzero(lv.colours == c) for c in range(nc)]
+
+    def sweep(self, x, f, forward=True):
+        if self.kind == "jacobi":
+            return x + self.omega * (f - self.S @ x) / self.d[:, None]
+        order = range(len(self.rows)) if forward else range(len(self.rows) - 1, -1, -1)
+        x = x.copy()
+        for c in order:
+            r = self.rows[c]
+            x[r] += (f[r] - self.S[r] @ x) / self.d[r][:, None]
+        return x
+
+
+class BMG:
+    """The BMG cycle on a fixed hierarchy and shift (see module docstring)."""
+
+    def __init__(self, levels, sigma, m, nu1=2, nu2=2, smoother="gs", omega=2.0 / 3.0,
+                 n_c=None, l_c=None):
+        self.levels = levels
+        self.sigma = float(sigma)
+        self.m = m
+        self.nu1, self.nu2 = nu1, nu2
+        L = len(levels) - 1
+        self.L = L
+        self.l_c = coarsest_level(levels, sigma) if l_c is None else l_c
+        self.smoothers = [Smoother(lv, sigma, smoother, omega) for lv in levels]
+        # Alg. 2 step 1: coarse eigensolve on level 0
+        lv0 = levels[0]
+        lam0, phi0 = sla.eigh(lv0.A.toarray(), lv0.M.toarray())
+        self.lam0, self.phi0 = lam0, phi0
+        self.n_c = min(lv0.n, 32) if n_c is None else n_c
+        idx = nearest_indices(lam0, self.sigma, self.n_c)
+        W = phi0[:, np.sort(idx)]
+        for l in range(1, L + 1):
+            W = levels[l].P @ W
+        self.W = W
+        # truncated spectral inverse of A_0 - sigma M_0 (used when l_c == 0)
+        x = lam0 - self.sigma
+        g = np.where(np.abs(x) >= 1e-2 * max(1.0, abs(self.sigma)), 1.0 / np.where(x == 0, 1, x), 0.0)
+        self.coarse_inv = (phi0 * g[None, :]) @ phi0.T
+
+    # ---- correction: one V(nu1, nu2) cycle for (A_l - sigma M_l) e = f ----
+    def vcycle(self, l, f):
+        sm = self.smoothers[l]
+        if l == self.l_c:
+            if l == 0:
+                return self.coarse_inv @ f
+            e = np.zeros_like(f)
+            for s in range(8):
+                e = sm.sweep(e, f, forward=(s % 2 == 0))
+            return e
+        e = np.zeros_like(f)
+        for _ in range(self.nu1):
+            e = sm.sweep(e, f, forward=True)
+        r = f - sm.S @ e
+        P = self.levels[l].P
+        ec = self.vcycle(l - 1, P.T @ r)
+        e = e + P @ ec
+        for _ in range(self.nu2):
+            e = sm.sweep(e, f, forward=False)
+        return e
+
+    # ---- enriched Rayleigh-Ritz ----
+    def rayleigh_ritz(self, U):
+        lv = self.levels[self.L]
+        Z = np.hstack([self.W, U])
+        GA = Z.T @ (lv.A @ Z)
+        GM = Z.T @ (lv.M @ Z)
+        GA = 0.5 * (GA + GA.T)
+        GM = 0.5 * (GM + GM.T)
+        # SVQB (Stathopoulos & Wu 2002): scale to unit diagonal, eigendecompose,
+        # drop directions with eigenvalue below 1e-12 of the largest.
+        s = 1.0 / np.sqrt(np.diag(GM))
+        d, V = np.linalg.eigh(GM * s[:, None] * s[None, :])
+        keep = d > 1e-12 * d.max()
+        T = (s[:, None] * V[:, keep]) / np.sqrt(d[keep])[None, :]
+        C = T.T @ (GA - self.sigma * GM) @ T
+        C = 0.5 * (C + C.T)
+        mu, Q = np.linalg.eigh(C)
+        if len(mu) < self.m:
+            raise RuntimeError("enriched space lost rank below m")
+        sel = nearest_indices(mu, 0.0, self.m)
+        sel = sel[np.argsort(mu[sel], kind="stable")]
+        Y = T @ Q[:, sel]
+        return Z @ Y, mu[sel] + self.sigma
+
+    def residual(self, U, theta):
+        lv = self.levels[self.L]
+        return lv.A @ U - (lv.M @ U) * theta[None, :]
+
+    def certificates(self, R, theta, ret):
+        """(rho, delta) for the returned Ritz pairs `ret` (indices into theta)."""
+        D = self.levels[self.L].D
+        rho = 2.0 * np.sqrt(np.sum(R * R / D[:, None], axis=0))
+        cl = cluster_ids(theta)
+        delta = np.empty(len(theta))
+        for i in range(len(theta)):
+            out = theta[cl != cl[i]]
+            delta[i] = np.min(np.abs(out - theta[i])) if len(out) else 1e-2 * max(abs(theta[i]), 1.0)
+        return rho[ret], delta[ret]
+
+
+def cluster_ids(theta):
+    """Cluster label of each (ascending) Ritz value: relative gap < 1e-2 joins."""
+    ids = np.zeros(len(theta), dtype=np.int64)
+    for j in range(1, len(theta)):
+        gap = theta[j] - theta[j - 1]
+        scale = max(abs(theta[j]), abs(theta[j - 1]), 1.0)
+        ids[j] = ids[j - 1] + (0 if gap < 1e-2 * scale else 1)
+    return ids
+
+
+def normalise_signs(U):
+    """Make the largest-magnitude entry of each column positive (first on ties)."""
+    U = U.copy()
+    for j in range(U.shape[1]):
+        i = int(np.argmax(np.abs(U[:, j])))
+        if U[i, j] < 0:
+            U[:, j] = -U[:, j]
+    return U
+
+
+def default_m(k, sigma):
+    """Block width: 4 ceil(1.25 k / 4) for sigma = 0, 4 ceil(1.5 k / 4) otherwise."""
+    f = 1.25 if sigma == 0 else 1.5
+    return 4 * int(math.ceil(f * k / 4.0))
+
+
+def solve(levels, k, sigma=0.0, tol=1e-8, m=None, nu1=2, nu2=2, smoother="gs",
+          omega=2.0 / 3.0, max_cycles=200, seed=0, angle_tol=1e-7, U0=None,
+          n_c=None, l_c=None, history=False):
+    """The k eigenpairs of (A_L, M_L) nearest sigma by BMG.
+
+    Returns (evals ascending, M-orthonormal evecs N_L x k, info dict).
+    """
+    m = default_m(k, sigma) if m is None else m
+    bmg = BMG(levels, sigma, m, nu1, nu2, smoother, omega, n_c, l_c)
+    lv = levels[-1]
+    U = rng.gaussian_block(lv.n, m, seed) if U0 is None else np.array(U0, dtype=np.float64)
+    U, theta = bmg.rayleigh_ritz(U)
+    hist = []
+    cycles = 0
+    converged = False
+    while True:
+        R = bmg.residual(U, theta)
+        ret = nearest_indices(theta, sigma, k)
+        rho, delta = bmg.certificates(R, theta, ret)
+        th = theta[ret]
+        ok_kt = np.all(rho ** 2 / delta <= 0.1 * tol * np.maximum(np.abs(th), 1.0))
+        ok_dk = np.max(rho / delta) <= angle_tol
+        if history:
+            hist.append((theta.copy(), rho.copy(), delta.copy()))
+        if ok_kt and ok_dk:
+            converged = True
+            break
+        if cycles >= max_cycles:
+            break
+        E = bmg.vcycle(bmg.L, -R)
+        U, theta = bmg.rayleigh_ritz(U + E)
+        cycles += 1
+    ret = np.sort(nearest_indices(theta, sigma, k))
+    order = ret[np.argsort(theta[ret], kind="stable")]
+    evals = theta[order]
+    evecs = normalise_signs(U[:, order])
+    info = dict(cycles=cycles, converged=converged, rho=rho, delta=delta, m=m,
+                l_c=bmg.l_c, n_c=bmg.n_c, history=hist)
+    return evals, evecs, info
