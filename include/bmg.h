@@ -1,0 +1,281 @@
+/*
+ * bmg.h - C ABI of the MI355X bootstrap multigrid (BMG) eigensolver.
+ *
+ * Problem (paper: Brannick & Cao, "A Bootstrap Multigrid Eigensolver",
+ * Sec. 2.2, eq. pb-eig-fea): on a closed surface Gamma approximated by flat
+ * triangles whose vertices lie on Gamma (Sec. 2.1), find the eigenpairs of the
+ * P1 surface-FEM pencil  A u = lambda M u  (A: stiffness, M: consistent mass),
+ * with M-orthonormal eigenvectors (Sec. 2.1).  The library computes the k pairs
+ * whose eigenvalues are nearest a shift sigma (Alg. 2, step 2 and Remark 4.1)
+ * with the bootstrap multigrid cycle of Alg. 2/3: a relaxation cycle for the
+ * shifted source problem (eq. pb-f-aux-mat, Remark 3.2) on a block of test
+ * vectors, geometric prolongation / restriction between uniformly refined
+ * meshes with projected midpoints (Sec. 3, eq. proj-1), and a Rayleigh-Ritz
+ * step in the coarse space enriched with the block (eq. pb-c-aux-mat).
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns BMG_OK (0) or a negative bmg_status.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *     memory of the current device (e.g. torch.cuda tensors).
+ *   - Blocks of vectors on the device are interleaved row-major [N][m]
+ *     (vertex-major: the m values of one vertex are contiguous).
+ *   - A `stream` argument is a hipStream_t passed as void*; NULL means the
+ *     default (null) stream.  Work is enqueued on it in order.
+ *   - The library never keeps a caller pointer after a call returns.
+ *   - Errors: BMG_EINVAL for invalid arguments (nothing is enqueued),
+ *     BMG_EDEVICE for a HIP runtime error (bmg_last_error() gives its text),
+ *     BMG_ENOMEM when a device allocation fails.
+ */
+#ifndef BMG_H
+#define BMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BMG_OK = 0,
+  BMG_EINVAL = -1,
+  BMG_ENOMEM = -2,
+  BMG_EDEVICE = -3,
+  BMG_ENOCONV = -4,
+  BMG_EBUSY = -5,
+  BMG_ECANCELED = -6
+} bmg_status;
+
+typedef enum {
+  BMG_SPHERE = 0,    /* regular icosahedron inscribed in the unit sphere      */
+  BMG_ELLIPSOID = 1, /* unit-sphere hierarchy mapped by x -> (a0 x, a1 y, a2 z) */
+  BMG_TORUS = 2,     /* nu x nv parametric grid of the torus (R, r)            */
+  BMG_CUSTOM = 3     /* caller's coarse mesh and projection onto Gamma         */
+} bmg_surface_kind;
+
+/* Description of the surface and of its coarsest triangulation (Sec. 2.1:
+ * vertices on Gamma; Sec. 3: refinement moves midpoints onto Gamma).
+ * Unused fields are ignored for the built-in kinds. */
+typedef struct {
+  int32_t kind;            /* bmg_surface_kind */
+  double axes[3];          /* BMG_ELLIPSOID semi-axes (a0, a1, a2) > 0 */
+  double R, r;             /* BMG_TORUS radii, R > r > 0 */
+  int32_t nu, nv;          /* BMG_TORUS grid, nu >= 3, nv >= 3 (benchmark: 64 x 32) */
+  int32_t n_vert, n_tri;   /* BMG_CUSTOM coarse mesh sizes */
+  const double* xyz;       /* BMG_CUSTOM host [n_vert][3], copied during the call */
+  const int32_t* tri;      /* BMG_CUSTOM host [n_tri][3], outward oriented, copied */
+  /* BMG_CUSTOM projection onto Gamma, called on each new midpoint (in place);
+   * NULL keeps the flat midpoint.  Called only during bmg_build_hierarchy. */
+  void (*project)(double p[3], void* ctx);
+  void* ctx;
+} bmg_surface_desc;
+
+typedef struct bmg_hierarchy bmg_hierarchy; /* opaque; device-resident after build */
+
+/* Build levels 0..n_refine (Sec. 3 uniform refinement with projected
+ * midpoints; Sec. 2.2 P1 assembly of A_l, M_l in FP64 with FP32 copies; vertex
+ * colouring; parent tables of the prolongation of eq. proj-1; the level-0
+ * generalized eigendecomposition of Alg. 2 step 1) and upload it to the
+ * current device on `stream`.  The call returns after the upload completes.
+ * Numbering: coarse edges (a<b) in lexicographic order, the midpoint of edge
+ * e is vertex N_{l-1}+e; triangle (a,b,c) -> (a,ab,ca),(ab,b,bc),(ca,bc,c),
+ * (ab,bc,ca).
+ * Errors: BMG_EINVAL for a NULL/ill-formed descriptor, n_refine outside
+ * [0, 10], a custom mesh that is not a closed, consistently oriented
+ * 2-manifold (every directed edge once, its reverse once), a vertex valence
+ * above 30, or a coarse mesh with more than 4096 vertices.
+ * Ownership: *out belongs to the caller until bmg_free_hierarchy. */
+int bmg_build_hierarchy(const bmg_surface_desc* desc, int32_t n_refine, void* stream,
+                        bmg_hierarchy** out);
+
+/* The same construction without any device work (no GPU needed): meshes,
+ * matrices, colouring, parent tables and the level-0 eigendecomposition are
+ * built on the host for inspection with bmg_hierarchy_info/_export.  Such a
+ * hierarchy is rejected by bmg_solve and bmg_apply (BMG_EINVAL). */
+int bmg_build_hierarchy_host(const bmg_surface_desc* desc, int32_t n_refine, bmg_hierarchy** out);
+
+void bmg_free_hierarchy(bmg_hierarchy* h);
+
+typedef struct {
+  int32_t n_levels;      /* n_refine + 1 */
+  int32_t level;         /* the level described below */
+  int64_t n_vert;        /* N_l */
+  int64_t n_tri;         /* triangles of level l */
+  int64_t nnz;           /* nonzeros of A_l (= of M_l; same pattern) */
+  int32_t ell_width;     /* padded row width of the ELL storage */
+  int32_t n_colours;     /* colours of the Gauss-Seidel colouring */
+  double area;           /* |Gamma_h| = sum of triangle areas = 1^T M_l 1 */
+  int64_t device_bytes;  /* device memory held for this level */
+} bmg_level_info;
+
+/* Sizes of one level (0 <= level < n_levels).  BMG_EINVAL on a bad level. */
+int bmg_hierarchy_info(const bmg_hierarchy* h, int32_t level, bmg_level_info* out);
+
+typedef enum {
+  BMG_EXPORT_XYZ = 0,      /* double [N][3] vertex coordinates                     */
+  BMG_EXPORT_TRI = 1,      /* int32  [F][3] triangles                              */
+  BMG_EXPORT_PARENTS = 2,  /* int32  [N_l - N_{l-1}][2] parents (a<b) of new vertices (l >= 1) */
+  BMG_EXPORT_ELL_COLS = 3, /* int32  [N][W] column indices; entry 0 is the diagonal; padding repeats the row index */
+  BMG_EXPORT_ELL_A = 4,    /* double [N][W] values of A_l (padding 0)              */
+  BMG_EXPORT_ELL_M = 5,    /* double [N][W] values of M_l (padding 0)              */
+  BMG_EXPORT_COLOURS = 6,  /* int32  [N] colour of each vertex                      */
+  BMG_EXPORT_LUMPED = 7,   /* double [N] row sums of M_l                            */
+  BMG_EXPORT_COARSE_EIG = 8 /* level 0 only: double [N_0] eigenvalues then [N_0][N_0]
+                               row-major M_0-orthonormal eigenvectors (column j = pair j) */
+} bmg_export_what;
+
+/* Copy one host-side array of a level into `host_out` (capacity in bytes).
+ * For inspection and for checking the hierarchy against an independent
+ * implementation.  BMG_EINVAL if the level/what is invalid or the capacity is
+ * too small; *bytes_needed (nullable) receives the size in every case. */
+int bmg_hierarchy_export(const bmg_hierarchy* h, int32_t level, int32_t what, void* host_out,
+                         int64_t capacity, int64_t* bytes_needed);
+
+/* ---------------------------------------------------------------- solve --- */
+
+typedef enum { BMG_SMOOTH_GS = 0, BMG_SMOOTH_JACOBI = 1 } bmg_smoother;
+typedef enum { BMG_FP64 = 0, BMG_MIXED = 1 } bmg_precision;
+
+typedef struct {
+  int32_t m;          /* test vectors; 0 -> 4 ceil(1.25 k / 4) (sigma = 0) or
+                         4 ceil(1.5 k / 4) (sigma != 0); must be a multiple of 4 */
+  int32_t nu1, nu2;   /* pre- and post-smoothing sweeps per level (2, 2) */
+  int32_t smoother;   /* bmg_smoother: multicolour symmetric Gauss-Seidel (colours
+                         ascending before, descending after the coarse correction)
+                         or weighted Jacobi with D = diag(A_l - sigma M_l) */
+  int32_t precision;  /* bmg_precision: BMG_MIXED runs the correction cycle in FP32
+                         (values and accumulation); residuals, Gram matrices, the
+                         Ritz problem and the iterate stay FP64 */
+  int32_t max_cycles; /* 200 */
+  int32_t n_c;        /* level-0 eigenvectors in the enrichment; 0 -> min(N_0, 32) */
+  int32_t l_c;        /* coarsest level of the correction cycle; -1 -> the coarsest
+                         l with N_l >= 8 |Gamma_h| sigma / (4 pi) */
+  double omega;       /* Jacobi weight (2/3) */
+  double angle_tol;   /* Davis-Kahan stopping bound on rho_i / delta_i (1e-7) */
+  uint64_t seed;      /* test vectors: element (i,j) ~ N(0,1) from SplitMix64
+                         counters 2c, 2c+1 with c = i m + j, Box-Muller */
+  const double* initial_block; /* optional host [N_L][m] block replacing the seeded one */
+} bmg_solve_opts;
+
+/* Fill *o with the defaults listed above. */
+void bmg_solve_opts_default(bmg_solve_opts* o);
+
+typedef struct {
+  int32_t cycles;      /* correction + Ritz cycles performed */
+  int32_t converged;   /* 1 if every returned pair met the certificate */
+  int32_t m, n_c, l_c; /* values actually used */
+  int32_t reserved;
+  double t_solve_ms;   /* HIP-event time on `stream` from entry to output */
+  double max_rho_over_delta; /* final max over returned pairs of rho_i / delta_i */
+  double max_kato_temple;    /* final max of rho_i^2 / (delta_i max(|theta_i|, 1)) */
+  double* rho;         /* nullable host [k]: rho_i = 2 ||r_i||_{D^-1} >= ||r_i||_{M^-1} */
+  double* delta;       /* nullable host [k]: distance to the nearest Ritz value outside
+                          the cluster of theta_i */
+} bmg_solve_stats;
+
+/* The k eigenpairs of (A_L, M_L) nearest sigma on the finest level L.
+ *   evals: host [k], ascending (unshifted lambda).
+ *   evecs: NULL, or column-major [k][ld] (column j = eigenvector j, ld >= N_L),
+ *          host memory if evecs_on_device == 0, device memory otherwise.
+ *          Columns are M_L-orthonormal; the entry of largest magnitude of each
+ *          column is positive (the lowest index on ties).
+ * Stopping rule (the paper runs a fixed number of cycles; this certificate is
+ * the library's reading): with r_i = A u_i - theta_i M u_i, rho_i = 2
+ * ||r_i||_{D^-1} (D = lumped mass) and delta_i the distance from theta_i to the
+ * nearest Ritz value outside its cluster (relative gap < 1e-2 joins a cluster),
+ * stop when rho_i^2 / delta_i <= 0.1 tol max(|theta_i|, 1) and
+ * rho_i / delta_i <= angle_tol for every returned pair.
+ * Errors: BMG_EINVAL if k < 1, m < k, m % 4 != 0, m > N_L / 2, n_c + m > 96,
+ * tol <= 0 or NaN, sigma not finite; BMG_ENOCONV when max_cycles is reached
+ * (evals, evecs and stats still hold the current pairs); BMG_ENOMEM.
+ * The call blocks until the result is on the host (evals) / in evecs.
+ * Concurrent calls on one hierarchy are allowed on different streams. */
+int bmg_solve(bmg_hierarchy* h, int32_t k, double sigma, double tol, const bmg_solve_opts* opts,
+              double* evals, double* evecs, int64_t ld, int32_t evecs_on_device, void* stream,
+              bmg_solve_stats* stats);
+
+/* ------------------------------------------------ single-operator hook --- */
+
+typedef enum {
+  BMG_OP_A = 0,          /* y = A_l x                         (FP64)            */
+  BMG_OP_M = 1,          /* y = M_l x                         (FP64)            */
+  BMG_OP_SHIFTED = 2,    /* y = (A_l - sigma M_l) x           (dtype)           */
+  BMG_OP_RESIDUAL = 3,   /* y = f - (A_l - sigma M_l) x       (dtype)           */
+  BMG_OP_SMOOTH_FWD = 4, /* y <- one smoothing sweep of (A_l - sigma M_l) y = f,
+                            colours ascending (GS) / one Jacobi step (dtype)      */
+  BMG_OP_SMOOTH_BWD = 5, /* as above, colours descending                        */
+  BMG_OP_RESTRICT = 6,   /* y [N_{l-1}][m] = P_l^T x [N_l][m]     (dtype)       */
+  BMG_OP_PROLONG_ADD = 7,/* y [N_l][m] += P_l x [N_{l-1}][m]      (dtype)       */
+  BMG_OP_VCYCLE = 8,     /* y = B_sigma x: one correction V-cycle from level l to
+                            l_c (the solver's cycle, dtype)                      */
+  BMG_OP_GAUSSIAN = 9,   /* y [N_l][m] = seeded N(0,1) block (FP64)             */
+  BMG_OP_GRAM = 10,      /* y [m][m2] = x^T f with x [N_l][m], f [N_l][m2] (FP64,
+                            matrix-core reduction over rows)                     */
+  BMG_OP_SYEV = 11,      /* x: symmetric [m][m] FP64; y: [m] eigenvalues ascending
+                            followed by [m][m] row-major orthonormal eigenvectors
+                            (column j = vector j); one-workgroup Jacobi, m <= 96 */
+  BMG_OP_EIGRES = 12     /* y = A_l x - (M_l x) diag(f), f: device [m] doubles;
+                            (FP64 in, output in dtype)                           */
+} bmg_op;
+
+typedef struct {
+  int32_t level;     /* level the operator acts on */
+  int32_t op;        /* bmg_op */
+  int32_t dtype;     /* 0 = FP64 blocks, 1 = FP32 blocks (where the op allows) */
+  int32_t m;         /* columns of the interleaved x / y blocks */
+  int32_t m2;        /* columns of f for BMG_OP_GRAM */
+  int32_t smoother;  /* bmg_smoother for the smoothing ops and BMG_OP_VCYCLE */
+  int32_t nu1, nu2;  /* BMG_OP_VCYCLE sweeps */
+  int32_t l_c;       /* BMG_OP_VCYCLE coarsest level (-1: Weyl rule as in bmg_solve) */
+  int32_t reserved;
+  double sigma;      /* shift of the shifted operator */
+  double omega;      /* Jacobi weight */
+  uint64_t seed;     /* BMG_OP_GAUSSIAN */
+} bmg_apply_args;
+
+/* Enqueue one operator of the solver on `stream` with caller-owned device
+ * blocks x, f, y (sizes as listed per op; f may be NULL where unused).  For
+ * checking each kernel against an independent implementation and for
+ * composing custom cycles.  Returns without synchronising. */
+int bmg_apply(const bmg_hierarchy* h, const bmg_apply_args* args, const void* x, const void* f,
+              void* y, void* stream);
+
+/* ------------------------------------------------------------- serving --- */
+
+typedef struct bmg_server bmg_server;
+
+/* A continuous-batching server: requests are admitted while the device memory
+ * they need (hierarchy + blocks) fits in hbm_budget_bytes and fewer than
+ * max_slots are active; active requests on equal levels advance together, one
+ * grouped launch per step of the cycle.  Each request gives the same result
+ * as a bmg_solve with the same arguments, within the stopping tolerance. */
+int bmg_server_create(int64_t hbm_budget_bytes, int32_t max_slots, bmg_server** out);
+
+/* Queue one request (the descriptor and opts are copied).  *request_id gets
+ * its id.  BMG_EINVAL on invalid arguments, BMG_ENOMEM if the request alone
+ * exceeds the budget. */
+int bmg_server_submit(bmg_server* s, const bmg_surface_desc* desc, int32_t n_refine, int32_t k,
+                      double sigma, double tol, const bmg_solve_opts* opts, uint64_t* request_id);
+
+/* BMG_EBUSY while the request is queued or running; otherwise its final status
+ * (BMG_OK, BMG_ENOCONV, BMG_ECANCELED, ...) after copying evals (host [k]),
+ * evecs (nullable host column-major [k][ld]) and stats (nullable).  A finished
+ * request is forgotten after a successful poll. */
+int bmg_server_poll(bmg_server* s, uint64_t request_id, double* evals, double* evecs, int64_t ld,
+                    bmg_solve_stats* stats, double* latency_ms);
+
+int bmg_server_cancel(bmg_server* s, uint64_t request_id);
+
+/* Stops the worker after finishing the active requests; frees everything. */
+void bmg_server_destroy(bmg_server* s);
+
+/* ---------------------------------------------------------------- misc --- */
+
+const char* bmg_status_string(int status);
+/* Text of the last HIP / validation error seen by the calling thread. */
+const char* bmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BMG_H */

@@ -1,0 +1,280 @@
+"""ctypes binding of libbmg (include/bmg.h): argument marshalling only.
+
+Every step of the solver runs in the HIP library; this module converts Python
+arguments to the C structures and back.  torch is used for device memory
+(torch.cuda tensors) and for the current HIP stream.  If the library is not
+built, importing the package raises; nothing falls back to a CPU path.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbmg.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
+_lib = C.CDLL(LIB_PATH)
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EBUSY, ECANCELED = 0, -1, -2, -3, -4, -5, -6
+KINDS = {"sphere": 0, "ellipsoid": 1, "torus": 2, "custom": 3}
+SMOOTHERS = {"gs": 0, "jacobi": 1}
+PRECISIONS = {"fp64": 0, "mixed": 1}
+EXPORTS = {"xyz": 0, "tri": 1, "parents": 2, "ell_cols": 3, "ell_a": 4, "ell_m": 5, "colours": 6,
+           "lumped": 7, "coarse_eig": 8}
+OPS = {"A": 0, "M": 1, "shifted": 2, "residual": 3, "smooth_fwd": 4, "smooth_bwd": 5,
+       "restrict": 6, "prolong_add": 7, "vcycle": 8, "gaussian": 9, "gram": 10, "syev": 11,
+       "eigres": 12}
+
+PROJECT_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.c_void_p)
+
+
+class SurfaceDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("axes", C.c_double * 3), ("R", C.c_double), ("r", C.c_double),
+                ("nu", C.c_int32), ("nv", C.c_int32), ("n_vert", C.c_int32), ("n_tri", C.c_int32),
+                ("xyz", C.POINTER(C.c_double)), ("tri", C.POINTER(C.c_int32)),
+                ("project", PROJECT_FN), ("ctx", C.c_void_p)]
+
+
+class LevelInfo(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("level", C.c_int32), ("n_vert", C.c_int64),
+                ("n_tri", C.c_int64), ("nnz", C.c_int64), ("ell_width", C.c_int32),
+                ("n_colours", C.c_int32), ("area", C.c_double), ("device_bytes", C.c_int64)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("m", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32), ("smoother", C.c_int32),
+                ("precision", C.c_int32), ("max_cycles", C.c_int32), ("n_c", C.c_int32),
+                ("l_c", C.c_int32), ("omega", C.c_double), ("angle_tol", C.c_double),
+                ("seed", C.c_uint64), ("initial_block", C.POINTER(C.c_double))]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("cycles", C.c_int32), ("converged", C.c_int32), ("m", C.c_int32),
+                ("n_c", C.c_int32), ("l_c", C.c_int32), ("reserved", C.c_int32),
+                ("t_solve_ms", C.c_double), ("max_rho_over_delta", C.c_double),
+                ("max_kato_temple", C.c_double), ("rho", C.POINTER(C.c_double)),
+                ("delta", C.POINTER(C.c_double))]
+
+
+class ApplyArgs(C.Structure):
+    _fields_ = [("level", C.c_int32), ("op", C.c_int32), ("dtype", C.c_int32), ("m", C.c_int32),
+                ("m2", C.c_int32), ("smoother", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
+                ("l_c", C.c_int32), ("reserved", C.c_int32), ("sigma", C.c_double),
+                ("omega", C.c_double), ("seed", C.c_uint64)]
+
+
+_H = C.c_void_p
+_sig = {
+    "bmg_build_hierarchy": (C.c_int, [C.POINTER(SurfaceDesc), C.c_int32, C.c_void_p, C.POINTER(_H)]),
+    "bmg_build_hierarchy_host": (C.c_int, [C.POINTER(SurfaceDesc), C.c_int32, C.POINTER(_H)]),
+    "bmg_free_hierarchy": (None, [_H]),
+    "bmg_hierarchy_info": (C.c_int, [_H, C.c_int32, C.POINTER(LevelInfo)]),
+    "bmg_hierarchy_export": (C.c_int, [_H, C.c_int32, C.c_int32, C.c_void_p, C.c_int64,
+                                       C.POINTER(C.c_int64)]),
+    "bmg_solve_opts_default": (None, [C.POINTER(SolveOpts)]),
+    "bmg_solve": (C.c_int, [_H, C.c_int32, C.c_double, C.c_double, C.POINTER(SolveOpts),
+                            C.POINTER(C.c_double), C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
+                            C.POINTER(SolveStats)]),
+    "bmg_apply": (C.c_int, [_H, C.POINTER(ApplyArgs), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "bmg_server_create": (C.c_int, [C.c_int64, C.c_int32, C.POINTER(C.c_void_p)]),
+    "bmg_server_submit": (C.c_int, [C.c_void_p, C.POINTER(SurfaceDesc), C.c_int32, C.c_int32,
+                                    C.c_double, C.c_double, C.POINTER(SolveOpts),
+                                    C.POINTER(C.c_uint64)]),
+    "bmg_server_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                  C.c_int64, C.POINTER(SolveStats), C.POINTER(C.c_double)]),
+    "bmg_server_cancel": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "bmg_server_destroy": (None, [C.c_void_p]),
+    "bmg_status_string": (C.c_char_p, [C.c_int]),
+    "bmg_last_error": (C.c_char_p, []),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = sorted(_sig)
+
+
+class BMGError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.bmg_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {_lib.bmg_status_string(status).decode()} ({status}): {msg}")
+
+
+def _check(st, where, allow=()):
+    if st != OK and st not in allow:
+        raise BMGError(st, where)
+    return st
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def surface_desc(kind="sphere", axes=(1.0, 1.0, 1.0), R=1.0, r=0.4, nu=64, nv=32, xyz=None, tri=None,
+                 project=None):
+    """Build a SurfaceDesc; returns (desc, keepalive) (keep both alive during the call)."""
+    d = SurfaceDesc()
+    d.kind = KINDS[kind]
+    d.axes = (C.c_double * 3)(*[float(a) for a in axes])
+    d.R, d.r, d.nu, d.nv = float(R), float(r), int(nu), int(nv)
+    keep = []
+    if kind == "custom":
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        keep += [xyz, tri]
+        d.n_vert, d.n_tri = len(xyz), len(tri)
+        d.xyz = xyz.ctypes.data_as(C.POINTER(C.c_double))
+        d.tri = tri.ctypes.data_as(C.POINTER(C.c_int32))
+        if project is not None:
+            def _cb(p, ctx):
+                arr = np.ctypeslib.as_array(p, shape=(3,))
+                arr[:] = project(arr.copy())
+            cb = PROJECT_FN(_cb)
+            keep.append(cb)
+            d.project = cb
+    return d, keep
+
+
+class Hierarchy:
+    """A device-resident (or host-only) BMG hierarchy of one surface."""
+
+    def __init__(self, kind="sphere", n_refine=3, axes=(1.0, 1.0, 1.0), R=1.0, r=0.4, nu=64, nv=32,
+                 xyz=None, tri=None, project=None, device=True, stream=None):
+        d, keep = surface_desc(kind, axes, R, r, nu, nv, xyz, tri, project)
+        h = _H()
+        if device:
+            st = _lib.bmg_build_hierarchy(C.byref(d), int(n_refine), _stream_ptr(stream), C.byref(h))
+        else:
+            st = _lib.bmg_build_hierarchy_host(C.byref(d), int(n_refine), C.byref(h))
+        _check(st, "bmg_build_hierarchy")
+        self._h = h
+        self.device = device
+        self.n_levels = self.info(0)["n_levels"]
+        self.N = self.info(self.n_levels - 1)["n_vert"]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.bmg_free_hierarchy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def info(self, level):
+        out = LevelInfo()
+        _check(_lib.bmg_hierarchy_info(self._h, int(level), C.byref(out)), "bmg_hierarchy_info")
+        return {f: getattr(out, f) for f, _ in LevelInfo._fields_}
+
+    def export(self, level, what):
+        need = C.c_int64(0)
+        _lib.bmg_hierarchy_export(self._h, int(level), EXPORTS[what], None, 0, C.byref(need))
+        inf = self.info(level)
+        n, W = inf["n_vert"], inf["ell_width"]
+        if what in ("xyz",):
+            arr = np.empty((n, 3), np.float64)
+        elif what == "tri":
+            arr = np.empty((inf["n_tri"], 3), np.int32)
+        elif what == "parents":
+            arr = np.empty((need.value // 8, 2), np.int32)
+        elif what == "ell_cols":
+            arr = np.empty((n, W), np.int32)
+        elif what in ("ell_a", "ell_m"):
+            arr = np.empty((n, W), np.float64)
+        elif what == "colours":
+            arr = np.empty(n, np.int32)
+        elif what == "lumped":
+            arr = np.empty(n, np.float64)
+        elif what == "coarse_eig":
+            arr = np.empty(need.value // 8, np.float64)
+        else:
+            raise KeyError(what)
+        _check(_lib.bmg_hierarchy_export(self._h, int(level), EXPORTS[what], arr.ctypes.data,
+                                         arr.nbytes, C.byref(need)), "bmg_hierarchy_export")
+        if what == "coarse_eig":
+            n0 = n
+            return arr[:n0], arr[n0:].reshape(n0, n0)
+        return arr
+
+    def solve(self, k, sigma=0.0, tol=1e-8, m=0, nu1=2, nu2=2, smoother="gs", precision="fp64",
+              max_cycles=200, n_c=0, l_c=-1, omega=2.0 / 3.0, angle_tol=1e-7, seed=0,
+              initial_block=None, evecs="host", stream=None, allow_noconv=False):
+        """Returns (evals [k], evecs [N, k] or None, stats dict).
+
+        evecs: "host" -> numpy array, "device" -> torch.cuda tensor view, None.
+        """
+        o = SolveOpts()
+        _lib.bmg_solve_opts_default(C.byref(o))
+        o.m, o.nu1, o.nu2 = int(m), int(nu1), int(nu2)
+        o.smoother = SMOOTHERS[smoother]
+        o.precision = PRECISIONS[precision]
+        o.max_cycles, o.n_c, o.l_c = int(max_cycles), int(n_c), int(l_c)
+        o.omega, o.angle_tol, o.seed = float(omega), float(angle_tol), int(seed)
+        keep = None
+        if initial_block is not None:
+            keep = np.ascontiguousarray(initial_block, dtype=np.float64)
+            o.initial_block = keep.ctypes.data_as(C.POINTER(C.c_double))
+        evals = np.zeros(k, np.float64)
+        rho = np.zeros(k, np.float64)
+        delta = np.zeros(k, np.float64)
+        st = SolveStats()
+        st.rho = rho.ctypes.data_as(C.POINTER(C.c_double))
+        st.delta = delta.ctypes.data_as(C.POINTER(C.c_double))
+        out = None
+        ptr, on_dev = None, 0
+        if evecs == "host":
+            out = np.zeros((k, self.N), np.float64)
+            ptr = out.ctypes.data
+        elif evecs == "device":
+            import torch
+            out = torch.empty((k, self.N), dtype=torch.float64, device="cuda")
+            ptr, on_dev = out.data_ptr(), 1
+        status = _lib.bmg_solve(self._h, int(k), float(sigma), float(tol), C.byref(o),
+                                evals.ctypes.data_as(C.POINTER(C.c_double)), ptr, int(self.N),
+                                on_dev, _stream_ptr(stream) if self.device else None, C.byref(st))
+        _check(status, "bmg_solve", allow=(ENOCONV,) if allow_noconv else ())
+        stats = {f: getattr(st, f) for f, _ in SolveStats._fields_ if f not in ("rho", "delta")}
+        stats.update(rho=rho, delta=delta, status=status)
+        V = None if out is None else out.T
+        return evals, V, stats
+
+    def apply(self, op, x=None, f=None, y=None, level=None, m=None, m2=0, dtype=None, sigma=0.0,
+              smoother="gs", nu1=2, nu2=2, l_c=-1, omega=2.0 / 3.0, seed=0, stream=None):
+        """Enqueue one operator on torch.cuda tensors (see bmg_op in include/bmg.h)."""
+        import torch
+        a = ApplyArgs()
+        a.level = self.n_levels - 1 if level is None else int(level)
+        a.op = OPS[op]
+        ref = x if x is not None else y
+        if dtype is None:
+            dtype = 1 if ref.dtype == torch.float32 else 0
+        a.dtype = int(dtype)
+        a.m = int(m if m is not None else ref.shape[-1])
+        a.m2 = int(m2)
+        a.smoother = SMOOTHERS[smoother]
+        a.nu1, a.nu2, a.l_c = int(nu1), int(nu2), int(l_c)
+        a.sigma, a.omega, a.seed = float(sigma), float(omega), int(seed)
+        for t in (x, f, y):
+            if t is not None:
+                assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+        p = lambda t: None if t is None else C.c_void_p(t.data_ptr())
+        _check(_lib.bmg_apply(self._h, C.byref(a), p(x), p(f), p(y), _stream_ptr(stream)), f"bmg_apply({op})")
+        return y
+
+
+def status_string(st):
+    return _lib.bmg_status_string(int(st)).decode()

@@ -1,0 +1,187 @@
+// Internal declarations of the BMG library: host-side hierarchy data, device
+// level data, per-solve workspace and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/bmg.h"
+
+namespace bmg {
+
+// ------------------------------------------------------------------ errors --
+void set_error(const char* fmt, ...);
+const char* get_error();
+
+#define BMG_HIP(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      ::bmg::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                       __LINE__);                                                      \
+      return BMG_EDEVICE;                                                              \
+    }                                                                                  \
+  } while (0)
+
+#define BMG_CHECK(cond, ...)          \
+  do {                                \
+    if (!(cond)) {                    \
+      ::bmg::set_error(__VA_ARGS__);  \
+      return BMG_EINVAL;              \
+    }                                 \
+  } while (0)
+
+#define BMG_TRY(expr)          \
+  do {                         \
+    int s_ = (expr);           \
+    if (s_ != BMG_OK) return s_; \
+  } while (0)
+
+// ------------------------------------------------------------- host level --
+struct HostLevel {
+  int64_t n = 0, n_prev = 0, n_tri = 0;
+  std::vector<double> xyz;        // [n][3]
+  std::vector<int32_t> tri;       // [n_tri][3]
+  std::vector<int32_t> parents;   // [n - n_prev][2], a < b
+  int32_t W = 0;                  // ELL row width (diagonal first)
+  std::vector<int32_t> cols;      // [n][W], padding repeats the row index
+  std::vector<double> a, mm;      // [n][W] values of A and M, padding 0
+  std::vector<double> lumped;     // [n] row sums of M
+  std::vector<int32_t> colour;    // [n]
+  int32_t n_colours = 0;
+  std::vector<int32_t> colour_ptr;   // [n_colours + 1]
+  std::vector<int32_t> colour_rows;  // [n] rows grouped by colour, ascending inside
+  int32_t RW = 0;                    // children per coarse vertex (restriction gather width)
+  std::vector<int32_t> rtab;         // [n_prev][RW] new vertices adjacent to coarse vertex i, -1 pad
+  double area = 0.0;
+  int64_t nnz = 0;
+};
+
+// Mesh construction (mesh.cpp).  Returns BMG_OK or BMG_EINVAL (+ set_error).
+int build_host_levels(const bmg_surface_desc* d, int n_refine, std::vector<HostLevel>& out);
+// P1 assembly to ELL + colouring + restriction tables (assemble.cpp).
+int assemble_level(HostLevel& lv, const HostLevel* coarser);
+// Setup-time dense generalized symmetric-definite eigensolver (dense_host.cpp):
+// A x = lambda M x, n x n row-major; lam ascending; X row-major, column j = x_j,
+// X^T M X = I.  Cholesky reduction + cyclic Jacobi.
+int dense_sygv(int n, const std::vector<double>& A, const std::vector<double>& M,
+               std::vector<double>& lam, std::vector<double>& X);
+
+// ----------------------------------------------------------- device level --
+struct DevLevel {
+  int64_t n = 0, n_prev = 0;
+  int32_t W = 0, RW = 0, n_colours = 0;
+  int32_t* cols = nullptr;
+  double* a64 = nullptr;
+  double* m64 = nullptr;
+  float* a32 = nullptr;
+  float* m32 = nullptr;
+  double* dinv = nullptr;         // 1 / lumped mass
+  int32_t* parents = nullptr;     // [n - n_prev][2]
+  int32_t* rtab = nullptr;        // [n_prev][RW]
+  int32_t* colour_rows = nullptr; // [n]
+  std::vector<int32_t> colour_ptr;
+  int64_t bytes = 0;
+};
+
+}  // namespace bmg
+
+struct bmg_hierarchy {
+  int device = 0;
+  std::vector<bmg::HostLevel> host;
+  std::vector<bmg::DevLevel> dev;
+  // level-0 generalized eigendecomposition (Alg. 2 step 1)
+  int64_t n0 = 0;
+  std::vector<double> lam0;  // [n0] ascending
+  std::vector<double> phi0;  // [n0][n0] row-major, column j = eigenvector j
+  double* d_phi0_64 = nullptr;   // [n0][n0]
+  double* d_phi0t_64 = nullptr;  // transpose
+  float* d_phi0_32 = nullptr;
+  float* d_phi0t_32 = nullptr;
+  std::mutex ws_mutex;
+  std::vector<struct bmg_workspace*> ws_pool;
+};
+
+namespace bmg {
+
+int upload_hierarchy(bmg_hierarchy* h, hipStream_t s);
+void free_device(bmg_hierarchy* h);
+
+// ------------------------------------------------------------- launchers --
+// Interleaved blocks [n][m]; T = double or float.  All launchers enqueue on s
+// and return BMG_OK or BMG_EDEVICE.
+enum RowMode { ROW_SHIFTED = 0, ROW_RESIDUAL = 1 };
+
+template <typename T>
+int launch_shifted(const DevLevel& L, int mode, double sigma, const T* x, const T* f, T* y, int m,
+                   hipStream_t s);
+int launch_spmm_am(const DevLevel& L, const double* x, double* ya, double* ym, int m,
+                   hipStream_t s);
+// y = A x - (M x) diag(theta) (FP64) stored as T with sign `sgn` (+1 or -1),
+// rho2_part[b][m] = per-block partial sums of r^2 / lumped (FP64) if non-null.
+template <typename T>
+int launch_eigres(const DevLevel& L, const double* x, const double* theta, double sgn, T* y,
+                  double* rho2_part, int nblk, int m, hipStream_t s);
+int eigres_blocks(const DevLevel& L, int m);
+int launch_colsum(const double* part, int nblk, int m, double* out, hipStream_t s);
+
+template <typename T>
+int launch_jacobi(const DevLevel& L, double sigma, double omega, const T* x, const T* f, T* y,
+                  bool x_is_zero, int m, hipStream_t s);
+template <typename T>
+int launch_gs_colour(const DevLevel& L, int colour, double sigma, T* x, const T* f, int m,
+                     hipStream_t s);
+template <typename T>
+int launch_restrict(const DevLevel& fine, const T* x, T* y, int m, hipStream_t s);
+template <typename T>
+int launch_prolong_add(const DevLevel& fine, const T* x, T* y, int m, hipStream_t s);
+template <typename T>
+int launch_fill(T* y, int64_t count, T value, hipStream_t s);
+template <typename T>
+int launch_dense_apply(int n, const T* mat, const T* g, const T* x, T* y, int m, hipStream_t s);
+// U (FP64) += e (T)
+template <typename T>
+int launch_add_to(double* u, const T* e, int64_t count, hipStream_t s);
+template <typename T>
+int launch_convert(const double* x, T* y, int64_t count, hipStream_t s);
+int launch_gaussian(double* y, int64_t n, int m, uint64_t seed, hipStream_t s);
+
+// Gram: G[nz][ny] = Z^T Y with Z = [z1 (w1 cols) | z2 (w2 cols)], Y = [y1 | y2]
+// (v1, v2 cols), all FP64 [n][w] blocks.  part: [nblk][nzp][nyp].
+struct GramPlan {
+  int nz, ny, nzp, nyp, nblk;
+};
+GramPlan gram_plan(int64_t n, int nz, int ny);
+int launch_gram(const GramPlan& p, int64_t n, const double* z1, int w1, const double* z2, int w2,
+                const double* y1, int v1, const double* y2, int v2, double* part, double* G,
+                hipStream_t s);
+// U[n][m] = Z Y, Z = [z1 (w1) | z2 (w2)], Y [w1+w2][m] device
+int launch_update_zy(int64_t n, const double* z1, int w1, const double* z2, int w2,
+                     const double* Y, double* U, int m, hipStream_t s);
+
+// One-workgroup Ritz step (see kernels_dense.hip).
+struct RitzArgs {
+  int n_c, m, nz;        // nz = n_c + m
+  double sigma;
+  const double* G;       // [nz][2m]: Z^T [A U | M U]
+  const double* GW;      // [n_c][2 n_c]: W^T [A W | M W] (constant during a solve)
+  double* Y;             // out [nz][m]
+  double* theta;         // out [m] ascending
+  double* scratch;       // [>= 6 nz nz + 4 nz] doubles
+  int* status;           // out: 0 ok, 1 rank loss below m, 2 Jacobi did not converge
+};
+int launch_ritz(const RitzArgs& a, hipStream_t s);
+int launch_syev(int n, const double* A, double* w, double* V, int* status, hipStream_t s);
+int ritz_scratch_doubles(int nz);
+
+// column-wise argmax |U[:, sel_j]| (lowest row on ties) and output writer
+int launch_signs(int64_t n, const double* U, int m, const int* sel, int k, double* sign_out,
+                 double* part_val, int* part_idx, int nblk, hipStream_t s);
+int launch_write_evecs(int64_t n, const double* U, int m, const int* sel, const double* sign,
+                       int k, double* out, int64_t ld, hipStream_t s);
+
+}  // namespace bmg

@@ -1,0 +1,86 @@
+// Device-resident hierarchy: upload of the host levels, the level-0
+// eigendecomposition, sizes and export for inspection.
+#include <cstring>
+
+#include "bmg_internal.h"
+
+namespace bmg {
+
+namespace {
+
+template <typename T>
+int upload(T** dst, const T* src, size_t count, hipStream_t s, int64_t& bytes) {
+  *dst = nullptr;
+  if (count == 0) return BMG_OK;
+  if (hipMalloc(reinterpret_cast<void**>(dst), count * sizeof(T)) != hipSuccess) {
+    set_error("hipMalloc of %zu bytes failed", count * sizeof(T));
+    return BMG_ENOMEM;
+  }
+  bytes += int64_t(count * sizeof(T));
+  BMG_HIP(hipMemcpyAsync(*dst, src, count * sizeof(T), hipMemcpyHostToDevice, s));
+  return BMG_OK;
+}
+
+}  // namespace
+
+int upload_hierarchy(bmg_hierarchy* h, hipStream_t s) {
+  const int nl = int(h->host.size());
+  h->dev.resize(nl);
+  std::vector<std::vector<float>> keep32;  // host staging must live until the stream syncs
+  for (int l = 0; l < nl; ++l) {
+    const HostLevel& H = h->host[l];
+    DevLevel& D = h->dev[l];
+    D.n = H.n;
+    D.n_prev = H.n_prev;
+    D.W = H.W;
+    D.RW = H.RW;
+    D.n_colours = H.n_colours;
+    D.colour_ptr = H.colour_ptr;
+    D.bytes = 0;
+    const size_t nw = size_t(H.n) * H.W;
+    BMG_TRY(upload(&D.cols, H.cols.data(), nw, s, D.bytes));
+    BMG_TRY(upload(&D.a64, H.a.data(), nw, s, D.bytes));
+    BMG_TRY(upload(&D.m64, H.mm.data(), nw, s, D.bytes));
+    keep32.emplace_back(H.a.begin(), H.a.end());
+    BMG_TRY(upload(&D.a32, keep32.back().data(), nw, s, D.bytes));
+    keep32.emplace_back(H.mm.begin(), H.mm.end());
+    BMG_TRY(upload(&D.m32, keep32.back().data(), nw, s, D.bytes));
+    std::vector<double> dinv(H.n);
+    for (int64_t i = 0; i < H.n; ++i) dinv[i] = 1.0 / H.lumped[i];
+    BMG_TRY(upload(&D.dinv, dinv.data(), size_t(H.n), s, D.bytes));
+    BMG_TRY(upload(&D.parents, H.parents.data(), H.parents.size(), s, D.bytes));
+    BMG_TRY(upload(&D.rtab, H.rtab.data(), H.rtab.size(), s, D.bytes));
+    BMG_TRY(upload(&D.colour_rows, H.colour_rows.data(), H.colour_rows.size(), s, D.bytes));
+    BMG_HIP(hipStreamSynchronize(s));  // dinv is a local
+  }
+  // level-0 eigendecomposition on the device (FP64 and FP32, with transposes)
+  const int64_t n0 = h->n0;
+  std::vector<double> t64(size_t(n0) * n0);
+  for (int64_t i = 0; i < n0; ++i)
+    for (int64_t j = 0; j < n0; ++j) t64[size_t(j) * n0 + i] = h->phi0[size_t(i) * n0 + j];
+  std::vector<float> p32(h->phi0.begin(), h->phi0.end()), t32(t64.begin(), t64.end());
+  int64_t b0 = 0;
+  BMG_TRY(upload(&h->d_phi0_64, h->phi0.data(), h->phi0.size(), s, b0));
+  BMG_TRY(upload(&h->d_phi0t_64, t64.data(), t64.size(), s, b0));
+  BMG_TRY(upload(&h->d_phi0_32, p32.data(), p32.size(), s, b0));
+  BMG_TRY(upload(&h->d_phi0t_32, t32.data(), t32.size(), s, b0));
+  h->dev[0].bytes += b0;
+  BMG_HIP(hipStreamSynchronize(s));
+  return BMG_OK;
+}
+
+void free_device(bmg_hierarchy* h) {
+  for (auto& D : h->dev) {
+    void* ptrs[] = {D.cols, D.a64, D.m64, D.a32, D.m32, D.dinv, D.parents, D.rtab, D.colour_rows};
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+    D = DevLevel();
+  }
+  void* ptrs[] = {h->d_phi0_64, h->d_phi0t_64, h->d_phi0_32, h->d_phi0t_32};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  h->d_phi0_64 = h->d_phi0t_64 = nullptr;
+  h->d_phi0_32 = h->d_phi0t_32 = nullptr;
+}
+
+}  // namespace bmg

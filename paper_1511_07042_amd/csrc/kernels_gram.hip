@@ -1,0 +1,199 @@
+// Tall-skinny FP64 products of the Rayleigh-Ritz step.
+//
+// Gram: G = Z^T Y over all n rows, Z = [z1 | z2] (nz columns), Y = [y1 | y2]
+// (ny columns), interleaved row-major blocks.  This is the dense contraction
+// of the enriched pencil (eq. pb-c-aux-mat: the blocks P_H A_h U^h, (U^h)^T
+// A_h U^h and their M counterparts, here evaluated on the finest level), and it
+// runs on the FP64 matrix cores: v_mfma_f64_16x16x4f64 takes a 16x4 slice of
+// Z^T and a 4x16 slice of Y, i.e. four rows of both blocks per instruction.
+// Each 256-thread block owns a contiguous range of rows; its four wavefronts
+// split the 16x16 output tiles by tile column.  Per-block results go to a
+// partial buffer that a second kernel sums in a fixed order (deterministic).
+//
+// Update: U = Z Y for a small Y (the new Ritz vectors U <- [W_c, U'] Y).
+#include "bmg_internal.h"
+
+namespace bmg {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+int check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error("kernel launch failed: %s", hipGetErrorString(e));
+    return BMG_EDEVICE;
+  }
+  return BMG_OK;
+}
+
+__device__ __forceinline__ double zcol(const double* __restrict__ z1, int w1,
+                                       const double* __restrict__ z2, int w2, int64_t r, int c) {
+  if (c < w1) return z1[r * w1 + c];
+  c -= w1;
+  if (c < w2) return z2[r * w2 + c];
+  return 0.0;
+}
+
+// TI: tiles along nz (<= 6), TJW: tile columns per wavefront (<= 3).
+template <int TI, int TJW>
+__global__ void __launch_bounds__(256) k_gram(int64_t n, int64_t rows_per_block, int nzp, int nyp,
+                                              const double* __restrict__ z1, int w1,
+                                              const double* __restrict__ z2, int w2,
+                                              const double* __restrict__ y1, int v1,
+                                              const double* __restrict__ y2, int v2,
+                                              double* __restrict__ part) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int TJ = nyp / 16;
+  const int li = lane & 15;   // row of A / column of B / column of D
+  const int lk = lane >> 4;   // k index of the fragment
+  d4 acc[TI][TJW];
+  for (int i = 0; i < TI; ++i)
+    for (int t = 0; t < TJW; ++t) acc[i][t] = d4{0.0, 0.0, 0.0, 0.0};
+  const int64_t rb = int64_t(blockIdx.x) * rows_per_block;
+  const int64_t re = rb + rows_per_block < n ? rb + rows_per_block : n;
+  for (int64_t r0 = rb; r0 < re; r0 += 4) {
+    const int64_t r = r0 + lk;
+    const bool ok = r < re;
+    double a[TI];
+    for (int i = 0; i < TI; ++i) a[i] = ok ? zcol(z1, w1, z2, w2, r, 16 * i + li) : 0.0;
+    for (int t = 0; t < TJW; ++t) {
+      const int tj = wave + 4 * t;
+      if (tj >= TJ) break;
+      const double b = ok ? zcol(y1, v1, y2, v2, r, 16 * tj + li) : 0.0;
+      for (int i = 0; i < TI; ++i)
+        acc[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b, acc[i][t], 0, 0, 0);
+    }
+  }
+  double* out = part + int64_t(blockIdx.x) * nzp * nyp;
+  for (int t = 0; t < TJW; ++t) {
+    const int tj = wave + 4 * t;
+    if (tj >= TJ) break;
+    for (int i = 0; i < TI; ++i)
+      for (int v = 0; v < 4; ++v) out[(16 * i + 4 * lk + v) * nyp + 16 * tj + li] = acc[i][t][v];
+  }
+}
+
+__global__ void k_gram_reduce(const double* __restrict__ part, int nblk, int nzp, int nyp, int nz,
+                              int ny, double* __restrict__ G) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nz * ny) return;
+  const int i = e / ny, j = e - (e / ny) * ny;
+  const int64_t off = int64_t(i) * nyp + j;
+  const int64_t stride = int64_t(nzp) * nyp;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[b * stride + off];
+  G[e] = s;
+}
+
+// U[r][c] = sum_i Z[r][i] Y[i][c];  Y staged in LDS.  Thread per (row, 2 cols).
+__global__ void __launch_bounds__(256) k_update_zy(int64_t n, const double* __restrict__ z1, int w1,
+                                                   const double* __restrict__ z2, int w2,
+                                                   const double* __restrict__ Y, int m, int cpr,
+                                                   int rpb, double* __restrict__ U) {
+  extern __shared__ double ys[];
+  const int nz = w1 + w2;
+  for (int e = threadIdx.x; e < nz * m; e += blockDim.x) ys[e] = Y[e];
+  __syncthreads();
+  const int rloc = threadIdx.x / cpr;
+  const int ch = threadIdx.x - rloc * cpr;
+  if (rloc >= rpb) return;
+  for (int64_t r = int64_t(blockIdx.x) * rpb + rloc; r < n; r += int64_t(gridDim.x) * rpb) {
+    double c0 = 0.0, c1 = 0.0;
+    for (int i = 0; i < w1; ++i) {
+      const double z = z1[r * w1 + i];
+      c0 += z * ys[i * m + 2 * ch];
+      c1 += z * ys[i * m + 2 * ch + 1];
+    }
+    for (int i = 0; i < w2; ++i) {
+      const double z = z2[r * w2 + i];
+      c0 += z * ys[(w1 + i) * m + 2 * ch];
+      c1 += z * ys[(w1 + i) * m + 2 * ch + 1];
+    }
+    U[r * m + 2 * ch] = c0;
+    U[r * m + 2 * ch + 1] = c1;
+  }
+}
+
+template <int TI, int TJW>
+void gram_dispatch_launch(const GramPlan& p, int64_t n, int64_t rpb, const double* z1, int w1,
+                          const double* z2, int w2, const double* y1, int v1, const double* y2,
+                          int v2, double* part, hipStream_t s) {
+  k_gram<TI, TJW><<<p.nblk, 256, 0, s>>>(n, rpb, p.nzp, p.nyp, z1, w1, z2, w2, y1, v1, y2, v2, part);
+}
+
+}  // namespace
+
+GramPlan gram_plan(int64_t n, int nz, int ny) {
+  GramPlan p;
+  p.nz = nz;
+  p.ny = ny;
+  p.nzp = (nz + 15) / 16 * 16;
+  p.nyp = (ny + 15) / 16 * 16;
+  int64_t blocks = (n + 255) / 256;  // at least 256 rows per block
+  p.nblk = int(blocks < 512 ? (blocks > 0 ? blocks : 1) : 512);
+  return p;
+}
+
+int launch_gram(const GramPlan& p, int64_t n, const double* z1, int w1, const double* z2, int w2,
+                const double* y1, int v1, const double* y2, int v2, double* part, double* G,
+                hipStream_t s) {
+  const int TI = p.nzp / 16;
+  const int TJ = p.nyp / 16;
+  const int TJW = (TJ + 3) / 4;
+  if (TI < 1 || TI > 6 || TJW < 1 || TJW > 3) {
+    set_error("gram: unsupported shape nz=%d ny=%d", p.nz, p.ny);
+    return BMG_EINVAL;
+  }
+  int64_t rpb = (n + p.nblk - 1) / p.nblk;
+  rpb = (rpb + 3) / 4 * 4;
+#define GL(a, b) \
+  gram_dispatch_launch<a, b>(p, n, rpb, z1, w1, z2, w2, y1, v1, y2, v2, part, s)
+  switch (TI * 4 + TJW) {
+    case 1 * 4 + 1: GL(1, 1); break;
+    case 1 * 4 + 2: GL(1, 2); break;
+    case 1 * 4 + 3: GL(1, 3); break;
+    case 2 * 4 + 1: GL(2, 1); break;
+    case 2 * 4 + 2: GL(2, 2); break;
+    case 2 * 4 + 3: GL(2, 3); break;
+    case 3 * 4 + 1: GL(3, 1); break;
+    case 3 * 4 + 2: GL(3, 2); break;
+    case 3 * 4 + 3: GL(3, 3); break;
+    case 4 * 4 + 1: GL(4, 1); break;
+    case 4 * 4 + 2: GL(4, 2); break;
+    case 4 * 4 + 3: GL(4, 3); break;
+    case 5 * 4 + 1: GL(5, 1); break;
+    case 5 * 4 + 2: GL(5, 2); break;
+    case 5 * 4 + 3: GL(5, 3); break;
+    case 6 * 4 + 1: GL(6, 1); break;
+    case 6 * 4 + 2: GL(6, 2); break;
+    case 6 * 4 + 3: GL(6, 3); break;
+  }
+#undef GL
+  int st = check_launch();
+  if (st != BMG_OK) return st;
+  const int tot = p.nz * p.ny;
+  k_gram_reduce<<<(tot + 255) / 256, 256, 0, s>>>(part, p.nblk, p.nzp, p.nyp, p.nz, p.ny, G);
+  return check_launch();
+}
+
+int launch_update_zy(int64_t n, const double* z1, int w1, const double* z2, int w2,
+                     const double* Y, double* U, int m, hipStream_t s) {
+  const int cpr = m / 2;
+  const int rpb = cpr >= 256 ? 1 : 256 / cpr;
+  const int block = rpb * cpr;
+  int64_t groups = (n + rpb - 1) / rpb;
+  const int grid = int(groups < 4096 ? groups : 4096);
+  const size_t shm = size_t(w1 + w2) * m * sizeof(double);
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_update_zy, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        160 * 1024);
+    attr_set = true;
+  }
+  k_update_zy<<<grid, block, shm, s>>>(n, z1, w1, z2, w2, Y, m, cpr, rpb, U);
+  return check_launch();
+}
+
+}  // namespace bmg

@@ -1,0 +1,575 @@
+// Row-parallel kernels of the BMG cycle on interleaved vector blocks [n][m].
+//
+// Thread mapping (all row kernels): a block covers `rpb` whole rows, each row
+// split into cpr = m / VW chunks of 16 bytes (VW = 2 doubles or 4 floats), so a
+// wavefront reads whole 16-byte chunks of consecutive rows: the gathered
+// neighbour rows x[j][*] are contiguous segments and the outputs are fully
+// coalesced.  Matrix rows are ELL with the diagonal in slot 0 and padding
+// slots that point at the row itself with value 0.  Blocks loop over row
+// groups (grid-stride) so grids stay a few thousand blocks at most.
+#include <cmath>
+
+#include "bmg_internal.h"
+
+namespace bmg {
+namespace {
+
+template <typename T>
+struct alignas(16) Vec {
+  static constexpr int N = 16 / sizeof(T);
+  T v[N];
+};
+
+template <typename T>
+__device__ __forceinline__ Vec<T> ld(const T* p) {
+  return *reinterpret_cast<const Vec<T>*>(p);
+}
+template <typename T>
+__device__ __forceinline__ void st(T* p, const Vec<T>& x) {
+  *reinterpret_cast<Vec<T>*>(p) = x;
+}
+
+struct Geom {
+  int cpr, rpb, block, grid;
+};
+
+template <typename T>
+Geom row_geom(int64_t n, int m, int max_grid = 8192) {
+  Geom g;
+  g.cpr = m / Vec<T>::N;
+  g.rpb = g.cpr >= 256 ? 1 : 256 / g.cpr;
+  g.block = g.rpb * g.cpr;
+  int64_t groups = (n + g.rpb - 1) / g.rpb;
+  g.grid = int(groups < max_grid ? (groups > 0 ? groups : 1) : max_grid);
+  return g;
+}
+
+int check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error("kernel launch failed: %s", hipGetErrorString(e));
+    return BMG_EDEVICE;
+  }
+  return BMG_OK;
+}
+
+// ---------------------------------------------------------- shifted ops --
+enum { K_SHIFTED = 0, K_RESIDUAL = 1, K_JACOBI = 2, K_JACOBI0 = 3 };
+
+// MODE K_SHIFTED: y = S x; K_RESIDUAL: y = f - S x;
+// K_JACOBI: y = x + omega (f - S x) / d; K_JACOBI0: y = omega f / d  (x = 0),
+// with S = A - sigma M combined on the fly and d = S_ii.
+// FUSE: also u[r] += y[r] (FP64 iterate update on the last sweep).
+template <typename T, int MODE, bool FUSE>
+__global__ void __launch_bounds__(256) k_rowop(int64_t n, int W, int m, int cpr, int rpb,
+                                               const int* __restrict__ cols,
+                                               const T* __restrict__ a, const T* __restrict__ mm,
+                                               T sigma, T omega, const T* __restrict__ x,
+                                               const T* __restrict__ f, T* __restrict__ y,
+                                               double* __restrict__ u) {
+  constexpr int VW = Vec<T>::N;
+  const int rloc = threadIdx.x / cpr;
+  const int ch = threadIdx.x - rloc * cpr;
+  for (int64_t r = int64_t(blockIdx.x) * rpb + rloc; r < n; r += int64_t(gridDim.x) * rpb) {
+    const int64_t base = r * W;
+    Vec<T> acc, xr;
+    for (int c = 0; c < VW; ++c) acc.v[c] = T(0);
+    T d = a[base] - sigma * mm[base];
+    if (MODE == K_JACOBI0) {
+      const Vec<T> fv = ld(f + r * m + ch * VW);
+      for (int c = 0; c < VW; ++c) acc.v[c] = omega * fv.v[c] / d;
+    } else {
+      for (int k = 0; k < W; ++k) {
+        const int j = cols[base + k];
+        const T s = a[base + k] - sigma * mm[base + k];
+        const Vec<T> xv = ld(x + int64_t(j) * m + ch * VW);
+        if (k == 0) xr = xv;
+        for (int c = 0; c < VW; ++c) acc.v[c] += s * xv.v[c];
+      }
+      if (MODE == K_RESIDUAL || MODE == K_JACOBI) {
+        const Vec<T> fv = ld(f + r * m + ch * VW);
+        for (int c = 0; c < VW; ++c) acc.v[c] = fv.v[c] - acc.v[c];
+      }
+      if (MODE == K_JACOBI)
+        for (int c = 0; c < VW; ++c) acc.v[c] = xr.v[c] + omega * acc.v[c] / d;
+    }
+    st(y + r * m + ch * VW, acc);
+    if (FUSE) {
+      double* up = u + r * m + ch * VW;
+      for (int c = 0; c < VW; ++c) up[c] += double(acc.v[c]);
+    }
+  }
+}
+
+// Gauss-Seidel update of the rows of one colour, in place:
+// x_r <- x_r + (f_r - (S x)_r) / S_rr.  Rows of one colour are never adjacent,
+// so the rows of a pass are independent.
+template <typename T, bool FUSE>
+__global__ void __launch_bounds__(256) k_gs(int64_t cnt, const int* __restrict__ rows, int W, int m,
+                                            int cpr, int rpb, const int* __restrict__ cols,
+                                            const T* __restrict__ a, const T* __restrict__ mm,
+                                            T sigma, T* x, const T* __restrict__ f,
+                                            double* __restrict__ u) {
+  constexpr int VW = Vec<T>::N;
+  const int rloc = threadIdx.x / cpr;
+  const int ch = threadIdx.x - rloc * cpr;
+  for (int64_t i = int64_t(blockIdx.x) * rpb + rloc; i < cnt; i += int64_t(gridDim.x) * rpb) {
+    const int64_t r = rows[i];
+    const int64_t base = r * W;
+    Vec<T> acc, xr;
+    for (int c = 0; c < VW; ++c) acc.v[c] = T(0);
+    const T d = a[base] - sigma * mm[base];
+    for (int k = 0; k < W; ++k) {
+      const int j = cols[base + k];
+      const T s = a[base + k] - sigma * mm[base + k];
+      const Vec<T> xv = ld(x + int64_t(j) * m + ch * VW);
+      if (k == 0) xr = xv;
+      for (int c = 0; c < VW; ++c) acc.v[c] += s * xv.v[c];
+    }
+    const Vec<T> fv = ld(f + r * m + ch * VW);
+    for (int c = 0; c < VW; ++c) xr.v[c] += (fv.v[c] - acc.v[c]) / d;
+    st(x + r * m + ch * VW, xr);
+    if (FUSE) {
+      double* up = u + r * m + ch * VW;
+      for (int c = 0; c < VW; ++c) up[c] += double(xr.v[c]);
+    }
+  }
+}
+
+// ------------------------------------------------------- FP64 SpMM (A, M) --
+__global__ void __launch_bounds__(256) k_spmm_am(int64_t n, int W, int m, int cpr, int rpb,
+                                                 const int* __restrict__ cols,
+                                                 const double* __restrict__ a,
+                                                 const double* __restrict__ mm,
+                                                 const double* __restrict__ x,
+                                                 double* __restrict__ ya, double* __restrict__ ym) {
+  const int rloc = threadIdx.x / cpr;
+  const int ch = threadIdx.x - rloc * cpr;
+  for (int64_t r = int64_t(blockIdx.x) * rpb + rloc; r < n; r += int64_t(gridDim.x) * rpb) {
+    const int64_t base = r * W;
+    double a0 = 0, a1 = 0, m0 = 0, m1 = 0;
+    for (int k = 0; k < W; ++k) {
+      const int j = cols[base + k];
+      const double av = a[base + k], mv = mm[base + k];
+      const Vec<double> xv = ld(x + int64_t(j) * m + ch * 2);
+      a0 += av * xv.v[0];
+      a1 += av * xv.v[1];
+      m0 += mv * xv.v[0];
+      m1 += mv * xv.v[1];
+    }
+    Vec<double> oa, om;
+    oa.v[0] = a0;
+    oa.v[1] = a1;
+    om.v[0] = m0;
+    om.v[1] = m1;
+    st(ya + r * m + ch * 2, oa);
+    st(ym + r * m + ch * 2, om);
+  }
+}
+
+// Eigen-residual R = A X - (M X) diag(theta), FP64 arithmetic, stored as
+// sgn * R in T; per-block partial sums of R^2 / lumped per column.
+template <typename T>
+__global__ void __launch_bounds__(256) k_eigres(int64_t n, int W, int m, int cpr, int rpb,
+                                                const int* __restrict__ cols,
+                                                const double* __restrict__ a,
+                                                const double* __restrict__ mm,
+                                                const double* __restrict__ dinv,
+                                                const double* __restrict__ x,
+                                                const double* __restrict__ theta, double sgn,
+                                                T* __restrict__ y, double* __restrict__ part) {
+  extern __shared__ double sred[];  // [rpb][m]
+  const int rloc = threadIdx.x / cpr;
+  const int ch = threadIdx.x - rloc * cpr;
+  const double t0 = theta[2 * ch], t1 = theta[2 * ch + 1];
+  double s0 = 0, s1 = 0;
+  for (int64_t r = int64_t(blockIdx.x) * rpb + rloc; r < n; r += int64_t(gridDim.x) * rpb) {
+    const int64_t base = r * W;
+    double a0 = 0, a1 = 0, m0 = 0, m1 = 0;
+    for (int k = 0; k < W; ++k) {
+      const int j = cols[base + k];
+      const double av = a[base + k], mv = mm[base + k];
+      const Vec<double> xv = ld(x + int64_t(j) * m + ch * 2);
+      a0 += av * xv.v[0];
+      a1 += av * xv.v[1];
+      m0 += mv * xv.v[0];
+      m1 += mv * xv.v[1];
+    }
+    const double r0 = a0 - m0 * t0, r1 = a1 - m1 * t1;
+    const double di = dinv[r];
+    s0 += r0 * r0 * di;
+    s1 += r1 * r1 * di;
+    T* yp = y + r * m + ch * 2;
+    yp[0] = T(sgn * r0);
+    yp[1] = T(sgn * r1);
+  }
+  if (part) {
+    sred[rloc * m + 2 * ch] = s0;
+    sred[rloc * m + 2 * ch + 1] = s1;
+    __syncthreads();
+    for (int c = threadIdx.x; c < m; c += blockDim.x) {
+      double s = 0;
+      for (int q = 0; q < rpb; ++q) s += sred[q * m + c];
+      part[int64_t(blockIdx.x) * m + c] = s;
+    }
+  }
+}
+
+// out[c] = sum_b part[b][c], one wavefront per column, fixed order.
+__global__ void k_colsum(const double* __restrict__ part, int nblk, int m, double* __restrict__ out) {
+  const int c = blockIdx.x;
+  double s = 0;
+  for (int b = threadIdx.x; b < nblk; b += 64) s += part[int64_t(b) * m + c];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (threadIdx.x == 0) out[c] = s;
+}
+
+// --------------------------------------------------------------- transfers --
+// y[i] = x[i] + 1/2 sum_{children c of i} x[c]   (P^T, eq. proj-1 transposed)
+template <typename T>
+__global__ void __launch_bounds__(256) k_restrict(int64_t nc, int RW, int m, int cpr, int rpb,
+                                                  const int* __restrict__ rtab,
+                                                  const T* __restrict__ x, T* __restrict__ y) {
+  constexpr int VW = Vec<T>::N;
+  const int rloc = threadIdx.x / cpr;
+  const int ch = threadIdx.x - rloc * cpr;
+  for (int64_t i = int64_t(blockIdx.x) * rpb + rloc; i < nc; i += int64_t(gridDim.x) * rpb) {
+    Vec<T> acc = ld(x + i * m + ch * VW);
+    Vec<T> h;
+    for (int c = 0; c < VW; ++c) h.v[c] = T(0);
+    for (int k = 0; k < RW; ++k) {
+      const int j = rtab[i * RW + k];
+      if (j < 0) break;
+      const Vec<T> xv = ld(x + int64_t(j) * m + ch * VW);
+      for (int c = 0; c < VW; ++c) h.v[c] += xv.v[c];
+    }
+    for (int c = 0; c < VW; ++c) acc.v[c] += T(0.5) * h.v[c];
+    st(y + i * m + ch * VW, acc);
+  }
+}
+
+// y[i] += x[i] (i < nc);  y[nc + e] += (x[a_e] + x[b_e]) / 2   (P, eq. proj-1)
+template <typename T>
+__global__ void __launch_bounds__(256) k_prolong_add(int64_t n, int64_t nc, int m, int cpr, int rpb,
+                                                     const int* __restrict__ parents,
+                                                     const T* __restrict__ x, T* __restrict__ y) {
+  constexpr int VW = Vec<T>::N;
+  const int rloc = threadIdx.x / cpr;
+  const int ch = threadIdx.x - rloc * cpr;
+  for (int64_t i = int64_t(blockIdx.x) * rpb + rloc; i < n; i += int64_t(gridDim.x) * rpb) {
+    Vec<T> v;
+    if (i < nc) {
+      v = ld(x + i * m + ch * VW);
+    } else {
+      const int64_t e = i - nc;
+      const Vec<T> xa = ld(x + int64_t(parents[2 * e]) * m + ch * VW);
+      const Vec<T> xb = ld(x + int64_t(parents[2 * e + 1]) * m + ch * VW);
+      for (int c = 0; c < VW; ++c) v.v[c] = T(0.5) * (xa.v[c] + xb.v[c]);
+    }
+    Vec<T> yv = ld(y + i * m + ch * VW);
+    for (int c = 0; c < VW; ++c) yv.v[c] += v.v[c];
+    st(y + i * m + ch * VW, yv);
+  }
+}
+
+// ------------------------------------------------------------ small dense --
+// y[i][:] = sum_k mat[i][k] g[k] x[k][:]   (g nullable), mat row-major [nr][nk]
+template <typename T>
+__global__ void __launch_bounds__(256) k_dense_mm(int nr, int nk, int m, int cpr, int rpb,
+                                                  const T* __restrict__ mat,
+                                                  const T* __restrict__ g,
+                                                  const T* __restrict__ x, T* __restrict__ y) {
+  constexpr int VW = Vec<T>::N;
+  const int rloc = threadIdx.x / cpr;
+  const int ch = threadIdx.x - rloc * cpr;
+  for (int64_t i = int64_t(blockIdx.x) * rpb + rloc; i < nr; i += int64_t(gridDim.x) * rpb) {
+    Vec<T> acc;
+    for (int c = 0; c < VW; ++c) acc.v[c] = T(0);
+    for (int k = 0; k < nk; ++k) {
+      const T w = mat[i * nk + k] * (g ? g[k] : T(1));
+      const Vec<T> xv = ld(x + int64_t(k) * m + ch * VW);
+      for (int c = 0; c < VW; ++c) acc.v[c] += w * xv.v[c];
+    }
+    st(y + i * m + ch * VW, acc);
+  }
+}
+
+// ----------------------------------------------------------- elementwise --
+template <typename T>
+__global__ void k_fill(T* y, int64_t cnt, T v) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < cnt;
+       i += int64_t(gridDim.x) * blockDim.x)
+    y[i] = v;
+}
+
+template <typename T>
+__global__ void k_add_to(double* u, const T* __restrict__ e, int64_t cnt) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < cnt;
+       i += int64_t(gridDim.x) * blockDim.x)
+    u[i] += double(e[i]);
+}
+
+template <typename T>
+__global__ void k_convert(const double* __restrict__ x, T* __restrict__ y, int64_t cnt) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < cnt;
+       i += int64_t(gridDim.x) * blockDim.x)
+    y[i] = T(x[i]);
+}
+
+// SplitMix64 output for state x (Steele, Lea & Flood 2014).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Element (i, j), counter c = i m + j: u1, u2 in (0, 1] from counters 2c and
+// 2c + 1; z = sqrt(-2 ln u1) cos(2 pi u2)  (Box-Muller).
+__global__ void k_gaussian(double* y, int64_t cnt, uint64_t seed) {
+  const double two53 = 1.0 / 9007199254740992.0;
+  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < cnt;
+       c += int64_t(gridDim.x) * blockDim.x) {
+    const uint64_t cc = uint64_t(c);
+    const double u1 = (double(splitmix64(seed ^ (2 * cc)) >> 11) + 1.0) * two53;
+    const double u2 = (double(splitmix64(seed ^ (2 * cc + 1)) >> 11) + 1.0) * two53;
+    y[c] = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+  }
+}
+
+// ---------------------------------------------------------------- output --
+// Per block and selected column j: (max |U[r][sel_j]|, lowest r attaining it).
+__global__ void k_argmax(int64_t n, const double* __restrict__ U, int m,
+                         const int* __restrict__ sel, int k, double* pv, int* pi) {
+  __shared__ double sv[256];
+  __shared__ int si[256];
+  for (int j = 0; j < k; ++j) {
+    const int col = sel[j];
+    double best = -1.0;
+    int bi = 0x7fffffff;
+    for (int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < n;
+         r += int64_t(gridDim.x) * blockDim.x) {
+      const double v = fabs(U[r * m + col]);
+      if (v > best) {
+        best = v;
+        bi = int(r);
+      }
+    }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) {
+        const double v2 = sv[threadIdx.x + off];
+        const int i2 = si[threadIdx.x + off];
+        if (v2 > sv[threadIdx.x] || (v2 == sv[threadIdx.x] && i2 < si[threadIdx.x])) {
+          sv[threadIdx.x] = v2;
+          si[threadIdx.x] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      pv[int64_t(blockIdx.x) * k + j] = sv[0];
+      pi[int64_t(blockIdx.x) * k + j] = si[0];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_sign_final(const double* __restrict__ U, int m, const int* __restrict__ sel, int k,
+                             const double* __restrict__ pv, const int* __restrict__ pi, int nblk,
+                             double* sign_out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  for (int b = 0; b < nblk; ++b) {
+    const double v = pv[int64_t(b) * k + j];
+    const int i = pi[int64_t(b) * k + j];
+    if (v > best || (v == best && i < bi)) {
+      best = v;
+      bi = i;
+    }
+  }
+  sign_out[j] = (U[int64_t(bi) * m + sel[j]] < 0) ? -1.0 : 1.0;
+}
+
+__global__ void k_write_evecs(int64_t n, const double* __restrict__ U, int m,
+                              const int* __restrict__ sel, const double* __restrict__ sign, int k,
+                              double* out, int64_t ld) {
+  const int64_t total = n * k;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int j = int(t / n);
+    const int64_t r = t - int64_t(j) * n;
+    out[int64_t(j) * ld + r] = sign[j] * U[r * m + sel[j]];
+  }
+}
+
+int grid1d(int64_t cnt) {
+  int64_t g = (cnt + 255) / 256;
+  return int(g < 4096 ? (g > 0 ? g : 1) : 4096);
+}
+
+template <typename T>
+const T* aval(const DevLevel& L);
+template <>
+const double* aval<double>(const DevLevel& L) { return L.a64; }
+template <>
+const float* aval<float>(const DevLevel& L) { return L.a32; }
+template <typename T>
+const T* mval(const DevLevel& L);
+template <>
+const double* mval<double>(const DevLevel& L) { return L.m64; }
+template <>
+const float* mval<float>(const DevLevel& L) { return L.m32; }
+
+}  // namespace
+
+template <typename T>
+int launch_shifted(const DevLevel& L, int mode, double sigma, const T* x, const T* f, T* y, int m,
+                   hipStream_t s) {
+  Geom g = row_geom<T>(L.n, m);
+  if (mode == ROW_SHIFTED)
+    k_rowop<T, K_SHIFTED, false><<<g.grid, g.block, 0, s>>>(L.n, L.W, m, g.cpr, g.rpb, L.cols,
+                                                            aval<T>(L), mval<T>(L), T(sigma), T(0),
+                                                            x, f, y, nullptr);
+  else
+    k_rowop<T, K_RESIDUAL, false><<<g.grid, g.block, 0, s>>>(L.n, L.W, m, g.cpr, g.rpb, L.cols,
+                                                             aval<T>(L), mval<T>(L), T(sigma), T(0),
+                                                             x, f, y, nullptr);
+  return check_launch();
+}
+
+template <typename T>
+int launch_jacobi(const DevLevel& L, double sigma, double omega, const T* x, const T* f, T* y,
+                  bool x_is_zero, int m, hipStream_t s) {
+  Geom g = row_geom<T>(L.n, m);
+  if (x_is_zero)
+    k_rowop<T, K_JACOBI0, false><<<g.grid, g.block, 0, s>>>(L.n, L.W, m, g.cpr, g.rpb, L.cols,
+                                                            aval<T>(L), mval<T>(L), T(sigma),
+                                                            T(omega), x, f, y, nullptr);
+  else
+    k_rowop<T, K_JACOBI, false><<<g.grid, g.block, 0, s>>>(L.n, L.W, m, g.cpr, g.rpb, L.cols,
+                                                           aval<T>(L), mval<T>(L), T(sigma),
+                                                           T(omega), x, f, y, nullptr);
+  return check_launch();
+}
+
+template <typename T>
+int launch_gs_colour(const DevLevel& L, int colour, double sigma, T* x, const T* f, int m,
+                     hipStream_t s) {
+  const int64_t b = L.colour_ptr[colour], e = L.colour_ptr[colour + 1];
+  if (e <= b) return BMG_OK;
+  Geom g = row_geom<T>(e - b, m);
+  k_gs<T, false><<<g.grid, g.block, 0, s>>>(e - b, L.colour_rows + b, L.W, m, g.cpr, g.rpb, L.cols,
+                                            aval<T>(L), mval<T>(L), T(sigma), x, f, nullptr);
+  return check_launch();
+}
+
+int launch_spmm_am(const DevLevel& L, const double* x, double* ya, double* ym, int m,
+                   hipStream_t s) {
+  Geom g = row_geom<double>(L.n, m);
+  k_spmm_am<<<g.grid, g.block, 0, s>>>(L.n, L.W, m, g.cpr, g.rpb, L.cols, L.a64, L.m64, x, ya, ym);
+  return check_launch();
+}
+
+int eigres_blocks(const DevLevel& L, int m) { return row_geom<double>(L.n, m, 1024).grid; }
+
+template <typename T>
+int launch_eigres(const DevLevel& L, const double* x, const double* theta, double sgn, T* y,
+                  double* rho2_part, int nblk, int m, hipStream_t s) {
+  Geom g = row_geom<double>(L.n, m, 1024);
+  if (nblk != g.grid) {
+    set_error("eigres grid mismatch");
+    return BMG_EINVAL;
+  }
+  const size_t shm = size_t(g.rpb) * m * sizeof(double);
+  k_eigres<T><<<g.grid, g.block, shm, s>>>(L.n, L.W, m, g.cpr, g.rpb, L.cols, L.a64, L.m64, L.dinv,
+                                           x, theta, sgn, y, rho2_part);
+  return check_launch();
+}
+
+int launch_colsum(const double* part, int nblk, int m, double* out, hipStream_t s) {
+  k_colsum<<<m, 64, 0, s>>>(part, nblk, m, out);
+  return check_launch();
+}
+
+template <typename T>
+int launch_restrict(const DevLevel& fine, const T* x, T* y, int m, hipStream_t s) {
+  Geom g = row_geom<T>(fine.n_prev, m);
+  k_restrict<T><<<g.grid, g.block, 0, s>>>(fine.n_prev, fine.RW, m, g.cpr, g.rpb, fine.rtab, x, y);
+  return check_launch();
+}
+
+template <typename T>
+int launch_prolong_add(const DevLevel& fine, const T* x, T* y, int m, hipStream_t s) {
+  Geom g = row_geom<T>(fine.n, m);
+  k_prolong_add<T><<<g.grid, g.block, 0, s>>>(fine.n, fine.n_prev, m, g.cpr, g.rpb, fine.parents, x,
+                                              y);
+  return check_launch();
+}
+
+template <typename T>
+int launch_dense_apply(int n, const T* mat, const T* g, const T* x, T* y, int m, hipStream_t s) {
+  Geom gm = row_geom<T>(n, m);
+  k_dense_mm<T><<<gm.grid, gm.block, 0, s>>>(n, n, m, gm.cpr, gm.rpb, mat, g, x, y);
+  return check_launch();
+}
+
+template <typename T>
+int launch_fill(T* y, int64_t count, T value, hipStream_t s) {
+  k_fill<T><<<grid1d(count), 256, 0, s>>>(y, count, value);
+  return check_launch();
+}
+
+template <typename T>
+int launch_add_to(double* u, const T* e, int64_t count, hipStream_t s) {
+  k_add_to<T><<<grid1d(count), 256, 0, s>>>(u, e, count);
+  return check_launch();
+}
+
+template <typename T>
+int launch_convert(const double* x, T* y, int64_t count, hipStream_t s) {
+  k_convert<T><<<grid1d(count), 256, 0, s>>>(x, y, count);
+  return check_launch();
+}
+
+int launch_gaussian(double* y, int64_t n, int m, uint64_t seed, hipStream_t s) {
+  k_gaussian<<<grid1d(n * m), 256, 0, s>>>(y, n * m, seed);
+  return check_launch();
+}
+
+int launch_signs(int64_t n, const double* U, int m, const int* sel, int k, double* sign_out,
+                 double* part_val, int* part_idx, int nblk, hipStream_t s) {
+  k_argmax<<<nblk, 256, 0, s>>>(n, U, m, sel, k, part_val, part_idx);
+  k_sign_final<<<(k + 63) / 64, 64, 0, s>>>(U, m, sel, k, part_val, part_idx, nblk, sign_out);
+  return check_launch();
+}
+
+int launch_write_evecs(int64_t n, const double* U, int m, const int* sel, const double* sign,
+                       int k, double* out, int64_t ld, hipStream_t s) {
+  k_write_evecs<<<grid1d(n * k), 256, 0, s>>>(n, U, m, sel, sign, k, out, ld);
+  return check_launch();
+}
+
+#define BMG_INST(T)                                                                              \
+  template int launch_shifted<T>(const DevLevel&, int, double, const T*, const T*, T*, int,     \
+                                 hipStream_t);                                                   \
+  template int launch_jacobi<T>(const DevLevel&, double, double, const T*, const T*, T*, bool,  \
+                                int, hipStream_t);                                               \
+  template int launch_gs_colour<T>(const DevLevel&, int, double, T*, const T*, int, hipStream_t); \
+  template int launch_eigres<T>(const DevLevel&, const double*, const double*, double, T*,       \
+                                double*, int, int, hipStream_t);                                 \
+  template int launch_restrict<T>(const DevLevel&, const T*, T*, int, hipStream_t);              \
+  template int launch_prolong_add<T>(const DevLevel&, const T*, T*, int, hipStream_t);           \
+  template int launch_dense_apply<T>(int, const T*, const T*, const T*, T*, int, hipStream_t);   \
+  template int launch_fill<T>(T*, int64_t, T, hipStream_t);                                      \
+  template int launch_add_to<T>(double*, const T*, int64_t, hipStream_t);                        \
+  template int launch_convert<T>(const double*, T*, int64_t, hipStream_t);
+BMG_INST(double)
+BMG_INST(float)
+#undef BMG_INST
+
+}  // namespace bmg
