@@ -6,7 +6,8 @@
 // A_h U^h and their M counterparts, here evaluated on the finest level), and it
 // runs on the FP64 matrix cores: v_mfma_f64_16x16x4f64 takes a 16x4 slice of
 // Z^T and a 4x16 slice of Y, i.e. four rows of both blocks per instruction.
-// Each 256-thread block owns a contiguous range of rows; its four wavefronts
+// The FP64 16x16x4 result layout: lane l holds column l % 16 of rows
+// (l / 16) + 4 v, v = 0..3.  Each 256-thread block owns a contiguous range of rows; its four wavefronts
 // split the 16x16 output tiles by tile column.  Per-block results go to a
 // partial buffer that a second kernel sums in a fixed order (deterministic).
 //
@@ -71,7 +72,7 @@ __global__ void __launch_bounds__(256) k_gram(int64_t n, int64_t rows_per_block,
     const int tj = wave + 4 * t;
     if (tj >= TJ) break;
     for (int i = 0; i < TI; ++i)
-      for (int v = 0; v < 4; ++v) out[(16 * i + 4 * lk + v) * nyp + 16 * tj + li] = acc[i][t][v];
+      for (int v = 0; v < 4; ++v) out[(16 * i + lk + 4 * v) * nyp + 16 * tj + li] = acc[i][t][v];
   }
 }
 

@@ -37,7 +37,8 @@ def test_spmm_A_M_fp64(env, m):
         h.apply(op, x=_dev(torch, x), y=y)
         torch.cuda.synchronize()
         scale = abs(Mat) @ np.abs(x) + 1e-300
-        assert _rel(_host(y), Mat @ x, scale) < 1e-14
+        err = _rel(_host(y), Mat @ x, scale)
+        assert err < 1e-14, (op, err)
 
 
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-14), ("f32", 3e-6)])
@@ -54,10 +55,12 @@ def test_shifted_and_residual(env, dtype, tol, sigma):
     y = torch.zeros_like(xd)
     h.apply("shifted", x=xd, y=y, sigma=sigma)
     torch.cuda.synchronize()
-    assert _rel(_host(y), S @ _host(xd), scale) < tol
+    err = _rel(_host(y), S @ _host(xd), scale)
+    assert err < tol, err
     h.apply("residual", x=xd, f=fd, y=y, sigma=sigma)
     torch.cuda.synchronize()
-    assert _rel(_host(y), _host(fd) - S @ _host(xd), scale) < tol
+    err = _rel(_host(y), _host(fd) - S @ _host(xd), scale)
+    assert err < tol, err
 
 
 @pytest.mark.parametrize("smoother", ["gs", "jacobi"])
@@ -151,7 +154,8 @@ def test_gram_mfma(env, level, wx, wf):
     torch.cuda.synchronize()
     ref = x.T @ f
     scale = np.abs(x).T @ np.abs(f)
-    assert _rel(_host(y), ref, scale) < 1e-14
+    err = _rel(_host(y), ref, scale)
+    assert err < 1e-14, err
 
 
 @pytest.mark.parametrize("n", [1, 2, 7, 44, 92, 96])
@@ -190,4 +194,5 @@ def test_eigen_residual(env, dt_name):
     ref = L.A @ x - (L.M @ x) * th[None, :]
     scale = abs(L.A) @ np.abs(x) + (abs(L.M) @ np.abs(x)) * th[None, :]
     tol = 1e-14 if dt_name == "f64" else 1e-7
-    assert _rel(_host(y), ref, scale) < tol
+    err = _rel(_host(y), ref, scale)
+    assert err < tol, err
