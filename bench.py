@@ -1,0 +1,159 @@
+#!/usr/bin/env python3
+"""Benchmark of the BMG eigensolver hot path on one MI355X.
+
+A step is one complete solve: the k eigenpairs nearest sigma of the workload's
+finest-level pencil, iterated to the 1e-8 certificate (every row of the cycle:
+residual SpMM, correction V-cycle, Gram, Ritz, update).  The inputs (hierarchy
+and matrices) are resident in HBM before the timed region; the test vectors are
+drawn on the device from the step's seed.  `value` is converged eigenpairs per
+second of the FP32/FP64 mixed path; the plain FP64 GPU path is timed beside it.
+
+Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2_sphere_ref6")
+    ap.add_argument("--smoother", default="gs", choices=["gs", "jacobi"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", default="both", choices=["both", "mixed", "fp64"])
+    ap.add_argument("--timed-kernel", default="smooth",
+                    help="kernel class timed with HIP events inside the timed region (roofline)")
+    ap.add_argument("--breakdown", action="store_true",
+                    help="after the timed region, time every kernel class in extra solves")
+    return ap.parse_args()
+
+
+# Kernel classes: bound and whether the library's figure counts bytes or flops.
+KCLASS = {"eigres": ("hbm", "GB/s"), "spmm_am": ("hbm", "GB/s"), "smooth": ("hbm", "GB/s"),
+          "residual": ("hbm", "GB/s"), "restrict": ("hbm", "GB/s"), "prolong": ("hbm", "GB/s"),
+          "gram": ("mfma", "TFLOP/s"), "update": ("mfma", "TFLOP/s"), "ritz": ("latency", "us")}
+FP64_PEAK_TFLOPS = 78.6
+
+
+def roofline(kclass, ms, amount, units):
+    bound, unit = KCLASS[kclass]
+    if bound == "hbm":
+        achieved = amount / (ms * 1e-3) / 1e9
+        peak = HBM_PEAK_GBS
+    elif bound == "mfma":
+        achieved = amount / (ms * 1e-3) / 1e12
+        peak = FP64_PEAK_TFLOPS
+    else:
+        return {"bound": "latency", "kernel": kclass, "avg_us": 1e3 * ms / max(units, 1)}
+    return {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
+            "frac": round(achieved / peak, 4), "traffic": None, "kernel": kclass,
+            "units": int(units), "avg_unit_us": round(1e3 * ms / max(units, 1), 3),
+            "per_unit": round(amount / max(units, 1), 1)}
+
+
+def timed_solves(h, cfg, precision, smoother, steps, warmup, timed_kernel=None):
+    import torch
+    kw = dict(m=cfg["m"], nu1=cfg["nu1"], nu2=cfg["nu2"], smoother=smoother, precision=precision,
+              evecs=None, timed_kernel=timed_kernel)
+    for s in range(warmup):
+        h.solve(cfg["k"], cfg["sigma"], cfg["tol"], seed=1000 + s, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for s in range(steps):
+        _, _, st = h.solve(cfg["k"], cfg["sigma"], cfg["tol"], seed=s, **kw)
+        assert st["converged"] == 1, st
+        stats.append(st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt, stats
+
+
+def cpu_baseline(cfg, smoother):
+    """The oracle on the host cores: one solve of the same workload (seed 0)."""
+    import threadpoolctl
+    from oracle import bmg as ob
+    lv = ob.build_levels(cfg["kind"], cfg["n_refine"], axes=cfg["axes"])
+    t0 = time.perf_counter()
+    ev, _, info = ob.solve(lv, cfg["k"], cfg["sigma"], cfg["tol"], m=cfg["m"], nu1=cfg["nu1"],
+                           nu2=cfg["nu2"], smoother=smoother)
+    dt = time.perf_counter() - t0
+    blas = max((p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()), default=1)
+    return dict(value=cfg["k"] / dt, unit="eigenpairs/s", cores=int(blas), kind="oracle",
+                sample=f"one full oracle solve of the same workload, seed 0 ({info['cycles']} cycles, "
+                       f"{dt:.1f} s; dense BLAS on {blas} threads, scipy.sparse products single-threaded)")
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+    import paper_1511_07042_amd as bmg
+    from workloads import CONFIGS
+    cfg = CONFIGS[a.workload]
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    h = bmg.Hierarchy(cfg["kind"], cfg["n_refine"], axes=cfg["axes"])
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    res = {}
+    roof = {}
+    for prec in (["fp64", "mixed"] if a.only == "both" else [a.only]):
+        dt, stats = timed_solves(h, cfg, prec, a.smoother, a.steps, a.warmup, a.timed_kernel)
+        res[prec] = dict(value=a.steps * cfg["k"] / dt, ms_per_step=1e3 * dt / a.steps,
+                         cycles=[s["cycles"] for s in stats],
+                         t_solve_ms=[round(s["t_solve_ms"], 3) for s in stats],
+                         ritz_sweeps_max=max(s["ritz_sweeps_max"] for s in stats),
+                         ritz_fallbacks=sum(s["ritz_fallbacks"] for s in stats))
+        roof[prec] = roofline(a.timed_kernel, sum(s["timed_kernel_ms"] for s in stats),
+                              sum(s["timed_kernel_bytes"] for s in stats),
+                              sum(s["timed_kernel_units"] for s in stats))
+        print(f"# {prec}: {res[prec]} roofline {roof[prec]}", file=sys.stderr, flush=True)
+        if a.breakdown:
+            bd = {}
+            for kc in KCLASS:
+                _, st = timed_solves(h, cfg, prec, a.smoother, 1, 0, kc)
+                bd[kc] = dict(ms=round(st[0]["timed_kernel_ms"], 3), **roofline(
+                    kc, st[0]["timed_kernel_ms"], st[0]["timed_kernel_bytes"], st[0]["timed_kernel_units"]))
+            res[prec]["breakdown"] = bd
+            print(f"# {prec} breakdown: {json.dumps(bd)}", file=sys.stderr, flush=True)
+    main_prec = "mixed" if "mixed" in res else a.only
+    out = {
+        "metric": "converged eigenpairs/s at 1e-8 rel (FP32/FP64 mixed BMG)",
+        "value": round(res[main_prec]["value"], 3),
+        "unit": "eigenpairs/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(res[main_prec]["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if main_prec == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": a.workload, **{k: v for k, v in cfg.items()}, "smoother": a.smoother,
+                   "hierarchy_build_s": round(build_s, 3)},
+        "roofline": roof[main_prec],
+        "fp64_path": res.get("fp64"),
+        "mixed_path": res.get("mixed"),
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, a.smoother)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

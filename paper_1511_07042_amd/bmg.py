@@ -23,6 +23,8 @@ SMOOTHERS = {"gs": 0, "jacobi": 1}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 EXPORTS = {"xyz": 0, "tri": 1, "parents": 2, "ell_cols": 3, "ell_a": 4, "ell_m": 5, "colours": 6,
            "lumped": 7, "coarse_eig": 8}
+KERNEL_CLASSES = {"eigres": 0, "spmm_am": 1, "smooth": 2, "residual": 3, "restrict": 4,
+                  "prolong": 5, "gram": 6, "update": 7, "ritz": 8}
 OPS = {"A": 0, "M": 1, "shifted": 2, "residual": 3, "smooth_fwd": 4, "smooth_bwd": 5,
        "restrict": 6, "prolong_add": 7, "vcycle": 8, "gaussian": 9, "gram": 10, "syev": 11,
        "eigres": 12}
@@ -47,7 +49,8 @@ class SolveOpts(C.Structure):
     _fields_ = [("m", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32), ("smoother", C.c_int32),
                 ("precision", C.c_int32), ("max_cycles", C.c_int32), ("n_c", C.c_int32),
                 ("l_c", C.c_int32), ("omega", C.c_double), ("angle_tol", C.c_double),
-                ("seed", C.c_uint64), ("initial_block", C.POINTER(C.c_double))]
+                ("seed", C.c_uint64), ("initial_block", C.POINTER(C.c_double)),
+                ("timed_kernel", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -55,7 +58,9 @@ class SolveStats(C.Structure):
                 ("n_c", C.c_int32), ("l_c", C.c_int32), ("reserved", C.c_int32),
                 ("t_solve_ms", C.c_double), ("max_rho_over_delta", C.c_double),
                 ("max_kato_temple", C.c_double), ("rho", C.POINTER(C.c_double)),
-                ("delta", C.POINTER(C.c_double))]
+                ("delta", C.POINTER(C.c_double)), ("timed_kernel_ms", C.c_double),
+                ("timed_kernel_bytes", C.c_double), ("timed_kernel_units", C.c_int64),
+                ("ritz_sweeps_max", C.c_int32), ("ritz_fallbacks", C.c_int32)]
 
 
 class ApplyArgs(C.Structure):
@@ -212,7 +217,7 @@ class Hierarchy:
 
     def solve(self, k, sigma=0.0, tol=1e-8, m=0, nu1=2, nu2=2, smoother="gs", precision="fp64",
               max_cycles=200, n_c=0, l_c=-1, omega=2.0 / 3.0, angle_tol=1e-7, seed=0,
-              initial_block=None, evecs="host", stream=None, allow_noconv=False):
+              initial_block=None, evecs="host", stream=None, allow_noconv=False, timed_kernel=None):
         """Returns (evals [k], evecs [N, k] or None, stats dict).
 
         evecs: "host" -> numpy array, "device" -> torch.cuda tensor view, None.
@@ -224,6 +229,7 @@ class Hierarchy:
         o.precision = PRECISIONS[precision]
         o.max_cycles, o.n_c, o.l_c = int(max_cycles), int(n_c), int(l_c)
         o.omega, o.angle_tol, o.seed = float(omega), float(angle_tol), int(seed)
+        o.timed_kernel = -1 if timed_kernel is None else KERNEL_CLASSES[timed_kernel]
         keep = None
         if initial_block is not None:
             keep = np.ascontiguousarray(initial_block, dtype=np.float64)

@@ -67,6 +67,7 @@ void bmg_solve_opts_default(bmg_solve_opts* o) {
   o->angle_tol = 1e-7;
   o->seed = 0;
   o->initial_block = nullptr;
+  o->timed_kernel = -1;
 }
 
 static int build_impl(const bmg_surface_desc* desc, int32_t n_refine, void* stream,

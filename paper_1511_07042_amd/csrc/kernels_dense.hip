@@ -1,20 +1,25 @@
 // One-workgroup FP64 dense kernels of the Rayleigh-Ritz step.
 //
 // The enriched pencil (eq. pb-c-aux-mat, Alg. 2 step 4 / Alg. 3 step 5) is
-// small (nz = n_c + m <= 96) and lives in LDS.  Its M-block is made orthonormal
-// by SVQB (Stathopoulos & Wu, SIAM J. Sci. Comput. 2002: scale to unit
-// diagonal, eigendecompose, drop directions whose eigenvalue is below 1e-12 of
-// the largest), which is the "orthogonalize with respect to b_h" step of
-// Alg. 2 step 3; the reduced standard problem is shifted by sigma and solved
-// again by Jacobi; the m eigenpairs nearest sigma are kept (Alg. 2 step 2,
-// Remark 4.1).
+// small (nz = n_c + m <= 96) and lives in LDS.  Its basis is ordered
+// [U', W_c] and made M-orthonormal (the "orthogonalize with respect to b_h"
+// step of Alg. 2 step 3) by a Cholesky factorisation of the unit-diagonal
+// scaled M-Gram matrix; because U' is close to the previous, already
+// M-orthonormal and A-diagonal Ritz block, the reduced matrix
+// C = L^-1 S (G_A - sigma G_M) S L^-T is then close to diagonal in its leading
+// m x m block and Jacobi needs few sweeps.  When a Cholesky pivot falls below
+// 1e-10 (the basis is numerically rank deficient) the kernel switches to SVQB
+// (Stathopoulos & Wu, SIAM J. Sci. Comput. 2002: eigendecompose the scaled
+// Gram matrix, drop directions below 1e-12 of the largest eigenvalue).  The m
+// eigenpairs nearest sigma are kept (Alg. 2 step 2, Remark 4.1).
 //
 // Jacobi method (Golub & Van Loan, Matrix Computations, Sec. 8.5): two-sided
 // rotations in parallel (round-robin) order.  In one round the n/2 disjoint
 // pairs (p, q) get their rotations at once; every 2x2 block [p1 q1] x [p2 q2]
-// of the matrix is then rotated on both sides by one thread, and each row of
-// the eigenvector matrix by one thread.  Sweeps repeat until the off-diagonal
-// Frobenius norm is below 1e-15 of the total.
+// of the matrix is rotated on both sides by one thread and each row of the
+// eigenvector matrix by one thread.  Sweeps stop after a sweep in which no
+// rotation was significant (|a_pq| > 1e-15 sqrt|a_pp a_qq| and
+// |a_pq| > 1e-18 ||A||_F).
 #include <cmath>
 
 #include "bmg_internal.h"
@@ -30,6 +35,8 @@ struct JacobiShared {
   int p[kMaxN / 2], q[kMaxN / 2];
   double red[2 * (kThreads / 64)];
   double bcast[2];
+  int sig[2];
+  int flag;
 };
 
 __device__ void block_sum2(double a, double b, JacobiShared& sh, double& ra, double& rb) {
@@ -60,25 +67,26 @@ __device__ void block_sum2(double a, double b, JacobiShared& sh, double& ra, dou
 
 // Diagonalise the symmetric n x n matrix X (row-major, LDS) in place:
 // on return X is diagonal (eigenvalues on the diagonal, unsorted) and
-// X_in = V diag V^T with V (LDS) orthogonal.  Returns sweeps used (-1 if the
-// sweep limit was hit).
+// X_in = V diag V^T with V (LDS) orthogonal.  Returns the sweeps used, or -1
+// if the sweep limit was hit.
 __device__ int block_jacobi(double* X, double* V, int n, JacobiShared& sh) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int ne = n + (n & 1);
   const int half = ne / 2;
-  for (int e = tid; e < n * n; e += nt) V[e] = (e / n == e % n) ? 1.0 : 0.0;
-  __syncthreads();
-  int sweep = 0;
-  for (; sweep < 40; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int e = tid; e < n * n; e += nt) {
-      const double v = X[e] * X[e];
-      tot += v;
-      if (e / n != e % n) off += v;
-    }
-    double so, stot;
-    block_sum2(off, tot, sh, so, stot);
-    if (so <= 1e-30 * stot) return sweep;
+  double f2 = 0.0;
+  for (int e = tid; e < n * n; e += nt) {
+    V[e] = (e / n == e % n) ? 1.0 : 0.0;
+    f2 += X[e] * X[e];
+  }
+  if (tid == 0) {
+    sh.sig[0] = 0;
+    sh.sig[1] = 0;
+  }
+  double fro2, dummy;
+  block_sum2(f2, 0.0, sh, fro2, dummy);
+  const double fro = sqrt(fro2);
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    const int cur = sweep & 1;
     for (int rd = 0; rd < ne - 1; ++rd) {
       if (tid < half) {
         int p = (tid + rd) % (ne - 1);
@@ -92,7 +100,8 @@ __device__ int block_jacobi(double* X, double* V, int n, JacobiShared& sh) {
         if (q < n) {
           const double apq = X[p * n + q];
           const double app = X[p * n + p], aqq = X[q * n + q];
-          if (apq != 0.0 && fabs(apq) > 1e-18 * sqrt(fabs(app * aqq))) {
+          if (fabs(apq) > 1e-300) {
+            if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-18 * fro) sh.sig[cur] = 1;
             const double tau = (aqq - app) / (2.0 * apq);
             if (fabs(tau) > 1e150) {
               t = 0.5 / tau;
@@ -110,16 +119,11 @@ __device__ int block_jacobi(double* X, double* V, int n, JacobiShared& sh) {
         sh.q[tid] = q;
       }
       __syncthreads();
+      if (rd == 0 && tid == 0) sh.sig[cur ^ 1] = 0;  // everyone has read it by now
       // two-sided update of the blocks (t1 <= t2), each written with its transpose
-      const int nblk = half * (half + 1) / 2;
-      for (int idx = tid; idx < nblk; idx += nt) {
-        // unrank idx -> (t1, t2) with t1 <= t2, row-wise over the upper triangle
-        int t1 = 0, rem = idx;
-        while (rem >= half - t1) {
-          rem -= half - t1;
-          ++t1;
-        }
-        const int t2 = t1 + rem;
+      for (int idx = tid; idx < half * half; idx += nt) {
+        const int t1 = idx / half, t2 = idx - (idx / half) * half;
+        if (t2 < t1) continue;
         const int p1 = sh.p[t1], q1 = sh.q[t1], p2 = sh.p[t2], q2 = sh.q[t2];
         const double c1 = sh.c[t1], s1 = sh.s[t1], c2 = sh.c[t2], s2 = sh.s[t2];
         if (t1 == t2) {
@@ -132,6 +136,7 @@ __device__ int block_jacobi(double* X, double* V, int n, JacobiShared& sh) {
           }
           continue;
         }
+        if (s1 == 0.0 && s2 == 0.0) continue;
         const bool hq1 = q1 < n, hq2 = q2 < n;
         const double bpp = X[p1 * n + p2];
         const double bpq = hq2 ? X[p1 * n + q2] : 0.0;
@@ -169,6 +174,7 @@ __device__ int block_jacobi(double* X, double* V, int n, JacobiShared& sh) {
       }
       __syncthreads();
     }
+    if (sh.sig[cur] == 0) return sweep + 1;
   }
   return -1;
 }
@@ -179,10 +185,40 @@ struct RitzShared {
   double d[kMaxN];
   int kk[kMaxN];
   int sel[kMaxN];
+  int dropmap[kMaxN];  // permuted column -> position among the kept ones, or -1
   int r;
 };
 
-// LDS: [RitzShared][X: nz*nz][V: nz*nz]
+// Ranks of the diagonal of X (r x r): select the mm values nearest 0 (ties by
+// value, then index) and order them ascending into sh.sel[0..mm).
+__device__ void select_nearest_zero(const double* X, int r, int mm, RitzShared& sh) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int j = tid; j < r; j += nt) {
+    const double mj = X[j * r + j], aj = fabs(mj);
+    int rank = 0;
+    for (int i = 0; i < r; ++i) {
+      const double mi = X[i * r + i], ai = fabs(mi);
+      if (ai < aj || (ai == aj && (mi < mj || (mi == mj && i < j)))) ++rank;
+    }
+    sh.kk[j] = rank;
+  }
+  __syncthreads();
+  for (int j = tid; j < r; j += nt) {
+    if (sh.kk[j] >= mm) continue;
+    const double mj = X[j * r + j];
+    int pos = 0;
+    for (int i = 0; i < r; ++i) {
+      if (sh.kk[i] >= mm) continue;
+      const double mi = X[i * r + i];
+      if (mi < mj || (mi == mj && i < j)) ++pos;
+    }
+    sh.sel[pos] = j;
+  }
+  __syncthreads();
+}
+
+// LDS: [RitzShared][X: nz*nz][V: nz*nz].  Global scratch: GA, GM (permuted
+// order [U', W_c]), L, Li (or T, Y1 on the SVQB path), W1.
 __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
                                                    const double* __restrict__ G,
                                                    const double* __restrict__ GW, double* Y,
@@ -190,17 +226,22 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
   extern __shared__ double lds[];
   RitzShared& sh = *reinterpret_cast<RitzShared*>(lds);
   const int nz = n_c + m;
+  const int n = nz;
   double* X = lds + (sizeof(RitzShared) + 7) / 8;
   double* V = X + nz * nz;
-  double* GA = scratch;             // [nz][nz]
-  double* GM = GA + nz * nz;        // [nz][nz]
-  double* T = GM + nz * nz;         // [nz][nz]
-  double* Y1 = T + nz * nz;         // [nz][nz]
+  double* GA = scratch;        // [nz][nz]
+  double* GM = GA + nz * nz;   // [nz][nz]
+  double* L = GM + nz * nz;    // [nz][nz] Cholesky factor / SVQB basis T
+  double* Li = L + nz * nz;    // [nz][nz] inverse of L / SVQB Y1
+  double* W1 = Li + nz * nz;   // [nz][nz]
   const int tid = threadIdx.x, nt = blockDim.x;
   const int m2 = 2 * m, nc2 = 2 * n_c;
-  // assemble the enriched pencil (Galerkin blocks, symmetrised)
+  // permuted position a -> original Z column: a < m -> U' column a, else W column a - m
+  auto orig = [&](int a) { return a < m ? n_c + a : a - m; };
+  // assemble the enriched pencil (Galerkin blocks, symmetrised) in order [U', W_c]
   for (int e = tid; e < nz * nz; e += nt) {
-    const int i = e / nz, j = e - (e / nz) * nz;
+    const int a = e / nz, b = e - (e / nz) * nz;
+    const int i = orig(a), j = orig(b);
     double va, vm;
     if (i < n_c && j < n_c) {
       va = 0.5 * (GW[i * nc2 + j] + GW[j * nc2 + i]);
@@ -218,55 +259,130 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
     GA[e] = va;
     GM[e] = vm;
     X[e] = vm;
+    L[e] = 0.0;
   }
   __syncthreads();
   for (int i = tid; i < nz; i += nt) {
     const double dg = X[i * nz + i];
     sh.sv[i] = dg > 0.0 ? 1.0 / sqrt(dg) : 0.0;
   }
+  if (tid == 0) sh.j.flag = 1;
   __syncthreads();
   for (int e = tid; e < nz * nz; e += nt) {
     const int i = e / nz, j = e - (e / nz) * nz;
     X[e] *= sh.sv[i] * sh.sv[j];
   }
   __syncthreads();
-  const int sw1 = block_jacobi(X, V, nz, sh.j);
-  if (tid == 0) {
-    double dmax = 0.0;
-    for (int j = 0; j < nz; ++j) dmax = fmax(dmax, X[j * nz + j]);
-    int r = 0;
-    for (int j = 0; j < nz; ++j) {
-      const double dj = X[j * nz + j];
-      if (dj > 1e-12 * dmax) {
-        sh.kk[r] = j;
-        sh.d[r] = dj;
-        ++r;
+  // ---- Cholesky of the scaled Gram matrix (right-looking, one barrier per
+  // column).  A column whose pivot (the squared sine of its angle to the
+  // span of the kept columns before it) is below 1e-10 is dropped: it adds
+  // nothing to the enriched space.  With sigma = 0 this happens to the
+  // constant vector of W_c once U' holds the converged constant mode.
+  if (tid == 0) sh.r = 0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const double piv = X[j * n + j];
+    if (piv > 1e-10) {  // uniform: every thread reads the same pivot
+      const double rp = sqrt(piv);
+      const int w = n - j;
+      for (int e = tid; e < w * w; e += nt) {
+        const int i = j + e / w, k = j + e - (e / w) * w;
+        if (k == j)
+          L[i * n + j] = X[i * n + j] / rp;
+        else if (k <= i)
+          X[i * n + k] -= X[i * n + j] * X[k * n + j] / piv;
+      }
+      if (tid == 0) sh.kk[sh.r++] = j;
+    }
+    __syncthreads();
+  }
+  int r = sh.r;
+  double* T = L;  // SVQB path: basis coefficients Y = T Q
+  const bool chol = r >= m;
+  for (int a = tid; a < n; a += nt) sh.dropmap[a] = -1;
+  __syncthreads();
+  for (int q = tid; q < r; q += nt) sh.dropmap[sh.kk[q]] = q;
+  if (chol) {
+    // compact factor Lc = L[kept, kept] (in W1) and its inverse Li, one column
+    // per thread (a column of the inverse depends only on itself)
+    for (int e = tid; e < r * r; e += nt) {
+      const int a = e / r, b = e - (e / r) * r;
+      W1[e] = (b <= a) ? L[sh.kk[a] * n + sh.kk[b]] : 0.0;
+    }
+    __syncthreads();
+    for (int c = tid; c < r; c += nt) {
+      for (int i = 0; i < c; ++i) Li[i * r + c] = 0.0;
+      for (int i = c; i < r; ++i) {
+        double acc = (i == c) ? 1.0 : 0.0;
+        for (int k = c; k < i; ++k) acc -= W1[i * r + k] * Li[k * r + c];
+        Li[i * r + c] = acc / W1[i * r + i];
       }
     }
-    sh.r = r;
+    __syncthreads();
+    // W1 = Li B, B = S (G_A - sigma G_M) S restricted to the kept columns
+    for (int e = tid; e < r * r; e += nt) {
+      const int i = e / r, j = e - (e / r) * r;
+      const int cj = sh.kk[j];
+      double acc = 0.0;
+      for (int k = 0; k <= i; ++k) {
+        const int ck = sh.kk[k];
+        acc += Li[i * r + k] * sh.sv[ck] * (GA[ck * n + cj] - sigma * GM[ck * n + cj]);
+      }
+      L[e] = acc * sh.sv[cj];  // L is free now: reuse as W1
+    }
+    __syncthreads();
+    // C = W1 Li^T
+    for (int e = tid; e < r * r; e += nt) {
+      const int i = e / r, j = e - (e / r) * r;
+      double acc = 0.0;
+      for (int k = 0; k <= j; ++k) acc += L[i * r + k] * Li[j * r + k];
+      X[e] = acc;
+    }
+    __syncthreads();
+  } else {
+    // ---- SVQB: eigendecompose the scaled Gram matrix, drop tiny directions
+    for (int e = tid; e < nz * nz; e += nt) {
+      const int i = e / nz, j = e - (e / nz) * nz;
+      X[e] = GM[e] * sh.sv[i] * sh.sv[j];
+    }
+    __syncthreads();
+    (void)block_jacobi(X, V, nz, sh.j);
+    if (tid == 0) {
+      double dmax = 0.0;
+      for (int j = 0; j < nz; ++j) dmax = fmax(dmax, X[j * nz + j]);
+      int rr = 0;
+      for (int j = 0; j < nz; ++j) {
+        const double dj = X[j * nz + j];
+        if (dj > 1e-12 * dmax) {
+          sh.kk[rr] = j;
+          sh.d[rr] = dj;
+          ++rr;
+        }
+      }
+      sh.r = rr;
+    }
+    __syncthreads();
+    r = sh.r;
+    for (int e = tid; e < nz * r; e += nt) {
+      const int i = e / r, q = e - (e / r) * r;
+      T[e] = sh.sv[i] * V[i * nz + sh.kk[q]] / sqrt(sh.d[q]);
+    }
+    __syncthreads();
+    for (int e = tid; e < nz * r; e += nt) {
+      const int i = e / r, q = e - (e / r) * r;
+      double acc = 0.0;
+      for (int k = 0; k < nz; ++k) acc += (GA[i * nz + k] - sigma * GM[i * nz + k]) * T[k * r + q];
+      W1[e] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < r * r; e += nt) {
+      const int p = e / r, q = e - (e / r) * r;
+      double acc = 0.0;
+      for (int i = 0; i < nz; ++i) acc += T[i * r + p] * W1[i * r + q];
+      X[e] = acc;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  const int r = sh.r;
-  for (int e = tid; e < nz * r; e += nt) {
-    const int i = e / r, q = e - (e / r) * r;
-    T[e] = sh.sv[i] * V[i * nz + sh.kk[q]] / sqrt(sh.d[q]);
-  }
-  __syncthreads();
-  for (int e = tid; e < nz * r; e += nt) {
-    const int i = e / r, q = e - (e / r) * r;
-    double acc = 0.0;
-    for (int k = 0; k < nz; ++k) acc += (GA[i * nz + k] - sigma * GM[i * nz + k]) * T[k * r + q];
-    Y1[e] = acc;
-  }
-  __syncthreads();
-  // C = T^T Y1 (r x r) into X
-  for (int e = tid; e < r * r; e += nt) {
-    const int p = e / r, q = e - (e / r) * r;
-    double acc = 0.0;
-    for (int i = 0; i < nz; ++i) acc += T[i * r + p] * Y1[i * r + q];
-    X[e] = acc;
-  }
-  __syncthreads();
   for (int e = tid; e < r * r; e += nt) {
     const int p = e / r, q = e - (e / r) * r;
     if (p < q) {
@@ -276,42 +392,34 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
     }
   }
   __syncthreads();
-  const int sw2 = block_jacobi(X, V, r, sh.j);
-  // select the m eigenvalues nearest 0 (ties: by value, then index), ascending
+  const int sw = block_jacobi(X, V, r, sh.j);
   const int mm = m < r ? m : r;
-  for (int j = tid; j < r; j += nt) {
-    const double mj = X[j * r + j], aj = fabs(mj);
-    int rank = 0;
-    for (int i = 0; i < r; ++i) {
-      const double mi = X[i * r + i], ai = fabs(mi);
-      if (ai < aj || (ai == aj && (mi < mj || (mi == mj && i < j)))) ++rank;
-    }
-    sh.kk[j] = rank;  // reuse: rank by distance
-  }
-  __syncthreads();
-  for (int j = tid; j < r; j += nt) {
-    if (sh.kk[j] >= mm) continue;
-    const double mj = X[j * r + j];
-    int pos = 0;
-    for (int i = 0; i < r; ++i) {
-      if (sh.kk[i] >= mm) continue;
-      const double mi = X[i * r + i];
-      if (mi < mj || (mi == mj && i < j)) ++pos;
-    }
-    sh.sel[pos] = j;
-  }
-  __syncthreads();
+  select_nearest_zero(X, r, mm, sh);
+  // Y (rows in the caller's order [W_c, U']) = basis coefficients of the selection
   for (int e = tid; e < nz * m; e += nt) {
-    const int i = e / m, c = e - (e / m) * m;
+    const int a = e / m, c = e - (e / m) * m;  // a: permuted row
     double acc = 0.0;
     if (c < mm) {
       const int col = sh.sel[c];
-      for (int q = 0; q < r; ++q) acc += T[i * r + q] * V[q * r + col];
+      if (chol) {
+        const int q = sh.dropmap[a];
+        if (q >= 0) {
+          for (int b = q; b < r; ++b) acc += Li[b * r + q] * V[b * r + col];
+          acc *= sh.sv[a];
+        }
+      } else {
+        for (int q = 0; q < r; ++q) acc += T[a * r + q] * V[q * r + col];
+      }
     }
-    Y[e] = acc;
+    Y[orig(a) * m + c] = acc;
   }
   for (int c = tid; c < m; c += nt) theta[c] = c < mm ? X[sh.sel[c] * r + sh.sel[c]] + sigma : 0.0;
-  if (tid == 0) *status = (r < m) ? 1 : ((sw1 < 0 || sw2 < 0) ? 2 : 0);
+  if (tid == 0) {
+    status[0] = (r < m) ? 1 : (sw < 0 ? 2 : 0);
+    status[1] = sw;
+    status[2] = chol ? 0 : 1;
+    status[3] = n - (chol ? r : n);
+  }
 }
 
 // Symmetric eigendecomposition of one n x n matrix (n <= 96), ascending.
@@ -367,7 +475,7 @@ void set_lds_attr() {
 
 }  // namespace
 
-int ritz_scratch_doubles(int nz) { return 4 * nz * nz; }
+int ritz_scratch_doubles(int nz) { return 5 * nz * nz; }
 
 int launch_ritz(const RitzArgs& a, hipStream_t s) {
   if (a.nz > kMaxN || a.nz != a.n_c + a.m) {

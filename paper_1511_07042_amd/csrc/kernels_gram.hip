@@ -12,6 +12,8 @@
 // partial buffer that a second kernel sums in a fixed order (deterministic).
 //
 // Update: U = Z Y for a small Y (the new Ritz vectors U <- [W_c, U'] Y).
+#include <algorithm>
+
 #include "bmg_internal.h"
 
 namespace bmg {
@@ -37,6 +39,8 @@ __device__ __forceinline__ double zcol(const double* __restrict__ z1, int w1,
 }
 
 // TI: tiles along nz (<= 6), TJW: tile columns per wavefront (<= 3).
+// Rows advance 16 at a time: the fragments of four 4-row steps are loaded
+// before their MFMAs are issued, so several loads are in flight per wavefront.
 template <int TI, int TJW>
 __global__ void __launch_bounds__(256) k_gram(int64_t n, int64_t rows_per_block, int nzp, int nyp,
                                               const double* __restrict__ z1, int w1,
@@ -54,18 +58,29 @@ __global__ void __launch_bounds__(256) k_gram(int64_t n, int64_t rows_per_block,
     for (int t = 0; t < TJW; ++t) acc[i][t] = d4{0.0, 0.0, 0.0, 0.0};
   const int64_t rb = int64_t(blockIdx.x) * rows_per_block;
   const int64_t re = rb + rows_per_block < n ? rb + rows_per_block : n;
-  for (int64_t r0 = rb; r0 < re; r0 += 4) {
-    const int64_t r = r0 + lk;
-    const bool ok = r < re;
-    double a[TI];
-    for (int i = 0; i < TI; ++i) a[i] = ok ? zcol(z1, w1, z2, w2, r, 16 * i + li) : 0.0;
-    for (int t = 0; t < TJW; ++t) {
-      const int tj = wave + 4 * t;
-      if (tj >= TJ) break;
-      const double b = ok ? zcol(y1, v1, y2, v2, r, 16 * tj + li) : 0.0;
-      for (int i = 0; i < TI; ++i)
-        acc[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b, acc[i][t], 0, 0, 0);
+  for (int64_t r0 = rb; r0 < re; r0 += 16) {
+    double a[4][TI], b[4][TJW];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t r = r0 + 4 * u + lk;
+      const bool ok = r < re;
+#pragma unroll
+      for (int i = 0; i < TI; ++i) a[u][i] = ok ? zcol(z1, w1, z2, w2, r, 16 * i + li) : 0.0;
+#pragma unroll
+      for (int t = 0; t < TJW; ++t) {
+        const int tj = wave + 4 * t;
+        b[u][t] = (ok && tj < TJ) ? zcol(y1, v1, y2, v2, r, 16 * tj + li) : 0.0;
+      }
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int t = 0; t < TJW; ++t) {
+        if (wave + 4 * t >= TJ) continue;
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+          acc[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][i], b[u][t], acc[i][t], 0, 0, 0);
+      }
   }
   double* out = part + int64_t(blockIdx.x) * nzp * nyp;
   for (int t = 0; t < TJW; ++t) {
@@ -76,44 +91,67 @@ __global__ void __launch_bounds__(256) k_gram(int64_t n, int64_t rows_per_block,
   }
 }
 
-__global__ void k_gram_reduce(const double* __restrict__ part, int nblk, int nzp, int nyp, int nz,
-                              int ny, double* __restrict__ G) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nz * ny) return;
-  const int i = e / ny, j = e - (e / ny) * ny;
-  const int64_t off = int64_t(i) * nyp + j;
-  const int64_t stride = int64_t(nzp) * nyp;
+// G[i][j] = sum_b part[b][i][j] in a fixed order: each block covers 64
+// consecutive outputs with 16 segments of the partials (b = seg mod 16), then
+// adds the 16 segment sums in order.
+__global__ void __launch_bounds__(1024) k_gram_reduce(const double* __restrict__ part, int nblk,
+                                                      int nzp, int nyp, int nz, int ny,
+                                                      double* __restrict__ G) {
+  __shared__ double red[16][64];
+  const int el = threadIdx.x & 63, seg = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + el;
+  const int tot = nz * ny;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[b * stride + off];
-  G[e] = s;
+  if (e < tot) {
+    const int i = e / ny, j = e - (e / ny) * ny;
+    const int64_t off = int64_t(i) * nyp + j;
+    const int64_t stride = int64_t(nzp) * nyp;
+    for (int b = seg; b < nblk; b += 16) s += part[b * stride + off];
+  }
+  red[seg][el] = s;
+  __syncthreads();
+  if (seg == 0 && e < tot) {
+    double t = 0.0;
+    for (int q = 0; q < 16; ++q) t += red[q][el];
+    G[e] = t;
+  }
 }
 
-// U[r][c] = sum_i Z[r][i] Y[i][c];  Y staged in LDS.  Thread per (row, 2 cols).
+// U[r][c] = sum_i Z[r][i] Y[i][c], Z = [z1 | z2].  Y and the block's rows of
+// Z are staged in LDS before any output is written, so U may alias z2 (the
+// update is done in place).  Thread per (row, 2 columns).
 __global__ void __launch_bounds__(256) k_update_zy(int64_t n, const double* __restrict__ z1, int w1,
-                                                   const double* __restrict__ z2, int w2,
+                                                   const double* z2, int w2,
                                                    const double* __restrict__ Y, int m, int cpr,
-                                                   int rpb, double* __restrict__ U) {
+                                                   int rpb, double* U) {
   extern __shared__ double ys[];
   const int nz = w1 + w2;
+  double* zs = ys + nz * m;  // [rpb][nz]
   for (int e = threadIdx.x; e < nz * m; e += blockDim.x) ys[e] = Y[e];
-  __syncthreads();
   const int rloc = threadIdx.x / cpr;
   const int ch = threadIdx.x - rloc * cpr;
-  if (rloc >= rpb) return;
-  for (int64_t r = int64_t(blockIdx.x) * rpb + rloc; r < n; r += int64_t(gridDim.x) * rpb) {
-    double c0 = 0.0, c1 = 0.0;
-    for (int i = 0; i < w1; ++i) {
-      const double z = z1[r * w1 + i];
-      c0 += z * ys[i * m + 2 * ch];
-      c1 += z * ys[i * m + 2 * ch + 1];
+  for (int64_t r0 = int64_t(blockIdx.x) * rpb; r0 < n; r0 += int64_t(gridDim.x) * rpb) {
+    __syncthreads();  // previous rows consumed (and Y staged on the first pass)
+    for (int e = threadIdx.x; e < rpb * nz; e += blockDim.x) {
+      const int q = e / nz, i = e - (e / nz) * nz;
+      const int64_t r = r0 + q;
+      double v = 0.0;
+      if (r < n) v = i < w1 ? z1[r * w1 + i] : z2[r * w2 + (i - w1)];
+      zs[e] = v;
     }
-    for (int i = 0; i < w2; ++i) {
-      const double z = z2[r * w2 + i];
-      c0 += z * ys[(w1 + i) * m + 2 * ch];
-      c1 += z * ys[(w1 + i) * m + 2 * ch + 1];
+    __syncthreads();
+    const int64_t r = r0 + rloc;
+    if (rloc < rpb && r < n) {
+      double c0 = 0.0, c1 = 0.0;
+      const double* zr = zs + rloc * nz;
+      for (int i = 0; i < nz; ++i) {
+        const double z = zr[i];
+        c0 += z * ys[i * m + 2 * ch];
+        c1 += z * ys[i * m + 2 * ch + 1];
+      }
+      U[r * m + 2 * ch] = c0;
+      U[r * m + 2 * ch + 1] = c1;
     }
-    U[r * m + 2 * ch] = c0;
-    U[r * m + 2 * ch + 1] = c1;
   }
 }
 
@@ -132,8 +170,12 @@ GramPlan gram_plan(int64_t n, int nz, int ny) {
   p.ny = ny;
   p.nzp = (nz + 15) / 16 * 16;
   p.nyp = (ny + 15) / 16 * 16;
-  int64_t blocks = (n + 255) / 256;  // at least 256 rows per block
-  p.nblk = int(blocks < 512 ? (blocks > 0 ? blocks : 1) : 512);
+  // at least 64 rows per block, at most 1024 blocks, and partial sums of at
+  // most a quarter of the bytes the kernel reads
+  int64_t blocks = (n + 63) / 64;
+  const int64_t cap = int64_t(0.25 * double(n) * (nz + ny) / (double(p.nzp) * p.nyp));
+  blocks = std::min<int64_t>(blocks, std::max<int64_t>(cap, 1));
+  p.nblk = int(std::max<int64_t>(1, std::min<int64_t>(blocks, 1024)));
   return p;
 }
 
@@ -148,7 +190,7 @@ int launch_gram(const GramPlan& p, int64_t n, const double* z1, int w1, const do
     return BMG_EINVAL;
   }
   int64_t rpb = (n + p.nblk - 1) / p.nblk;
-  rpb = (rpb + 3) / 4 * 4;
+  rpb = (rpb + 15) / 16 * 16;
 #define GL(a, b) \
   gram_dispatch_launch<a, b>(p, n, rpb, z1, w1, z2, w2, y1, v1, y2, v2, part, s)
   switch (TI * 4 + TJW) {
@@ -175,7 +217,7 @@ int launch_gram(const GramPlan& p, int64_t n, const double* z1, int w1, const do
   int st = check_launch();
   if (st != BMG_OK) return st;
   const int tot = p.nz * p.ny;
-  k_gram_reduce<<<(tot + 255) / 256, 256, 0, s>>>(part, p.nblk, p.nzp, p.nyp, p.nz, p.ny, G);
+  k_gram_reduce<<<(tot + 63) / 64, 1024, 0, s>>>(part, p.nblk, p.nzp, p.nyp, p.nz, p.ny, G);
   return check_launch();
 }
 
@@ -186,7 +228,7 @@ int launch_update_zy(int64_t n, const double* z1, int w1, const double* z2, int 
   const int block = rpb * cpr;
   int64_t groups = (n + rpb - 1) / rpb;
   const int grid = int(groups < 4096 ? groups : 4096);
-  const size_t shm = size_t(w1 + w2) * m * sizeof(double);
+  const size_t shm = size_t(w1 + w2) * (m + rpb) * sizeof(double);
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute((const void*)k_update_zy, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -25,7 +25,7 @@ struct bmg_workspace {
   int m = 0, n_c = 0, prec = 0, nl = 0;
   bool busy = false;
   double *W = nullptr, *AW = nullptr, *MW = nullptr;
-  double *U = nullptr, *Unew = nullptr, *AU = nullptr, *MU = nullptr;
+  double *U = nullptr, *AU = nullptr, *MU = nullptr;
   std::vector<void*> e, f, t;  // per level, correction precision
   void* ctmp = nullptr;        // [N0][m]
   void* gco = nullptr;         // [N0]
@@ -86,7 +86,6 @@ int make_workspace(bmg_hierarchy* h, int m, int n_c, int prec, bmg_workspace** o
   AL(w->AW, sizeof(double) * N * n_c);
   AL(w->MW, sizeof(double) * N * n_c);
   AL(w->U, sizeof(double) * N * m);
-  AL(w->Unew, sizeof(double) * N * m);
   AL(w->AU, sizeof(double) * N * m);
   AL(w->MU, sizeof(double) * N * m);
   w->e.resize(nl);
@@ -163,6 +162,52 @@ void free_workspaces(bmg_hierarchy* h) {
   h->ws_pool.clear();
 }
 
+// ----------------------------------------------------------- kernel timer --
+// Brackets the launches of one kernel class (finest level only) with HIP events
+// on the solve's stream; durations are summed after the final synchronisation.
+struct KTimer {
+  int which = -1;
+  hipStream_t s = nullptr;
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  double bytes = 0.0;
+  int64_t units = 0;
+  int begin(int k) {
+    if (k != which) return BMG_OK;
+    if (2 * used + 2 > ev.size()) {
+      hipEvent_t a, b;
+      BMG_HIP(hipEventCreate(&a));
+      BMG_HIP(hipEventCreate(&b));
+      ev.push_back(a);
+      ev.push_back(b);
+    }
+    BMG_HIP(hipEventRecord(ev[2 * used], s));
+    return BMG_OK;
+  }
+  int end(int k) {
+    if (k != which) return BMG_OK;
+    BMG_HIP(hipEventRecord(ev[2 * used + 1], s));
+    ++used;
+    return BMG_OK;
+  }
+  void add(int k, double b, int64_t u) {
+    if (k != which) return;
+    bytes += b;
+    units += u;
+  }
+  double total_ms() {
+    double t = 0.0;
+    for (size_t i = 0; i < used; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) == hipSuccess) t += ms;
+    }
+    return t;
+  }
+  ~KTimer() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
 // ------------------------------------------------------- correction cycle --
 struct CycleCfg {
   int m, nu1, nu2, smoother, l_c;
@@ -177,18 +222,29 @@ struct Cycle {
   T* ctmp;
   const T* g0;  // truncated inverse spectrum at level 0
   hipStream_t s;
+  KTimer* kt = nullptr;  // timing of finest-level launches (level L)
+  int L = -1;
+
+  int kclass(int l, int k) const { return (kt && l == L) ? k : -2; }
 
   int sweep(int l, bool forward, bool from_zero) {
     const DevLevel& D = h->dev[l];
+    const int kc = kclass(l, BMG_K_SMOOTH);
+    const double b = sizeof(T);
+    if (kt) kt->add(kc, (4 + 2 * b) * double(h->host[l].nnz) + 4.0 * D.n + 3 * b * D.n * c.m, 1);
     if (c.smoother == BMG_SMOOTH_JACOBI) {
+      if (kt) BMG_TRY(kt->begin(kc));
       BMG_TRY(launch_jacobi<T>(D, c.sigma, c.omega, e[l], f[l], t[l], from_zero, c.m, s));
+      if (kt) BMG_TRY(kt->end(kc));
       std::swap(e[l], t[l]);
       return BMG_OK;
     }
     if (from_zero) BMG_TRY(launch_fill<T>(e[l], D.n * c.m, T(0), s));
     for (int k = 0; k < D.n_colours; ++k) {
       const int col = forward ? k : D.n_colours - 1 - k;
+      if (kt) BMG_TRY(kt->begin(kc));
       BMG_TRY(launch_gs_colour<T>(D, col, c.sigma, e[l], f[l], c.m, s));
+      if (kt) BMG_TRY(kt->end(kc));
     }
     return BMG_OK;
   }
@@ -210,10 +266,24 @@ struct Cycle {
     }
     for (int k = 0; k < c.nu1; ++k) BMG_TRY(sweep(l, true, k == 0));
     if (c.nu1 == 0) BMG_TRY(launch_fill<T>(e[l], D.n * c.m, T(0), s));
+    const double b = sizeof(T);
+    const double nnz = double(h->host[l].nnz), n = double(D.n), nc = double(D.n_prev);
+    int kc = kclass(l, BMG_K_RESIDUAL);
+    if (kt) kt->add(kc, (4 + 2 * b) * nnz + 3 * b * n * c.m, 1);
+    if (kt) BMG_TRY(kt->begin(kc));
     BMG_TRY(launch_shifted<T>(D, ROW_RESIDUAL, c.sigma, e[l], f[l], t[l], c.m, s));
+    if (kt) BMG_TRY(kt->end(kc));
+    kc = kclass(l, BMG_K_RESTRICT);
+    if (kt) kt->add(kc, b * n * c.m + b * nc * c.m + 4.0 * nc * D.RW, 1);
+    if (kt) BMG_TRY(kt->begin(kc));
     BMG_TRY(launch_restrict<T>(D, t[l], f[l - 1], c.m, s));
+    if (kt) BMG_TRY(kt->end(kc));
     BMG_TRY(vcycle(l - 1));
+    kc = kclass(l, BMG_K_PROLONG);
+    if (kt) kt->add(kc, b * nc * c.m + 2 * b * n * c.m + 8.0 * (n - nc), 1);
+    if (kt) BMG_TRY(kt->begin(kc));
     BMG_TRY(launch_prolong_add<T>(D, e[l - 1], e[l], c.m, s));
+    if (kt) BMG_TRY(kt->end(kc));
     for (int k = 0; k < c.nu2; ++k) BMG_TRY(sweep(l, false, false));
     return BMG_OK;
   }
@@ -327,6 +397,11 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   else
     BMG_TRY(launch_gaussian(w->U, N, m, o.seed, s));
 
+  KTimer kt;
+  kt.which = o.timed_kernel;
+  kt.s = s;
+  const double nnzL = double(h->host[L].nnz), Nd = double(N);
+  int ritz_sweeps_max = 0, ritz_fallbacks = 0;
   RitzArgs ra;
   ra.n_c = n_c;
   ra.m = m;
@@ -339,11 +414,22 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   ra.scratch = w->rscratch;
   ra.status = w->status;
   auto ritz_step = [&]() -> int {
+    kt.add(BMG_K_SPMM_AM, 20 * nnzL + 24 * Nd * m, 1);
+    BMG_TRY(kt.begin(BMG_K_SPMM_AM));
     BMG_TRY(launch_spmm_am(DL, w->U, w->AU, w->MU, m, s));
+    BMG_TRY(kt.end(BMG_K_SPMM_AM));
+    kt.add(BMG_K_GRAM, 4.0 * Nd * nz * m, 1);
+    BMG_TRY(kt.begin(BMG_K_GRAM));
     BMG_TRY(launch_gram(w->gp, N, w->W, n_c, w->U, m, w->AU, m, w->MU, m, w->gpart, w->G, s));
+    BMG_TRY(kt.end(BMG_K_GRAM));
+    kt.add(BMG_K_RITZ, 0.0, 1);
+    BMG_TRY(kt.begin(BMG_K_RITZ));
     BMG_TRY(launch_ritz(ra, s));
-    BMG_TRY(launch_update_zy(N, w->W, n_c, w->U, m, w->Y, w->Unew, m, s));
-    std::swap(w->U, w->Unew);
+    BMG_TRY(kt.end(BMG_K_RITZ));
+    kt.add(BMG_K_UPDATE, 2.0 * Nd * nz * m, 1);
+    BMG_TRY(kt.begin(BMG_K_UPDATE));
+    BMG_TRY(launch_update_zy(N, w->W, n_c, w->U, m, w->Y, w->U, m, s));  // in place
+    BMG_TRY(kt.end(BMG_K_UPDATE));
     return BMG_OK;
   };
   BMG_TRY(ritz_step());
@@ -362,6 +448,8 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   cyc.ctmp = static_cast<T*>(w->ctmp);
   cyc.g0 = static_cast<const T*>(w->gco);
   cyc.s = s;
+  cyc.kt = o.timed_kernel >= 0 ? &kt : nullptr;
+  cyc.L = L;
 
   std::vector<double> theta(m), rho2(m);
   Cert cert;
@@ -369,16 +457,22 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   int status = BMG_OK;
   for (;;) {
     // H1: -R in the correction precision and rho^2
+    kt.add(BMG_K_EIGRES, 20 * nnzL + (8.0 + sizeof(T)) * Nd * m + 8 * Nd, 1);
+    BMG_TRY(kt.begin(BMG_K_EIGRES));
     BMG_TRY(launch_eigres<T>(DL, w->U, w->theta, -1.0, cyc.f[L], w->rho2part, w->nblk_res, m, s));
+    BMG_TRY(kt.end(BMG_K_EIGRES));
     BMG_TRY(launch_colsum(w->rho2part, w->nblk_res, m, w->rho2, s));
     BMG_HIP(hipMemcpyAsync(w->hbuf, w->theta, sizeof(double) * m, hipMemcpyDeviceToHost, s));
     BMG_HIP(hipMemcpyAsync(w->hbuf + m, w->rho2, sizeof(double) * m, hipMemcpyDeviceToHost, s));
-    BMG_HIP(hipMemcpyAsync(w->hbuf + 2 * m, w->status, sizeof(int), hipMemcpyDeviceToHost, s));
+    BMG_HIP(hipMemcpyAsync(w->hbuf + 2 * m, w->status, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
     BMG_HIP(hipStreamSynchronize(s));
     std::memcpy(theta.data(), w->hbuf, sizeof(double) * m);
     std::memcpy(rho2.data(), w->hbuf + m, sizeof(double) * m);
-    int rstat = 0;
-    std::memcpy(&rstat, w->hbuf + 2 * m, sizeof(int));
+    int rs3[3] = {0, 0, 0};
+    std::memcpy(rs3, w->hbuf + 2 * m, 3 * sizeof(int));
+    const int rstat = rs3[0];
+    ritz_sweeps_max = std::max(ritz_sweeps_max, rs3[1]);
+    ritz_fallbacks += rs3[2];
     if (rstat == 1) {
       set_error("enriched space lost rank below m");
       status = BMG_ENOCONV;
@@ -437,6 +531,11 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     stats->t_solve_ms = ms;
     stats->max_rho_over_delta = cert.max_dk;
     stats->max_kato_temple = cert.max_kt;
+    stats->timed_kernel_ms = kt.total_ms();
+    stats->timed_kernel_bytes = kt.bytes;
+    stats->timed_kernel_units = kt.units;
+    stats->ritz_sweeps_max = ritz_sweeps_max;
+    stats->ritz_fallbacks = ritz_fallbacks;
     // report in the output order (ascending)
     for (int j = 0; j < k && j < int(cert.ret.size()); ++j) {
       const int pos = int(std::find(cert.ret.begin(), cert.ret.end(), sel[j]) - cert.ret.begin());
