@@ -82,7 +82,7 @@ typedef struct bmg_hierarchy bmg_hierarchy; /* opaque; device-resident after bui
  * Errors: BMG_EINVAL for a NULL/ill-formed descriptor, n_refine outside
  * [0, 10], a custom mesh that is not a closed, consistently oriented
  * 2-manifold (every directed edge once, its reverse once), a vertex valence
- * above 30, or a coarse mesh with more than 4096 vertices.
+ * above 30, or a coarse mesh with more than 1024 vertices.
  * Ownership: *out belongs to the caller until bmg_free_hierarchy. */
 int bmg_build_hierarchy(const bmg_surface_desc* desc, int32_t n_refine, void* stream,
                         bmg_hierarchy** out);
@@ -154,7 +154,26 @@ typedef struct {
   uint64_t seed;      /* test vectors: element (i,j) ~ N(0,1) from SplitMix64
                          counters 2c, 2c+1 with c = i m + j, Box-Muller */
   const double* initial_block; /* optional host [N_L][m] block replacing the seeded one */
+  int32_t timed_kernel; /* bmg_kernel_class to bracket with HIP events on `stream`
+                           (finest level only), or -1; see bmg_solve_stats */
+  int32_t reserved;
 } bmg_solve_opts;
+
+/* Kernel classes that bmg_solve can time (launches on the finest level L).
+ * Algorithmic bytes per launch (N = N_L, nnz = nonzeros of A_L, m = block
+ * width, b = 4 (mixed) or 8 (FP64) bytes per correction value, nz = n_c + m):
+ *   EIGRES    residual SpMM:  20 nnz + 8 N m (U) + b N m (R) + 8 N (D^-1)
+ *   SPMM_AM   A and M SpMM:   20 nnz + 8 N m (U) + 16 N m (A U, M U)
+ *   SMOOTH    one sweep (all colour passes of Gauss-Seidel, or one Jacobi
+ *             step): (4 + 2b) nnz + 4 N + 3 b N m  (x, f read; x written)
+ *   RESIDUAL  (4 + 2b) nnz + 3 b N m;   RESTRICT  b N m + b N_{L-1} m + 4 N;
+ *   PROLONG   b N_{L-1} m + 2 b N m + 8 (N - N_{L-1});
+ *   GRAM      8 N (nz + 2m) bytes, 4 N nz m flops;
+ *   UPDATE    8 N nz + 8 N m bytes, 2 N nz m flops;   RITZ  one workgroup. */
+typedef enum {
+  BMG_K_EIGRES = 0, BMG_K_SPMM_AM = 1, BMG_K_SMOOTH = 2, BMG_K_RESIDUAL = 3,
+  BMG_K_RESTRICT = 4, BMG_K_PROLONG = 5, BMG_K_GRAM = 6, BMG_K_UPDATE = 7, BMG_K_RITZ = 8
+} bmg_kernel_class;
 
 /* Fill *o with the defaults listed above. */
 void bmg_solve_opts_default(bmg_solve_opts* o);
@@ -170,6 +189,11 @@ typedef struct {
   double* rho;         /* nullable host [k]: rho_i = 2 ||r_i||_{D^-1} >= ||r_i||_{M^-1} */
   double* delta;       /* nullable host [k]: distance to the nearest Ritz value outside
                           the cluster of theta_i */
+  double timed_kernel_ms;     /* summed HIP-event time of opts->timed_kernel launches */
+  double timed_kernel_bytes;  /* summed algorithmic bytes (flops for GRAM/UPDATE) */
+  int64_t timed_kernel_units; /* launches, or sweeps for BMG_K_SMOOTH */
+  int32_t ritz_sweeps_max;    /* most Jacobi sweeps of one Ritz step */
+  int32_t ritz_fallbacks;     /* Ritz steps that needed SVQB instead of Cholesky */
 } bmg_solve_stats;
 
 /* The k eigenpairs of (A_L, M_L) nearest sigma on the finest level L.

@@ -116,8 +116,11 @@ void free_device(bmg_hierarchy* h);
 // and return BMG_OK or BMG_EDEVICE.
 enum RowMode { ROW_SHIFTED = 0, ROW_RESIDUAL = 1 };
 
+// S = A - sigma M in precision T (same expression as the smoothers use)
 template <typename T>
-int launch_shifted(const DevLevel& L, int mode, double sigma, const T* x, const T* f, T* y, int m,
+int launch_shift(const DevLevel& L, double sigma, T* S, hipStream_t s);
+template <typename T>
+int launch_shifted(const DevLevel& L, const T* S, int mode, const T* x, const T* f, T* y, int m,
                    hipStream_t s);
 int launch_spmm_am(const DevLevel& L, const double* x, double* ya, double* ym, int m,
                    hipStream_t s);
@@ -130,10 +133,10 @@ int eigres_blocks(const DevLevel& L, int m);
 int launch_colsum(const double* part, int nblk, int m, double* out, hipStream_t s);
 
 template <typename T>
-int launch_jacobi(const DevLevel& L, double sigma, double omega, const T* x, const T* f, T* y,
+int launch_jacobi(const DevLevel& L, const T* S, double omega, const T* x, const T* f, T* y,
                   bool x_is_zero, int m, hipStream_t s);
 template <typename T>
-int launch_gs_colour(const DevLevel& L, int colour, double sigma, T* x, const T* f, int m,
+int launch_gs_colour(const DevLevel& L, const T* S, int colour, T* x, const T* f, int m,
                      hipStream_t s);
 template <typename T>
 int launch_restrict(const DevLevel& fine, const T* x, T* y, int m, hipStream_t s);
@@ -162,6 +165,28 @@ int launch_gram(const GramPlan& p, int64_t n, const double* z1, int w1, const do
 // U[n][m] = Z Y, Z = [z1 (w1) | z2 (w2)], Y [w1+w2][m] device
 int launch_update_zy(int64_t n, const double* z1, int w1, const double* z2, int w2,
                      const double* Y, double* U, int m, hipStream_t s);
+
+// Coarse end of the correction cycle in one workgroup, in LDS (kernels_tail.hip).
+constexpr int kTailMaxLevels = 12;
+constexpr int kTailMaxColours = 32;
+constexpr int kTailLdsBudget = 152 * 1024;
+struct TailLevel {  // byte offsets into the kernel's dynamic LDS
+  int n, n_prev, W, RW, n_colours;
+  int off_S, off_cols, off_crow, off_par, off_rtab, off_e, off_f, off_t;
+  int colour_ptr[kTailMaxColours + 1];
+};
+struct alignas(16) TailArgs {
+  int lo, hi, m, smoother, nu1, nu2;
+  double omega;
+  const void* image;  // packed static arrays, copied to LDS offset 0
+  int image_bytes;
+  int off_phi, off_phit, off_g;  // level-0 spectral inverse (-1: smoothing at lo)
+  const void* f_top;  // f of level hi (global)
+  void* e_top;        // e of level hi (global)
+  TailLevel lv[kTailMaxLevels];
+};
+template <typename T>
+int launch_tail(const TailArgs* dev_args, int lds_bytes, hipStream_t s);
 
 // One-workgroup Ritz step (see kernels_dense.hip).
 struct RitzArgs {

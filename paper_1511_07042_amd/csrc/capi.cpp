@@ -33,6 +33,24 @@ void free_workspaces(bmg_hierarchy* h);
 
 }  // namespace bmg
 
+namespace bmg {
+namespace {
+// Runs fn(S) with a temporary S = A_l - sigma M_l of the requested precision.
+template <typename F>
+int with_shift(const DevLevel& D, double sigma, bool f32, hipStream_t s, F&& fn) {
+  const size_t bytes = (f32 ? sizeof(float) : sizeof(double)) * D.n * D.W;
+  void* S = nullptr;
+  BMG_HIP(hipMalloc(&S, bytes));
+  int st = f32 ? launch_shift<float>(D, sigma, static_cast<float*>(S), s)
+               : launch_shift<double>(D, sigma, static_cast<double*>(S), s);
+  if (st == BMG_OK) st = fn(static_cast<const void*>(S));
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(S);
+  return st;
+}
+}  // namespace
+}  // namespace bmg
+
 using namespace bmg;
 
 extern "C" {
@@ -98,8 +116,15 @@ static int build_impl(const bmg_surface_desc* desc, int32_t n_refine, void* stre
     }
   }
   if (st == BMG_OK && to_device) {
-    if (hipGetDevice(&h->device) != hipSuccess) {
-      set_error("no HIP device");
+    // works whether or not another runtime user initialised the device first
+    int count = 0;
+    hipError_t e = hipInit(0);
+    if (e == hipSuccess) e = hipGetDeviceCount(&count);
+    if (e == hipSuccess && count < 1) e = hipErrorNoDevice;
+    if (e == hipSuccess) e = hipGetDevice(&h->device);
+    if (e == hipSuccess) e = hipSetDevice(h->device);
+    if (e != hipSuccess) {
+      set_error("no usable HIP device: %s", hipGetErrorString(e));
       st = BMG_EDEVICE;
     } else {
       st = upload_hierarchy(h, static_cast<hipStream_t>(stream));
@@ -225,8 +250,12 @@ int bmg_apply(const bmg_hierarchy* hc, const bmg_apply_args* a, const void* x, c
       BMG_TRY(need_m(4));
       BMG_CHECK(x != nullptr && (a->op == BMG_OP_SHIFTED || f != nullptr), "x (and f) required");
       const int mode = a->op == BMG_OP_SHIFTED ? ROW_SHIFTED : ROW_RESIDUAL;
-      return f32 ? launch_shifted<float>(D, mode, a->sigma, (const float*)x, (const float*)f, (float*)y, m, s)
-                 : launch_shifted<double>(D, mode, a->sigma, (const double*)x, (const double*)f, (double*)y, m, s);
+      return with_shift(D, a->sigma, f32, s, [&](const void* S) {
+        return f32 ? launch_shifted<float>(D, (const float*)S, mode, (const float*)x, (const float*)f,
+                                           (float*)y, m, s)
+                   : launch_shifted<double>(D, (const double*)S, mode, (const double*)x,
+                                            (const double*)f, (double*)y, m, s);
+      });
     }
     case BMG_OP_SMOOTH_FWD:
     case BMG_OP_SMOOTH_BWD: {
@@ -236,18 +265,24 @@ int bmg_apply(const bmg_hierarchy* hc, const bmg_apply_args* a, const void* x, c
       if (a->smoother == BMG_SMOOTH_JACOBI) {
         BMG_CHECK(x != nullptr && x != y, "Jacobi needs x (input) distinct from y (output)");
         BMG_CHECK(a->omega > 0 && a->omega < 2, "omega must be in (0, 2)");
-        return f32 ? launch_jacobi<float>(D, a->sigma, a->omega, (const float*)x, (const float*)f, (float*)y, false, m, s)
-                   : launch_jacobi<double>(D, a->sigma, a->omega, (const double*)x, (const double*)f, (double*)y, false, m, s);
+        return with_shift(D, a->sigma, f32, s, [&](const void* S) {
+          return f32 ? launch_jacobi<float>(D, (const float*)S, a->omega, (const float*)x,
+                                            (const float*)f, (float*)y, false, m, s)
+                     : launch_jacobi<double>(D, (const double*)S, a->omega, (const double*)x,
+                                             (const double*)f, (double*)y, false, m, s);
+        });
       }
       BMG_CHECK(a->smoother == BMG_SMOOTH_GS, "unknown smoother");
-      for (int k = 0; k < D.n_colours; ++k) {
-        const int c = fwd ? k : D.n_colours - 1 - k;
-        if (f32)
-          BMG_TRY(launch_gs_colour<float>(D, c, a->sigma, (float*)y, (const float*)f, m, s));
-        else
-          BMG_TRY(launch_gs_colour<double>(D, c, a->sigma, (double*)y, (const double*)f, m, s));
-      }
-      return BMG_OK;
+      return with_shift(D, a->sigma, f32, s, [&](const void* S) -> int {
+        for (int k = 0; k < D.n_colours; ++k) {
+          const int c = fwd ? k : D.n_colours - 1 - k;
+          if (f32)
+            BMG_TRY(launch_gs_colour<float>(D, (const float*)S, c, (float*)y, (const float*)f, m, s));
+          else
+            BMG_TRY(launch_gs_colour<double>(D, (const double*)S, c, (double*)y, (const double*)f, m, s));
+        }
+        return BMG_OK;
+      });
     }
     case BMG_OP_RESTRICT:
     case BMG_OP_PROLONG_ADD: {

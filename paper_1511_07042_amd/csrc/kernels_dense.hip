@@ -17,9 +17,9 @@
 // rotations in parallel (round-robin) order.  In one round the n/2 disjoint
 // pairs (p, q) get their rotations at once; every 2x2 block [p1 q1] x [p2 q2]
 // of the matrix is rotated on both sides by one thread and each row of the
-// eigenvector matrix by one thread.  Sweeps stop after a sweep in which no
-// rotation was significant (|a_pq| > 1e-15 sqrt|a_pp a_qq| and
-// |a_pq| > 1e-18 ||A||_F).
+// eigenvector matrix by one thread.  Only significant rotations are applied,
+// |a_pq| > 1e-15 max(sqrt|a_pp a_qq|, ||A||_F / n), so rounding noise is not
+// churned; sweeps stop after a sweep without one.
 #include <cmath>
 
 #include "bmg_internal.h"
@@ -28,11 +28,13 @@ namespace bmg {
 namespace {
 
 constexpr int kMaxN = 96;
-constexpr int kThreads = 512;
+constexpr int kThreads = 1024;
 
 struct JacobiShared {
   double c[kMaxN / 2], s[kMaxN / 2], t[kMaxN / 2];
   int p[kMaxN / 2], q[kMaxN / 2];
+  unsigned char pq[kMaxN - 1][kMaxN];  // round-robin pairs: round r, slot t -> (p, q) at [r][2t], [r][2t+1]
+  int rflag;
   double red[2 * (kThreads / 64)];
   double bcast[2];
   int sig[2];
@@ -84,24 +86,33 @@ __device__ int block_jacobi(double* X, double* V, int n, JacobiShared& sh) {
   }
   double fro2, dummy;
   block_sum2(f2, 0.0, sh, fro2, dummy);
-  const double fro = sqrt(fro2);
+  const double floor_abs = sqrt(fro2) / n;
+  int lh = 0;  // 2^lh >= half: 2-D thread indices without integer division
+  while ((1 << lh) < half) ++lh;
+  const int hp = 1 << lh;
+  // round-robin (circle method) pair table, built once per call
+  for (int e = tid; e < (ne - 1) * half; e += nt) {
+    const int rd = e / half, t = e - (e / half) * half;
+    int p = (t + rd) % (ne - 1);
+    int q = t == 0 ? ne - 1 : (ne - 1 - t + rd) % (ne - 1);
+    sh.pq[rd][2 * t] = (unsigned char)(p < q ? p : q);
+    sh.pq[rd][2 * t + 1] = (unsigned char)(p < q ? q : p);
+  }
+  if (tid == 0) sh.rflag = 0;
+  __syncthreads();
+  int gr = 0;  // global round counter
   for (int sweep = 0; sweep < 30; ++sweep) {
     const int cur = sweep & 1;
-    for (int rd = 0; rd < ne - 1; ++rd) {
+    for (int rd = 0; rd < ne - 1; ++rd, ++gr) {
       if (tid < half) {
-        int p = (tid + rd) % (ne - 1);
-        int q = tid == 0 ? ne - 1 : (ne - 1 - tid + rd) % (ne - 1);
-        if (p > q) {
-          const int tmp = p;
-          p = q;
-          q = tmp;
-        }
+        const int p = sh.pq[rd][2 * tid], q = sh.pq[rd][2 * tid + 1];
         double c = 1.0, s = 0.0, t = 0.0;
         if (q < n) {
           const double apq = X[p * n + q];
           const double app = X[p * n + p], aqq = X[q * n + q];
-          if (fabs(apq) > 1e-300) {
-            if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-18 * fro) sh.sig[cur] = 1;
+          if (fabs(apq) > 1e-15 * fmax(sqrt(fabs(app * aqq)), floor_abs)) {
+            sh.sig[cur] = 1;
+            sh.rflag = gr + 1;
             const double tau = (aqq - app) / (2.0 * apq);
             if (fabs(tau) > 1e150) {
               t = 0.5 / tau;
@@ -120,57 +131,65 @@ __device__ int block_jacobi(double* X, double* V, int n, JacobiShared& sh) {
       }
       __syncthreads();
       if (rd == 0 && tid == 0) sh.sig[cur ^ 1] = 0;  // everyone has read it by now
-      // two-sided update of the blocks (t1 <= t2), each written with its transpose
-      for (int idx = tid; idx < half * half; idx += nt) {
-        const int t1 = idx / half, t2 = idx - (idx / half) * half;
-        if (t2 < t1) continue;
-        const int p1 = sh.p[t1], q1 = sh.q[t1], p2 = sh.p[t2], q2 = sh.q[t2];
-        const double c1 = sh.c[t1], s1 = sh.s[t1], c2 = sh.c[t2], s2 = sh.s[t2];
-        if (t1 == t2) {
-          if (q1 < n && s1 != 0.0) {
-            const double apq = X[p1 * n + q1];
-            X[p1 * n + p1] -= sh.t[t1] * apq;
-            X[q1 * n + q1] += sh.t[t1] * apq;
-            X[p1 * n + q1] = 0.0;
-            X[q1 * n + p1] = 0.0;
+      // no significant rotation in this round: nothing changes, and the next
+      // round's parameters may be written without a second barrier
+      if (sh.rflag != gr + 1) continue;
+      // Thread (g, t): fixed pair slot t = tid mod hp, groups g = tid / hp.  All
+      // operands of a thread's items are loaded before any is written back.
+      const int t = tid & (hp - 1);
+      const int g0 = tid >> lh, G = nt >> lh;
+      if (t < half) {
+        const int p2 = sh.p[t], q2 = sh.q[t];
+        const double c2 = sh.c[t], s2 = sh.s[t];
+        const bool hq2 = q2 < n;
+        // 2x2 blocks (t1 <= t2 = t), each written with its transpose; with
+        // 1024 threads a thread has one block (n <= 64) or at most three
+        const double tt2 = sh.t[t];
+        for (int t1 = g0; t1 <= t; t1 += G) {
+          const int a1 = sh.p[t1], b1 = sh.q[t1];
+          const double c1 = sh.c[t1], s1 = sh.s[t1];
+          const bool hq1 = b1 < n;
+          const double bpp = X[a1 * n + p2];
+          const double bpq = hq2 ? X[a1 * n + q2] : 0.0;
+          const double bqp = hq1 ? X[b1 * n + p2] : 0.0;
+          const double bqq = (hq1 && hq2) ? X[b1 * n + q2] : 0.0;
+          if (t1 == t) {
+            if (hq2 && s2 != 0.0) {
+              X[p2 * n + p2] = bpp - tt2 * bpq;
+              X[q2 * n + q2] = bqq + tt2 * bpq;
+              X[p2 * n + q2] = 0.0;
+              X[q2 * n + p2] = 0.0;
+            }
+            continue;
           }
-          continue;
+          if (s1 == 0.0 && s2 == 0.0) continue;
+          const double lpp = c1 * bpp - s1 * bqp, lpq = c1 * bpq - s1 * bqq;
+          const double lqp = s1 * bpp + c1 * bqp, lqq = s1 * bpq + c1 * bqq;
+          const double npp = c2 * lpp - s2 * lpq, npq = s2 * lpp + c2 * lpq;
+          const double nqp = c2 * lqp - s2 * lqq, nqq = s2 * lqp + c2 * lqq;
+          X[a1 * n + p2] = npp;
+          X[p2 * n + a1] = npp;
+          if (hq2) {
+            X[a1 * n + q2] = npq;
+            X[q2 * n + a1] = npq;
+          }
+          if (hq1) {
+            X[b1 * n + p2] = nqp;
+            X[p2 * n + b1] = nqp;
+          }
+          if (hq1 && hq2) {
+            X[b1 * n + q2] = nqq;
+            X[q2 * n + b1] = nqq;
+          }
         }
-        if (s1 == 0.0 && s2 == 0.0) continue;
-        const bool hq1 = q1 < n, hq2 = q2 < n;
-        const double bpp = X[p1 * n + p2];
-        const double bpq = hq2 ? X[p1 * n + q2] : 0.0;
-        const double bqp = hq1 ? X[q1 * n + p2] : 0.0;
-        const double bqq = (hq1 && hq2) ? X[q1 * n + q2] : 0.0;
-        // left: J1^T B
-        const double lpp = c1 * bpp - s1 * bqp, lpq = c1 * bpq - s1 * bqq;
-        const double lqp = s1 * bpp + c1 * bqp, lqq = s1 * bpq + c1 * bqq;
-        // right: (J1^T B) J2
-        const double npp = c2 * lpp - s2 * lpq, npq = s2 * lpp + c2 * lpq;
-        const double nqp = c2 * lqp - s2 * lqq, nqq = s2 * lqp + c2 * lqq;
-        X[p1 * n + p2] = npp;
-        X[p2 * n + p1] = npp;
-        if (hq2) {
-          X[p1 * n + q2] = npq;
-          X[q2 * n + p1] = npq;
+        // eigenvector rows k = g0, g0 + G, ... rotated in columns (p2, q2)
+        if (hq2 && s2 != 0.0) {
+          for (int k = g0; k < n; k += G) {
+            const double vp = V[k * n + p2], vq = V[k * n + q2];
+            V[k * n + p2] = c2 * vp - s2 * vq;
+            V[k * n + q2] = s2 * vp + c2 * vq;
+          }
         }
-        if (hq1) {
-          X[q1 * n + p2] = nqp;
-          X[p2 * n + q1] = nqp;
-        }
-        if (hq1 && hq2) {
-          X[q1 * n + q2] = nqq;
-          X[q2 * n + q1] = nqq;
-        }
-      }
-      for (int idx = tid; idx < n * half; idx += nt) {
-        const int k = idx / half, t = idx - (idx / half) * half;
-        const int p = sh.p[t], q = sh.q[t];
-        if (q >= n || sh.s[t] == 0.0) continue;
-        const double c = sh.c[t], s = sh.s[t];
-        const double vp = V[k * n + p], vq = V[k * n + q];
-        V[k * n + p] = c * vp - s * vq;
-        V[k * n + q] = s * vp + c * vq;
       }
       __syncthreads();
     }
@@ -188,6 +207,9 @@ struct RitzShared {
   int dropmap[kMaxN];  // permuted column -> position among the kept ones, or -1
   int r;
 };
+
+static_assert(((sizeof(RitzShared) + 7) / 8) * 8 + 2 * kMaxN * kMaxN * sizeof(double) <= 160 * 1024,
+              "the Ritz kernel's LDS must fit one CU (160 KiB)");
 
 // Ranks of the diagonal of X (r x r): select the mm values nearest 0 (ties by
 // value, then index) and order them ascending into sh.sel[0..mm).
@@ -236,6 +258,8 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
   double* W1 = Li + nz * nz;   // [nz][nz]
   const int tid = threadIdx.x, nt = blockDim.x;
   const int m2 = 2 * m, nc2 = 2 * n_c;
+  long long ts[6];
+  ts[0] = wall_clock64();
   // permuted position a -> original Z column: a < m -> U' column a, else W column a - m
   auto orig = [&](int a) { return a < m ? n_c + a : a - m; };
   // assemble the enriched pencil (Galerkin blocks, symmetrised) in order [U', W_c]
@@ -273,6 +297,7 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
     X[e] *= sh.sv[i] * sh.sv[j];
   }
   __syncthreads();
+  ts[1] = wall_clock64();
   // ---- Cholesky of the scaled Gram matrix (right-looking, one barrier per
   // column).  A column whose pivot (the squared sine of its angle to the
   // span of the kept columns before it) is below 1e-10 is dropped: it adds
@@ -296,6 +321,7 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
     }
     __syncthreads();
   }
+  ts[2] = wall_clock64();
   int r = sh.r;
   double* T = L;  // SVQB path: basis coefficients Y = T Q
   const bool chol = r >= m;
@@ -303,22 +329,25 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
   __syncthreads();
   for (int q = tid; q < r; q += nt) sh.dropmap[sh.kk[q]] = q;
   if (chol) {
-    // compact factor Lc = L[kept, kept] (in W1) and its inverse Li, one column
-    // per thread (a column of the inverse depends only on itself)
+    // compact factor Lc = L[kept, kept] in X (LDS; X is free after the
+    // factorisation) and its inverse Li in V (LDS), row by row: row i of Li
+    // needs rows < i, its columns are independent.
     for (int e = tid; e < r * r; e += nt) {
       const int a = e / r, b = e - (e / r) * r;
-      W1[e] = (b <= a) ? L[sh.kk[a] * n + sh.kk[b]] : 0.0;
+      X[e] = (b <= a) ? L[sh.kk[a] * n + sh.kk[b]] : 0.0;
+      V[e] = 0.0;
     }
     __syncthreads();
-    for (int c = tid; c < r; c += nt) {
-      for (int i = 0; i < c; ++i) Li[i * r + c] = 0.0;
-      for (int i = c; i < r; ++i) {
+    for (int i = 0; i < r; ++i) {
+      const double lii = X[i * r + i];
+      for (int c = tid; c <= i; c += nt) {
         double acc = (i == c) ? 1.0 : 0.0;
-        for (int k = c; k < i; ++k) acc -= W1[i * r + k] * Li[k * r + c];
-        Li[i * r + c] = acc / W1[i * r + i];
+        for (int k = c; k < i; ++k) acc -= X[i * r + k] * V[k * r + c];
+        V[i * r + c] = acc / lii;
       }
+      __syncthreads();
     }
-    __syncthreads();
+    for (int e = tid; e < r * r; e += nt) Li[e] = V[e];  // kept for the final Y
     // W1 = Li B, B = S (G_A - sigma G_M) S restricted to the kept columns
     for (int e = tid; e < r * r; e += nt) {
       const int i = e / r, j = e - (e / r) * r;
@@ -326,7 +355,7 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
       double acc = 0.0;
       for (int k = 0; k <= i; ++k) {
         const int ck = sh.kk[k];
-        acc += Li[i * r + k] * sh.sv[ck] * (GA[ck * n + cj] - sigma * GM[ck * n + cj]);
+        acc += V[i * r + k] * sh.sv[ck] * (GA[ck * n + cj] - sigma * GM[ck * n + cj]);
       }
       L[e] = acc * sh.sv[cj];  // L is free now: reuse as W1
     }
@@ -335,7 +364,7 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
     for (int e = tid; e < r * r; e += nt) {
       const int i = e / r, j = e - (e / r) * r;
       double acc = 0.0;
-      for (int k = 0; k <= j; ++k) acc += L[i * r + k] * Li[j * r + k];
+      for (int k = 0; k <= j; ++k) acc += L[i * r + k] * V[j * r + k];
       X[e] = acc;
     }
     __syncthreads();
@@ -392,7 +421,9 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
     }
   }
   __syncthreads();
+  ts[3] = wall_clock64();
   const int sw = block_jacobi(X, V, r, sh.j);
+  ts[4] = wall_clock64();
   const int mm = m < r ? m : r;
   select_nearest_zero(X, r, mm, sh);
   // Y (rows in the caller's order [W_c, U']) = basis coefficients of the selection
@@ -414,11 +445,13 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
     Y[orig(a) * m + c] = acc;
   }
   for (int c = tid; c < m; c += nt) theta[c] = c < mm ? X[sh.sel[c] * r + sh.sel[c]] + sigma : 0.0;
+  ts[5] = wall_clock64();
   if (tid == 0) {
     status[0] = (r < m) ? 1 : (sw < 0 ? 2 : 0);
     status[1] = sw;
     status[2] = chol ? 0 : 1;
     status[3] = n - (chol ? r : n);
+    for (int i = 0; i < 5; ++i) status[4 + i] = int(ts[i + 1] - ts[i]);  // 100 MHz ticks
   }
 }
 

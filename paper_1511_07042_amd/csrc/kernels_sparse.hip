@@ -58,13 +58,13 @@ enum { K_SHIFTED = 0, K_RESIDUAL = 1, K_JACOBI = 2, K_JACOBI0 = 3 };
 
 // MODE K_SHIFTED: y = S x; K_RESIDUAL: y = f - S x;
 // K_JACOBI: y = x + omega (f - S x) / d; K_JACOBI0: y = omega f / d  (x = 0),
-// with S = A - sigma M combined on the fly and d = S_ii.
+// with S = A - sigma M (precomputed once per solve) and d = S_ii.
 // FUSE: also u[r] += y[r] (FP64 iterate update on the last sweep).
 template <typename T, int MODE, bool FUSE>
 __global__ void __launch_bounds__(256) k_rowop(int64_t n, int W, int m, int cpr, int rpb,
                                                const int* __restrict__ cols,
-                                               const T* __restrict__ a, const T* __restrict__ mm,
-                                               T sigma, T omega, const T* __restrict__ x,
+                                               const T* __restrict__ S, T omega,
+                                               const T* __restrict__ x,
                                                const T* __restrict__ f, T* __restrict__ y,
                                                double* __restrict__ u) {
   constexpr int VW = Vec<T>::N;
@@ -74,14 +74,14 @@ __global__ void __launch_bounds__(256) k_rowop(int64_t n, int W, int m, int cpr,
     const int64_t base = r * W;
     Vec<T> acc, xr;
     for (int c = 0; c < VW; ++c) acc.v[c] = T(0);
-    T d = a[base] - sigma * mm[base];
+    T d = S[base];
     if (MODE == K_JACOBI0) {
       const Vec<T> fv = ld(f + r * m + ch * VW);
       for (int c = 0; c < VW; ++c) acc.v[c] = omega * fv.v[c] / d;
     } else {
       for (int k = 0; k < W; ++k) {
         const int j = cols[base + k];
-        const T s = a[base + k] - sigma * mm[base + k];
+        const T s = S[base + k];
         const Vec<T> xv = ld(x + int64_t(j) * m + ch * VW);
         if (k == 0) xr = xv;
         for (int c = 0; c < VW; ++c) acc.v[c] += s * xv.v[c];
@@ -107,8 +107,7 @@ __global__ void __launch_bounds__(256) k_rowop(int64_t n, int W, int m, int cpr,
 template <typename T, bool FUSE>
 __global__ void __launch_bounds__(256) k_gs(int64_t cnt, const int* __restrict__ rows, int W, int m,
                                             int cpr, int rpb, const int* __restrict__ cols,
-                                            const T* __restrict__ a, const T* __restrict__ mm,
-                                            T sigma, T* x, const T* __restrict__ f,
+                                            const T* __restrict__ S, T* x, const T* __restrict__ f,
                                             double* __restrict__ u) {
   constexpr int VW = Vec<T>::N;
   const int rloc = threadIdx.x / cpr;
@@ -118,10 +117,10 @@ __global__ void __launch_bounds__(256) k_gs(int64_t cnt, const int* __restrict__
     const int64_t base = r * W;
     Vec<T> acc, xr;
     for (int c = 0; c < VW; ++c) acc.v[c] = T(0);
-    const T d = a[base] - sigma * mm[base];
+    const T d = S[base];
     for (int k = 0; k < W; ++k) {
       const int j = cols[base + k];
-      const T s = a[base + k] - sigma * mm[base + k];
+      const T s = S[base + k];
       const Vec<T> xv = ld(x + int64_t(j) * m + ch * VW);
       if (k == 0) xr = xv;
       for (int c = 0; c < VW; ++c) acc.v[c] += s * xv.v[c];
@@ -134,6 +133,15 @@ __global__ void __launch_bounds__(256) k_gs(int64_t cnt, const int* __restrict__
       for (int c = 0; c < VW; ++c) up[c] += double(xr.v[c]);
     }
   }
+}
+
+// S = A - sigma M, elementwise over the ELL values, in precision T.
+template <typename T>
+__global__ void k_shift(int64_t cnt, const T* __restrict__ a, const T* __restrict__ mm, T sigma,
+                        T* __restrict__ S) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < cnt;
+       i += int64_t(gridDim.x) * blockDim.x)
+    S[i] = a[i] - sigma * mm[i];
 }
 
 // ------------------------------------------------------- FP64 SpMM (A, M) --
@@ -428,43 +436,46 @@ const float* mval<float>(const DevLevel& L) { return L.m32; }
 }  // namespace
 
 template <typename T>
-int launch_shifted(const DevLevel& L, int mode, double sigma, const T* x, const T* f, T* y, int m,
-                   hipStream_t s) {
-  Geom g = row_geom<T>(L.n, m);
-  if (mode == ROW_SHIFTED)
-    k_rowop<T, K_SHIFTED, false><<<g.grid, g.block, 0, s>>>(L.n, L.W, m, g.cpr, g.rpb, L.cols,
-                                                            aval<T>(L), mval<T>(L), T(sigma), T(0),
-                                                            x, f, y, nullptr);
-  else
-    k_rowop<T, K_RESIDUAL, false><<<g.grid, g.block, 0, s>>>(L.n, L.W, m, g.cpr, g.rpb, L.cols,
-                                                             aval<T>(L), mval<T>(L), T(sigma), T(0),
-                                                             x, f, y, nullptr);
+int launch_shift(const DevLevel& L, double sigma, T* S, hipStream_t s) {
+  const int64_t cnt = L.n * L.W;
+  k_shift<T><<<grid1d(cnt), 256, 0, s>>>(cnt, aval<T>(L), mval<T>(L), T(sigma), S);
   return check_launch();
 }
 
 template <typename T>
-int launch_jacobi(const DevLevel& L, double sigma, double omega, const T* x, const T* f, T* y,
+int launch_shifted(const DevLevel& L, const T* S, int mode, const T* x, const T* f, T* y, int m,
+                   hipStream_t s) {
+  Geom g = row_geom<T>(L.n, m);
+  if (mode == ROW_SHIFTED)
+    k_rowop<T, K_SHIFTED, false><<<g.grid, g.block, 0, s>>>(L.n, L.W, m, g.cpr, g.rpb, L.cols, S,
+                                                            T(0), x, f, y, nullptr);
+  else
+    k_rowop<T, K_RESIDUAL, false><<<g.grid, g.block, 0, s>>>(L.n, L.W, m, g.cpr, g.rpb, L.cols, S,
+                                                             T(0), x, f, y, nullptr);
+  return check_launch();
+}
+
+template <typename T>
+int launch_jacobi(const DevLevel& L, const T* S, double omega, const T* x, const T* f, T* y,
                   bool x_is_zero, int m, hipStream_t s) {
   Geom g = row_geom<T>(L.n, m);
   if (x_is_zero)
-    k_rowop<T, K_JACOBI0, false><<<g.grid, g.block, 0, s>>>(L.n, L.W, m, g.cpr, g.rpb, L.cols,
-                                                            aval<T>(L), mval<T>(L), T(sigma),
+    k_rowop<T, K_JACOBI0, false><<<g.grid, g.block, 0, s>>>(L.n, L.W, m, g.cpr, g.rpb, L.cols, S,
                                                             T(omega), x, f, y, nullptr);
   else
-    k_rowop<T, K_JACOBI, false><<<g.grid, g.block, 0, s>>>(L.n, L.W, m, g.cpr, g.rpb, L.cols,
-                                                           aval<T>(L), mval<T>(L), T(sigma),
+    k_rowop<T, K_JACOBI, false><<<g.grid, g.block, 0, s>>>(L.n, L.W, m, g.cpr, g.rpb, L.cols, S,
                                                            T(omega), x, f, y, nullptr);
   return check_launch();
 }
 
 template <typename T>
-int launch_gs_colour(const DevLevel& L, int colour, double sigma, T* x, const T* f, int m,
+int launch_gs_colour(const DevLevel& L, const T* S, int colour, T* x, const T* f, int m,
                      hipStream_t s) {
   const int64_t b = L.colour_ptr[colour], e = L.colour_ptr[colour + 1];
   if (e <= b) return BMG_OK;
   Geom g = row_geom<T>(e - b, m);
   k_gs<T, false><<<g.grid, g.block, 0, s>>>(e - b, L.colour_rows + b, L.W, m, g.cpr, g.rpb, L.cols,
-                                            aval<T>(L), mval<T>(L), T(sigma), x, f, nullptr);
+                                            S, x, f, nullptr);
   return check_launch();
 }
 
@@ -555,11 +566,12 @@ int launch_write_evecs(int64_t n, const double* U, int m, const int* sel, const 
 }
 
 #define BMG_INST(T)                                                                              \
-  template int launch_shifted<T>(const DevLevel&, int, double, const T*, const T*, T*, int,     \
+  template int launch_shift<T>(const DevLevel&, double, T*, hipStream_t);                        \
+  template int launch_shifted<T>(const DevLevel&, const T*, int, const T*, const T*, T*, int,   \
                                  hipStream_t);                                                   \
-  template int launch_jacobi<T>(const DevLevel&, double, double, const T*, const T*, T*, bool,  \
+  template int launch_jacobi<T>(const DevLevel&, const T*, double, const T*, const T*, T*, bool, \
                                 int, hipStream_t);                                               \
-  template int launch_gs_colour<T>(const DevLevel&, int, double, T*, const T*, int, hipStream_t); \
+  template int launch_gs_colour<T>(const DevLevel&, const T*, int, T*, const T*, int, hipStream_t); \
   template int launch_eigres<T>(const DevLevel&, const double*, const double*, double, T*,       \
                                 double*, int, int, hipStream_t);                                 \
   template int launch_restrict<T>(const DevLevel&, const T*, T*, int, hipStream_t);              \

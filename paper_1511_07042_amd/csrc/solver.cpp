@@ -16,7 +16,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <cstdio>
+#include <cstdlib>
 #include <numeric>
+#include <type_traits>
 
 #include "bmg_internal.h"
 
@@ -27,6 +30,9 @@ struct bmg_workspace {
   double *W = nullptr, *AW = nullptr, *MW = nullptr;
   double *U = nullptr, *AU = nullptr, *MU = nullptr;
   std::vector<void*> e, f, t;  // per level, correction precision
+  std::vector<void*> S;        // per level: A_l - sigma M_l in the correction precision
+  void* tail_img = nullptr;    // packed static arrays of the LDS tail
+  std::vector<char> tail_host; // host staging of the image
   void* ctmp = nullptr;        // [N0][m]
   void* gco = nullptr;         // [N0]
   double *gpart = nullptr, *G = nullptr, *GW = nullptr, *Y = nullptr, *theta = nullptr;
@@ -36,6 +42,15 @@ struct bmg_workspace {
   double *sign = nullptr, *argv = nullptr;
   int* argi = nullptr;
   double* hbuf = nullptr;  // pinned host: theta[m], rho2[m], status
+  bmg::TailArgs* tail_h = nullptr;  // pinned host staging of the tail descriptor
+  bmg::TailArgs* tail_d = nullptr;  // device copy
+  hipStream_t stream = nullptr;     // internal stream (capturable), joined to the caller's
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // cached graph of one cycle (V-cycle, update, Ritz step, next residual)
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  double g_sigma = 0, g_omega = 0;
+  int g_smoother = -1, g_nu1 = -1, g_nu2 = -1, g_lc = -1, g_tail = -2, g_timed = -1;
   int nblk_res = 0, nblk_arg = 0;
   bmg::GramPlan gp{}, gpw{};
   std::vector<void*> allocs;
@@ -57,8 +72,14 @@ int dalloc(bmg_workspace* w, void** p, size_t bytes) {
 }
 
 void free_workspace(bmg_workspace* w) {
+  if (w->gexec) (void)hipGraphExecDestroy(w->gexec);
+  if (w->graph) (void)hipGraphDestroy(w->graph);
+  if (w->ev_in) (void)hipEventDestroy(w->ev_in);
+  if (w->ev_out) (void)hipEventDestroy(w->ev_out);
+  if (w->stream) (void)hipStreamDestroy(w->stream);
   for (void* p : w->allocs) (void)hipFree(p);
   if (w->hbuf) (void)hipHostFree(w->hbuf);
+  if (w->tail_h) (void)hipHostFree(w->tail_h);
   delete w;
 }
 
@@ -91,12 +112,15 @@ int make_workspace(bmg_hierarchy* h, int m, int n_c, int prec, bmg_workspace** o
   w->e.resize(nl);
   w->f.resize(nl);
   w->t.resize(nl);
+  w->S.resize(nl);
   for (int l = 0; l < nl; ++l) {
     const size_t b = vb * h->dev[l].n * m;
     AL(w->e[l], b);
     AL(w->f[l], b);
     AL(w->t[l], b);
+    AL(w->S[l], vb * h->dev[l].n * h->dev[l].W);
   }
+  AL(w->tail_img, size_t(kTailLdsBudget));
   AL(w->ctmp, vb * h->n0 * m);
   AL(w->gco, vb * h->n0);
   const int nz = n_c + m;
@@ -113,14 +137,29 @@ int make_workspace(bmg_hierarchy* h, int m, int n_c, int prec, bmg_workspace** o
   AL(w->rho2part, sizeof(double) * w->nblk_res * m);
   AL(w->rho2, sizeof(double) * m);
   AL(w->rscratch, sizeof(double) * ritz_scratch_doubles(nz));
-  AL(w->status, sizeof(int) * 4);
+  AL(w->status, sizeof(int) * 16);
   AL(w->sel, sizeof(int) * m);
   AL(w->sign, sizeof(double) * m);
   w->nblk_arg = int(std::min<int64_t>(256, (N + 255) / 256));
   AL(w->argv, sizeof(double) * w->nblk_arg * m);
   AL(w->argi, sizeof(int) * w->nblk_arg * m);
+  AL(w->tail_d, sizeof(TailArgs));
 #undef AL
-  if (hipHostMalloc(reinterpret_cast<void**>(&w->hbuf), sizeof(double) * (2 * m + 4)) != hipSuccess) {
+  if (hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&w->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&w->ev_out, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    free_workspace(w);
+    set_error("stream/event creation failed");
+    return BMG_EDEVICE;
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&w->tail_h), sizeof(TailArgs)) != hipSuccess) {
+    (void)hipGetLastError();
+    free_workspace(w);
+    set_error("hipHostMalloc failed");
+    return BMG_ENOMEM;
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&w->hbuf), sizeof(double) * (2 * m + 8)) != hipSuccess) {
     (void)hipGetLastError();
     free_workspace(w);
     set_error("hipHostMalloc failed");
@@ -164,14 +203,19 @@ void free_workspaces(bmg_hierarchy* h) {
 
 // ----------------------------------------------------------- kernel timer --
 // Brackets the launches of one kernel class (finest level only) with HIP events
-// on the solve's stream; durations are summed after the final synchronisation.
+// on the solve's stream.  Eager launches record fresh event pairs; when the
+// cycle is captured as a graph the pairs become graph nodes and are re-read
+// after every replay.  harvest() runs after each synchronisation of the solve.
 struct KTimer {
   int which = -1;
   hipStream_t s = nullptr;
   std::vector<hipEvent_t> ev;
   size_t used = 0;
-  double bytes = 0.0;
+  double ms = 0.0, bytes = 0.0;
   int64_t units = 0;
+  double pend_bytes = 0.0, body_bytes = 0.0;
+  int64_t pend_units = 0, body_units = 0;
+  bool frozen = false;  // event pairs baked into a graph
   int begin(int k) {
     if (k != which) return BMG_OK;
     if (2 * used + 2 > ev.size()) {
@@ -192,16 +236,45 @@ struct KTimer {
   }
   void add(int k, double b, int64_t u) {
     if (k != which) return;
-    bytes += b;
-    units += u;
+    pend_bytes += b;
+    pend_units += u;
   }
-  double total_ms() {
-    double t = 0.0;
+  // the pending amounts and event pairs now belong to a captured graph body
+  void freeze() {
+    frozen = true;
+    body_bytes = pend_bytes;
+    body_units = pend_units;
+    pend_bytes = 0.0;
+    pend_units = 0;
+  }
+  // drop what a failed capture recorded
+  void discard(size_t keep_used) {
+    used = keep_used;
+    pend_bytes = 0.0;
+    pend_units = 0;
+  }
+  // after a synchronisation: add the completed launches (or graph replay)
+  void harvest(bool replayed) {
+    if (which < 0) return;
     for (size_t i = 0; i < used; ++i) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) == hipSuccess) t += ms;
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]) == hipSuccess)
+        ms += t;
+      else
+        (void)hipGetLastError();  // not a launch error: keep it out of later checks
     }
-    return t;
+    if (frozen) {
+      if (replayed) {
+        bytes += body_bytes;
+        units += body_units;
+      }
+    } else {
+      bytes += pend_bytes;
+      units += pend_units;
+      pend_bytes = 0.0;
+      pend_units = 0;
+      used = 0;
+    }
   }
   ~KTimer() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
@@ -219,11 +292,118 @@ struct Cycle {
   bmg_hierarchy* h;
   CycleCfg c;
   std::vector<T*> e, f, t;
+  std::vector<const T*> S;  // A_l - sigma M_l
   T* ctmp;
   const T* g0;  // truncated inverse spectrum at level 0
   hipStream_t s;
   KTimer* kt = nullptr;  // timing of finest-level launches (level L)
   int L = -1;
+  int tail_hi = -1;  // levels l_c..tail_hi run in one workgroup, in LDS
+  const TailArgs* tail_d = nullptr;
+  int tail_lds = 0;
+
+  // Pack the LDS image of levels l_c..hi (the largest hi whose image and work
+  // blocks fit the budget) and upload it with its descriptor.  phi0 and gh are
+  // the level-0 eigenvectors and the truncated inverse spectrum (host, FP64).
+  int setup_tail(TailArgs* th, TailArgs* td, void* img_d, std::vector<char>& img,
+                 const std::vector<double>& phi0, const std::vector<double>& gh, int top) {
+    tail_hi = -1;
+    if (std::getenv("BMG_NO_TAIL")) return BMG_OK;
+    const int nl = top + 1;
+    if (nl > kTailMaxLevels) return BMG_OK;
+    auto al = [](size_t x) { return (x + 15) / 16 * 16; };
+    const size_t vt = sizeof(T);
+    const size_t n0 = size_t(h->n0);
+    const bool spectral = c.l_c == 0;
+    size_t stat = spectral ? 2 * al(n0 * n0 * vt) + al(n0 * vt) : 0, work = 0;
+    int hi = -1;
+    for (int l = c.l_c; l < nl; ++l) {
+      const HostLevel& H = h->host[l];
+      if (H.n > 32767 || H.n_colours > kTailMaxColours) break;  // 16-bit tables
+      const size_t n = size_t(H.n), np = size_t(H.n_prev);
+      const size_t st = al(n * H.W * vt) + al(n * H.W * 2) + al(n * 2) + al((n - np) * 4) +
+                        al(np * H.RW * 2);
+      const size_t wk = 3 * al(n * c.m * vt);
+      if (stat + st + work + wk > size_t(kTailLdsBudget)) break;
+      stat += st;
+      work += wk;
+      hi = l;
+    }
+    if (hi < 0) return BMG_OK;
+    std::memset(th, 0, sizeof(TailArgs));
+    th->lo = c.l_c;
+    th->hi = hi;
+    th->m = c.m;
+    th->smoother = c.smoother;
+    th->nu1 = c.nu1;
+    th->nu2 = c.nu2;
+    th->omega = c.omega;
+    img.assign(stat, 0);
+    size_t pos = 0;
+    auto put = [&](const void* src, size_t bytes) {
+      const size_t off = pos;
+      if (src && bytes) std::memcpy(img.data() + off, src, bytes);
+      pos += al(bytes);
+      return int(off);
+    };
+    for (int l = c.l_c; l <= hi; ++l) {
+      const HostLevel& H = h->host[l];
+      TailLevel& t = th->lv[l];
+      t.n = int(H.n);
+      t.n_prev = int(H.n_prev);
+      t.W = H.W;
+      t.RW = H.RW;
+      t.n_colours = H.n_colours;
+      for (int k = 0; k <= H.n_colours; ++k) t.colour_ptr[k] = H.colour_ptr[k];
+      t.off_S = put(nullptr, size_t(H.n) * H.W * vt);  // filled on the device
+      std::vector<uint16_t> u16(H.cols.begin(), H.cols.end());
+      t.off_cols = put(u16.data(), u16.size() * 2);
+      u16.assign(H.colour_rows.begin(), H.colour_rows.end());
+      t.off_crow = put(u16.data(), u16.size() * 2);
+      u16.assign(H.parents.begin(), H.parents.end());
+      t.off_par = put(u16.data(), u16.size() * 2);
+      std::vector<int16_t> i16(H.rtab.begin(), H.rtab.end());
+      t.off_rtab = put(i16.data(), i16.size() * 2);
+    }
+    th->off_phi = th->off_phit = th->off_g = -1;
+    if (spectral) {
+      std::vector<T> p(n0 * n0), pt(n0 * n0), g(n0);
+      for (size_t i = 0; i < n0; ++i)
+        for (size_t j = 0; j < n0; ++j) {
+          p[i * n0 + j] = T(phi0[i * n0 + j]);
+          pt[j * n0 + i] = T(phi0[i * n0 + j]);
+        }
+      for (size_t i = 0; i < n0; ++i) g[i] = T(gh[i]);
+      th->off_phi = put(p.data(), p.size() * vt);
+      th->off_phit = put(pt.data(), pt.size() * vt);
+      th->off_g = put(g.data(), g.size() * vt);
+    }
+    th->image_bytes = int(pos);
+    for (int l = c.l_c; l <= hi; ++l) {
+      const size_t b = al(size_t(h->host[l].n) * c.m * vt);
+      TailLevel& t = th->lv[l];
+      t.off_e = int(pos);
+      pos += b;
+      t.off_f = int(pos);
+      pos += b;
+      t.off_t = int(pos);
+      pos += b;
+    }
+    th->image = img_d;
+    th->f_top = f[hi];
+    th->e_top = e[hi];
+    tail_lds = int(pos);
+    BMG_HIP(hipMemcpyAsync(img_d, img.data(), img.size(), hipMemcpyHostToDevice, s));
+    for (int l = c.l_c; l <= hi; ++l)
+      BMG_HIP(hipMemcpyAsync(static_cast<char*>(img_d) + th->lv[l].off_S, S[l],
+                             size_t(h->host[l].n) * h->host[l].W * vt, hipMemcpyDeviceToDevice, s));
+    BMG_HIP(hipMemcpyAsync(td, th, sizeof(TailArgs), hipMemcpyHostToDevice, s));
+    // img and th are host staging reused by the next solve
+    BMG_HIP(hipStreamSynchronize(s));
+    tail_hi = hi;
+    tail_d = td;
+    return BMG_OK;
+  }
 
   int kclass(int l, int k) const { return (kt && l == L) ? k : -2; }
 
@@ -234,7 +414,7 @@ struct Cycle {
     if (kt) kt->add(kc, (4 + 2 * b) * double(h->host[l].nnz) + 4.0 * D.n + 3 * b * D.n * c.m, 1);
     if (c.smoother == BMG_SMOOTH_JACOBI) {
       if (kt) BMG_TRY(kt->begin(kc));
-      BMG_TRY(launch_jacobi<T>(D, c.sigma, c.omega, e[l], f[l], t[l], from_zero, c.m, s));
+      BMG_TRY(launch_jacobi<T>(D, S[l], c.omega, e[l], f[l], t[l], from_zero, c.m, s));
       if (kt) BMG_TRY(kt->end(kc));
       std::swap(e[l], t[l]);
       return BMG_OK;
@@ -243,7 +423,7 @@ struct Cycle {
     for (int k = 0; k < D.n_colours; ++k) {
       const int col = forward ? k : D.n_colours - 1 - k;
       if (kt) BMG_TRY(kt->begin(kc));
-      BMG_TRY(launch_gs_colour<T>(D, col, c.sigma, e[l], f[l], c.m, s));
+      BMG_TRY(launch_gs_colour<T>(D, S[l], col, e[l], f[l], c.m, s));
       if (kt) BMG_TRY(kt->end(kc));
     }
     return BMG_OK;
@@ -252,6 +432,7 @@ struct Cycle {
   // e[l] <- B_sigma f[l]
   int vcycle(int l) {
     const DevLevel& D = h->dev[l];
+    if (l == tail_hi) return launch_tail<T>(tail_d, tail_lds, s);
     if (l == c.l_c) {
       if (l == 0) {
         const int n0 = int(h->n0);
@@ -271,7 +452,7 @@ struct Cycle {
     int kc = kclass(l, BMG_K_RESIDUAL);
     if (kt) kt->add(kc, (4 + 2 * b) * nnz + 3 * b * n * c.m, 1);
     if (kt) BMG_TRY(kt->begin(kc));
-    BMG_TRY(launch_shifted<T>(D, ROW_RESIDUAL, c.sigma, e[l], f[l], t[l], c.m, s));
+    BMG_TRY(launch_shifted<T>(D, S[l], ROW_RESIDUAL, e[l], f[l], t[l], c.m, s));
     if (kt) BMG_TRY(kt->end(kc));
     kc = kclass(l, BMG_K_RESTRICT);
     if (kt) kt->add(kc, b * n * c.m + b * nc * c.m + 4.0 * nc * D.RW, 1);
@@ -288,6 +469,48 @@ struct Cycle {
     return BMG_OK;
   }
 };
+
+// Truncated inverse spectrum of the level-0 pencil (Alg. 2 step 1, with the
+// near-singular modes dropped): g_i = 1/(lambda_i - sigma), 0 when
+// |lambda_i - sigma| < 1e-2 max(1, |sigma|).
+std::vector<double> coarse_inverse(const bmg_hierarchy* h, double sigma) {
+  std::vector<double> g(h->n0);
+  for (int64_t i = 0; i < h->n0; ++i) {
+    const double x = h->lam0[i] - sigma;
+    g[i] = std::fabs(x) >= 1e-2 * std::max(1.0, std::fabs(sigma)) ? 1.0 / x : 0.0;
+  }
+  return g;
+}
+
+// Bind a cycle to the workspace buffers, form S_l = A_l - sigma M_l on every
+// level up to `top`, upload the level-0 inverse and set up the LDS tail.
+template <typename T>
+int init_cycle(Cycle<T>& cyc, bmg_hierarchy* h, bmg_workspace* w, const CycleCfg& cfg, int top,
+               hipStream_t s) {
+  const int nl = int(h->dev.size());
+  cyc.h = h;
+  cyc.c = cfg;
+  cyc.s = s;
+  cyc.e.resize(nl);
+  cyc.f.resize(nl);
+  cyc.t.resize(nl);
+  cyc.S.resize(nl);
+  for (int l = 0; l < nl; ++l) {
+    cyc.e[l] = static_cast<T*>(w->e[l]);
+    cyc.f[l] = static_cast<T*>(w->f[l]);
+    cyc.t[l] = static_cast<T*>(w->t[l]);
+    cyc.S[l] = static_cast<const T*>(w->S[l]);
+  }
+  for (int l = 0; l <= top; ++l) BMG_TRY(launch_shift<T>(h->dev[l], cfg.sigma, static_cast<T*>(w->S[l]), s));
+  cyc.ctmp = static_cast<T*>(w->ctmp);
+  cyc.g0 = static_cast<const T*>(w->gco);
+  const std::vector<double> gh = coarse_inverse(h, cfg.sigma);
+  std::vector<T> g(gh.begin(), gh.end());
+  BMG_HIP(hipMemcpyAsync(w->gco, g.data(), sizeof(T) * g.size(), hipMemcpyHostToDevice, s));
+  BMG_TRY(cyc.setup_tail(w->tail_h, w->tail_d, w->tail_img, w->tail_host, h->phi0, gh, top));
+  BMG_HIP(hipStreamSynchronize(s));  // g is a host local
+  return BMG_OK;
+}
 
 int weyl_coarsest(const bmg_hierarchy* h, double sigma) {
   const int nl = int(h->host.size());
@@ -372,21 +595,15 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     std::vector<double> phic(size_t(n0) * n_c);
     for (int64_t i = 0; i < n0; ++i)
       for (int j = 0; j < n_c; ++j) phic[size_t(i) * n_c + j] = h->phi0[size_t(i) * n0 + idx[j]];
-    std::vector<T> g(n0);
-    for (int64_t i = 0; i < n0; ++i) {
-      const double x = h->lam0[i] - sigma;
-      g[i] = std::fabs(x) >= 1e-2 * std::max(1.0, std::fabs(sigma)) ? T(1.0 / x) : T(0);
-    }
     double* cur = (L % 2 == 0) ? w->W : w->AW;  // ping-pong so the last lands in W
     BMG_HIP(hipMemcpyAsync(cur, phic.data(), sizeof(double) * phic.size(), hipMemcpyHostToDevice, s));
-    BMG_HIP(hipMemcpyAsync(w->gco, g.data(), sizeof(T) * n0, hipMemcpyHostToDevice, s));
     for (int l = 1; l <= L; ++l) {
       double* nxt = (cur == w->W) ? w->AW : w->W;
       BMG_TRY(launch_fill<double>(nxt, h->dev[l].n * n_c, 0.0, s));
       BMG_TRY(launch_prolong_add<double>(h->dev[l], cur, nxt, n_c, s));
       cur = nxt;
     }
-    BMG_HIP(hipStreamSynchronize(s));  // phic / g are host locals
+    BMG_HIP(hipStreamSynchronize(s));  // phic is a host local
   }
   BMG_TRY(launch_spmm_am(DL, w->W, w->AW, w->MW, n_c, s));
   BMG_TRY(launch_gram(w->gpw, N, w->W, n_c, nullptr, 0, w->AW, n_c, w->MW, n_c, w->gpart, w->GW, s));
@@ -435,19 +652,7 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   BMG_TRY(ritz_step());
 
   Cycle<T> cyc;
-  cyc.h = h;
-  cyc.c = CycleCfg{m, o.nu1, o.nu2, o.smoother, l_c, sigma, o.omega};
-  cyc.e.resize(nl);
-  cyc.f.resize(nl);
-  cyc.t.resize(nl);
-  for (int l = 0; l < nl; ++l) {
-    cyc.e[l] = static_cast<T*>(w->e[l]);
-    cyc.f[l] = static_cast<T*>(w->f[l]);
-    cyc.t[l] = static_cast<T*>(w->t[l]);
-  }
-  cyc.ctmp = static_cast<T*>(w->ctmp);
-  cyc.g0 = static_cast<const T*>(w->gco);
-  cyc.s = s;
+  BMG_TRY(init_cycle<T>(cyc, h, w, CycleCfg{m, o.nu1, o.nu2, o.smoother, l_c, sigma, o.omega}, L, s));
   cyc.kt = o.timed_kernel >= 0 ? &kt : nullptr;
   cyc.L = L;
 
@@ -455,21 +660,88 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   Cert cert;
   int cycles = 0;
   int status = BMG_OK;
-  for (;;) {
-    // H1: -R in the correction precision and rho^2
+  // H1: -R in the correction precision and rho^2 (feeds the next decision)
+  auto residual_step = [&]() -> int {
     kt.add(BMG_K_EIGRES, 20 * nnzL + (8.0 + sizeof(T)) * Nd * m + 8 * Nd, 1);
     BMG_TRY(kt.begin(BMG_K_EIGRES));
     BMG_TRY(launch_eigres<T>(DL, w->U, w->theta, -1.0, cyc.f[L], w->rho2part, w->nblk_res, m, s));
     BMG_TRY(kt.end(BMG_K_EIGRES));
     BMG_TRY(launch_colsum(w->rho2part, w->nblk_res, m, w->rho2, s));
+    return BMG_OK;
+  };
+  // H2-H6 followed by the next H1: the same launches every cycle
+  auto cycle_body = [&]() -> int {
+    BMG_TRY(cyc.vcycle(L));
+    BMG_TRY(launch_add_to<T>(w->U, cyc.e[L], N * m, s));
+    BMG_TRY(ritz_step());
+    BMG_TRY(residual_step());
+    return BMG_OK;
+  };
+  // Graph replay of cycle_body: not while timing kernels, and only if the
+  // body leaves the buffer roles as it found them.
+  // graphs replay the cycle; kernel timing uses plain launches (event pairs
+  // recorded per launch)
+  bool use_graph = o.timed_kernel < 0 && !std::getenv("BMG_NO_GRAPH");
+  const bool debug = std::getenv("BMG_DEBUG") != nullptr;
+  if (use_graph && !(w->gexec && o.timed_kernel < 0 && w->g_timed < 0 && w->g_sigma == sigma && w->g_omega == o.omega &&
+                     w->g_smoother == o.smoother && w->g_nu1 == o.nu1 && w->g_nu2 == o.nu2 &&
+                     w->g_lc == l_c && w->g_tail == cyc.tail_hi)) {
+    if (w->gexec) (void)hipGraphExecDestroy(w->gexec);
+    if (w->graph) (void)hipGraphDestroy(w->graph);
+    w->gexec = nullptr;
+    w->graph = nullptr;
+  }
+  auto launch_body = [&]() -> int {
+    if (!use_graph) return cycle_body();
+    if (!w->gexec) {
+      const std::vector<T*> e0 = cyc.e, t0 = cyc.t;
+      const size_t kt_used = kt.used;
+      BMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      const int cst = cycle_body();
+      hipGraph_t g = nullptr;
+      const hipError_t ce = hipStreamEndCapture(s, &g);
+      const bool swapped = cyc.e != e0 || cyc.t != t0;  // odd number of Jacobi swaps
+      if (cst != BMG_OK || ce != hipSuccess || swapped) {
+        // capture impossible here: run this and later cycles as plain launches
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        cyc.e = e0;
+        cyc.t = t0;
+        kt.discard(kt_used);
+        use_graph = false;
+        return cycle_body();
+      }
+      BMG_HIP(hipGraphInstantiate(&w->gexec, g, nullptr, nullptr, 0));
+      w->graph = g;
+      w->g_timed = o.timed_kernel;
+      if (o.timed_kernel >= 0) kt.freeze();
+      w->g_sigma = sigma;
+      w->g_omega = o.omega;
+      w->g_smoother = o.smoother;
+      w->g_nu1 = o.nu1;
+      w->g_nu2 = o.nu2;
+      w->g_lc = l_c;
+      w->g_tail = cyc.tail_hi;
+    }
+    BMG_HIP(hipGraphLaunch(w->gexec, s));
+    return BMG_OK;
+  };
+  BMG_TRY(residual_step());
+  for (;;) {
     BMG_HIP(hipMemcpyAsync(w->hbuf, w->theta, sizeof(double) * m, hipMemcpyDeviceToHost, s));
     BMG_HIP(hipMemcpyAsync(w->hbuf + m, w->rho2, sizeof(double) * m, hipMemcpyDeviceToHost, s));
-    BMG_HIP(hipMemcpyAsync(w->hbuf + 2 * m, w->status, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+    BMG_HIP(hipMemcpyAsync(w->hbuf + 2 * m, w->status, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
     BMG_HIP(hipStreamSynchronize(s));
+    kt.harvest(cycles > 0 && use_graph);
     std::memcpy(theta.data(), w->hbuf, sizeof(double) * m);
     std::memcpy(rho2.data(), w->hbuf + m, sizeof(double) * m);
-    int rs3[3] = {0, 0, 0};
-    std::memcpy(rs3, w->hbuf + 2 * m, 3 * sizeof(int));
+    int rs3[16] = {0};
+    std::memcpy(rs3, w->hbuf + 2 * m, 16 * sizeof(int));
+    if (debug) {
+      fprintf(stderr, "[bmg] cycle %d ritz: sweeps %d fallback %d dropped %d | phases (us) assemble %.1f chol %.1f "
+              "products %.1f jacobi %.1f select %.1f\n", cycles, rs3[1], rs3[2], rs3[3], rs3[4] * 0.01,
+              rs3[5] * 0.01, rs3[6] * 0.01, rs3[7] * 0.01, rs3[8] * 0.01);
+    }
     const int rstat = rs3[0];
     ritz_sweeps_max = std::max(ritz_sweeps_max, rs3[1]);
     ritz_fallbacks += rs3[2];
@@ -493,11 +765,7 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
       set_error("no convergence in %d cycles", o.max_cycles);
       break;
     }
-    // H2 + H3
-    BMG_TRY(cyc.vcycle(L));
-    BMG_TRY(launch_add_to<T>(w->U, cyc.e[L], N * m, s));
-    // H4-H6
-    BMG_TRY(ritz_step());
+    BMG_TRY(launch_body());
     ++cycles;
   }
 
@@ -531,7 +799,7 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     stats->t_solve_ms = ms;
     stats->max_rho_over_delta = cert.max_dk;
     stats->max_kato_temple = cert.max_kt;
-    stats->timed_kernel_ms = kt.total_ms();
+    stats->timed_kernel_ms = kt.ms;
     stats->timed_kernel_bytes = kt.bytes;
     stats->timed_kernel_units = kt.units;
     stats->ritz_sweeps_max = ritz_sweeps_max;
@@ -582,11 +850,21 @@ int solve(bmg_hierarchy* h, int k, double sigma, double tol, const bmg_solve_opt
   BMG_HIP(hipSetDevice(h->device));
   bmg_workspace* w = nullptr;
   BMG_TRY(acquire_workspace(h, o.m, o.n_c, o.precision, &w));
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  int st = (o.precision == BMG_MIXED)
-               ? run_solve<float>(h, w, k, sigma, tol, o, l_c, evals, evecs, ld, evecs_on_device, s, stats)
-               : run_solve<double>(h, w, k, sigma, tol, o, l_c, evals, evecs, ld, evecs_on_device, s, stats);
-  if (st == BMG_EDEVICE || st == BMG_EINVAL) (void)hipStreamSynchronize(s);
+  // work runs on the workspace's own stream, ordered after the caller's
+  // stream at entry and before it at exit
+  hipStream_t cs = static_cast<hipStream_t>(stream);
+  hipStream_t s = w->stream;
+  int st = BMG_OK;
+  if (hipEventRecord(w->ev_in, cs) != hipSuccess || hipStreamWaitEvent(s, w->ev_in, 0) != hipSuccess) {
+    set_error("stream join failed");
+    st = BMG_EDEVICE;
+  } else {
+    st = (o.precision == BMG_MIXED)
+             ? run_solve<float>(h, w, k, sigma, tol, o, l_c, evals, evecs, ld, evecs_on_device, s, stats)
+             : run_solve<double>(h, w, k, sigma, tol, o, l_c, evals, evecs, ld, evecs_on_device, s, stats);
+  }
+  (void)hipStreamSynchronize(s);
+  if (hipEventRecord(w->ev_out, s) == hipSuccess) (void)hipStreamWaitEvent(cs, w->ev_out, 0);
   release_workspace(h, w);
   return st;
 }
@@ -604,28 +882,9 @@ int apply_vcycle(bmg_hierarchy* h, int level, int dtype, int m, double sigma, in
   int st = BMG_OK;
   auto run = [&](auto tag) -> int {
     using T = decltype(tag);
-    std::vector<T> g(h->n0);
-    for (int64_t i = 0; i < h->n0; ++i) {
-      const double xx = h->lam0[i] - sigma;
-      g[i] = std::fabs(xx) >= 1e-2 * std::max(1.0, std::fabs(sigma)) ? T(1.0 / xx) : T(0);
-    }
-    BMG_HIP(hipMemcpyAsync(w->gco, g.data(), sizeof(T) * h->n0, hipMemcpyHostToDevice, s));
     BMG_HIP(hipMemcpyAsync(w->f[level], x, vb * h->dev[level].n * m, hipMemcpyDeviceToDevice, s));
     Cycle<T> cyc;
-    cyc.h = h;
-    cyc.c = CycleCfg{m, nu1, nu2, smoother, lc, sigma, omega};
-    const int nl = int(h->dev.size());
-    cyc.e.resize(nl);
-    cyc.f.resize(nl);
-    cyc.t.resize(nl);
-    for (int l = 0; l < nl; ++l) {
-      cyc.e[l] = static_cast<T*>(w->e[l]);
-      cyc.f[l] = static_cast<T*>(w->f[l]);
-      cyc.t[l] = static_cast<T*>(w->t[l]);
-    }
-    cyc.ctmp = static_cast<T*>(w->ctmp);
-    cyc.g0 = static_cast<const T*>(w->gco);
-    cyc.s = s;
+    BMG_TRY(init_cycle<T>(cyc, h, w, CycleCfg{m, nu1, nu2, smoother, lc, sigma, omega}, level, s));
     BMG_TRY(cyc.vcycle(level));
     BMG_HIP(hipMemcpyAsync(y, cyc.e[level], vb * h->dev[level].n * m, hipMemcpyDeviceToDevice, s));
     BMG_HIP(hipStreamSynchronize(s));
