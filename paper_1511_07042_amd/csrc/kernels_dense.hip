@@ -1,25 +1,34 @@
 // One-workgroup FP64 dense kernels of the Rayleigh-Ritz step.
 //
 // The enriched pencil (eq. pb-c-aux-mat, Alg. 2 step 4 / Alg. 3 step 5) is
-// small (nz = n_c + m <= 96) and lives in LDS.  Its basis is ordered
+// small (nz = n_c + m <= 96) and is worked on in LDS.  Its basis is ordered
 // [U', W_c] and made M-orthonormal (the "orthogonalize with respect to b_h"
 // step of Alg. 2 step 3) by a Cholesky factorisation of the unit-diagonal
 // scaled M-Gram matrix; because U' is close to the previous, already
 // M-orthonormal and A-diagonal Ritz block, the reduced matrix
 // C = L^-1 S (G_A - sigma G_M) S L^-T is then close to diagonal in its leading
-// m x m block and Jacobi needs few sweeps.  When a Cholesky pivot falls below
-// 1e-10 (the basis is numerically rank deficient) the kernel switches to SVQB
-// (Stathopoulos & Wu, SIAM J. Sci. Comput. 2002: eigendecompose the scaled
-// Gram matrix, drop directions below 1e-12 of the largest eigenvalue).  The m
-// eigenpairs nearest sigma are kept (Alg. 2 step 2, Remark 4.1).
+// m x m block and Jacobi needs few sweeps.  When fewer than m Cholesky pivots
+// exceed 1e-10 (the basis is numerically rank deficient) the kernel switches
+// to SVQB (Stathopoulos & Wu, SIAM J. Sci. Comput. 2002: eigendecompose the
+// scaled Gram matrix, drop directions below 1e-12 of the largest eigenvalue).
+// The m eigenpairs nearest sigma are kept (Alg. 2 step 2, Remark 4.1).
+//
+// The work is latency-bound: the kernel runs eight waves (two per SIMD),
+// stores symmetric matrices packed (lower triangle by rows) so two of them and
+// the full eigenvector matrix fit one CU's LDS for nz <= 96, and every loop that
+// runs once per column or per Jacobi round touches LDS only.
 //
 // Jacobi method (Golub & Van Loan, Matrix Computations, Sec. 8.5): two-sided
-// rotations in parallel (round-robin) order.  In one round the n/2 disjoint
-// pairs (p, q) get their rotations at once; every 2x2 block [p1 q1] x [p2 q2]
-// of the matrix is rotated on both sides by one thread and each row of the
-// eigenvector matrix by one thread.  Only significant rotations are applied,
-// |a_pq| > 1e-15 max(sqrt|a_pp a_qq|, ||A||_F / n), so rounding noise is not
-// churned; sweeps stop after a sweep without one.
+// rotations in parallel (round-robin) order.  In a round the n/2 disjoint
+// pairs (p, q) are rotated at once.  Each wave computes the round's rotations
+// (lane i: pair i) into its own LDS slot, so no barrier is needed to share
+// them; a round in which no rotation is significant is skipped by every wave
+// (the vote is identical in all of them).  The matrix is double-buffered:
+// every 2x2 block [p1 q1] x [p2 q2] is read from one buffer, rotated on both
+// sides and written to the other, so a round costs one barrier.  Only
+// significant rotations are applied, |a_pq| > 1e-15 max(sqrt|a_pp a_qq|,
+// ||A||_F / n), so rounding noise is not churned; sweeps stop after a sweep
+// without one.
 #include <cmath>
 
 #include "bmg_internal.h"
@@ -28,18 +37,33 @@ namespace bmg {
 namespace {
 
 constexpr int kMaxN = 96;
-constexpr int kThreads = 1024;
+constexpr int kMaxHalf = kMaxN / 2;
+constexpr int kThreads = 512;
+constexpr int kWaves = kThreads / 64;
+
+// packed lower-triangular index, i >= j
+__device__ __forceinline__ int tri(int i, int j) { return ((i * (i + 1)) >> 1) + j; }
+// packed symmetric index, any order
+__device__ __forceinline__ int sym(int i, int j) { return i >= j ? tri(i, j) : tri(j, i); }
+
+struct alignas(16) RotRec {
+  double c, s, t;
+  int p, q;
+};
 
 struct JacobiShared {
-  double c[kMaxN / 2], s[kMaxN / 2], t[kMaxN / 2];
-  int p[kMaxN / 2], q[kMaxN / 2];
-  unsigned char pq[kMaxN - 1][kMaxN];  // round-robin pairs: round r, slot t -> (p, q) at [r][2t], [r][2t+1]
-  int rflag;
-  double red[2 * (kThreads / 64)];
+  RotRec rot[kWaves][kMaxHalf];  // per-wave copy of the round's rotations
+  double red[2 * kWaves];
   double bcast[2];
-  int sig[2];
-  int flag;
+  int sig[3];  // per sweep (mod 3): a significant rotation was applied
+  int rounds;  // rounds with at least one significant rotation
 };
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __device__ void block_sum2(double a, double b, JacobiShared& sh, double& ra, double& rb) {
   for (int off = 32; off > 0; off >>= 1) {
@@ -67,133 +91,157 @@ __device__ void block_sum2(double a, double b, JacobiShared& sh, double& ra, dou
   __syncthreads();
 }
 
-// Diagonalise the symmetric n x n matrix X (row-major, LDS) in place:
-// on return X is diagonal (eigenvalues on the diagonal, unsorted) and
-// X_in = V diag V^T with V (LDS) orthogonal.  Returns the sweeps used, or -1
-// if the sweep limit was hit.
-__device__ int block_jacobi(double* X, double* V, int n, JacobiShared& sh) {
-  const int tid = threadIdx.x, nt = blockDim.x;
+// Pair of slot t in round rd of the circle method on ne (even) indices, p < q.
+__device__ __forceinline__ void rr_pair(int t, int rd, int ne, int& p, int& q) {
+  const int m1 = ne - 1;
+  int a = t + rd;
+  if (a >= m1) a -= m1;
+  int b = m1;
+  if (t != 0) {
+    b = m1 - t + rd;
+    if (b >= m1) b -= m1;
+  }
+  p = a < b ? a : b;
+  q = a < b ? b : a;
+}
+
+// Symmetric Schur rotation of the pair (p, q) of the packed matrix X
+// (Golub & Van Loan, Alg. 8.5.1, with tau = d / b folded into
+// t = sign(d) b / (|d| + hypot(d, b))), or the identity (s = 0) when a_pq is
+// not significant.
+__device__ __forceinline__ RotRec rot_params(const double* X, int p, int q, int n, double floor2) {
+  RotRec r{1.0, 0.0, 0.0, p, q};
+  if (q >= n) return r;
+  const double apq = X[tri(q, p)], app = X[tri(p, p)], aqq = X[tri(q, q)];
+  if (apq * apq > 1e-30 * fmax(fabs(app * aqq), floor2)) {
+    const double d = aqq - app, b = 2.0 * apq;
+    const double t = (d >= 0.0 ? b : -b) / (fabs(d) + sqrt(d * d + b * b));
+    r.c = rsqrt(1.0 + t * t);
+    r.s = t * r.c;
+    r.t = t;
+  }
+  return r;
+}
+
+// Diagonalise the packed symmetric n x n matrix in cur (LDS); nxt is a second
+// packed buffer.  On return cur holds the diagonal form (eigenvalues on the
+// diagonal, unsorted) and V (LDS, n x n row-major) is orthogonal with
+// X_in = V diag V^T.  Returns the sweeps used, or -1 if the limit was hit.
+__device__ int block_jacobi(double*& cur, double*& nxt, double* V, int n, JacobiShared& sh) {
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
   const int ne = n + (n & 1);
   const int half = ne / 2;
+  const int nb = half * (half + 1) / 2;  // blocks (t1 <= t2)
+  constexpr int kNB = (kMaxHalf * (kMaxHalf + 1) / 2 + kThreads - 1) / kThreads;
   double f2 = 0.0;
   for (int e = tid; e < n * n; e += nt) {
-    V[e] = (e / n == e % n) ? 1.0 : 0.0;
-    f2 += X[e] * X[e];
+    const int i = e / n, j = e - (e / n) * n;
+    V[e] = (i == j) ? 1.0 : 0.0;
+    const double x = cur[sym(i, j)];
+    f2 += x * x;
   }
   if (tid == 0) {
     sh.sig[0] = 0;
     sh.sig[1] = 0;
+    sh.sig[2] = 0;
+    sh.rounds = 0;
   }
   double fro2, dummy;
   block_sum2(f2, 0.0, sh, fro2, dummy);
-  const double floor_abs = sqrt(fro2) / n;
-  int lh = 0;  // 2^lh >= half: 2-D thread indices without integer division
+  const double floor2 = fro2 / (double(n) * n);  // (||X||_F / n)^2
+  // this thread's blocks b = tid + i nt, decoded once: (t1, t2), t1 <= t2
+  int bt1[kNB], bt2[kNB];
+#pragma unroll
+  for (int i = 0; i < kNB; ++i) {
+    const int b = tid + i * nt;
+    int t2 = -1, t1 = 0;
+    if (b < nb) {
+      t2 = int((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+      if (tri(t2, 0) > b) --t2;
+      if (tri(t2 + 1, 0) <= b) ++t2;
+      t1 = b - tri(t2, 0);
+    }
+    bt1[i] = t1;
+    bt2[i] = t2;
+  }
+  // eigenvector work items: pair slot tv = tid mod hp, rows k0, k0 + GV, ...
+  int lh = 0;
   while ((1 << lh) < half) ++lh;
   const int hp = 1 << lh;
-  // round-robin (circle method) pair table, built once per call
-  for (int e = tid; e < (ne - 1) * half; e += nt) {
-    const int rd = e / half, t = e - (e / half) * half;
-    int p = (t + rd) % (ne - 1);
-    int q = t == 0 ? ne - 1 : (ne - 1 - t + rd) % (ne - 1);
-    sh.pq[rd][2 * t] = (unsigned char)(p < q ? p : q);
-    sh.pq[rd][2 * t + 1] = (unsigned char)(p < q ? q : p);
-  }
-  if (tid == 0) sh.rflag = 0;
-  __syncthreads();
-  int gr = 0;  // global round counter
+  const int tv = tid & (hp - 1), k0 = tid >> lh, GV = nt >> lh;
+  RotRec* rot = sh.rot[wave];
   for (int sweep = 0; sweep < 30; ++sweep) {
-    const int cur = sweep & 1;
-    for (int rd = 0; rd < ne - 1; ++rd, ++gr) {
-      if (tid < half) {
-        const int p = sh.pq[rd][2 * tid], q = sh.pq[rd][2 * tid + 1];
-        double c = 1.0, s = 0.0, t = 0.0;
-        if (q < n) {
-          const double apq = X[p * n + q];
-          const double app = X[p * n + p], aqq = X[q * n + q];
-          if (fabs(apq) > 1e-15 * fmax(sqrt(fabs(app * aqq)), floor_abs)) {
-            sh.sig[cur] = 1;
-            sh.rflag = gr + 1;
-            const double tau = (aqq - app) / (2.0 * apq);
-            if (fabs(tau) > 1e150) {
-              t = 0.5 / tau;
-            } else {
-              t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            }
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-          }
-        }
-        sh.c[tid] = c;
-        sh.s[tid] = s;
-        sh.t[tid] = t;
-        sh.p[tid] = p;
-        sh.q[tid] = q;
+    // this slot was last read at the end of sweep - 2, before the barriers of
+    // sweep - 1 (a sweep that continues had one); the next sweep writes it only
+    // after a barrier of this sweep
+    if (tid == 0) sh.sig[(sweep + 1) % 3] = 0;
+    for (int rd = 0; rd < ne - 1; ++rd) {
+      bool sg = false;
+      if (lane < half) {
+        int p, q;
+        rr_pair(lane, rd, ne, p, q);
+        const RotRec r = rot_params(cur, p, q, n, floor2);
+        rot[lane] = r;
+        sg = r.s != 0.0;
       }
-      __syncthreads();
-      if (rd == 0 && tid == 0) sh.sig[cur ^ 1] = 0;  // everyone has read it by now
-      // no significant rotation in this round: nothing changes, and the next
-      // round's parameters may be written without a second barrier
-      if (sh.rflag != gr + 1) continue;
-      // Thread (g, t): fixed pair slot t = tid mod hp, groups g = tid / hp.  All
-      // operands of a thread's items are loaded before any is written back.
-      const int t = tid & (hp - 1);
-      const int g0 = tid >> lh, G = nt >> lh;
-      if (t < half) {
-        const int p2 = sh.p[t], q2 = sh.q[t];
-        const double c2 = sh.c[t], s2 = sh.s[t];
+      // identical in every wave: skip the round (no writes, no barrier)
+      if (!__any(sg)) continue;
+      if (wave == 0 && sg) sh.sig[sweep % 3] = 1;
+      if (tid == 0) ++sh.rounds;
+      wave_sync();
+#pragma unroll
+      for (int i = 0; i < kNB; ++i) {
+        if (bt2[i] < 0) continue;
+        const int t1 = bt1[i], t2 = bt2[i];
+        const RotRec r2 = rot[t2];
+        const int p2 = r2.p, q2 = r2.q;
         const bool hq2 = q2 < n;
-        // 2x2 blocks (t1 <= t2 = t), each written with its transpose; with
-        // 1024 threads a thread has one block (n <= 64) or at most three
-        const double tt2 = sh.t[t];
-        for (int t1 = g0; t1 <= t; t1 += G) {
-          const int a1 = sh.p[t1], b1 = sh.q[t1];
-          const double c1 = sh.c[t1], s1 = sh.s[t1];
-          const bool hq1 = b1 < n;
-          const double bpp = X[a1 * n + p2];
-          const double bpq = hq2 ? X[a1 * n + q2] : 0.0;
-          const double bqp = hq1 ? X[b1 * n + p2] : 0.0;
-          const double bqq = (hq1 && hq2) ? X[b1 * n + q2] : 0.0;
-          if (t1 == t) {
-            if (hq2 && s2 != 0.0) {
-              X[p2 * n + p2] = bpp - tt2 * bpq;
-              X[q2 * n + q2] = bqq + tt2 * bpq;
-              X[p2 * n + q2] = 0.0;
-              X[q2 * n + p2] = 0.0;
-            }
-            continue;
-          }
-          if (s1 == 0.0 && s2 == 0.0) continue;
-          const double lpp = c1 * bpp - s1 * bqp, lpq = c1 * bpq - s1 * bqq;
-          const double lqp = s1 * bpp + c1 * bqp, lqq = s1 * bpq + c1 * bqq;
-          const double npp = c2 * lpp - s2 * lpq, npq = s2 * lpp + c2 * lpq;
-          const double nqp = c2 * lqp - s2 * lqq, nqq = s2 * lqp + c2 * lqq;
-          X[a1 * n + p2] = npp;
-          X[p2 * n + a1] = npp;
+        if (t1 == t2) {
+          const double app = cur[tri(p2, p2)];
           if (hq2) {
-            X[a1 * n + q2] = npq;
-            X[q2 * n + a1] = npq;
+            const double aqq = cur[tri(q2, q2)], apq = cur[tri(q2, p2)];
+            const bool s = r2.s != 0.0;
+            nxt[tri(p2, p2)] = s ? app - r2.t * apq : app;
+            nxt[tri(q2, q2)] = s ? aqq + r2.t * apq : aqq;
+            nxt[tri(q2, p2)] = s ? 0.0 : apq;
+          } else {
+            nxt[tri(p2, p2)] = app;
           }
-          if (hq1) {
-            X[b1 * n + p2] = nqp;
-            X[p2 * n + b1] = nqp;
-          }
-          if (hq1 && hq2) {
-            X[b1 * n + q2] = nqq;
-            X[q2 * n + b1] = nqq;
-          }
+          continue;
         }
-        // eigenvector rows k = g0, g0 + G, ... rotated in columns (p2, q2)
-        if (hq2 && s2 != 0.0) {
-          for (int k = g0; k < n; k += G) {
-            const double vp = V[k * n + p2], vq = V[k * n + q2];
-            V[k * n + p2] = c2 * vp - s2 * vq;
-            V[k * n + q2] = s2 * vp + c2 * vq;
+        const RotRec r1 = rot[t1];
+        const int a1 = r1.p, b1 = r1.q;
+        const bool hq1 = b1 < n;
+        const double bpp = cur[sym(a1, p2)];
+        const double bpq = hq2 ? cur[sym(a1, q2)] : 0.0;
+        const double bqp = hq1 ? cur[sym(b1, p2)] : 0.0;
+        const double bqq = (hq1 && hq2) ? cur[sym(b1, q2)] : 0.0;
+        const double c1 = r1.c, s1 = r1.s, c2 = r2.c, s2 = r2.s;
+        const double lpp = c1 * bpp - s1 * bqp, lpq = c1 * bpq - s1 * bqq;
+        const double lqp = s1 * bpp + c1 * bqp, lqq = s1 * bpq + c1 * bqq;
+        nxt[sym(a1, p2)] = c2 * lpp - s2 * lpq;
+        if (hq2) nxt[sym(a1, q2)] = s2 * lpp + c2 * lpq;
+        if (hq1) nxt[sym(b1, p2)] = c2 * lqp - s2 * lqq;
+        if (hq1 && hq2) nxt[sym(b1, q2)] = s2 * lqp + c2 * lqq;
+      }
+      // eigenvector rows rotated in columns (p, q) of pair tv
+      if (tv < half) {
+        const RotRec r = rot[tv];
+        if (r.s != 0.0) {
+          for (int k = k0; k < n; k += GV) {
+            double* vr = V + k * n;
+            const double vp = vr[r.p], vq = vr[r.q];
+            vr[r.p] = r.c * vp - r.s * vq;
+            vr[r.q] = r.s * vp + r.c * vq;
           }
         }
       }
       __syncthreads();
+      double* tmp = cur;
+      cur = nxt;
+      nxt = tmp;
     }
-    if (sh.sig[cur] == 0) return sweep + 1;
+    if (sh.sig[sweep % 3] == 0) return sweep + 1;
   }
   return -1;
 }
@@ -208,18 +256,25 @@ struct RitzShared {
   int r;
 };
 
-static_assert(((sizeof(RitzShared) + 7) / 8) * 8 + 2 * kMaxN * kMaxN * sizeof(double) <= 160 * 1024,
+constexpr int shared_doubles() { return int((sizeof(RitzShared) + 7) / 8); }
+
+// LDS: [RitzShared][R0: n*n][Ra: n(n+1)/2][Rb: n(n+1)/2]
+size_t lds_bytes(int n) { return (size_t(shared_doubles()) + size_t(n) * n + size_t(n) * (n + 1)) * 8; }
+
+static_assert((shared_doubles() + kMaxN * kMaxN + kMaxN * (kMaxN + 1)) * 8 <= 160 * 1024,
               "the Ritz kernel's LDS must fit one CU (160 KiB)");
 
-// Ranks of the diagonal of X (r x r): select the mm values nearest 0 (ties by
-// value, then index) and order them ascending into sh.sel[0..mm).
+// Select the mm diagonal entries of the packed r x r matrix X nearest 0 (ties
+// by value, then index) and order them ascending into sh.sel[0..mm).
 __device__ void select_nearest_zero(const double* X, int r, int mm, RitzShared& sh) {
   const int tid = threadIdx.x, nt = blockDim.x;
+  for (int j = tid; j < r; j += nt) sh.d[j] = X[tri(j, j)];
+  __syncthreads();
   for (int j = tid; j < r; j += nt) {
-    const double mj = X[j * r + j], aj = fabs(mj);
+    const double mj = sh.d[j], aj = fabs(mj);
     int rank = 0;
     for (int i = 0; i < r; ++i) {
-      const double mi = X[i * r + i], ai = fabs(mi);
+      const double mi = sh.d[i], ai = fabs(mi);
       if (ai < aj || (ai == aj && (mi < mj || (mi == mj && i < j)))) ++rank;
     }
     sh.kk[j] = rank;
@@ -227,11 +282,11 @@ __device__ void select_nearest_zero(const double* X, int r, int mm, RitzShared& 
   __syncthreads();
   for (int j = tid; j < r; j += nt) {
     if (sh.kk[j] >= mm) continue;
-    const double mj = X[j * r + j];
+    const double mj = sh.d[j];
     int pos = 0;
     for (int i = 0; i < r; ++i) {
       if (sh.kk[i] >= mm) continue;
-      const double mi = X[i * r + i];
+      const double mi = sh.d[i];
       if (mi < mj || (mi == mj && i < j)) ++pos;
     }
     sh.sel[pos] = j;
@@ -239,8 +294,8 @@ __device__ void select_nearest_zero(const double* X, int r, int mm, RitzShared& 
   __syncthreads();
 }
 
-// LDS: [RitzShared][X: nz*nz][V: nz*nz].  Global scratch: GA, GM (permuted
-// order [U', W_c]), L, Li (or T, Y1 on the SVQB path), W1.
+// Global scratch: GA, GM (permuted order [U', W_c]), Bs = S (GA - sigma GM) S,
+// Lg (packed inverse Cholesky factor, or the SVQB basis T), W1 (SVQB only).
 __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
                                                    const double* __restrict__ G,
                                                    const double* __restrict__ GW, double* Y,
@@ -249,13 +304,14 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
   RitzShared& sh = *reinterpret_cast<RitzShared*>(lds);
   const int nz = n_c + m;
   const int n = nz;
-  double* X = lds + (sizeof(RitzShared) + 7) / 8;
-  double* V = X + nz * nz;
-  double* GA = scratch;        // [nz][nz]
-  double* GM = GA + nz * nz;   // [nz][nz]
-  double* L = GM + nz * nz;    // [nz][nz] Cholesky factor / SVQB basis T
-  double* Li = L + nz * nz;    // [nz][nz] inverse of L / SVQB Y1
-  double* W1 = Li + nz * nz;   // [nz][nz]
+  double* R0 = lds + shared_doubles();  // [nz][nz]
+  double* Ra = R0 + nz * nz;            // packed
+  double* Rb = Ra + nz * (nz + 1) / 2;  // packed
+  double* GA = scratch;
+  double* GM = GA + nz * nz;
+  double* Bs = GM + nz * nz;
+  double* Lg = Bs + nz * nz;
+  double* W1 = Lg + nz * nz;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int m2 = 2 * m, nc2 = 2 * n_c;
   long long ts[6];
@@ -282,106 +338,150 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
     }
     GA[e] = va;
     GM[e] = vm;
-    X[e] = vm;
-    L[e] = 0.0;
+    R0[e] = vm;
   }
   __syncthreads();
   for (int i = tid; i < nz; i += nt) {
-    const double dg = X[i * nz + i];
+    const double dg = R0[i * nz + i];
     sh.sv[i] = dg > 0.0 ? 1.0 / sqrt(dg) : 0.0;
   }
-  if (tid == 0) sh.j.flag = 1;
+  if (tid == 0) sh.r = 0;
   __syncthreads();
   for (int e = tid; e < nz * nz; e += nt) {
     const int i = e / nz, j = e - (e / nz) * nz;
-    X[e] *= sh.sv[i] * sh.sv[j];
+    const double sij = sh.sv[i] * sh.sv[j];
+    if (j <= i) {
+      Ra[tri(i, j)] = R0[e] * sij;
+      Rb[tri(i, j)] = (i == j) ? 1.0 : 0.0;
+    }
+    Bs[e] = (GA[e] - sigma * R0[e]) * sij;
   }
   __syncthreads();
   ts[1] = wall_clock64();
-  // ---- Cholesky of the scaled Gram matrix (right-looking, one barrier per
-  // column).  A column whose pivot (the squared sine of its angle to the
-  // span of the kept columns before it) is below 1e-10 is dropped: it adds
-  // nothing to the enriched space.  With sigma = 0 this happens to the
+  // ---- Cholesky of the scaled Gram matrix X (Ra), right-looking, one
+  // barrier per column.  Step j subtracts f_i = X_ij / X_jj times the pivot
+  // row from every row i > j: on the trailing part of X (columns j < c <= i)
+  // and, in the same pass, on Z (Rb, columns c <= j), which starts as I and
+  // so ends as the unit lower-triangular inverse of the LDL^T factor:
+  // L^-1 = D^-1/2 Z.  A column whose pivot (the squared sine of its angle to
+  // the span of the kept columns before it) is below 1e-10 is dropped: it
+  // adds nothing to the enriched space.  With sigma = 0 this happens to the
   // constant vector of W_c once U' holds the converged constant mode.
-  if (tid == 0) sh.r = 0;
-  __syncthreads();
   for (int j = 0; j < n; ++j) {
-    const double piv = X[j * n + j];
+    const double piv = Ra[tri(j, j)];
     if (piv > 1e-10) {  // uniform: every thread reads the same pivot
-      const double rp = sqrt(piv);
-      const int w = n - j;
-      for (int e = tid; e < w * w; e += nt) {
-        const int i = j + e / w, k = j + e - (e / w) * w;
-        if (k == j)
-          L[i * n + j] = X[i * n + j] / rp;
-        else if (k <= i)
-          X[i * n + k] -= X[i * n + j] * X[k * n + j] / piv;
+      const int w = n - 1 - j;
+      const double ip = 1.0 / piv;
+      constexpr int kCW = 16, kCE = (kMaxN + kCW - 1) / kCW;
+      for (int idx = tid; idx < w * kCW; idx += nt) {
+        const int i = j + 1 + idx / kCW, cl = idx % kCW;
+        double src[kCE], dst[kCE];
+#pragma unroll
+        for (int u = 0; u < kCE; ++u) {
+          const int c = cl + kCW * u;
+          src[u] = dst[u] = 0.0;
+          if (c <= i) {
+            src[u] = c <= j ? Rb[tri(j, c)] : Ra[tri(c, j)];
+            dst[u] = c <= j ? Rb[tri(i, c)] : Ra[tri(i, c)];
+          }
+        }
+        const double f = Ra[tri(i, j)] * ip;
+#pragma unroll
+        for (int u = 0; u < kCE; ++u) {
+          const int c = cl + kCW * u;
+          if (c <= i) {
+            const double v = dst[u] - f * src[u];
+            if (c <= j)
+              Rb[tri(i, c)] = v;
+            else
+              Ra[tri(i, c)] = v;
+          }
+        }
       }
       if (tid == 0) sh.kk[sh.r++] = j;
     }
     __syncthreads();
   }
+  for (int j = tid; j < n; j += nt) sh.d[j] = Ra[tri(j, j)];
+  __syncthreads();
   ts[2] = wall_clock64();
   int r = sh.r;
-  double* T = L;  // SVQB path: basis coefficients Y = T Q
   const bool chol = r >= m;
   for (int a = tid; a < n; a += nt) sh.dropmap[a] = -1;
   __syncthreads();
   for (int q = tid; q < r; q += nt) sh.dropmap[sh.kk[q]] = q;
+  double* cur = Rb;
+  double* nxt = Ra;
   if (chol) {
-    // compact factor Lc = L[kept, kept] in X (LDS; X is free after the
-    // factorisation) and its inverse Li in V (LDS), row by row: row i of Li
-    // needs rows < i, its columns are independent.
+    // Li = D^-1/2 Z on the kept rows and columns into Ra (and Lg)
     for (int e = tid; e < r * r; e += nt) {
       const int a = e / r, b = e - (e / r) * r;
-      X[e] = (b <= a) ? L[sh.kk[a] * n + sh.kk[b]] : 0.0;
-      V[e] = 0.0;
+      if (b <= a) {
+        const int ka = sh.kk[a], kb = sh.kk[b];
+        const double v = Rb[tri(ka, kb)] / sqrt(sh.d[ka]);
+        Ra[tri(a, b)] = v;
+        Lg[tri(a, b)] = v;
+      }
     }
     __syncthreads();
-    for (int i = 0; i < r; ++i) {
-      const double lii = X[i * r + i];
-      for (int c = tid; c <= i; c += nt) {
-        double acc = (i == c) ? 1.0 : 0.0;
-        for (int k = c; k < i; ++k) acc -= X[i * r + k] * V[k * r + c];
-        V[i * r + c] = acc / lii;
-      }
-      __syncthreads();
-    }
-    for (int e = tid; e < r * r; e += nt) Li[e] = V[e];  // kept for the final Y
-    // W1 = Li B, B = S (G_A - sigma G_M) S restricted to the kept columns
+    // Bk = Bs on the kept rows and columns, packed, into Rb
     for (int e = tid; e < r * r; e += nt) {
-      const int i = e / r, j = e - (e / r) * r;
-      const int cj = sh.kk[j];
-      double acc = 0.0;
-      for (int k = 0; k <= i; ++k) {
-        const int ck = sh.kk[k];
-        acc += V[i * r + k] * sh.sv[ck] * (GA[ck * n + cj] - sigma * GM[ck * n + cj]);
-      }
-      L[e] = acc * sh.sv[cj];  // L is free now: reuse as W1
+      const int a = e / r, b = e - (e / r) * r;
+      if (b <= a) Rb[tri(a, b)] = Bs[sh.kk[a] * n + sh.kk[b]];
     }
     __syncthreads();
-    // C = W1 Li^T
+    // W1 = Li Bk into R0 (r x r)
     for (int e = tid; e < r * r; e += nt) {
       const int i = e / r, j = e - (e / r) * r;
-      double acc = 0.0;
-      for (int k = 0; k <= j; ++k) acc += L[i * r + k] * V[j * r + k];
-      X[e] = acc;
+      const double* li = Ra + tri(i, 0);
+      double a0 = 0.0, a1 = 0.0;
+      int k = 0;
+      for (; k + 1 <= i; k += 2) {
+        a0 += li[k] * Rb[sym(k, j)];
+        a1 += li[k + 1] * Rb[sym(k + 1, j)];
+      }
+      if (k <= i) a0 += li[k] * Rb[sym(k, j)];
+      R0[e] = a0 + a1;
+    }
+    __syncthreads();
+    // C = W1 Li^T, symmetrised, into Rb
+    for (int e = tid; e < r * r; e += nt) {
+      const int i = e / r, j = e - (e / r) * r;
+      if (j > i) continue;
+      const double* wi = R0 + i * r;
+      const double* wj = R0 + j * r;
+      const double* li = Ra + tri(i, 0);
+      const double* lj = Ra + tri(j, 0);
+      double a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0;
+      int k = 0;
+      for (; k + 1 <= j; k += 2) {
+        a1 += wi[k] * lj[k];
+        a3 += wi[k + 1] * lj[k + 1];
+      }
+      if (k <= j) a1 += wi[k] * lj[k];
+      k = 0;
+      for (; k + 1 <= i; k += 2) {
+        a2 += wj[k] * li[k];
+        a4 += wj[k + 1] * li[k + 1];
+      }
+      if (k <= i) a2 += wj[k] * li[k];
+      Rb[tri(i, j)] = 0.5 * ((a1 + a3) + (a2 + a4));
     }
     __syncthreads();
   } else {
     // ---- SVQB: eigendecompose the scaled Gram matrix, drop tiny directions
     for (int e = tid; e < nz * nz; e += nt) {
       const int i = e / nz, j = e - (e / nz) * nz;
-      X[e] = GM[e] * sh.sv[i] * sh.sv[j];
+      if (j <= i) Rb[tri(i, j)] = GM[e] * sh.sv[i] * sh.sv[j];
     }
     __syncthreads();
-    (void)block_jacobi(X, V, nz, sh.j);
+    (void)block_jacobi(cur, nxt, R0, nz, sh.j);
     if (tid == 0) {
       double dmax = 0.0;
-      for (int j = 0; j < nz; ++j) dmax = fmax(dmax, X[j * nz + j]);
+      for (int j = 0; j < nz; ++j) dmax = fmax(dmax, cur[tri(j, j)]);
       int rr = 0;
       for (int j = 0; j < nz; ++j) {
-        const double dj = X[j * nz + j];
+        const double dj = cur[tri(j, j)];
         if (dj > 1e-12 * dmax) {
           sh.kk[rr] = j;
           sh.d[rr] = dj;
@@ -392,9 +492,10 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
     }
     __syncthreads();
     r = sh.r;
+    double* T = Lg;  // [nz][r]: basis coefficients
     for (int e = tid; e < nz * r; e += nt) {
       const int i = e / r, q = e - (e / r) * r;
-      T[e] = sh.sv[i] * V[i * nz + sh.kk[q]] / sqrt(sh.d[q]);
+      T[e] = sh.sv[i] * R0[i * nz + sh.kk[q]] / sqrt(sh.d[q]);
     }
     __syncthreads();
     for (int e = tid; e < nz * r; e += nt) {
@@ -404,28 +505,29 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
       W1[e] = acc;
     }
     __syncthreads();
+    cur = Rb;
+    nxt = Ra;
     for (int e = tid; e < r * r; e += nt) {
       const int p = e / r, q = e - (e / r) * r;
-      double acc = 0.0;
-      for (int i = 0; i < nz; ++i) acc += T[i * r + p] * W1[i * r + q];
-      X[e] = acc;
+      if (q > p) continue;
+      double a1 = 0.0, a2 = 0.0;
+      for (int i = 0; i < nz; ++i) {
+        a1 += T[i * r + p] * W1[i * r + q];
+        a2 += T[i * r + q] * W1[i * r + p];
+      }
+      Rb[tri(p, q)] = 0.5 * (a1 + a2);
     }
     __syncthreads();
   }
-  for (int e = tid; e < r * r; e += nt) {
-    const int p = e / r, q = e - (e / r) * r;
-    if (p < q) {
-      const double avg = 0.5 * (X[p * r + q] + X[q * r + p]);
-      X[p * r + q] = avg;
-      X[q * r + p] = avg;
-    }
-  }
-  __syncthreads();
   ts[3] = wall_clock64();
-  const int sw = block_jacobi(X, V, r, sh.j);
+  const int sw = block_jacobi(cur, nxt, R0, r, sh.j);
   ts[4] = wall_clock64();
   const int mm = m < r ? m : r;
-  select_nearest_zero(X, r, mm, sh);
+  select_nearest_zero(cur, r, mm, sh);
+  if (chol) {  // the inverse factor back into LDS (nxt is free)
+    for (int e = tid; e < r * (r + 1) / 2; e += nt) nxt[e] = Lg[e];
+    __syncthreads();
+  }
   // Y (rows in the caller's order [W_c, U']) = basis coefficients of the selection
   for (int e = tid; e < nz * m; e += nt) {
     const int a = e / m, c = e - (e / m) * m;  // a: permuted row
@@ -435,22 +537,23 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
       if (chol) {
         const int q = sh.dropmap[a];
         if (q >= 0) {
-          for (int b = q; b < r; ++b) acc += Li[b * r + q] * V[b * r + col];
+          for (int b = q; b < r; ++b) acc += nxt[tri(b, q)] * R0[b * r + col];
           acc *= sh.sv[a];
         }
       } else {
-        for (int q = 0; q < r; ++q) acc += T[a * r + q] * V[q * r + col];
+        for (int q = 0; q < r; ++q) acc += Lg[a * r + q] * R0[q * r + col];
       }
     }
     Y[orig(a) * m + c] = acc;
   }
-  for (int c = tid; c < m; c += nt) theta[c] = c < mm ? X[sh.sel[c] * r + sh.sel[c]] + sigma : 0.0;
+  for (int c = tid; c < m; c += nt) theta[c] = c < mm ? sh.d[sh.sel[c]] + sigma : 0.0;
   ts[5] = wall_clock64();
   if (tid == 0) {
     status[0] = (r < m) ? 1 : (sw < 0 ? 2 : 0);
     status[1] = sw;
     status[2] = chol ? 0 : 1;
     status[3] = n - (chol ? r : n);
+    status[9] = sh.j.rounds;
     for (int i = 0; i < 5; ++i) status[4 + i] = int(ts[i + 1] - ts[i]);  // 100 MHz ticks
   }
 }
@@ -460,34 +563,35 @@ __global__ void __launch_bounds__(kThreads) k_syev(int n, const double* __restri
                                                    double* Vout, int* status) {
   extern __shared__ double lds[];
   RitzShared& sh = *reinterpret_cast<RitzShared*>(lds);
-  double* X = lds + (sizeof(RitzShared) + 7) / 8;
-  double* V = X + n * n;
+  double* R0 = lds + shared_doubles();
+  double* cur = R0 + n * n;
+  double* nxt = cur + n * (n + 1) / 2;
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int e = tid; e < n * n; e += nt) {
     const int i = e / n, j = e - (e / n) * n;
-    X[e] = 0.5 * (A[i * n + j] + A[j * n + i]);
+    if (j <= i) cur[tri(i, j)] = 0.5 * (A[i * n + j] + A[j * n + i]);
   }
   __syncthreads();
-  const int sw = block_jacobi(X, V, n, sh.j);
+  const int sw = block_jacobi(cur, nxt, R0, n, sh.j);
+  for (int j = tid; j < n; j += nt) sh.d[j] = cur[tri(j, j)];
+  __syncthreads();
   for (int j = tid; j < n; j += nt) {
-    const double mj = X[j * n + j];
+    const double mj = sh.d[j];
     int pos = 0;
     for (int i = 0; i < n; ++i) {
-      const double mi = X[i * n + i];
+      const double mi = sh.d[i];
       if (mi < mj || (mi == mj && i < j)) ++pos;
     }
     sh.sel[pos] = j;
   }
   __syncthreads();
-  for (int c = tid; c < n; c += nt) w[c] = X[sh.sel[c] * n + sh.sel[c]];
+  for (int c = tid; c < n; c += nt) w[c] = sh.d[sh.sel[c]];
   for (int e = tid; e < n * n; e += nt) {
     const int i = e / n, c = e - (e / n) * n;
-    Vout[e] = V[i * n + sh.sel[c]];
+    Vout[e] = R0[i * n + sh.sel[c]];
   }
   if (tid == 0) *status = sw < 0 ? 2 : 0;
 }
-
-size_t lds_bytes(int n) { return ((sizeof(RitzShared) + 7) / 8) * 8 + 2 * size_t(n) * n * sizeof(double); }
 
 int check_launch() {
   hipError_t e = hipGetLastError();

@@ -738,9 +738,9 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     int rs3[16] = {0};
     std::memcpy(rs3, w->hbuf + 2 * m, 16 * sizeof(int));
     if (debug) {
-      fprintf(stderr, "[bmg] cycle %d ritz: sweeps %d fallback %d dropped %d | phases (us) assemble %.1f chol %.1f "
-              "products %.1f jacobi %.1f select %.1f\n", cycles, rs3[1], rs3[2], rs3[3], rs3[4] * 0.01,
-              rs3[5] * 0.01, rs3[6] * 0.01, rs3[7] * 0.01, rs3[8] * 0.01);
+      fprintf(stderr, "[bmg] cycle %d ritz: sweeps %d rounds %d fallback %d dropped %d | phases (us) assemble %.1f "
+              "chol %.1f products %.1f jacobi %.1f select %.1f\n", cycles, rs3[1], rs3[9], rs3[2], rs3[3],
+              rs3[4] * 0.01, rs3[5] * 0.01, rs3[6] * 0.01, rs3[7] * 0.01, rs3[8] * 0.01);
     }
     const int rstat = rs3[0];
     ritz_sweeps_max = std::max(ritz_sweeps_max, rs3[1]);
