@@ -28,14 +28,28 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2_sphere_ref6")
-    ap.add_argument("--smoother", default="gs", choices=["gs", "jacobi"])
+    ap.add_argument("--smoother", default="jacobi", choices=["gs", "jacobi"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default="both", choices=["both", "mixed", "fp64"])
     ap.add_argument("--timed-kernel", default="smooth",
                     help="kernel class timed with HIP events inside the timed region (roofline)")
     ap.add_argument("--breakdown", action="store_true",
                     help="after the timed region, time every kernel class in extra solves")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this many MiB (5 times) and exit: the "
+                         "reference for scaling hardware byte counters")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    import torch
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4, "launches": 5}))
 
 
 # Kernel classes: bound and whether the library's figure counts bytes or flops.
@@ -43,6 +57,35 @@ KCLASS = {"eigres": ("hbm", "GB/s"), "spmm_am": ("hbm", "GB/s"), "smooth": ("hbm
           "residual": ("hbm", "GB/s"), "restrict": ("hbm", "GB/s"), "prolong": ("hbm", "GB/s"),
           "gram": ("mfma", "TFLOP/s"), "update": ("mfma", "TFLOP/s"), "ritz": ("latency", "us")}
 FP64_PEAK_TFLOPS = 78.6
+
+
+TRAFFIC_FILES = {("smooth", "jacobi", "c2_sphere_ref6", "mixed"):
+                 "profiles/jacobi_sweep_c2_sphere_ref6_traffic.txt"}
+
+
+def kernel_source_hash():
+    """sha256 of the weighted-Jacobi row kernel's source text (its template)."""
+    import hashlib
+    import re
+    src = open(os.path.join(ROOT, "paper_1511_07042_amd", "csrc", "kernels_sparse.hip")).read()
+    m = re.search(r"template <typename T, int MODE, bool FUSE>\n__global__.*?\n}\n", src, re.S)
+    return hashlib.sha256(m.group(0).encode()).hexdigest() if m else None
+
+
+def measured_traffic(kclass, smoother, workload, prec):
+    """HBM bytes per launch from committed counter runs, or None when there are
+    none for this kernel and workload or the kernel changed since they were taken."""
+    rel = TRAFFIC_FILES.get((kclass, smoother, workload, prec))
+    if rel is None or not os.path.exists(os.path.join(ROOT, rel)):
+        return None
+    kv = {}
+    for line in open(os.path.join(ROOT, rel)):
+        if "=" in line and not line.startswith("#"):
+            key, val = line.split("=", 1)
+            kv[key.strip()] = val.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def roofline(kclass, ms, amount, units):
@@ -96,6 +139,9 @@ def cpu_baseline(cfg, smoother):
 
 def main():
     a = parse()
+    if a.copy_calibration:
+        copy_calibration(a.copy_calibration)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": a.gpus}))
@@ -125,6 +171,11 @@ def main():
         roof[prec] = roofline(a.timed_kernel, sum(s["timed_kernel_ms"] for s in tst),
                               sum(s["timed_kernel_bytes"] for s in tst),
                               sum(s["timed_kernel_units"] for s in tst))
+        if "frac" in roof[prec]:
+            roof[prec]["traffic"] = measured_traffic(a.timed_kernel, a.smoother, a.workload, prec)
+            tb = "float" if prec == "mixed" else "double"
+            roof[prec]["kernel"] = (f"k_rowop<{tb}, 2, false> (weighted-Jacobi sweep, levels >= 3)"
+                                    if a.timed_kernel == "smooth" and a.smoother == "jacobi" else a.timed_kernel)
         print(f"# {prec}: {res[prec]} roofline {roof[prec]}", file=sys.stderr, flush=True)
         if a.breakdown:
             bd = {}

@@ -154,20 +154,29 @@ typedef struct {
   uint64_t seed;      /* test vectors: element (i,j) ~ N(0,1) from SplitMix64
                          counters 2c, 2c+1 with c = i m + j, Box-Muller */
   const double* initial_block; /* optional host [N_L][m] block replacing the seeded one */
-  int32_t timed_kernel; /* bmg_kernel_class to bracket with HIP events on `stream`
-                           (finest level only), or -1; see bmg_solve_stats */
+  int32_t timed_kernel; /* bmg_kernel_class to bracket with HIP events on `stream`,
+                           or -1; see bmg_solve_stats */
   int32_t reserved;
 } bmg_solve_opts;
 
-/* Kernel classes that bmg_solve can time (launches on the finest level L).
- * Algorithmic bytes per launch (N = N_L, nnz = nonzeros of A_L, m = block
- * width, b = 4 (mixed) or 8 (FP64) bytes per correction value, nz = n_c + m):
+/* Kernel classes that bmg_solve can time.  EIGRES, SPMM_AM, GRAM, UPDATE and
+ * RITZ run once per cycle on the finest level L; the V-cycle classes are timed
+ * on every level that runs as multi-block kernels (the levels below those run
+ * inside the one-workgroup LDS tail and are not counted).  Each class is one
+ * kernel symbol, so its average launch time is comparable with a profiler's.
+ * Algorithmic bytes per launch at a level with n rows, nnz nonzeros (ELL rows
+ * of width W), m block columns, b = 4 (mixed) or 8 (FP64) bytes per correction
+ * value, N = N_L, nz = n_c + m:
  *   EIGRES    residual SpMM:  20 nnz + 8 N m (U) + b N m (R) + 8 N (D^-1)
  *   SPMM_AM   A and M SpMM:   20 nnz + 8 N m (U) + 16 N m (A U, M U)
- *   SMOOTH    one sweep (all colour passes of Gauss-Seidel, or one Jacobi
- *             step): (4 + 2b) nnz + 4 N + 3 b N m  (x, f read; x written)
- *   RESIDUAL  (4 + 2b) nnz + 3 b N m;   RESTRICT  b N m + b N_{L-1} m + 4 N;
- *   PROLONG   b N_{L-1} m + 2 b N m + 8 (N - N_{L-1});
+ *   SMOOTH    Jacobi: one sweep from a nonzero iterate (the zero-start sweep
+ *             is a different kernel and is not counted):
+ *             (4 + b) nnz + 3 b n m   (S and columns; x, f read; y written);
+ *             Gauss-Seidel: one colour pass over n_k rows:
+ *             (4 + b) W n_k + b m (n + 2 n_k)   (its rows of S; x read once;
+ *             f read and x written on its rows)
+ *   RESIDUAL  (4 + b) nnz + 3 b n m;   RESTRICT  b n m + b n_prev m + 4 n_prev RW;
+ *   PROLONG   b n_prev m + 2 b n m + 8 (n - n_prev);
  *   GRAM      8 N (nz + 2m) bytes, 4 N nz m flops;
  *   UPDATE    8 N nz + 8 N m bytes, 2 N nz m flops;   RITZ  one workgroup. */
 typedef enum {
@@ -191,7 +200,7 @@ typedef struct {
                           the cluster of theta_i */
   double timed_kernel_ms;     /* summed HIP-event time of opts->timed_kernel launches */
   double timed_kernel_bytes;  /* summed algorithmic bytes (flops for GRAM/UPDATE) */
-  int64_t timed_kernel_units; /* launches, or sweeps for BMG_K_SMOOTH */
+  int64_t timed_kernel_units; /* launches */
   int32_t ritz_sweeps_max;    /* most Jacobi sweeps of one Ritz step */
   int32_t ritz_fallbacks;     /* Ritz steps that needed SVQB instead of Cholesky */
 } bmg_solve_stats;

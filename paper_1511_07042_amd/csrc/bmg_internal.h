@@ -2,6 +2,7 @@
 // level data, per-solve workspace and the kernel launchers.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -112,6 +113,27 @@ int upload_hierarchy(bmg_hierarchy* h, hipStream_t s);
 void free_device(bmg_hierarchy* h);
 
 // ------------------------------------------------------------- launchers --
+// Kernel timing: a caller that wants the next launch timed sets `start` and
+// `stop`; the launcher consumes them and records them at the kernel's own
+// start and end (hipExtLaunchKernelGGL), so the elapsed time excludes the
+// queueing around it.  A class of two kernels takes start on the first and
+// stop on the second.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local LaunchEvents g_launch_events;
+
+#define BMG_LAUNCH(kernel, grid, block, shmem, stream, ...)                                  \
+  do {                                                                                       \
+    const ::bmg::LaunchEvents ev_ = ::bmg::g_launch_events;                                  \
+    ::bmg::g_launch_events = ::bmg::LaunchEvents{};                                          \
+    if (ev_.start || ev_.stop)                                                               \
+      hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), (shmem), (stream), ev_.start,   \
+                            ev_.stop, 0, __VA_ARGS__);                                       \
+    else                                                                                     \
+      kernel<<<(grid), (block), (shmem), (stream)>>>(__VA_ARGS__);                           \
+  } while (0)
+
 // Interleaved blocks [n][m]; T = double or float.  All launchers enqueue on s
 // and return BMG_OK or BMG_EDEVICE.
 enum RowMode { ROW_SHIFTED = 0, ROW_RESIDUAL = 1 };

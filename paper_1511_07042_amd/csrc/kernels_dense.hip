@@ -620,7 +620,7 @@ int launch_ritz(const RitzArgs& a, hipStream_t s) {
     return BMG_EINVAL;
   }
   set_lds_attr();
-  k_ritz<<<1, kThreads, lds_bytes(a.nz), s>>>(a.n_c, a.m, a.sigma, a.G, a.GW, a.Y, a.theta,
+  BMG_LAUNCH((k_ritz), 1, kThreads, lds_bytes(a.nz), s, a.n_c, a.m, a.sigma, a.G, a.GW, a.Y, a.theta,
                                               a.scratch, a.status);
   return check_launch();
 }

@@ -159,7 +159,12 @@ template <int TI, int TJW>
 void gram_dispatch_launch(const GramPlan& p, int64_t n, int64_t rpb, const double* z1, int w1,
                           const double* z2, int w2, const double* y1, int v1, const double* y2,
                           int v2, double* part, hipStream_t s) {
-  k_gram<TI, TJW><<<p.nblk, 256, 0, s>>>(n, rpb, p.nzp, p.nyp, z1, w1, z2, w2, y1, v1, y2, v2, part);
+  {
+    const LaunchEvents ev = g_launch_events;
+    g_launch_events = LaunchEvents{ev.start, nullptr};
+    BMG_LAUNCH((k_gram<TI, TJW>), p.nblk, 256, 0, s, n, rpb, p.nzp, p.nyp, z1, w1, z2, w2, y1, v1, y2, v2, part);
+    g_launch_events = LaunchEvents{nullptr, ev.stop};
+  }
 }
 
 }  // namespace
@@ -217,7 +222,7 @@ int launch_gram(const GramPlan& p, int64_t n, const double* z1, int w1, const do
   int st = check_launch();
   if (st != BMG_OK) return st;
   const int tot = p.nz * p.ny;
-  k_gram_reduce<<<(tot + 63) / 64, 1024, 0, s>>>(part, p.nblk, p.nzp, p.nyp, p.nz, p.ny, G);
+  BMG_LAUNCH((k_gram_reduce), (tot + 63) / 64, 1024, 0, s, part, p.nblk, p.nzp, p.nyp, p.nz, p.ny, G);
   return check_launch();
 }
 
@@ -235,7 +240,7 @@ int launch_update_zy(int64_t n, const double* z1, int w1, const double* z2, int 
                         160 * 1024);
     attr_set = true;
   }
-  k_update_zy<<<grid, block, shm, s>>>(n, z1, w1, z2, w2, Y, m, cpr, rpb, U);
+  BMG_LAUNCH((k_update_zy), grid, block, shm, s, n, z1, w1, z2, w2, Y, m, cpr, rpb, U);
   return check_launch();
 }
 

@@ -447,10 +447,10 @@ int launch_shifted(const DevLevel& L, const T* S, int mode, const T* x, const T*
                    hipStream_t s) {
   Geom g = row_geom<T>(L.n, m);
   if (mode == ROW_SHIFTED)
-    k_rowop<T, K_SHIFTED, false><<<g.grid, g.block, 0, s>>>(L.n, L.W, m, g.cpr, g.rpb, L.cols, S,
+    BMG_LAUNCH((k_rowop<T, K_SHIFTED, false>), g.grid, g.block, 0, s, L.n, L.W, m, g.cpr, g.rpb, L.cols, S,
                                                             T(0), x, f, y, nullptr);
   else
-    k_rowop<T, K_RESIDUAL, false><<<g.grid, g.block, 0, s>>>(L.n, L.W, m, g.cpr, g.rpb, L.cols, S,
+    BMG_LAUNCH((k_rowop<T, K_RESIDUAL, false>), g.grid, g.block, 0, s, L.n, L.W, m, g.cpr, g.rpb, L.cols, S,
                                                              T(0), x, f, y, nullptr);
   return check_launch();
 }
@@ -460,10 +460,10 @@ int launch_jacobi(const DevLevel& L, const T* S, double omega, const T* x, const
                   bool x_is_zero, int m, hipStream_t s) {
   Geom g = row_geom<T>(L.n, m);
   if (x_is_zero)
-    k_rowop<T, K_JACOBI0, false><<<g.grid, g.block, 0, s>>>(L.n, L.W, m, g.cpr, g.rpb, L.cols, S,
+    BMG_LAUNCH((k_rowop<T, K_JACOBI0, false>), g.grid, g.block, 0, s, L.n, L.W, m, g.cpr, g.rpb, L.cols, S,
                                                             T(omega), x, f, y, nullptr);
   else
-    k_rowop<T, K_JACOBI, false><<<g.grid, g.block, 0, s>>>(L.n, L.W, m, g.cpr, g.rpb, L.cols, S,
+    BMG_LAUNCH((k_rowop<T, K_JACOBI, false>), g.grid, g.block, 0, s, L.n, L.W, m, g.cpr, g.rpb, L.cols, S,
                                                            T(omega), x, f, y, nullptr);
   return check_launch();
 }
@@ -474,7 +474,7 @@ int launch_gs_colour(const DevLevel& L, const T* S, int colour, T* x, const T* f
   const int64_t b = L.colour_ptr[colour], e = L.colour_ptr[colour + 1];
   if (e <= b) return BMG_OK;
   Geom g = row_geom<T>(e - b, m);
-  k_gs<T, false><<<g.grid, g.block, 0, s>>>(e - b, L.colour_rows + b, L.W, m, g.cpr, g.rpb, L.cols,
+  BMG_LAUNCH((k_gs<T, false>), g.grid, g.block, 0, s, e - b, L.colour_rows + b, L.W, m, g.cpr, g.rpb, L.cols,
                                             S, x, f, nullptr);
   return check_launch();
 }
@@ -482,7 +482,7 @@ int launch_gs_colour(const DevLevel& L, const T* S, int colour, T* x, const T* f
 int launch_spmm_am(const DevLevel& L, const double* x, double* ya, double* ym, int m,
                    hipStream_t s) {
   Geom g = row_geom<double>(L.n, m);
-  k_spmm_am<<<g.grid, g.block, 0, s>>>(L.n, L.W, m, g.cpr, g.rpb, L.cols, L.a64, L.m64, x, ya, ym);
+  BMG_LAUNCH((k_spmm_am), g.grid, g.block, 0, s, L.n, L.W, m, g.cpr, g.rpb, L.cols, L.a64, L.m64, x, ya, ym);
   return check_launch();
 }
 
@@ -497,7 +497,7 @@ int launch_eigres(const DevLevel& L, const double* x, const double* theta, doubl
     return BMG_EINVAL;
   }
   const size_t shm = size_t(g.rpb) * m * sizeof(double);
-  k_eigres<T><<<g.grid, g.block, shm, s>>>(L.n, L.W, m, g.cpr, g.rpb, L.cols, L.a64, L.m64, L.dinv,
+  BMG_LAUNCH((k_eigres<T>), g.grid, g.block, shm, s, L.n, L.W, m, g.cpr, g.rpb, L.cols, L.a64, L.m64, L.dinv,
                                            x, theta, sgn, y, rho2_part);
   return check_launch();
 }
@@ -510,14 +510,14 @@ int launch_colsum(const double* part, int nblk, int m, double* out, hipStream_t 
 template <typename T>
 int launch_restrict(const DevLevel& fine, const T* x, T* y, int m, hipStream_t s) {
   Geom g = row_geom<T>(fine.n_prev, m);
-  k_restrict<T><<<g.grid, g.block, 0, s>>>(fine.n_prev, fine.RW, m, g.cpr, g.rpb, fine.rtab, x, y);
+  BMG_LAUNCH((k_restrict<T>), g.grid, g.block, 0, s, fine.n_prev, fine.RW, m, g.cpr, g.rpb, fine.rtab, x, y);
   return check_launch();
 }
 
 template <typename T>
 int launch_prolong_add(const DevLevel& fine, const T* x, T* y, int m, hipStream_t s) {
   Geom g = row_geom<T>(fine.n, m);
-  k_prolong_add<T><<<g.grid, g.block, 0, s>>>(fine.n, fine.n_prev, m, g.cpr, g.rpb, fine.parents, x,
+  BMG_LAUNCH((k_prolong_add<T>), g.grid, g.block, 0, s, fine.n, fine.n_prev, m, g.cpr, g.rpb, fine.parents, x,
                                               y);
   return check_launch();
 }

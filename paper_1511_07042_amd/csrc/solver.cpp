@@ -57,6 +57,9 @@ struct bmg_workspace {
 };
 
 namespace bmg {
+
+thread_local LaunchEvents g_launch_events;
+
 namespace {
 
 int dalloc(bmg_workspace* w, void** p, size_t bytes) {
@@ -132,12 +135,14 @@ int make_workspace(bmg_hierarchy* h, int m, int n_c, int prec, bmg_workspace** o
   AL(w->G, sizeof(double) * nz * 2 * m);
   AL(w->GW, sizeof(double) * n_c * 2 * n_c);
   AL(w->Y, sizeof(double) * nz * m);
-  AL(w->theta, sizeof(double) * m);
+  // theta [m], rho2 [m] and the Ritz status words [16] are contiguous: one
+  // device-to-host copy per cycle reads all three
+  AL(w->theta, sizeof(double) * (2 * m + 8));
+  w->rho2 = w->theta + m;
+  w->status = reinterpret_cast<int*>(w->theta + 2 * m);
   w->nblk_res = eigres_blocks(h->dev[nl - 1], m);
   AL(w->rho2part, sizeof(double) * w->nblk_res * m);
-  AL(w->rho2, sizeof(double) * m);
   AL(w->rscratch, sizeof(double) * ritz_scratch_doubles(nz));
-  AL(w->status, sizeof(int) * 16);
   AL(w->sel, sizeof(int) * m);
   AL(w->sign, sizeof(double) * m);
   w->nblk_arg = int(std::min<int64_t>(256, (N + 255) / 256));
@@ -202,10 +207,10 @@ void free_workspaces(bmg_hierarchy* h) {
 }
 
 // ----------------------------------------------------------- kernel timer --
-// Brackets the launches of one kernel class (finest level only) with HIP events
-// on the solve's stream.  Eager launches record fresh event pairs; when the
-// cycle is captured as a graph the pairs become graph nodes and are re-read
-// after every replay.  harvest() runs after each synchronisation of the solve.
+// Times the launches of one kernel class with HIP events that the launcher
+// records at the kernel's own start and end (no queueing inside the interval).
+// Eager launches record fresh event pairs; harvest() runs after each
+// synchronisation of the solve.
 struct KTimer {
   int which = -1;
   hipStream_t s = nullptr;
@@ -225,12 +230,12 @@ struct KTimer {
       ev.push_back(a);
       ev.push_back(b);
     }
-    BMG_HIP(hipEventRecord(ev[2 * used], s));
+    g_launch_events = LaunchEvents{ev[2 * used], ev[2 * used + 1]};
     return BMG_OK;
   }
   int end(int k) {
     if (k != which) return BMG_OK;
-    BMG_HIP(hipEventRecord(ev[2 * used + 1], s));
+    g_launch_events = LaunchEvents{};
     ++used;
     return BMG_OK;
   }
@@ -405,14 +410,15 @@ struct Cycle {
     return BMG_OK;
   }
 
-  int kclass(int l, int k) const { return (kt && l == L) ? k : -2; }
+  int kclass(int k) const { return kt ? k : -2; }
 
   int sweep(int l, bool forward, bool from_zero) {
     const DevLevel& D = h->dev[l];
-    const int kc = kclass(l, BMG_K_SMOOTH);
-    const double b = sizeof(T);
-    if (kt) kt->add(kc, (4 + 2 * b) * double(h->host[l].nnz) + 4.0 * D.n + 3 * b * D.n * c.m, 1);
+    const HostLevel& H = h->host[l];
+    const double b = sizeof(T), n = double(D.n);
     if (c.smoother == BMG_SMOOTH_JACOBI) {
+      const int kc = from_zero ? -2 : kclass(BMG_K_SMOOTH);
+      if (kt) kt->add(kc, (4 + b) * double(H.nnz) + 3 * b * n * c.m, 1);
       if (kt) BMG_TRY(kt->begin(kc));
       BMG_TRY(launch_jacobi<T>(D, S[l], c.omega, e[l], f[l], t[l], from_zero, c.m, s));
       if (kt) BMG_TRY(kt->end(kc));
@@ -420,8 +426,11 @@ struct Cycle {
       return BMG_OK;
     }
     if (from_zero) BMG_TRY(launch_fill<T>(e[l], D.n * c.m, T(0), s));
+    const int kc = kclass(BMG_K_SMOOTH);
     for (int k = 0; k < D.n_colours; ++k) {
       const int col = forward ? k : D.n_colours - 1 - k;
+      const double nk = double(H.colour_ptr[col + 1] - H.colour_ptr[col]);
+      if (kt) kt->add(kc, (4 + b) * H.W * nk + b * c.m * (n + 2 * nk), 1);
       if (kt) BMG_TRY(kt->begin(kc));
       BMG_TRY(launch_gs_colour<T>(D, S[l], col, e[l], f[l], c.m, s));
       if (kt) BMG_TRY(kt->end(kc));
@@ -449,18 +458,18 @@ struct Cycle {
     if (c.nu1 == 0) BMG_TRY(launch_fill<T>(e[l], D.n * c.m, T(0), s));
     const double b = sizeof(T);
     const double nnz = double(h->host[l].nnz), n = double(D.n), nc = double(D.n_prev);
-    int kc = kclass(l, BMG_K_RESIDUAL);
-    if (kt) kt->add(kc, (4 + 2 * b) * nnz + 3 * b * n * c.m, 1);
+    int kc = kclass(BMG_K_RESIDUAL);
+    if (kt) kt->add(kc, (4 + b) * nnz + 3 * b * n * c.m, 1);
     if (kt) BMG_TRY(kt->begin(kc));
     BMG_TRY(launch_shifted<T>(D, S[l], ROW_RESIDUAL, e[l], f[l], t[l], c.m, s));
     if (kt) BMG_TRY(kt->end(kc));
-    kc = kclass(l, BMG_K_RESTRICT);
+    kc = kclass(BMG_K_RESTRICT);
     if (kt) kt->add(kc, b * n * c.m + b * nc * c.m + 4.0 * nc * D.RW, 1);
     if (kt) BMG_TRY(kt->begin(kc));
     BMG_TRY(launch_restrict<T>(D, t[l], f[l - 1], c.m, s));
     if (kt) BMG_TRY(kt->end(kc));
     BMG_TRY(vcycle(l - 1));
-    kc = kclass(l, BMG_K_PROLONG);
+    kc = kclass(BMG_K_PROLONG);
     if (kt) kt->add(kc, b * nc * c.m + 2 * b * n * c.m + 8.0 * (n - nc), 1);
     if (kt) BMG_TRY(kt->begin(kc));
     BMG_TRY(launch_prolong_add<T>(D, e[l - 1], e[l], c.m, s));
@@ -728,9 +737,7 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   };
   BMG_TRY(residual_step());
   for (;;) {
-    BMG_HIP(hipMemcpyAsync(w->hbuf, w->theta, sizeof(double) * m, hipMemcpyDeviceToHost, s));
-    BMG_HIP(hipMemcpyAsync(w->hbuf + m, w->rho2, sizeof(double) * m, hipMemcpyDeviceToHost, s));
-    BMG_HIP(hipMemcpyAsync(w->hbuf + 2 * m, w->status, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
+    BMG_HIP(hipMemcpyAsync(w->hbuf, w->theta, sizeof(double) * (2 * m + 8), hipMemcpyDeviceToHost, s));
     BMG_HIP(hipStreamSynchronize(s));
     kt.harvest(cycles > 0 && use_graph);
     std::memcpy(theta.data(), w->hbuf, sizeof(double) * m);
