@@ -35,6 +35,14 @@ def parse():
                     help="kernel class timed with HIP events inside the timed region (roofline)")
     ap.add_argument("--breakdown", action="store_true",
                     help="after the timed region, time every kernel class in extra solves")
+    ap.add_argument("--serving", type=int, default=0, metavar="N",
+                    help="instead of the solve benchmark, serve a seeded stream of N requests "
+                         "(Poisson arrivals at 0.8x the measured capacity) and report latency")
+    ap.add_argument("--serving-slots", type=int, default=8)
+    ap.add_argument("--serving-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serving-no-shift", action="store_true",
+                    help="all requests at sigma = 0 (no interior shifts)")
+    ap.add_argument("--serving-kinds", default="sphere,ellipsoid,torus")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (5 times) and exit: the "
                          "reference for scaling hardware byte counters")
@@ -137,6 +145,87 @@ def cpu_baseline(cfg, smoother):
                        f"{dt:.1f} s; dense BLAS on {blas} threads, scipy.sparse products single-threaded)")
 
 
+def _serve(bmg, reqs, slots, budget, rate=None, smoother="jacobi"):
+    """Submit the requests at their arrival times (all at once if rate is None)
+    and collect every result.  Returns (results, makespan_s)."""
+    import numpy as np
+    t_arr = [0.0] * len(reqs) if rate is None else [r["arrival_s"] for r in reqs]
+    out = [None] * len(reqs)
+    ids = {}
+    with bmg.Server(budget, max_slots=slots) as srv:
+        t0 = time.perf_counter()
+        nxt = 0
+        while nxt < len(reqs) or ids:
+            now = time.perf_counter() - t0
+            while nxt < len(reqs) and t_arr[nxt] <= now:
+                r = reqs[nxt]
+                ids[srv.submit(r["kind"], r["n_refine"], r["k"], r["sigma"], r["tol"], axes=r["axes"],
+                               smoother=smoother, precision="mixed", seed=r["seed"])] = nxt
+                nxt += 1
+            for rid in list(ids):
+                res = srv.poll(rid, evecs=False)
+                if res is not None:
+                    out[ids.pop(rid)] = res
+            time.sleep(0.0005)
+        makespan = time.perf_counter() - t0
+    return out, makespan
+
+
+def serving(a):
+    """Serving stream (seeded): surface, level, k and shift per request drawn as
+    in workloads.serving_stream; arrivals Poisson at 0.8x the capacity measured
+    on the same stream submitted all at once."""
+    import numpy as np
+    import torch
+    import paper_1511_07042_amd as bmg
+    from workloads import serving_stream
+    torch.cuda.set_device(0)
+    kinds = set(a.serving_kinds.split(","))
+    full = serving_stream(4 * a.serving, seed=0, rate_per_s=1.0, sigma_positive=not a.serving_no_shift)
+    reqs = [r for r in full if r["kind"] in kinds][:a.serving]
+    budget = int(a.serving_budget_gib * (1 << 30))
+    # capacity: every request submitted at t = 0, hierarchies built on demand
+    res, span = _serve(bmg, reqs, a.serving_slots, budget, None, a.smoother)
+    capacity = len(reqs) / span
+    rate = 0.8 * capacity
+    print(f"# capacity {capacity:.2f} req/s over {span:.2f} s; serving at {rate:.2f} req/s",
+          file=sys.stderr, flush=True)
+    # timed run: Poisson arrivals (the stream's seeded exponential gaps, rescaled)
+    gaps = np.diff([0.0] + [r["arrival_s"] for r in reqs])
+    t = np.cumsum(gaps / rate)
+    for r, ti in zip(reqs, t):
+        r["arrival_s"] = float(ti)
+    res, span = _serve(bmg, reqs, a.serving_slots, budget, rate, a.smoother)
+    lat = np.array([r["latency_ms"] for r in res])
+    ok = [r["status"] == 0 for r in res]
+    pairs = sum(q["k"] for q, good in zip(reqs, ok) if good)
+    status = {}
+    for r in res:
+        status[bmg.status_string(r["status"])] = status.get(bmg.status_string(r["status"]), 0) + 1
+    by_kind = {}
+    for q, r in zip(reqs, res):
+        d = by_kind.setdefault(q["kind"] + ("/shift" if q["sigma"] else ""), {"n": 0, "ok": 0, "lat": []})
+        d["n"] += 1
+        d["ok"] += int(r["status"] == 0)
+        d["lat"].append(r["latency_ms"])
+    for d in by_kind.values():
+        d["p50_ms"] = round(float(np.percentile(d.pop("lat"), 50)), 2)
+    out = {
+        "metric": "serving: converged eigenpairs/s and request latency (BMG, mixed precision)",
+        "value": round(pairs / span, 3), "unit": "eigenpairs/s", "n_gpus": 1,
+        "p50_ms": round(float(np.percentile(lat, 50)), 2),
+        "p99_ms": round(float(np.percentile(lat, 99)), 2),
+        "requests": len(reqs), "converged": int(sum(ok)), "status": status, "by_kind": by_kind,
+        "rate_req_s": round(rate, 3), "capacity_req_s": round(capacity, 3),
+        "makespan_s": round(span, 3), "slots": a.serving_slots,
+        "budget_gib": a.serving_budget_gib, "seed": 0, "data": "synthetic",
+        "cycles_p50": float(np.percentile([r["stats"]["cycles"] for r in res], 50)),
+        "config": {"workload": "c5_serving_stream", "kinds": sorted(kinds),
+                   "shifts": not a.serving_no_shift, "smoother": a.smoother},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.copy_calibration:
@@ -146,6 +235,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": a.gpus}))
         sys.exit(2)
+    if a.serving:
+        serving(a)
+        return
     import torch
     import paper_1511_07042_amd as bmg
     from workloads import CONFIGS

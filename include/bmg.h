@@ -276,29 +276,51 @@ int bmg_apply(const bmg_hierarchy* h, const bmg_apply_args* args, const void* x,
 
 typedef struct bmg_server bmg_server;
 
-/* A continuous-batching server: requests are admitted while the device memory
- * they need (hierarchy + blocks) fits in hbm_budget_bytes and fewer than
- * max_slots are active; active requests on equal levels advance together, one
- * grouped launch per step of the cycle.  Each request gives the same result
- * as a bmg_solve with the same arguments, within the stopping tolerance. */
+/* A continuous-batching server for many independent eigenproblems (the
+ * request-level form of bmg_solve).  Requests wait in arrival order and are
+ * admitted while fewer than max_slots run and the device memory they need (an
+ * upper bound of the solve's workspace, plus the hierarchy if it is not yet
+ * resident) fits in hbm_budget_bytes beside the resident hierarchies, their
+ * pooled workspaces and the running requests.  A smaller request may start
+ * before a waiting larger one; once the oldest waiting request has been passed
+ * 4 * max_slots times, nothing else starts before it.  Admitted requests run
+ * concurrently, each on a stream of its own, so their kernels overlap on the
+ * device.  Hierarchies are built on first use and cached per surface and
+ * level; idle workspaces, then idle hierarchies (least recently used first),
+ * are freed when the budget needs their memory.
+ * Each request's result is bit-for-bit the result of bmg_solve with the same
+ * arguments (the kernels are deterministic and requests share only read-only
+ * hierarchy data).  Uses the current device; BMG_EDEVICE if there is none.
+ * BMG_EINVAL if hbm_budget_bytes <= 0 or max_slots is outside [1, 64].
+ * Ownership: *out belongs to the caller until bmg_server_destroy. */
 int bmg_server_create(int64_t hbm_budget_bytes, int32_t max_slots, bmg_server** out);
 
-/* Queue one request (the descriptor and opts are copied).  *request_id gets
- * its id.  BMG_EINVAL on invalid arguments, BMG_ENOMEM if the request alone
- * exceeds the budget. */
+/* Queue one request.  The descriptor (and a custom mesh's arrays) and opts are
+ * copied; opts->initial_block and opts->timed_kernel are ignored; opts == NULL
+ * means bmg_solve_opts_default.  *request_id gets its id.  BMG_EINVAL on the
+ * arguments bmg_build_hierarchy or bmg_solve would reject (those detected only
+ * while building are reported by bmg_server_poll), BMG_ENOMEM if the request
+ * alone exceeds the budget. */
 int bmg_server_submit(bmg_server* s, const bmg_surface_desc* desc, int32_t n_refine, int32_t k,
                       double sigma, double tol, const bmg_solve_opts* opts, uint64_t* request_id);
 
-/* BMG_EBUSY while the request is queued or running; otherwise its final status
- * (BMG_OK, BMG_ENOCONV, BMG_ECANCELED, ...) after copying evals (host [k]),
- * evecs (nullable host column-major [k][ld]) and stats (nullable).  A finished
- * request is forgotten after a successful poll. */
+/* BMG_EBUSY while the request is queued or running.  Otherwise its final status
+ * (BMG_OK, BMG_ENOCONV, BMG_ECANCELED, a build or solve error) after copying
+ * evals (nullable host [k]), evecs (nullable host column-major [k][ld],
+ * ld >= N_L, else BMG_EINVAL and the request is kept), stats (nullable; its
+ * rho / delta pointers, if set, receive [k] doubles) and latency_ms (nullable:
+ * milliseconds from submit to completion, hierarchy build included).  A
+ * finished request is forgotten once polled; BMG_EINVAL for an unknown id. */
 int bmg_server_poll(bmg_server* s, uint64_t request_id, double* evals, double* evecs, int64_t ld,
                     bmg_solve_stats* stats, double* latency_ms);
 
+/* A queued request finishes at once with BMG_ECANCELED; a running one stops
+ * with BMG_ECANCELED at the end of its current cycle; a finished one is not
+ * changed.  BMG_EINVAL for an unknown id. */
 int bmg_server_cancel(bmg_server* s, uint64_t request_id);
 
-/* Stops the worker after finishing the active requests; frees everything. */
+/* Cancels the queued requests, waits for the running ones, frees every
+ * hierarchy and workspace of the server. */
 void bmg_server_destroy(bmg_server* s);
 
 /* ---------------------------------------------------------------- misc --- */

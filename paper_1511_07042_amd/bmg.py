@@ -282,5 +282,105 @@ class Hierarchy:
         return y
 
 
+def finest_vertices(kind="sphere", n_refine=0, nu=64, nv=32, n_vert=0, n_tri=0):
+    """Vertices of the finest level of a uniformly refined hierarchy (each edge
+    gains a midpoint, each triangle splits into four)."""
+    if kind in ("sphere", "ellipsoid"):
+        n, e, f = 12, 30, 20
+    elif kind == "torus":
+        n = nu * nv
+        e, f = 3 * n, 2 * n
+    else:
+        n, f = n_vert, n_tri
+        e = 3 * n_tri // 2
+    for _ in range(int(n_refine)):
+        n, e, f = n + e, 2 * e + 3 * f, 4 * f
+    return n
+
+
+def _opts(m=0, nu1=2, nu2=2, smoother="jacobi", precision="mixed", max_cycles=200, n_c=0, l_c=-1,
+          omega=2.0 / 3.0, angle_tol=1e-7, seed=0):
+    o = SolveOpts()
+    _lib.bmg_solve_opts_default(C.byref(o))
+    o.m, o.nu1, o.nu2 = int(m), int(nu1), int(nu2)
+    o.smoother = SMOOTHERS[smoother]
+    o.precision = PRECISIONS[precision]
+    o.max_cycles, o.n_c, o.l_c = int(max_cycles), int(n_c), int(l_c)
+    o.omega, o.angle_tol, o.seed = float(omega), float(angle_tol), int(seed)
+    return o
+
+
+class Server:
+    """Continuous-batching server over bmg_server_* (see include/bmg.h)."""
+
+    def __init__(self, hbm_budget_bytes, max_slots=8):
+        s = C.c_void_p()
+        _check(_lib.bmg_server_create(int(hbm_budget_bytes), int(max_slots), C.byref(s)),
+               "bmg_server_create")
+        self._s = s
+        self._n = {}
+
+    def submit(self, kind="sphere", n_refine=3, k=8, sigma=0.0, tol=1e-8, axes=(1.0, 1.0, 1.0),
+               R=1.0, r=0.4, nu=64, nv=32, xyz=None, tri=None, project=None, **solve_opts):
+        """Queue one request; returns its id.  solve_opts as in Hierarchy.solve."""
+        d, keep = surface_desc(kind, axes, R, r, nu, nv, xyz, tri, project)
+        o = _opts(**solve_opts)
+        rid = C.c_uint64(0)
+        _check(_lib.bmg_server_submit(self._s, C.byref(d), int(n_refine), int(k), float(sigma),
+                                      float(tol), C.byref(o), C.byref(rid)), "bmg_server_submit")
+        nvtx = finest_vertices(kind, n_refine, nu, nv, d.n_vert, d.n_tri)
+        self._n[rid.value] = (int(k), nvtx, keep)
+        return rid.value
+
+    def poll(self, rid, evecs=True):
+        """None while the request runs; else a dict with status, evals, evecs
+        ([N, k] numpy or None), stats and latency_ms."""
+        k, n, _ = self._n[rid]
+        evals = np.zeros(k, np.float64)
+        V = np.zeros((k, n), np.float64) if evecs else None
+        rho = np.zeros(k, np.float64)
+        delta = np.zeros(k, np.float64)
+        st = SolveStats()
+        st.rho = rho.ctypes.data_as(C.POINTER(C.c_double))
+        st.delta = delta.ctypes.data_as(C.POINTER(C.c_double))
+        lat = C.c_double(0.0)
+        status = _lib.bmg_server_poll(self._s, C.c_uint64(rid), evals.ctypes.data_as(C.POINTER(C.c_double)),
+                                      None if V is None else V.ctypes.data_as(C.POINTER(C.c_double)),
+                                      int(n), C.byref(st), C.byref(lat))
+        if status == EBUSY:
+            return None
+        del self._n[rid]
+        stats = {f: getattr(st, f) for f, _ in SolveStats._fields_ if f not in ("rho", "delta")}
+        stats.update(rho=rho, delta=delta)
+        err = _lib.bmg_last_error().decode(errors="replace") if status != OK else ""
+        return dict(status=status, evals=evals, evecs=None if V is None else V.T, stats=stats,
+                    latency_ms=lat.value, error=err)
+
+    def wait(self, rid, evecs=True, poll_s=0.0005):
+        import time
+        while True:
+            res = self.poll(rid, evecs)
+            if res is not None:
+                return res
+            time.sleep(poll_s)
+
+    def cancel(self, rid):
+        _check(_lib.bmg_server_cancel(self._s, C.c_uint64(rid)), "bmg_server_cancel")
+
+    def close(self):
+        if getattr(self, "_s", None):
+            _lib.bmg_server_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
 def status_string(st):
     return _lib.bmg_status_string(int(st)).decode()

@@ -5,6 +5,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <mutex>
 #include <string>
@@ -111,6 +112,14 @@ namespace bmg {
 
 int upload_hierarchy(bmg_hierarchy* h, hipStream_t s);
 void free_device(bmg_hierarchy* h);
+// Solve workspaces pooled per hierarchy (solver.cpp): bytes held by the idle
+// ones, and freeing them.
+void free_workspaces(bmg_hierarchy* h);
+int64_t idle_workspace_bytes(bmg_hierarchy* h);
+void trim_idle_workspaces(bmg_hierarchy* h);
+int solve(bmg_hierarchy* h, int k, double sigma, double tol, const bmg_solve_opts* opts,
+          double* evals, double* evecs, int64_t ld, int evecs_on_device, void* stream,
+          bmg_solve_stats* stats);
 
 // ------------------------------------------------------------- launchers --
 // Kernel timing: a caller that wants the next launch timed sets `start` and
@@ -122,6 +131,9 @@ struct LaunchEvents {
   hipEvent_t start = nullptr, stop = nullptr;
 };
 extern thread_local LaunchEvents g_launch_events;
+// Set by a serving worker around a solve: the cycle loop stops with
+// BMG_ECANCELED when it reads nonzero.
+extern thread_local const std::atomic<int>* g_cancel;
 
 #define BMG_LAUNCH(kernel, grid, block, shmem, stream, ...)                                  \
   do {                                                                                       \

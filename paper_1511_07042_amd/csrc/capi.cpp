@@ -29,7 +29,6 @@ int solve(bmg_hierarchy* h, int k, double sigma, double tol, const bmg_solve_opt
           bmg_solve_stats* stats);
 int apply_vcycle(bmg_hierarchy* h, int level, int dtype, int m, double sigma, int smoother,
                  int nu1, int nu2, int l_c, double omega, const void* x, void* y, hipStream_t s);
-void free_workspaces(bmg_hierarchy* h);
 
 }  // namespace bmg
 

@@ -1,26 +1,487 @@
-// Continuous-batching server (placeholder until the grouped launcher lands).
+// Request-level continuous batching (serving).
+//
+// Independent eigenproblems (surface, refinement level, k, sigma, options) are
+// admitted against a device-memory budget and a slot count and then run
+// concurrently: every slot is a worker thread with its own HIP stream, and a
+// solve runs on a pooled workspace of its hierarchy with a stream of its own,
+// so the device interleaves the kernels of all active requests.  A request
+// that arrives while others run is admitted as soon as a slot is free and its
+// footprint fits beside the resident hierarchies, the pooled workspaces and
+// the active requests; smaller requests may pass a waiting larger one, a
+// bounded number of times.
+//
+// A request's result is the result of bmg_solve with the same arguments, bit
+// for bit: the kernels are deterministic and solves share only read-only
+// hierarchy data.  Hierarchies are built on first use and cached by surface
+// and level; idle workspaces and then idle hierarchies (least recently used
+// first) are freed when the budget needs their memory.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <thread>
+#include <vector>
+
 #include "bmg_internal.h"
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+enum ReqState { QUEUED, RUNNING, DONE };
+
+struct Request {
+  uint64_t id = 0;
+  bmg_surface_desc desc{};
+  std::vector<double> xyz;
+  std::vector<int32_t> tri;
+  int32_t n_refine = 0, k = 0;
+  double sigma = 0.0, tol = 0.0;
+  bmg_solve_opts opts{};
+  std::string key;
+  int64_t n_est = 0;   // finest-level vertices
+  int64_t need = 0;    // workspace bytes reserved while running
+  int64_t hier = 0;    // hierarchy bytes if it must be built
+  int bypassed = 0;    // times a later request was admitted before it
+  ReqState state = QUEUED;
+  std::atomic<int> cancel{0};
+  int status = BMG_OK;
+  std::string error;
+  int64_t N = 0;
+  std::vector<double> evals, evecs, rho, delta;
+  bmg_solve_stats stats{};
+  clk::time_point t_submit, t_done;
+};
+
+struct Cached {
+  bmg_hierarchy* h = nullptr;
+  int64_t bytes = 0;   // device bytes of the levels (estimate while building)
+  int users = 0;
+  bool building = false;
+  uint64_t last_use = 0;
+};
+
+// Coarse-mesh sizes (vertices, edges, triangles) of a surface description.
+void coarse_counts(const bmg_surface_desc& d, int64_t* n, int64_t* e, int64_t* f) {
+  if (d.kind == BMG_SPHERE || d.kind == BMG_ELLIPSOID) {
+    *n = 12, *e = 30, *f = 20;
+  } else if (d.kind == BMG_TORUS) {
+    *n = int64_t(d.nu) * d.nv, *e = 3 * *n, *f = 2 * *n;
+  } else {
+    *n = d.n_vert, *f = d.n_tri, *e = int64_t(d.n_tri) * 3 / 2;
+  }
+}
+
+// Per-level vertex counts of uniform refinement (every edge gains a midpoint,
+// every triangle splits into four).
+std::vector<int64_t> level_vertices(const bmg_surface_desc& d, int n_refine) {
+  int64_t n, e, f;
+  coarse_counts(d, &n, &e, &f);
+  std::vector<int64_t> v{n};
+  for (int l = 0; l < n_refine; ++l) {
+    n += e;
+    e = 2 * e + 3 * f;
+    f *= 4;
+    v.push_back(n);
+  }
+  return v;
+}
+
+// ELL row width assumed for footprints: valence 6 (+ diagonal) on the built-in
+// surfaces; a custom mesh may have vertices of valence up to 30.
+int ell_width(const bmg_surface_desc& d) { return d.kind == BMG_CUSTOM ? 31 : 7; }
+
+// Device bytes of a hierarchy: per level FP64 and FP32 values of A and M,
+// columns, lumped mass, colours and transfer tables.
+int64_t hierarchy_estimate(const bmg_surface_desc& d, int n_refine) {
+  const int W = ell_width(d);
+  int64_t b = 0;
+  for (int64_t n : level_vertices(d, n_refine)) b += n * (int64_t(W) * (2 * 8 + 2 * 4 + 4) + 64);
+  return b + (1 << 20);
+}
+
+// Device bytes of one solve's workspace (an upper bound of what the solver
+// allocates): FP64 W, AW, MW [N][n_c] and U, AU, MU [N][m]; per level e, f, t
+// [n_l][m] and the shifted operator [n_l][W] in the correction precision;
+// Gram partial sums (at most a quarter of the bytes the Gram kernel reads);
+// the LDS-tail image and small buffers.
+int64_t workspace_estimate(const bmg_surface_desc& d, int n_refine, int m, int n_c, int prec) {
+  const std::vector<int64_t> lv = level_vertices(d, n_refine);
+  const int64_t N = lv.back();
+  const int64_t vb = prec == BMG_MIXED ? 4 : 8;
+  int64_t b = 8 * N * (3 * int64_t(n_c) + 3 * int64_t(m));
+  for (int64_t n : lv) b += vb * n * (3 * int64_t(m) + ell_width(d));
+  b += 2 * N * (int64_t(n_c) + 3 * int64_t(m));
+  return b + 2 * (1 << 20);
+}
+
+// Finest-level vertex count and the device bytes of all levels.
+void hierarchy_totals(const bmg_hierarchy* h, int64_t* n_finest, int64_t* bytes) {
+  *n_finest = 0;
+  *bytes = 0;
+  bmg_level_info li{};
+  if (bmg_hierarchy_info(h, 0, &li) != BMG_OK) return;
+  const int nl = li.n_levels;
+  for (int l = 0; l < nl; ++l) {
+    if (bmg_hierarchy_info(h, l, &li) != BMG_OK) return;
+    *bytes += li.device_bytes;
+    *n_finest = li.n_vert;
+  }
+}
+
+std::string surface_key(const Request& r) {
+  std::ostringstream k;
+  const bmg_surface_desc& d = r.desc;
+  k.precision(17);
+  k << d.kind << '/' << r.n_refine << '/';
+  if (d.kind == BMG_ELLIPSOID) k << d.axes[0] << ',' << d.axes[1] << ',' << d.axes[2];
+  if (d.kind == BMG_TORUS) k << d.R << ',' << d.r << ',' << d.nu << ',' << d.nv;
+  if (d.kind == BMG_CUSTOM) {
+    // FNV-1a of the arrays, plus the projection callback, identify a custom surface
+    uint64_t hsh = 1469598103934665603ull;
+    auto mix = [&](const void* p, size_t n) {
+      const unsigned char* c = static_cast<const unsigned char*>(p);
+      for (size_t i = 0; i < n; ++i) hsh = (hsh ^ c[i]) * 1099511628211ull;
+    };
+    mix(r.xyz.data(), r.xyz.size() * sizeof(double));
+    mix(r.tri.data(), r.tri.size() * sizeof(int32_t));
+    k << std::hex << hsh << '/' << reinterpret_cast<uintptr_t>(d.project) << '/'
+      << reinterpret_cast<uintptr_t>(d.ctx);
+  }
+  return k.str();
+}
+
+// Sets the calling thread's cancel flag for the duration of a solve.
+struct CancelScope {
+  explicit CancelScope(const std::atomic<int>* f) { bmg::g_cancel = f; }
+  ~CancelScope() { bmg::g_cancel = nullptr; }
+};
+
+}  // namespace
+
+struct bmg_server {
+  int device = 0;
+  int64_t budget = 0;
+  int slots = 0;
+  std::mutex mu;
+  std::condition_variable cv;  // queue, admission, cache and completion changes
+  std::deque<uint64_t> queue;
+  std::map<uint64_t, std::unique_ptr<Request>> reqs;
+  std::map<std::string, Cached> cache;
+  int64_t active_bytes = 0;
+  int running = 0;
+  uint64_t next_id = 1, tick = 0;
+  bool stopping = false;
+  std::vector<std::thread> workers;
+
+  // ---- everything below runs with mu held
+  // Device bytes held now: cached hierarchies, their idle pooled workspaces,
+  // and the workspaces reserved by running requests.
+  int64_t resident() {
+    int64_t b = active_bytes;
+    for (auto& kv : cache) {
+      b += kv.second.bytes;
+      if (kv.second.h) b += bmg::idle_workspace_bytes(kv.second.h);
+    }
+    return b;
+  }
+  int64_t cost(const Request& r) const {
+    return r.need + (cache.count(r.key) ? 0 : r.hier);
+  }
+  // Free idle workspaces, then idle hierarchies other than `keep` (least
+  // recently used first), until `need` more bytes fit.
+  void make_room(int64_t need, const std::string& keep) {
+    if (resident() + need <= budget) return;
+    for (auto& kv : cache)
+      if (kv.second.h) bmg::trim_idle_workspaces(kv.second.h);
+    while (resident() + need > budget) {
+      auto victim = cache.end();
+      for (auto it = cache.begin(); it != cache.end(); ++it)
+        if (it->second.users == 0 && !it->second.building && it->first != keep &&
+            (victim == cache.end() || it->second.last_use < victim->second.last_use))
+          victim = it;
+      if (victim == cache.end()) return;
+      bmg_free_hierarchy(victim->second.h);
+      cache.erase(victim);
+    }
+  }
+  // The next request to start, or nullptr.  First fit in arrival order; once
+  // the head of the queue has been passed 4 * slots times only it may start.
+  Request* admit() {
+    if (running >= slots || queue.empty()) return nullptr;
+    Request& head = *reqs.at(queue.front());
+    const bool head_only = head.bypassed >= 4 * slots;
+    for (size_t i = 0; i < queue.size(); ++i) {
+      Request& r = *reqs.at(queue[i]);
+      const int64_t c = cost(r);
+      make_room(c, r.key);
+      if (resident() + c <= budget || running == 0) {
+        if (i > 0) head.bypassed += 1;
+        queue.erase(queue.begin() + i);
+        return &r;
+      }
+      if (head_only) break;
+    }
+    return nullptr;
+  }
+
+  void finish(Request* r, int st) {
+    r->stats.rho = nullptr;
+    r->stats.delta = nullptr;
+    r->status = st;
+    r->state = DONE;
+    r->t_done = clk::now();
+    cv.notify_all();
+  }
+
+  // Finds or builds the request's hierarchy; returns it with one more user.
+  int acquire_hierarchy(Request* r, hipStream_t stream, std::unique_lock<std::mutex>& lk,
+                        bmg_hierarchy** out) {
+    for (;;) {
+      auto it = cache.find(r->key);
+      if (it != cache.end() && it->second.building) {
+        cv.wait(lk);
+        continue;
+      }
+      if (it != cache.end()) {
+        it->second.users += 1;
+        it->second.last_use = ++tick;
+        *out = it->second.h;
+        return BMG_OK;
+      }
+      Cached& c = cache[r->key];
+      c.building = true;
+      c.bytes = r->hier;
+      lk.unlock();
+      bmg_surface_desc d = r->desc;
+      if (d.kind == BMG_CUSTOM) {
+        d.xyz = r->xyz.data();
+        d.tri = r->tri.data();
+      }
+      bmg_hierarchy* nh = nullptr;
+      const int st = stream ? bmg_build_hierarchy(&d, r->n_refine, stream, &nh) : BMG_EDEVICE;
+      const std::string err = st == BMG_OK ? "" : bmg_last_error();
+      int64_t bytes = 0, nf = 0;
+      if (st == BMG_OK) hierarchy_totals(nh, &nf, &bytes);
+      lk.lock();
+      Cached& c2 = cache[r->key];
+      c2.building = false;
+      cv.notify_all();
+      if (st != BMG_OK) {
+        cache.erase(r->key);
+        r->error = err.empty() ? "hierarchy build failed" : err;
+        return st;
+      }
+      c2.h = nh;
+      c2.bytes = bytes;
+    }
+  }
+
+  void worker_main() {
+    hipStream_t stream = nullptr;
+    if (hipSetDevice(device) != hipSuccess ||
+        hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      stream = nullptr;
+    }
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+      Request* r = nullptr;
+      while (!(stopping && queue.empty()) && (r = admit()) == nullptr) cv.wait(lk);
+      if (r == nullptr) break;
+      r->state = RUNNING;
+      active_bytes += r->need;
+      ++running;
+      bmg_hierarchy* h = nullptr;
+      int st = acquire_hierarchy(r, stream, lk, &h);
+      if (st == BMG_OK) {
+        lk.unlock();
+        int64_t nf = 0, hb = 0;
+        hierarchy_totals(h, &nf, &hb);
+        r->N = nf;
+        r->evals.assign(r->k, 0.0);
+        r->evecs.assign(size_t(r->N) * r->k, 0.0);
+        r->rho.assign(r->k, 0.0);
+        r->delta.assign(r->k, 0.0);
+        r->stats.rho = r->rho.data();
+        r->stats.delta = r->delta.data();
+        {
+          CancelScope scope(&r->cancel);
+          st = bmg::solve(h, r->k, r->sigma, r->tol, &r->opts, r->evals.data(), r->evecs.data(),
+                          r->N, 0, stream, &r->stats);
+        }
+        if (st != BMG_OK) r->error = bmg_last_error();
+        lk.lock();
+        auto it = cache.find(r->key);
+        if (it != cache.end()) {
+          it->second.users -= 1;
+          it->second.last_use = ++tick;
+        }
+      }
+      active_bytes -= r->need;
+      --running;
+      finish(r, st);
+    }
+    lk.unlock();
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+};
 
 extern "C" {
 
-int bmg_server_create(int64_t, int32_t, bmg_server** out) {
-  if (out) *out = nullptr;
-  bmg::set_error("serving is not available in this build");
-  return BMG_EINVAL;
+int bmg_server_create(int64_t hbm_budget_bytes, int32_t max_slots, bmg_server** out) {
+  BMG_CHECK(out != nullptr, "out must be non-NULL");
+  *out = nullptr;
+  BMG_CHECK(hbm_budget_bytes > 0, "the memory budget must be positive");
+  BMG_CHECK(max_slots >= 1 && max_slots <= 64, "max_slots must be in [1, 64]");
+  int dev = 0, n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n < 1 || hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    bmg::set_error("no HIP device");
+    return BMG_EDEVICE;
+  }
+  auto* s = new (std::nothrow) bmg_server();
+  if (!s) return BMG_ENOMEM;
+  s->device = dev;
+  s->budget = hbm_budget_bytes;
+  s->slots = max_slots;
+  for (int i = 0; i < max_slots; ++i) s->workers.emplace_back([s] { s->worker_main(); });
+  *out = s;
+  return BMG_OK;
 }
-int bmg_server_submit(bmg_server*, const bmg_surface_desc*, int32_t, int32_t, double, double,
-                      const bmg_solve_opts*, uint64_t*) {
-  bmg::set_error("serving is not available in this build");
-  return BMG_EINVAL;
-}
-int bmg_server_poll(bmg_server*, uint64_t, double*, double*, int64_t, bmg_solve_stats*, double*) {
-  bmg::set_error("serving is not available in this build");
-  return BMG_EINVAL;
-}
-int bmg_server_cancel(bmg_server*, uint64_t) {
-  bmg::set_error("serving is not available in this build");
-  return BMG_EINVAL;
-}
-void bmg_server_destroy(bmg_server*) {}
 
+int bmg_server_submit(bmg_server* s, const bmg_surface_desc* desc, int32_t n_refine, int32_t k,
+                      double sigma, double tol, const bmg_solve_opts* opts, uint64_t* request_id) {
+  BMG_CHECK(s && desc && request_id, "NULL argument");
+  BMG_CHECK(n_refine >= 0 && n_refine <= 10, "n_refine must be in [0, 10]");
+  BMG_CHECK(k >= 1, "k must be >= 1");
+  BMG_CHECK(std::isfinite(sigma), "sigma must be finite");
+  BMG_CHECK(tol > 0 && std::isfinite(tol), "tol must be positive and finite");
+  BMG_CHECK(desc->kind >= BMG_SPHERE && desc->kind <= BMG_CUSTOM, "unknown surface kind");
+  if (desc->kind == BMG_TORUS) BMG_CHECK(desc->nu >= 3 && desc->nv >= 3, "torus grid too small");
+  auto r = std::make_unique<Request>();
+  r->desc = *desc;
+  r->desc.xyz = nullptr;
+  r->desc.tri = nullptr;
+  if (desc->kind == BMG_CUSTOM) {
+    BMG_CHECK(desc->xyz && desc->tri && desc->n_vert > 0 && desc->n_tri > 0,
+              "custom mesh arrays missing");
+    r->xyz.assign(desc->xyz, desc->xyz + 3 * int64_t(desc->n_vert));
+    r->tri.assign(desc->tri, desc->tri + 3 * int64_t(desc->n_tri));
+  }
+  r->n_refine = n_refine;
+  r->k = k;
+  r->sigma = sigma;
+  r->tol = tol;
+  bmg_solve_opts_default(&r->opts);
+  if (opts) r->opts = *opts;
+  r->opts.initial_block = nullptr;  // not kept: the caller's pointer dies with the call
+  r->opts.timed_kernel = -1;
+  if (r->opts.m <= 0) {
+    const double fac = sigma == 0.0 ? 1.25 : 1.5;
+    r->opts.m = 4 * int(std::ceil(fac * k / 4.0));
+  }
+  int64_t n0, e0, f0;
+  coarse_counts(r->desc, &n0, &e0, &f0);
+  const int n_c = r->opts.n_c > 0 ? r->opts.n_c : int(std::min<int64_t>(n0, 32));
+  r->key = surface_key(*r);
+  r->n_est = level_vertices(r->desc, n_refine).back();
+  r->hier = hierarchy_estimate(r->desc, n_refine);
+  r->need = workspace_estimate(r->desc, n_refine, r->opts.m, n_c, r->opts.precision);
+  BMG_CHECK(r->opts.m >= k && int64_t(r->opts.m) <= r->n_est / 2, "m must be in [k, N_L / 2]");
+  std::lock_guard<std::mutex> g(s->mu);
+  BMG_CHECK(!s->stopping, "the server is shutting down");
+  if (r->need + r->hier > s->budget) {
+    bmg::set_error("request needs about %lld bytes; the budget is %lld",
+                   (long long)(r->need + r->hier), (long long)s->budget);
+    return BMG_ENOMEM;
+  }
+  r->id = s->next_id++;
+  r->t_submit = clk::now();
+  *request_id = r->id;
+  s->queue.push_back(r->id);
+  s->reqs[r->id] = std::move(r);
+  s->cv.notify_all();
+  return BMG_OK;
 }
+
+int bmg_server_poll(bmg_server* s, uint64_t request_id, double* evals, double* evecs, int64_t ld,
+                    bmg_solve_stats* stats, double* latency_ms) {
+  BMG_CHECK(s != nullptr, "NULL server");
+  std::unique_ptr<Request> r;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->reqs.find(request_id);
+    BMG_CHECK(it != s->reqs.end(), "unknown request id %llu", (unsigned long long)request_id);
+    if (it->second->state != DONE) return BMG_EBUSY;
+    Request& q = *it->second;
+    if (evecs && !q.evecs.empty() && ld < q.N) {
+      bmg::set_error("ld = %lld must be >= N_L = %lld", (long long)ld, (long long)q.N);
+      return BMG_EINVAL;
+    }
+    r = std::move(it->second);
+    s->reqs.erase(it);
+  }
+  if (evals && !r->evals.empty()) std::memcpy(evals, r->evals.data(), sizeof(double) * r->k);
+  if (evecs && !r->evecs.empty())
+    for (int j = 0; j < r->k; ++j)
+      std::memcpy(evecs + int64_t(j) * ld, r->evecs.data() + int64_t(j) * r->N,
+                  sizeof(double) * r->N);
+  if (stats) {
+    double* rho = stats->rho;
+    double* delta = stats->delta;
+    *stats = r->stats;
+    stats->rho = rho;
+    stats->delta = delta;
+    if (rho && !r->rho.empty()) std::memcpy(rho, r->rho.data(), sizeof(double) * r->k);
+    if (delta && !r->delta.empty()) std::memcpy(delta, r->delta.data(), sizeof(double) * r->k);
+  }
+  if (latency_ms)
+    *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+  if (r->status != BMG_OK) bmg::set_error("%s", r->error.c_str());
+  return r->status;
+}
+
+int bmg_server_cancel(bmg_server* s, uint64_t request_id) {
+  BMG_CHECK(s != nullptr, "NULL server");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->reqs.find(request_id);
+  BMG_CHECK(it != s->reqs.end(), "unknown request id %llu", (unsigned long long)request_id);
+  Request& r = *it->second;
+  if (r.state == QUEUED) {
+    s->queue.erase(std::remove(s->queue.begin(), s->queue.end(), request_id), s->queue.end());
+    r.error = "canceled before it started";
+    s->finish(&r, BMG_ECANCELED);
+  } else if (r.state == RUNNING) {
+    r.cancel.store(1);
+  }
+  return BMG_OK;
+}
+
+void bmg_server_destroy(bmg_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stopping = true;
+    for (uint64_t id : s->queue) {
+      Request& r = *s->reqs.at(id);
+      r.error = "server destroyed before the request started";
+      s->finish(&r, BMG_ECANCELED);
+    }
+    s->queue.clear();
+    s->cv.notify_all();
+  }
+  for (auto& t : s->workers) t.join();
+  for (auto& kv : s->cache)
+    if (kv.second.h) bmg_free_hierarchy(kv.second.h);
+  delete s;
+}
+
+}  // extern "C"

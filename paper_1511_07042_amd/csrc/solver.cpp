@@ -54,11 +54,13 @@ struct bmg_workspace {
   int nblk_res = 0, nblk_arg = 0;
   bmg::GramPlan gp{}, gpw{};
   std::vector<void*> allocs;
+  int64_t bytes = 0;  // device bytes held by allocs
 };
 
 namespace bmg {
 
 thread_local LaunchEvents g_launch_events;
+thread_local const std::atomic<int>* g_cancel = nullptr;
 
 namespace {
 
@@ -71,6 +73,7 @@ int dalloc(bmg_workspace* w, void** p, size_t bytes) {
     return BMG_ENOMEM;
   }
   w->allocs.push_back(*p);
+  w->bytes += int64_t(bytes);
   return BMG_OK;
 }
 
@@ -204,6 +207,26 @@ void free_workspaces(bmg_hierarchy* h) {
   std::lock_guard<std::mutex> g(h->ws_mutex);
   for (auto* w : h->ws_pool) free_workspace(w);
   h->ws_pool.clear();
+}
+
+int64_t idle_workspace_bytes(bmg_hierarchy* h) {
+  std::lock_guard<std::mutex> g(h->ws_mutex);
+  int64_t b = 0;
+  for (auto* w : h->ws_pool)
+    if (!w->busy) b += w->bytes;
+  return b;
+}
+
+void trim_idle_workspaces(bmg_hierarchy* h) {
+  std::lock_guard<std::mutex> g(h->ws_mutex);
+  std::vector<bmg_workspace*> keep;
+  for (auto* w : h->ws_pool) {
+    if (w->busy)
+      keep.push_back(w);
+    else
+      free_workspace(w);
+  }
+  h->ws_pool.swap(keep);
 }
 
 // ----------------------------------------------------------- kernel timer --
@@ -767,6 +790,11 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     }
     cert = certify(theta, rho2, sigma, k, tol, o.angle_tol);
     if (cert.ok) break;
+    if (g_cancel && g_cancel->load(std::memory_order_relaxed)) {
+      status = BMG_ECANCELED;
+      set_error("canceled after %d cycles", cycles);
+      break;
+    }
     if (cycles >= o.max_cycles) {
       status = BMG_ENOCONV;
       set_error("no convergence in %d cycles", o.max_cycles);

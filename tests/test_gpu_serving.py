@@ -1,0 +1,119 @@
+"""Serving (continuous batching) through the C ABI: requests that arrive while
+others run are admitted as slots and memory free up, run concurrently, and
+each result equals the result of the same solve alone, bit for bit."""
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+# mixed surfaces, levels, k, shifts, precisions and smoothers; two requests
+# share a hierarchy (and run on it concurrently)
+REQUESTS = [
+    dict(kind="sphere", n_refine=3, k=9, sigma=0.0, m=12, precision="mixed", smoother="jacobi", seed=0),
+    dict(kind="sphere", n_refine=4, k=16, sigma=0.0, m=20, precision="fp64", smoother="gs", seed=1),
+    dict(kind="ellipsoid", n_refine=3, k=8, sigma=0.0, axes=(1.2, 1.5, 1.9), precision="mixed",
+         smoother="jacobi", seed=2),
+    dict(kind="sphere", n_refine=4, k=5, sigma=6.0, m=12, precision="mixed", smoother="gs", seed=3),
+    dict(kind="ellipsoid", n_refine=4, k=12, sigma=0.0, axes=(1.0, 1.5, 2.0), precision="fp64",
+         smoother="jacobi", seed=4),
+    dict(kind="sphere", n_refine=3, k=9, sigma=0.0, m=12, precision="mixed", smoother="jacobi", seed=5),
+    dict(kind="sphere", n_refine=5, k=25, sigma=0.0, m=32, precision="mixed", smoother="jacobi", seed=6),
+]
+
+SURF = ("kind", "n_refine", "axes")
+SOLVE = ("m", "precision", "smoother", "seed")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1511_07042_amd as p
+    return p
+
+
+def _alone(lib, req):
+    with lib.Hierarchy(req["kind"], req["n_refine"], axes=req.get("axes", (1.0, 1.0, 1.0))) as h:
+        kw = {k: req[k] for k in SOLVE if k in req}
+        return h.solve(req["k"], req["sigma"], 1e-8, **kw)
+
+
+def _submit(lib, srv, req):
+    kw = {k: req[k] for k in SOLVE if k in req}
+    return srv.submit(req["kind"], req["n_refine"], req["k"], req["sigma"], 1e-8,
+                      axes=req.get("axes", (1.0, 1.0, 1.0)), **kw)
+
+
+def _same(res, alone, what):
+    ev, V, st = alone
+    assert res["status"] == 0, (what, res["error"])
+    assert res["stats"]["cycles"] == st["cycles"], what
+    assert np.array_equal(res["evals"], ev), (what, np.max(np.abs(res["evals"] - ev)))
+    assert np.array_equal(res["evecs"], V), (what, np.max(np.abs(res["evecs"] - V)))
+
+
+def test_mix_equals_alone(lib):
+    alone = [_alone(lib, r) for r in REQUESTS]
+    with lib.Server(8 << 30, max_slots=4) as srv:
+        ids = [_submit(lib, srv, r) for r in REQUESTS[:3]]
+        # later arrivals: submitted while the first ones are queued or running
+        time.sleep(0.002)
+        ids += [_submit(lib, srv, r) for r in REQUESTS[3:]]
+        res = [srv.wait(i) for i in ids]
+    lat = [r["latency_ms"] for r in res]
+    print("latencies ms:", [round(x, 1) for x in lat])
+    for i, (r, a) in enumerate(zip(res, alone)):
+        _same(r, a, i)
+        assert r["stats"]["converged"] == 1 and r["latency_ms"] > 0
+
+
+def test_tight_budget_evicts_and_still_matches(lib):
+    # a budget that holds about one problem at a time: requests wait for memory,
+    # idle hierarchies and workspaces are freed, results do not change
+    reqs = [REQUESTS[0], REQUESTS[2], REQUESTS[0], REQUESTS[1]]
+    alone = [_alone(lib, r) for r in reqs]
+    with lib.Server(10 << 20, max_slots=3) as srv:
+        ids = [_submit(lib, srv, r) for r in reqs]
+        res = [srv.wait(i) for i in ids]
+    for i, (r, a) in enumerate(zip(res, alone)):
+        _same(r, a, i)
+
+
+def test_cancel_enomem_and_errors(lib):
+    with lib.Server(8 << 30, max_slots=1) as srv:
+        # the single slot is busy with a long request; a queued one is canceled
+        # at once, the running one at the end of its current cycle
+        # an unreachable certificate keeps it cycling until canceled
+        long_id = srv.submit("sphere", 5, 25, 0.0, 1e-300, m=32, max_cycles=100000,
+                             angle_tol=1e-300)
+        queued = srv.submit("sphere", 3, 9, 0.0, 1e-8, m=12)
+        srv.cancel(queued)
+        r = srv.wait(queued)
+        assert r["status"] == lib.ECANCELED
+        time.sleep(0.05)
+        srv.cancel(long_id)
+        r = srv.wait(long_id)
+        assert r["status"] == lib.ECANCELED and r["stats"]["cycles"] >= 1
+        # unknown ids and invalid requests
+        with pytest.raises(lib.BMGError) as e:
+            srv.cancel(123456)
+        assert e.value.status == lib.EINVAL
+        with pytest.raises(lib.BMGError) as e:
+            srv.submit("sphere", 3, 0)
+        assert e.value.status == lib.EINVAL
+        # the server still serves after all that
+        rid = srv.submit("sphere", 3, 9, 0.0, 1e-8, m=12, seed=0, smoother="jacobi",
+                         precision="mixed")
+        _same(srv.wait(rid), _alone(lib, REQUESTS[0]), "after-cancel")
+    with lib.Server(1 << 20, max_slots=2) as srv:
+        with pytest.raises(lib.BMGError) as e:
+            srv.submit("sphere", 5, 25, m=32)
+        assert e.value.status == lib.ENOMEM
+
+
+def test_poll_busy_then_done(lib):
+    with lib.Server(8 << 30, max_slots=2) as srv:
+        rid = srv.submit("sphere", 5, 25, 0.0, 1e-8, m=32)
+        assert srv.poll(rid) is None  # still queued or running right after submit
+        r = srv.wait(rid)
+        assert r["status"] == lib.OK and r["evecs"].shape == (10 * 4 ** 5 + 2, 25)

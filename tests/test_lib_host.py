@@ -116,3 +116,26 @@ def test_invalid_inputs_rejected(lib):
     h = lib.Hierarchy("sphere", 1, device=False)
     with pytest.raises(lib.BMGError):  # host-only hierarchy cannot solve
         h.solve(3)
+
+
+def test_server_arguments_and_missing_device(lib):
+    # argument checks come first; with no GPU visible a valid call reports
+    # BMG_EDEVICE instead of queueing work that could never run
+    import torch
+    with pytest.raises(lib.BMGError) as e:
+        lib.Server(0, 4)
+    assert e.value.status == lib.EINVAL
+    with pytest.raises(lib.BMGError) as e:
+        lib.Server(1 << 30, 0)
+    assert e.value.status == lib.EINVAL
+    if not torch.cuda.is_available():
+        with pytest.raises(lib.BMGError) as e:
+            lib.Server(1 << 30, 4)
+        assert e.value.status == lib.EDEVICE
+
+
+@pytest.mark.parametrize("kind,nref,kw", [("sphere", 4, {}), ("torus", 2, dict(nu=64, nv=32)),
+                                          ("ellipsoid", 3, dict(axes=(1.0, 1.5, 2.0)))])
+def test_finest_vertex_formula(lib, kind, nref, kw):
+    h = lib.Hierarchy(kind, nref, device=False, **kw)
+    assert lib.finest_vertices(kind, nref, **{k: v for k, v in kw.items() if k in ("nu", "nv")}) == h.N
