@@ -246,8 +246,11 @@ typedef enum {
   BMG_OP_SYEV = 11,      /* x: symmetric [m][m] FP64; y: [m] eigenvalues ascending
                             followed by [m][m] row-major orthonormal eigenvectors
                             (column j = vector j); one-workgroup Jacobi, m <= 96 */
-  BMG_OP_EIGRES = 12     /* y = A_l x - (M_l x) diag(f), f: device [m] doubles;
+  BMG_OP_EIGRES = 12,    /* y = A_l x - (M_l x) diag(f), f: device [m] doubles;
                             (FP64 in, output in dtype)                           */
+  BMG_OP_UPDATE = 13     /* y [N_l][m] <- [x | y] f in place: x [N_l][m2] (NULL if
+                            m2 = 0), f = Y [m2 + m][m] row-major; the Ritz update
+                            U <- [W_c, U'] Y (FP64, matrix cores, m2 + m <= 96)  */
 } bmg_op;
 
 typedef struct {

@@ -341,6 +341,14 @@ int bmg_apply(const bmg_hierarchy* hc, const bmg_apply_args* a, const void* x, c
       return f32 ? launch_eigres<float>(D, (const double*)x, (const double*)f, 1.0, (float*)y, nullptr, eigres_blocks(D, m), m, s)
                  : launch_eigres<double>(D, (const double*)x, (const double*)f, 1.0, (double*)y, nullptr, eigres_blocks(D, m), m, s);
     }
+    case BMG_OP_UPDATE: {
+      BMG_CHECK(f && !f32, "UPDATE takes FP64 blocks and an FP64 Y in f");
+      BMG_CHECK(m >= 4 && m % 4 == 0 && m <= 96, "UPDATE needs m a multiple of 4 in [4, 96]");
+      BMG_CHECK(a->m2 >= 0 && a->m2 + m <= 96 && (a->m2 == 0 || x != nullptr),
+                "UPDATE needs 0 <= m2, m2 + m <= 96 and x when m2 > 0");
+      return launch_update_zy(D.n, (const double*)x, a->m2, (const double*)y, m, (const double*)f,
+                              (double*)y, m, s);
+    }
     default:
       BMG_CHECK(false, "unknown op %d", a->op);
   }

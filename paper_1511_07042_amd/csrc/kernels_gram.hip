@@ -117,40 +117,67 @@ __global__ void __launch_bounds__(1024) k_gram_reduce(const double* __restrict__
   }
 }
 
-// U[r][c] = sum_i Z[r][i] Y[i][c], Z = [z1 | z2].  Y and the block's rows of
-// Z are staged in LDS before any output is written, so U may alias z2 (the
-// update is done in place).  Thread per (row, 2 columns).
-__global__ void __launch_bounds__(256) k_update_zy(int64_t n, const double* __restrict__ z1, int w1,
+// U[r][c] = sum_i Z[r][i] Y[i][c], Z = [z1 | z2] (nz <= 96 columns), on the
+// FP64 matrix cores.  Y (zero-padded to KS*4 rows and TJ*16 columns) is staged
+// in LDS once per block; each wavefront owns 16-row tiles of Z.  For one tile a
+// lane loads its A fragments for every k step (row l % 16, column 4 s + l / 16)
+// into registers, the wavefront runs KS x TJ MFMAs with B fragments read from
+// LDS, and then writes the tile's 16 x m outputs.  A tile is read completely
+// before any of its outputs is written and no other wavefront touches its rows,
+// so U may alias z2 (the update is done in place).
+constexpr int kUpdKMax = 24;  // k steps of 4: nz <= 96
+
+template <int TJ>
+__global__ void __launch_bounds__(256) k_update_zy(int64_t n, const double* z1, int w1,
                                                    const double* z2, int w2,
-                                                   const double* __restrict__ Y, int m, int cpr,
-                                                   int rpb, double* U) {
-  extern __shared__ double ys[];
+                                                   const double* __restrict__ Y, int m, int ks,
+                                                   double* U) {
+  extern __shared__ double ys[];  // [ks * 4][TJ * 16]
+  constexpr int MP = TJ * 16;
   const int nz = w1 + w2;
-  double* zs = ys + nz * m;  // [rpb][nz]
-  for (int e = threadIdx.x; e < nz * m; e += blockDim.x) ys[e] = Y[e];
-  const int rloc = threadIdx.x / cpr;
-  const int ch = threadIdx.x - rloc * cpr;
-  for (int64_t r0 = int64_t(blockIdx.x) * rpb; r0 < n; r0 += int64_t(gridDim.x) * rpb) {
-    __syncthreads();  // previous rows consumed (and Y staged on the first pass)
-    for (int e = threadIdx.x; e < rpb * nz; e += blockDim.x) {
-      const int q = e / nz, i = e - (e / nz) * nz;
-      const int64_t r = r0 + q;
-      double v = 0.0;
-      if (r < n) v = i < w1 ? z1[r * w1 + i] : z2[r * w2 + (i - w1)];
-      zs[e] = v;
+  for (int e = threadIdx.x; e < ks * 4 * MP; e += blockDim.x) {
+    const int i = e / MP, c = e - (e / MP) * MP;
+    ys[e] = (i < nz && c < m) ? Y[i * m + c] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t tiles = (n + 15) / 16;
+  const int64_t wstride = int64_t(gridDim.x) * (blockDim.x >> 6);
+  for (int64_t tile = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); tile < tiles;
+       tile += wstride) {
+    const int64_t r = tile * 16 + li;
+    // this lane's row of z1 and of z2, indexed by the column c of Z
+    const double* p1 = z1 + (r < n ? r : 0) * w1;
+    const double* p2 = z2 + (r < n ? r : 0) * w2 - w1;
+    const bool live = r < n;
+    double a[kUpdKMax];
+#pragma unroll
+    for (int s = 0; s < kUpdKMax; ++s) {
+      const int c = 4 * s + lk;
+      a[s] = (live && c < w1) ? p1[c] : ((live && c >= w1 && c < nz) ? p2[c] : 0.0);
     }
-    __syncthreads();
-    const int64_t r = r0 + rloc;
-    if (rloc < rpb && r < n) {
-      double c0 = 0.0, c1 = 0.0;
-      const double* zr = zs + rloc * nz;
-      for (int i = 0; i < nz; ++i) {
-        const double z = zr[i];
-        c0 += z * ys[i * m + 2 * ch];
-        c1 += z * ys[i * m + 2 * ch + 1];
+    d4 acc[TJ];
+#pragma unroll
+    for (int t = 0; t < TJ; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < kUpdKMax; ++s) {
+      if (s < ks) {
+        const double* yrow = ys + (4 * s + lk) * MP + li;
+#pragma unroll
+        for (int t = 0; t < TJ; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], yrow[16 * t], acc[t], 0, 0, 0);
       }
-      U[r * m + 2 * ch] = c0;
-      U[r * m + 2 * ch + 1] = c1;
+    }
+#pragma unroll
+    for (int t = 0; t < TJ; ++t) {
+      const int c = 16 * t + li;
+      if (c >= m) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = tile * 16 + lk + 4 * v;
+        if (row < n) U[row * m + c] = acc[t][v];
+      }
     }
   }
 }
@@ -228,19 +255,34 @@ int launch_gram(const GramPlan& p, int64_t n, const double* z1, int w1, const do
 
 int launch_update_zy(int64_t n, const double* z1, int w1, const double* z2, int w2,
                      const double* Y, double* U, int m, hipStream_t s) {
-  const int cpr = m / 2;
-  const int rpb = cpr >= 256 ? 1 : 256 / cpr;
-  const int block = rpb * cpr;
-  int64_t groups = (n + rpb - 1) / rpb;
-  const int grid = int(groups < 4096 ? groups : 4096);
-  const size_t shm = size_t(w1 + w2) * (m + rpb) * sizeof(double);
+  const int nz = w1 + w2;
+  const int ks = (nz + 3) / 4;
+  const int TJ = (m + 15) / 16;
+  if (ks < 1 || ks > kUpdKMax || TJ < 1 || TJ > 6 || m % 4 != 0) {
+    set_error("update: unsupported shape nz=%d m=%d", nz, m);
+    return BMG_EINVAL;
+  }
+  const size_t shm = size_t(ks) * 4 * TJ * 16 * sizeof(double);
+  const int64_t tiles = (n + 15) / 16;
+  const int grid = int(std::min<int64_t>((tiles + 3) / 4, 512));
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_update_zy, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        160 * 1024);
+    (void)hipFuncSetAttribute((const void*)k_update_zy<5>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              96 * 1024);
+    (void)hipFuncSetAttribute((const void*)k_update_zy<6>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              96 * 1024);
     attr_set = true;
   }
-  BMG_LAUNCH((k_update_zy), grid, block, shm, s, n, z1, w1, z2, w2, Y, m, cpr, rpb, U);
+#define UL(tj) BMG_LAUNCH((k_update_zy<tj>), grid, 256, shm, s, n, z1, w1, z2, w2, Y, m, ks, U)
+  switch (TJ) {
+    case 1: UL(1); break;
+    case 2: UL(2); break;
+    case 3: UL(3); break;
+    case 4: UL(4); break;
+    case 5: UL(5); break;
+    default: UL(6); break;
+  }
+#undef UL
   return check_launch();
 }
 

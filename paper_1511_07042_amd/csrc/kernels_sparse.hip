@@ -53,85 +53,99 @@ int check_launch() {
   return BMG_OK;
 }
 
+// Neighbour gather of one ELL row: acc = sum_k S[base+k] x[cols[base+k]][off..]
+// and xr = x[row][off..] (slot 0 is the diagonal).  With WT > 0 the width is a
+// compile-time constant: every column index and value is loaded first, then
+// every x segment, so a thread has all 2 WT loads of the row in flight at once.
+template <typename T, int WT>
+__device__ __forceinline__ void row_gather(const int* __restrict__ cols, const T* __restrict__ S,
+                                           int64_t base, int W, const T* __restrict__ x, int m,
+                                           int off, Vec<T>& acc, Vec<T>& xr) {
+  constexpr int VW = Vec<T>::N;
+  for (int c = 0; c < VW; ++c) acc.v[c] = T(0);
+  if (WT > 0) {
+    int j[WT > 0 ? WT : 1];
+    T sv[WT > 0 ? WT : 1];
+    Vec<T> xv[WT > 0 ? WT : 1];
+#pragma unroll
+    for (int k = 0; k < WT; ++k) {
+      j[k] = cols[base + k];
+      sv[k] = S[base + k];
+    }
+#pragma unroll
+    for (int k = 0; k < WT; ++k) xv[k] = ld(x + int64_t(j[k]) * m + off);
+#pragma unroll
+    for (int k = 0; k < WT; ++k)
+      for (int c = 0; c < VW; ++c) acc.v[c] += sv[k] * xv[k].v[c];
+    xr = xv[0];
+  } else {
+    for (int k = 0; k < W; ++k) {
+      const int jj = cols[base + k];
+      const T s = S[base + k];
+      const Vec<T> v = ld(x + int64_t(jj) * m + off);
+      if (k == 0) xr = v;
+      for (int c = 0; c < VW; ++c) acc.v[c] += s * v.v[c];
+    }
+  }
+}
+
 // ---------------------------------------------------------- shifted ops --
 enum { K_SHIFTED = 0, K_RESIDUAL = 1, K_JACOBI = 2, K_JACOBI0 = 3 };
 
 // MODE K_SHIFTED: y = S x; K_RESIDUAL: y = f - S x;
 // K_JACOBI: y = x + omega (f - S x) / d; K_JACOBI0: y = omega f / d  (x = 0),
 // with S = A - sigma M (precomputed once per solve) and d = S_ii.
-// FUSE: also u[r] += y[r] (FP64 iterate update on the last sweep).
-template <typename T, int MODE, bool FUSE>
+// WT: ELL width when it is the built-in 7, else 0 (runtime W).
+template <typename T, int MODE, int WT>
 __global__ void __launch_bounds__(256) k_rowop(int64_t n, int W, int m, int cpr, int rpb,
                                                const int* __restrict__ cols,
                                                const T* __restrict__ S, T omega,
                                                const T* __restrict__ x,
-                                               const T* __restrict__ f, T* __restrict__ y,
-                                               double* __restrict__ u) {
+                                               const T* __restrict__ f, T* __restrict__ y) {
   constexpr int VW = Vec<T>::N;
   const int rloc = threadIdx.x / cpr;
   const int ch = threadIdx.x - rloc * cpr;
+  if (rloc >= rpb) return;
   for (int64_t r = int64_t(blockIdx.x) * rpb + rloc; r < n; r += int64_t(gridDim.x) * rpb) {
     const int64_t base = r * W;
     Vec<T> acc, xr;
-    for (int c = 0; c < VW; ++c) acc.v[c] = T(0);
-    T d = S[base];
+    const T d = S[base];
     if (MODE == K_JACOBI0) {
       const Vec<T> fv = ld(f + r * m + ch * VW);
       for (int c = 0; c < VW; ++c) acc.v[c] = omega * fv.v[c] / d;
     } else {
-      for (int k = 0; k < W; ++k) {
-        const int j = cols[base + k];
-        const T s = S[base + k];
-        const Vec<T> xv = ld(x + int64_t(j) * m + ch * VW);
-        if (k == 0) xr = xv;
-        for (int c = 0; c < VW; ++c) acc.v[c] += s * xv.v[c];
-      }
-      if (MODE == K_RESIDUAL || MODE == K_JACOBI) {
-        const Vec<T> fv = ld(f + r * m + ch * VW);
+      Vec<T> fv;
+      if (MODE == K_RESIDUAL || MODE == K_JACOBI) fv = ld(f + r * m + ch * VW);
+      row_gather<T, WT>(cols, S, base, W, x, m, ch * VW, acc, xr);
+      if (MODE == K_RESIDUAL || MODE == K_JACOBI)
         for (int c = 0; c < VW; ++c) acc.v[c] = fv.v[c] - acc.v[c];
-      }
       if (MODE == K_JACOBI)
         for (int c = 0; c < VW; ++c) acc.v[c] = xr.v[c] + omega * acc.v[c] / d;
     }
     st(y + r * m + ch * VW, acc);
-    if (FUSE) {
-      double* up = u + r * m + ch * VW;
-      for (int c = 0; c < VW; ++c) up[c] += double(acc.v[c]);
-    }
   }
 }
 
 // Gauss-Seidel update of the rows of one colour, in place:
 // x_r <- x_r + (f_r - (S x)_r) / S_rr.  Rows of one colour are never adjacent,
 // so the rows of a pass are independent.
-template <typename T, bool FUSE>
+template <typename T, int WT>
 __global__ void __launch_bounds__(256) k_gs(int64_t cnt, const int* __restrict__ rows, int W, int m,
                                             int cpr, int rpb, const int* __restrict__ cols,
-                                            const T* __restrict__ S, T* x, const T* __restrict__ f,
-                                            double* __restrict__ u) {
+                                            const T* __restrict__ S, T* x, const T* __restrict__ f) {
   constexpr int VW = Vec<T>::N;
   const int rloc = threadIdx.x / cpr;
   const int ch = threadIdx.x - rloc * cpr;
+  if (rloc >= rpb) return;
   for (int64_t i = int64_t(blockIdx.x) * rpb + rloc; i < cnt; i += int64_t(gridDim.x) * rpb) {
     const int64_t r = rows[i];
     const int64_t base = r * W;
     Vec<T> acc, xr;
-    for (int c = 0; c < VW; ++c) acc.v[c] = T(0);
     const T d = S[base];
-    for (int k = 0; k < W; ++k) {
-      const int j = cols[base + k];
-      const T s = S[base + k];
-      const Vec<T> xv = ld(x + int64_t(j) * m + ch * VW);
-      if (k == 0) xr = xv;
-      for (int c = 0; c < VW; ++c) acc.v[c] += s * xv.v[c];
-    }
     const Vec<T> fv = ld(f + r * m + ch * VW);
+    row_gather<T, WT>(cols, S, base, W, x, m, ch * VW, acc, xr);
     for (int c = 0; c < VW; ++c) xr.v[c] += (fv.v[c] - acc.v[c]) / d;
     st(x + r * m + ch * VW, xr);
-    if (FUSE) {
-      double* up = u + r * m + ch * VW;
-      for (int c = 0; c < VW; ++c) up[c] += double(xr.v[c]);
-    }
   }
 }
 
@@ -144,7 +158,49 @@ __global__ void k_shift(int64_t cnt, const T* __restrict__ a, const T* __restric
     S[i] = a[i] - sigma * mm[i];
 }
 
+// FP64 gather of one ELL row against both matrices: (A x)[row][off, off+1] and
+// (M x)[row][off, off+1]; same load order as row_gather.
+template <int WT>
+__device__ __forceinline__ void row_gather_am(const int* __restrict__ cols,
+                                              const double* __restrict__ a,
+                                              const double* __restrict__ mm, int64_t base, int W,
+                                              const double* __restrict__ x, int m, int off,
+                                              double& a0, double& a1, double& m0, double& m1) {
+  a0 = a1 = m0 = m1 = 0.0;
+  if (WT > 0) {
+    int j[WT > 0 ? WT : 1];
+    double av[WT > 0 ? WT : 1], mv[WT > 0 ? WT : 1];
+    Vec<double> xv[WT > 0 ? WT : 1];
+#pragma unroll
+    for (int k = 0; k < WT; ++k) {
+      j[k] = cols[base + k];
+      av[k] = a[base + k];
+      mv[k] = mm[base + k];
+    }
+#pragma unroll
+    for (int k = 0; k < WT; ++k) xv[k] = ld(x + int64_t(j[k]) * m + off);
+#pragma unroll
+    for (int k = 0; k < WT; ++k) {
+      a0 += av[k] * xv[k].v[0];
+      a1 += av[k] * xv[k].v[1];
+      m0 += mv[k] * xv[k].v[0];
+      m1 += mv[k] * xv[k].v[1];
+    }
+  } else {
+    for (int k = 0; k < W; ++k) {
+      const int jj = cols[base + k];
+      const double av = a[base + k], mv = mm[base + k];
+      const Vec<double> xv = ld(x + int64_t(jj) * m + off);
+      a0 += av * xv.v[0];
+      a1 += av * xv.v[1];
+      m0 += mv * xv.v[0];
+      m1 += mv * xv.v[1];
+    }
+  }
+}
+
 // ------------------------------------------------------- FP64 SpMM (A, M) --
+template <int WT>
 __global__ void __launch_bounds__(256) k_spmm_am(int64_t n, int W, int m, int cpr, int rpb,
                                                  const int* __restrict__ cols,
                                                  const double* __restrict__ a,
@@ -153,18 +209,10 @@ __global__ void __launch_bounds__(256) k_spmm_am(int64_t n, int W, int m, int cp
                                                  double* __restrict__ ya, double* __restrict__ ym) {
   const int rloc = threadIdx.x / cpr;
   const int ch = threadIdx.x - rloc * cpr;
+  if (rloc >= rpb) return;
   for (int64_t r = int64_t(blockIdx.x) * rpb + rloc; r < n; r += int64_t(gridDim.x) * rpb) {
-    const int64_t base = r * W;
-    double a0 = 0, a1 = 0, m0 = 0, m1 = 0;
-    for (int k = 0; k < W; ++k) {
-      const int j = cols[base + k];
-      const double av = a[base + k], mv = mm[base + k];
-      const Vec<double> xv = ld(x + int64_t(j) * m + ch * 2);
-      a0 += av * xv.v[0];
-      a1 += av * xv.v[1];
-      m0 += mv * xv.v[0];
-      m1 += mv * xv.v[1];
-    }
+    double a0, a1, m0, m1;
+    row_gather_am<WT>(cols, a, mm, r * W, W, x, m, ch * 2, a0, a1, m0, m1);
     Vec<double> oa, om;
     oa.v[0] = a0;
     oa.v[1] = a1;
@@ -177,7 +225,7 @@ __global__ void __launch_bounds__(256) k_spmm_am(int64_t n, int W, int m, int cp
 
 // Eigen-residual R = A X - (M X) diag(theta), FP64 arithmetic, stored as
 // sgn * R in T; per-block partial sums of R^2 / lumped per column.
-template <typename T>
+template <typename T, int WT>
 __global__ void __launch_bounds__(256) k_eigres(int64_t n, int W, int m, int cpr, int rpb,
                                                 const int* __restrict__ cols,
                                                 const double* __restrict__ a,
@@ -189,31 +237,27 @@ __global__ void __launch_bounds__(256) k_eigres(int64_t n, int W, int m, int cpr
   extern __shared__ double sred[];  // [rpb][m]
   const int rloc = threadIdx.x / cpr;
   const int ch = threadIdx.x - rloc * cpr;
-  const double t0 = theta[2 * ch], t1 = theta[2 * ch + 1];
+  const bool active = rloc < rpb;
   double s0 = 0, s1 = 0;
-  for (int64_t r = int64_t(blockIdx.x) * rpb + rloc; r < n; r += int64_t(gridDim.x) * rpb) {
-    const int64_t base = r * W;
-    double a0 = 0, a1 = 0, m0 = 0, m1 = 0;
-    for (int k = 0; k < W; ++k) {
-      const int j = cols[base + k];
-      const double av = a[base + k], mv = mm[base + k];
-      const Vec<double> xv = ld(x + int64_t(j) * m + ch * 2);
-      a0 += av * xv.v[0];
-      a1 += av * xv.v[1];
-      m0 += mv * xv.v[0];
-      m1 += mv * xv.v[1];
+  if (active) {
+    const double t0 = theta[2 * ch], t1 = theta[2 * ch + 1];
+    for (int64_t r = int64_t(blockIdx.x) * rpb + rloc; r < n; r += int64_t(gridDim.x) * rpb) {
+      double a0, a1, m0, m1;
+      row_gather_am<WT>(cols, a, mm, r * W, W, x, m, ch * 2, a0, a1, m0, m1);
+      const double r0 = a0 - m0 * t0, r1 = a1 - m1 * t1;
+      const double di = dinv[r];
+      s0 += r0 * r0 * di;
+      s1 += r1 * r1 * di;
+      T* yp = y + r * m + ch * 2;
+      yp[0] = T(sgn * r0);
+      yp[1] = T(sgn * r1);
     }
-    const double r0 = a0 - m0 * t0, r1 = a1 - m1 * t1;
-    const double di = dinv[r];
-    s0 += r0 * r0 * di;
-    s1 += r1 * r1 * di;
-    T* yp = y + r * m + ch * 2;
-    yp[0] = T(sgn * r0);
-    yp[1] = T(sgn * r1);
   }
   if (part) {
-    sred[rloc * m + 2 * ch] = s0;
-    sred[rloc * m + 2 * ch + 1] = s1;
+    if (active) {
+      sred[rloc * m + 2 * ch] = s0;
+      sred[rloc * m + 2 * ch + 1] = s1;
+    }
     __syncthreads();
     for (int c = threadIdx.x; c < m; c += blockDim.x) {
       double s = 0;
@@ -442,16 +486,25 @@ int launch_shift(const DevLevel& L, double sigma, T* S, hipStream_t s) {
   return check_launch();
 }
 
+// Launch `kern<..., 7>` for the built-in ELL width 7, `kern<..., 0>` otherwise.
+#define BMG_BY_WIDTH(W, KT7, KT0, grid, block, shm, s, ...)   \
+  do {                                                        \
+    if ((W) == 7)                                             \
+      BMG_LAUNCH(KT7, grid, block, shm, s, __VA_ARGS__);      \
+    else                                                      \
+      BMG_LAUNCH(KT0, grid, block, shm, s, __VA_ARGS__);      \
+  } while (0)
+
 template <typename T>
 int launch_shifted(const DevLevel& L, const T* S, int mode, const T* x, const T* f, T* y, int m,
                    hipStream_t s) {
   Geom g = row_geom<T>(L.n, m);
   if (mode == ROW_SHIFTED)
-    BMG_LAUNCH((k_rowop<T, K_SHIFTED, false>), g.grid, g.block, 0, s, L.n, L.W, m, g.cpr, g.rpb, L.cols, S,
-                                                            T(0), x, f, y, nullptr);
+    BMG_BY_WIDTH(L.W, (k_rowop<T, K_SHIFTED, 7>), (k_rowop<T, K_SHIFTED, 0>), g.grid, g.block, 0, s,
+                 L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(0), x, f, y);
   else
-    BMG_LAUNCH((k_rowop<T, K_RESIDUAL, false>), g.grid, g.block, 0, s, L.n, L.W, m, g.cpr, g.rpb, L.cols, S,
-                                                             T(0), x, f, y, nullptr);
+    BMG_BY_WIDTH(L.W, (k_rowop<T, K_RESIDUAL, 7>), (k_rowop<T, K_RESIDUAL, 0>), g.grid, g.block, 0, s,
+                 L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(0), x, f, y);
   return check_launch();
 }
 
@@ -460,11 +513,11 @@ int launch_jacobi(const DevLevel& L, const T* S, double omega, const T* x, const
                   bool x_is_zero, int m, hipStream_t s) {
   Geom g = row_geom<T>(L.n, m);
   if (x_is_zero)
-    BMG_LAUNCH((k_rowop<T, K_JACOBI0, false>), g.grid, g.block, 0, s, L.n, L.W, m, g.cpr, g.rpb, L.cols, S,
-                                                            T(omega), x, f, y, nullptr);
+    BMG_LAUNCH((k_rowop<T, K_JACOBI0, 0>), g.grid, g.block, 0, s, L.n, L.W, m, g.cpr, g.rpb, L.cols,
+               S, T(omega), x, f, y);
   else
-    BMG_LAUNCH((k_rowop<T, K_JACOBI, false>), g.grid, g.block, 0, s, L.n, L.W, m, g.cpr, g.rpb, L.cols, S,
-                                                           T(omega), x, f, y, nullptr);
+    BMG_BY_WIDTH(L.W, (k_rowop<T, K_JACOBI, 7>), (k_rowop<T, K_JACOBI, 0>), g.grid, g.block, 0, s,
+                 L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(omega), x, f, y);
   return check_launch();
 }
 
@@ -474,31 +527,32 @@ int launch_gs_colour(const DevLevel& L, const T* S, int colour, T* x, const T* f
   const int64_t b = L.colour_ptr[colour], e = L.colour_ptr[colour + 1];
   if (e <= b) return BMG_OK;
   Geom g = row_geom<T>(e - b, m);
-  BMG_LAUNCH((k_gs<T, false>), g.grid, g.block, 0, s, e - b, L.colour_rows + b, L.W, m, g.cpr, g.rpb, L.cols,
-                                            S, x, f, nullptr);
+  BMG_BY_WIDTH(L.W, (k_gs<T, 7>), (k_gs<T, 0>), g.grid, g.block, 0, s, e - b, L.colour_rows + b,
+               L.W, m, g.cpr, g.rpb, L.cols, S, x, f);
   return check_launch();
 }
 
 int launch_spmm_am(const DevLevel& L, const double* x, double* ya, double* ym, int m,
                    hipStream_t s) {
   Geom g = row_geom<double>(L.n, m);
-  BMG_LAUNCH((k_spmm_am), g.grid, g.block, 0, s, L.n, L.W, m, g.cpr, g.rpb, L.cols, L.a64, L.m64, x, ya, ym);
+  BMG_BY_WIDTH(L.W, (k_spmm_am<7>), (k_spmm_am<0>), g.grid, g.block, 0, s, L.n, L.W, m, g.cpr,
+               g.rpb, L.cols, L.a64, L.m64, x, ya, ym);
   return check_launch();
 }
 
-int eigres_blocks(const DevLevel& L, int m) { return row_geom<double>(L.n, m, 1024).grid; }
+int eigres_blocks(const DevLevel& L, int m) { return row_geom<double>(L.n, m, 4096).grid; }
 
 template <typename T>
 int launch_eigres(const DevLevel& L, const double* x, const double* theta, double sgn, T* y,
                   double* rho2_part, int nblk, int m, hipStream_t s) {
-  Geom g = row_geom<double>(L.n, m, 1024);
+  Geom g = row_geom<double>(L.n, m, 4096);
   if (nblk != g.grid) {
     set_error("eigres grid mismatch");
     return BMG_EINVAL;
   }
   const size_t shm = size_t(g.rpb) * m * sizeof(double);
-  BMG_LAUNCH((k_eigres<T>), g.grid, g.block, shm, s, L.n, L.W, m, g.cpr, g.rpb, L.cols, L.a64, L.m64, L.dinv,
-                                           x, theta, sgn, y, rho2_part);
+  BMG_BY_WIDTH(L.W, (k_eigres<T, 7>), (k_eigres<T, 0>), g.grid, g.block, shm, s, L.n, L.W, m, g.cpr,
+               g.rpb, L.cols, L.a64, L.m64, L.dinv, x, theta, sgn, y, rho2_part);
   return check_launch();
 }
 

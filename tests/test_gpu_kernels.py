@@ -196,3 +196,74 @@ def test_eigen_residual(env, dt_name):
     tol = 1e-14 if dt_name == "f64" else 1e-7
     err = _rel(_host(y), ref, scale)
     assert err < tol, err
+
+
+@pytest.mark.parametrize("level", [0, 2, 4])
+@pytest.mark.parametrize("m2,m", [(12, 12), (12, 32), (0, 8), (12, 80), (16, 80), (32, 40), (4, 92)])
+def test_update_in_place(env, level, m2, m):
+    # U <- [W | U] Y in place: the Ritz update of the iterate block
+    torch, p, h, lv = env
+    n = lv[level].n
+    rng = np.random.default_rng(100 * m2 + m + level)
+    W, U, Y = rng.standard_normal((n, m2)), rng.standard_normal((n, m)), rng.standard_normal((m2 + m, m))
+    Ud = _dev(torch, U)
+    h.apply("update", x=_dev(torch, W) if m2 else None, f=_dev(torch, Y), y=Ud, m=m, m2=m2,
+            level=level)
+    torch.cuda.synchronize()
+    Z = np.hstack([W, U])
+    err = _rel(_host(Ud), Z @ Y, np.abs(Z) @ np.abs(Y))
+    assert err < 1e-14, err
+
+
+def _bipyramid(k=8):
+    # closed surface with two vertices of valence k (ELL width k + 1 != 7):
+    # exercises the kernels' runtime-width path
+    ang = 2 * np.pi * np.arange(k) / k
+    xyz = np.vstack([[0, 0, 1.0], [0, 0, -1.0], np.c_[np.cos(ang), np.sin(ang), np.zeros(k)]])
+    tri = []
+    for i in range(k):
+        a, b = 2 + i, 2 + (i + 1) % k
+        for t in ((0, a, b), (1, b, a)):
+            p0, p1, p2 = xyz[list(t)]
+            if np.dot(np.cross(p1 - p0, p2 - p0), p0 + p1 + p2) < 0:
+                t = (t[0], t[2], t[1])
+            tri.append(t)
+    return xyz, np.array(tri, dtype=np.int32)
+
+
+def test_runtime_width_kernels(env):
+    torch, p, _, _ = env
+    from oracle import fem, mesh
+    xyz, tri = _bipyramid(8)
+    h = p.Hierarchy("custom", 3, xyz=xyz, tri=tri, project=mesh.project_sphere)
+    L = h.n_levels - 1
+    assert h.info(L)["ell_width"] == 9
+    X, T = xyz, tri
+    for _ in range(3):
+        X, T, _par = mesh.refine(X, T, mesh.project_sphere)
+    A, M = fem.assemble(X, T)
+    n, m = A.shape[0], 12
+    rng = np.random.default_rng(3)
+    x, f = rng.standard_normal((n, m)), rng.standard_normal((n, m))
+    for op, Mat in (("A", A), ("M", M)):
+        y = torch.zeros((n, m), dtype=torch.float64, device="cuda")
+        h.apply(op, x=_dev(torch, x), y=y)
+        torch.cuda.synchronize()
+        assert _rel(_host(y), Mat @ x, abs(Mat) @ np.abs(x) + 1e-300) < 1e-14, op
+    sigma = 3.0
+    S = (A - sigma * M).tocsr()
+    scale = (abs(A) + sigma * abs(M)) @ np.abs(x) + np.abs(f)
+    y = torch.zeros((n, m), dtype=torch.float64, device="cuda")
+    h.apply("residual", x=_dev(torch, x), f=_dev(torch, f), y=y, sigma=sigma)
+    torch.cuda.synchronize()
+    assert _rel(_host(y), f - S @ x, scale) < 1e-14
+    d = S.diagonal()
+    h.apply("smooth_fwd", x=_dev(torch, x), f=_dev(torch, f), y=y, sigma=sigma, smoother="jacobi")
+    torch.cuda.synchronize()
+    ref = x + (2.0 / 3.0) * (f - S @ x) / d[:, None]
+    assert _rel(_host(y), ref, np.abs(x) + scale / np.abs(d)[:, None]) < 1e-13
+    th = np.sort(rng.uniform(0, 30, m))
+    h.apply("eigres", x=_dev(torch, x), f=_dev(torch, th), y=y)
+    torch.cuda.synchronize()
+    ref = A @ x - (M @ x) * th[None, :]
+    assert _rel(_host(y), ref, abs(A) @ np.abs(x) + (abs(M) @ np.abs(x)) * th[None, :]) < 1e-14

@@ -134,7 +134,7 @@ def test_server_arguments_and_missing_device(lib):
         assert e.value.status == lib.EDEVICE
 
 
-@pytest.mark.parametrize("kind,nref,kw", [("sphere", 4, {}), ("torus", 2, dict(nu=64, nv=32)),
+@pytest.mark.parametrize("kind,nref,kw", [("sphere", 4, {}), ("torus", 2, dict(nu=16, nv=8)),
                                           ("ellipsoid", 3, dict(axes=(1.0, 1.5, 2.0)))])
 def test_finest_vertex_formula(lib, kind, nref, kw):
     h = lib.Hierarchy(kind, nref, device=False, **kw)
