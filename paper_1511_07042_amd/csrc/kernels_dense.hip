@@ -37,6 +37,10 @@ namespace bmg {
 namespace {
 
 constexpr int kMaxN = 96;
+// Significance threshold (squared) of a rotation in the Ritz step: a_pq below
+// 1e-13 of the diagonal scale changes the Ritz pairs by far less than the
+// residual certificate resolves (an eigenvector of C off by ~1e-13 relative).
+constexpr double kRitzRtol2 = 1e-26;
 constexpr int kMaxHalf = kMaxN / 2;
 constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
@@ -52,7 +56,11 @@ struct alignas(16) RotRec {
 };
 
 struct JacobiShared {
-  RotRec rot[kWaves][kMaxHalf];  // per-wave copy of the round's rotations
+  // each wave's copy of the round's rotations (written and read by that wave
+  // only): (c, s), t, and the pair (p, q)
+  double2 cs[kWaves][kMaxHalf];
+  double tt[kWaves][kMaxHalf];
+  int2 pq[kWaves][kMaxHalf];
   double red[2 * kWaves];
   double bcast[2];
   int sig[3];  // per sweep (mod 3): a significant rotation was applied
@@ -108,26 +116,60 @@ __device__ __forceinline__ void rr_pair(int t, int rd, int ne, int& p, int& q) {
 // Symmetric Schur rotation of the pair (p, q) of the packed matrix X
 // (Golub & Van Loan, Alg. 8.5.1, with tau = d / b folded into
 // t = sign(d) b / (|d| + hypot(d, b))), or the identity (s = 0) when a_pq is
-// not significant.
-__device__ __forceinline__ RotRec rot_params(const double* X, int p, int q, int n, double floor2) {
+// not significant.  The square roots and the division start from the
+// hardware estimates (v_rsq_f64, v_rcp_f64) refined by Newton steps: t only
+// has to be close to the annihilating tangent (a small error leaves a tiny
+// a_pq for the next sweep), but c = (1 + t^2)^-1/2 is refined to full
+// precision so that c^2 + s^2 = 1 to rounding and V stays orthogonal.
+__device__ __forceinline__ double rsq_refined(double u, int steps) {
+  double r = __builtin_amdgcn_rsq(u);
+  for (int i = 0; i < steps; ++i) r = r * fma(-0.5 * u * r, r, 1.5);
+  return r;
+}
+
+__device__ __forceinline__ RotRec rot_params(const double* X, int p, int q, int n, double floor2,
+                                             double rtol2) {
   RotRec r{1.0, 0.0, 0.0, p, q};
   if (q >= n) return r;
   const double apq = X[tri(q, p)], app = X[tri(p, p)], aqq = X[tri(q, q)];
-  if (apq * apq > 1e-30 * fmax(fabs(app * aqq), floor2)) {
+  if (apq * apq > rtol2 * fmax(fabs(app * aqq), floor2)) {
     const double d = aqq - app, b = 2.0 * apq;
-    const double t = (d >= 0.0 ? b : -b) / (fabs(d) + sqrt(d * d + b * b));
-    r.c = rsqrt(1.0 + t * t);
+    const double h2 = fma(d, d, b * b);
+    double t;
+    if (h2 > 1e-280 && h2 < 1e280) {
+      const double h = h2 * rsq_refined(h2, 1);
+      const double den = fabs(d) + h;
+      double rc = __builtin_amdgcn_rcp(den);
+      rc = rc * fma(-den, rc, 2.0);
+      t = (d >= 0.0 ? b : -b) * rc;
+    } else {
+      t = (d >= 0.0 ? b : -b) / (fabs(d) + sqrt(d * d + b * b));
+    }
+    const double u = fma(t, t, 1.0);
+    r.c = rsq_refined(u, 2);
     r.s = t * r.c;
     r.t = t;
   }
   return r;
 }
 
-// Diagonalise the packed symmetric n x n matrix in cur (LDS); nxt is a second
-// packed buffer.  On return cur holds the diagonal form (eigenvalues on the
-// diagonal, unsorted) and V (LDS, n x n row-major) is orthogonal with
-// X_in = V diag V^T.  Returns the sweeps used, or -1 if the limit was hit.
-__device__ int block_jacobi(double*& cur, double*& nxt, double* V, int n, JacobiShared& sh) {
+// Diagonalise the packed symmetric n x n matrix X (LDS) in place.  On return
+// X holds the diagonal form (eigenvalues on the diagonal, unsorted) and V (LDS,
+// n x n row-major) is orthogonal with X_in = V diag V^T.  A rotation is
+// significant when a_pq^2 > rtol2 max(|a_pp a_qq|, (||X||_F / n)^2); sweeps
+// stop after a sweep without one.  Returns the sweeps used, or -1 if the limit
+// was hit.
+//
+// A round costs two barriers (rotations computed, then updates done), and
+// nothing when none of its rotations is significant.  Every wave computes the
+// round's rotations (lane i: pair i) into its own LDS slot and keeps the
+// ballot of significant pairs in a scalar register: a thread touches a 2x2
+// block of X only if one of its two rotations is significant, and an
+// eigenvector item only if its rotation is.  The blocks of a round partition X
+// and the (row, pair) items partition the changed entries of V, so the
+// updates are done in place: no element is read by one thread and written by
+// another within a round.
+__device__ int block_jacobi(double* X, double* V, int n, JacobiShared& sh, double rtol2) {
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
   const int ne = n + (n & 1);
   const int half = ne / 2;
@@ -137,7 +179,7 @@ __device__ int block_jacobi(double*& cur, double*& nxt, double* V, int n, Jacobi
   for (int e = tid; e < n * n; e += nt) {
     const int i = e / n, j = e - (e / n) * n;
     V[e] = (i == j) ? 1.0 : 0.0;
-    const double x = cur[sym(i, j)];
+    const double x = X[sym(i, j)];
     f2 += x * x;
   }
   if (tid == 0) {
@@ -164,82 +206,83 @@ __device__ int block_jacobi(double*& cur, double*& nxt, double* V, int n, Jacobi
     bt1[i] = t1;
     bt2[i] = t2;
   }
-  // eigenvector work items: pair slot tv = tid mod hp, rows k0, k0 + GV, ...
-  int lh = 0;
-  while ((1 << lh) < half) ++lh;
-  const int hp = 1 << lh;
-  const int tv = tid & (hp - 1), k0 = tid >> lh, GV = nt >> lh;
-  RotRec* rot = sh.rot[wave];
+  // eigenvector items: pair slot vt = tid mod half (threads below half * G),
+  // rows vr0, vr0 + G, ...  (G = nt / half row groups)
+  const int G = nt / half;
+  const int vt = tid % half, vr0 = tid / half;
+  const bool vlive = vr0 < G;
+  double2* cs = sh.cs[wave];
+  double* tt = sh.tt[wave];
+  int2* pq = sh.pq[wave];
   for (int sweep = 0; sweep < 30; ++sweep) {
-    // this slot was last read at the end of sweep - 2, before the barriers of
-    // sweep - 1 (a sweep that continues had one); the next sweep writes it only
-    // after a barrier of this sweep
+    // this flag was last read at the end of sweep - 2, before the barriers of
+    // sweep - 1; the next sweep writes it only after a barrier of this sweep
     if (tid == 0) sh.sig[(sweep + 1) % 3] = 0;
     for (int rd = 0; rd < ne - 1; ++rd) {
       bool sg = false;
       if (lane < half) {
         int p, q;
         rr_pair(lane, rd, ne, p, q);
-        const RotRec r = rot_params(cur, p, q, n, floor2);
-        rot[lane] = r;
+        const RotRec r = rot_params(X, p, q, n, floor2, rtol2);
+        cs[lane] = double2{r.c, r.s};
+        tt[lane] = r.t;
+        pq[lane] = int2{p, q};
         sg = r.s != 0.0;
       }
       // identical in every wave: skip the round (no writes, no barrier)
-      if (!__any(sg)) continue;
-      if (wave == 0 && sg) sh.sig[sweep % 3] = 1;
-      if (tid == 0) ++sh.rounds;
-      wave_sync();
+      const uint64_t mask = __ballot(sg);
+      if (mask == 0) continue;
+      if (wave == 0 && lane == 0) {
+        sh.sig[sweep % 3] = 1;
+        ++sh.rounds;
+      }
+      // every wave has read X for its rotations before any thread updates X
+      __syncthreads();
 #pragma unroll
       for (int i = 0; i < kNB; ++i) {
         if (bt2[i] < 0) continue;
         const int t1 = bt1[i], t2 = bt2[i];
-        const RotRec r2 = rot[t2];
-        const int p2 = r2.p, q2 = r2.q;
-        const bool hq2 = q2 < n;
+        const bool g1 = (mask >> t1) & 1, g2 = (mask >> t2) & 1;
+        if (!g1 && !g2) continue;
+        const int2 P2 = pq[t2];
+        const double2 C2 = cs[t2];
         if (t1 == t2) {
-          const double app = cur[tri(p2, p2)];
-          if (hq2) {
-            const double aqq = cur[tri(q2, q2)], apq = cur[tri(q2, p2)];
-            const bool s = r2.s != 0.0;
-            nxt[tri(p2, p2)] = s ? app - r2.t * apq : app;
-            nxt[tri(q2, q2)] = s ? aqq + r2.t * apq : aqq;
-            nxt[tri(q2, p2)] = s ? 0.0 : apq;
-          } else {
-            nxt[tri(p2, p2)] = app;
-          }
+          const int p = P2.x, q = P2.y;  // significant: q < n
+          const double app = X[tri(p, p)], apq = X[tri(q, p)], aqq = X[tri(q, q)];
+          const double t = tt[t2];
+          X[tri(p, p)] = app - t * apq;
+          X[tri(q, q)] = aqq + t * apq;
+          X[tri(q, p)] = 0.0;
           continue;
         }
-        const RotRec r1 = rot[t1];
-        const int a1 = r1.p, b1 = r1.q;
-        const bool hq1 = b1 < n;
-        const double bpp = cur[sym(a1, p2)];
-        const double bpq = hq2 ? cur[sym(a1, q2)] : 0.0;
-        const double bqp = hq1 ? cur[sym(b1, p2)] : 0.0;
-        const double bqq = (hq1 && hq2) ? cur[sym(b1, q2)] : 0.0;
-        const double c1 = r1.c, s1 = r1.s, c2 = r2.c, s2 = r2.s;
+        const int2 P1 = pq[t1];
+        const double2 C1 = cs[t1];
+        const int a1 = P1.x, b1 = P1.y, p2 = P2.x, q2 = P2.y;
+        const bool hq1 = b1 < n, hq2 = q2 < n;
+        const double bpp = X[sym(a1, p2)];
+        const double bpq = hq2 ? X[sym(a1, q2)] : 0.0;
+        const double bqp = hq1 ? X[sym(b1, p2)] : 0.0;
+        const double bqq = (hq1 && hq2) ? X[sym(b1, q2)] : 0.0;
+        const double c1 = C1.x, s1 = C1.y, c2 = C2.x, s2 = C2.y;
         const double lpp = c1 * bpp - s1 * bqp, lpq = c1 * bpq - s1 * bqq;
         const double lqp = s1 * bpp + c1 * bqp, lqq = s1 * bpq + c1 * bqq;
-        nxt[sym(a1, p2)] = c2 * lpp - s2 * lpq;
-        if (hq2) nxt[sym(a1, q2)] = s2 * lpp + c2 * lpq;
-        if (hq1) nxt[sym(b1, p2)] = c2 * lqp - s2 * lqq;
-        if (hq1 && hq2) nxt[sym(b1, q2)] = s2 * lqp + c2 * lqq;
+        X[sym(a1, p2)] = c2 * lpp - s2 * lpq;
+        if (hq2) X[sym(a1, q2)] = s2 * lpp + c2 * lpq;
+        if (hq1) X[sym(b1, p2)] = c2 * lqp - s2 * lqq;
+        if (hq1 && hq2) X[sym(b1, q2)] = s2 * lqp + c2 * lqq;
       }
-      // eigenvector rows rotated in columns (p, q) of pair tv
-      if (tv < half) {
-        const RotRec r = rot[tv];
-        if (r.s != 0.0) {
-          for (int k = k0; k < n; k += GV) {
-            double* vr = V + k * n;
-            const double vp = vr[r.p], vq = vr[r.q];
-            vr[r.p] = r.c * vp - r.s * vq;
-            vr[r.q] = r.s * vp + r.c * vq;
-          }
+      if (vlive && ((mask >> vt) & 1)) {
+        const int2 P = pq[vt];
+        const double2 C = cs[vt];
+        constexpr int kVR = kMaxN;  // G >= 1 rows apart; at most n rows
+        for (int k = vr0; k < n && k < kVR; k += G) {
+          double* vr = V + k * n;
+          const double vp = vr[P.x], vq = vr[P.y];
+          vr[P.x] = C.x * vp - C.y * vq;
+          vr[P.y] = C.y * vp + C.x * vq;
         }
       }
       __syncthreads();
-      double* tmp = cur;
-      cur = nxt;
-      nxt = tmp;
     }
     if (sh.sig[sweep % 3] == 0) return sweep + 1;
   }
@@ -475,7 +518,7 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
       if (j <= i) Rb[tri(i, j)] = GM[e] * sh.sv[i] * sh.sv[j];
     }
     __syncthreads();
-    (void)block_jacobi(cur, nxt, R0, nz, sh.j);
+    (void)block_jacobi(cur, R0, nz, sh.j, 1e-30);
     if (tid == 0) {
       double dmax = 0.0;
       for (int j = 0; j < nz; ++j) dmax = fmax(dmax, cur[tri(j, j)]);
@@ -520,7 +563,7 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
     __syncthreads();
   }
   ts[3] = wall_clock64();
-  const int sw = block_jacobi(cur, nxt, R0, r, sh.j);
+  const int sw = block_jacobi(cur, R0, r, sh.j, kRitzRtol2);
   ts[4] = wall_clock64();
   const int mm = m < r ? m : r;
   select_nearest_zero(cur, r, mm, sh);
@@ -572,7 +615,7 @@ __global__ void __launch_bounds__(kThreads) k_syev(int n, const double* __restri
     if (j <= i) cur[tri(i, j)] = 0.5 * (A[i * n + j] + A[j * n + i]);
   }
   __syncthreads();
-  const int sw = block_jacobi(cur, nxt, R0, n, sh.j);
+  const int sw = block_jacobi(cur, R0, n, sh.j, 1e-30);
   for (int j = tid; j < n; j += nt) sh.d[j] = cur[tri(j, j)];
   __syncthreads();
   for (int j = tid; j < n; j += nt) {
