@@ -82,7 +82,10 @@ typedef struct bmg_hierarchy bmg_hierarchy; /* opaque; device-resident after bui
  * Errors: BMG_EINVAL for a NULL/ill-formed descriptor, n_refine outside
  * [0, 10], a custom mesh that is not a closed, consistently oriented
  * 2-manifold (every directed edge once, its reverse once), a vertex valence
- * above 30, or a coarse mesh with more than 1024 vertices.
+ * above 30, or a coarse mesh with more than 4096 vertices.  The level-0
+ * eigendecomposition runs on the host (Jacobi) for coarse meshes of up to 1024
+ * vertices and with rocSOLVER's dsygvd on the device above that (the 64 x 32
+ * torus grid has 2048).
  * Ownership: *out belongs to the caller until bmg_free_hierarchy. */
 int bmg_build_hierarchy(const bmg_surface_desc* desc, int32_t n_refine, void* stream,
                         bmg_hierarchy** out);
@@ -90,7 +93,8 @@ int bmg_build_hierarchy(const bmg_surface_desc* desc, int32_t n_refine, void* st
 /* The same construction without any device work (no GPU needed): meshes,
  * matrices, colouring, parent tables and the level-0 eigendecomposition are
  * built on the host for inspection with bmg_hierarchy_info/_export.  Such a
- * hierarchy is rejected by bmg_solve and bmg_apply (BMG_EINVAL). */
+ * hierarchy is rejected by bmg_solve and bmg_apply (BMG_EINVAL).  Coarse
+ * meshes are limited to 1024 vertices here (BMG_EINVAL above). */
 int bmg_build_hierarchy_host(const bmg_surface_desc* desc, int32_t n_refine, bmg_hierarchy** out);
 
 void bmg_free_hierarchy(bmg_hierarchy* h);

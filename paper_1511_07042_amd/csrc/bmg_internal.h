@@ -110,6 +110,12 @@ struct bmg_hierarchy {
 
 namespace bmg {
 
+// Level-0 generalized eigensolvers (Alg. 2 step 1): host Jacobi up to
+// kHostEigMax vertices, rocSOLVER on the device up to kDeviceEigMax.
+constexpr int kHostEigMax = 1024;
+constexpr int kDeviceEigMax = 4096;
+int device_sygv(int n, const std::vector<double>& A, const std::vector<double>& M,
+                std::vector<double>& lam, std::vector<double>& X, hipStream_t s);
 int upload_hierarchy(bmg_hierarchy* h, hipStream_t s);
 void free_device(bmg_hierarchy* h);
 // Solve workspaces pooled per hierarchy (solver.cpp): bytes held by the idle

@@ -96,24 +96,6 @@ static int build_impl(const bmg_surface_desc* desc, int32_t n_refine, void* stre
   int st = build_host_levels(desc, n_refine, h->host);
   for (size_t l = 0; st == BMG_OK && l < h->host.size(); ++l)
     st = assemble_level(h->host[l], l ? &h->host[l - 1] : nullptr);
-  if (st == BMG_OK) {
-    const HostLevel& L0 = h->host[0];
-    const int n0 = int(L0.n);
-    if (n0 > 1024) {
-      set_error("coarse mesh has %d vertices; the setup eigensolver accepts at most 1024", n0);
-      st = BMG_EINVAL;
-    } else {
-      std::vector<double> A(size_t(n0) * n0, 0.0), M(size_t(n0) * n0, 0.0);
-      for (int i = 0; i < n0; ++i)
-        for (int k = 0; k < L0.W; ++k) {
-          const int j = L0.cols[size_t(i) * L0.W + k];
-          A[size_t(i) * n0 + j] += L0.a[size_t(i) * L0.W + k];
-          M[size_t(i) * n0 + j] += L0.mm[size_t(i) * L0.W + k];
-        }
-      h->n0 = n0;
-      st = dense_sygv(n0, A, M, h->lam0, h->phi0);
-    }
-  }
   if (st == BMG_OK && to_device) {
     // works whether or not another runtime user initialised the device first
     int count = 0;
@@ -125,10 +107,32 @@ static int build_impl(const bmg_surface_desc* desc, int32_t n_refine, void* stre
     if (e != hipSuccess) {
       set_error("no usable HIP device: %s", hipGetErrorString(e));
       st = BMG_EDEVICE;
-    } else {
-      st = upload_hierarchy(h, static_cast<hipStream_t>(stream));
     }
   }
+  if (st == BMG_OK) {
+    // Alg. 2 step 1: all eigenpairs of the level-0 pencil.  Up to
+    // kHostEigMax vertices on the host (Jacobi); larger coarse meshes (the
+    // torus grid) on the device with rocSOLVER, so only a device build takes them.
+    const HostLevel& L0 = h->host[0];
+    const int n0 = int(L0.n);
+    if (n0 > kDeviceEigMax || (n0 > kHostEigMax && !to_device)) {
+      set_error("coarse mesh has %d vertices; the setup eigensolver accepts at most %d (%d for a "
+                "host-only build)", n0, kDeviceEigMax, kHostEigMax);
+      st = BMG_EINVAL;
+    } else {
+      std::vector<double> A(size_t(n0) * n0, 0.0), M(size_t(n0) * n0, 0.0);
+      for (int i = 0; i < n0; ++i)
+        for (int k = 0; k < L0.W; ++k) {
+          const int j = L0.cols[size_t(i) * L0.W + k];
+          A[size_t(i) * n0 + j] += L0.a[size_t(i) * L0.W + k];
+          M[size_t(i) * n0 + j] += L0.mm[size_t(i) * L0.W + k];
+        }
+      h->n0 = n0;
+      st = n0 > kHostEigMax ? device_sygv(n0, A, M, h->lam0, h->phi0, static_cast<hipStream_t>(stream))
+                            : dense_sygv(n0, A, M, h->lam0, h->phi0);
+    }
+  }
+  if (st == BMG_OK && to_device) st = upload_hierarchy(h, static_cast<hipStream_t>(stream));
   if (st != BMG_OK) {
     free_device(h);
     delete h;

@@ -99,11 +99,13 @@ std::vector<int64_t> level_vertices(const bmg_surface_desc& d, int n_refine) {
 int ell_width(const bmg_surface_desc& d) { return d.kind == BMG_CUSTOM ? 31 : 7; }
 
 // Device bytes of a hierarchy: per level FP64 and FP32 values of A and M,
-// columns, lumped mass, colours and transfer tables.
+// columns, lumped mass, colours and transfer tables; the level-0 eigenvectors
+// and their transpose in FP64 and FP32.
 int64_t hierarchy_estimate(const bmg_surface_desc& d, int n_refine) {
   const int W = ell_width(d);
-  int64_t b = 0;
-  for (int64_t n : level_vertices(d, n_refine)) b += n * (int64_t(W) * (2 * 8 + 2 * 4 + 4) + 64);
+  const std::vector<int64_t> lv = level_vertices(d, n_refine);
+  int64_t b = 24 * lv[0] * lv[0];
+  for (int64_t n : lv) b += n * (int64_t(W) * (2 * 8 + 2 * 4 + 4) + 64);
   return b + (1 << 20);
 }
 

@@ -209,3 +209,22 @@ def test_custom_mesh_runtime_width_solve(lib):
         lv = [_L()]
         lv[0].M = M
         _check_pairs(ev, U, lv, ref_ev, ref_U, 9)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_torus_64x32_coarse_grid(lib, precision):
+    # The benchmark torus: R = 1, r = 0.4, a 64 x 32 parametric grid (2048
+    # vertices, the level-0 eigensolve runs on the device) refined once; the
+    # 32 coarse eigenvectors nearest sigma enrich the Ritz space.
+    from oracle import bmg as ob, reference
+    lv = ob.build_levels("torus", 1)
+    ref_ev, ref_U = reference.discrete_eigs(lv[-1].A, lv[-1].M, 24, 0.0)
+    h = lib.Hierarchy("torus", 1)
+    lam0, phi0 = h.export(0, "coarse_eig")
+    import scipy.linalg as sla
+    w = sla.eigh(lv[0].A.toarray(), lv[0].M.toarray(), eigvals_only=True)
+    assert np.max(np.abs(lam0 - w) / np.maximum(np.abs(w), 1.0)) < 1e-10
+    assert np.max(np.abs(phi0.T @ (lv[0].M @ phi0) - np.eye(len(w)))) < 1e-10
+    ev, U, st = h.solve(12, 0.0, 1e-8, m=16, precision=precision, smoother="jacobi")
+    assert st["converged"] == 1 and st["n_c"] == 32
+    _check_pairs(ev, U, lv, ref_ev, ref_U, 12)
