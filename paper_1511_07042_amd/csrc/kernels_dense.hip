@@ -214,7 +214,9 @@ __device__ int block_jacobi(double* X, double* V, int n, JacobiShared& sh, doubl
   double2* cs = sh.cs[wave];
   double* tt = sh.tt[wave];
   int2* pq = sh.pq[wave];
-  for (int sweep = 0; sweep < 30; ++sweep) {
+  int rounds = 0;  // thread 0: rounds with a significant rotation
+  int ret = -1;
+  for (int sweep = 0; sweep < 30 && ret < 0; ++sweep) {
     // this flag was last read at the end of sweep - 2, before the barriers of
     // sweep - 1; the next sweep writes it only after a barrier of this sweep
     if (tid == 0) sh.sig[(sweep + 1) % 3] = 0;
@@ -232,9 +234,9 @@ __device__ int block_jacobi(double* X, double* V, int n, JacobiShared& sh, doubl
       // identical in every wave: skip the round (no writes, no barrier)
       const uint64_t mask = __ballot(sg);
       if (mask == 0) continue;
-      if (wave == 0 && lane == 0) {
+      if (tid == 0) {
         sh.sig[sweep % 3] = 1;
-        ++sh.rounds;
+        ++rounds;
       }
       // every wave has read X for its rotations before any thread updates X
       __syncthreads();
@@ -284,9 +286,11 @@ __device__ int block_jacobi(double* X, double* V, int n, JacobiShared& sh, doubl
       }
       __syncthreads();
     }
-    if (sh.sig[sweep % 3] == 0) return sweep + 1;
+    if (sh.sig[sweep % 3] == 0) ret = sweep + 1;
   }
-  return -1;
+  if (tid == 0) sh.rounds = rounds;
+  __syncthreads();
+  return ret;
 }
 
 struct RitzShared {
