@@ -63,7 +63,9 @@ def copy_calibration(mib):
 # Kernel classes: bound and whether the library's figure counts bytes or flops.
 KCLASS = {"eigres": ("hbm", "GB/s"), "spmm_am": ("hbm", "GB/s"), "smooth": ("hbm", "GB/s"),
           "residual": ("hbm", "GB/s"), "restrict": ("hbm", "GB/s"), "prolong": ("hbm", "GB/s"),
-          "gram": ("mfma", "TFLOP/s"), "update": ("mfma", "TFLOP/s"), "ritz": ("latency", "us")}
+          "gram": ("mfma", "TFLOP/s"), "update": ("mfma", "TFLOP/s"), "ritz": ("latency", "us"),
+          "smooth_pair": ("hbm", "GB/s"), "restrict_res": ("hbm", "GB/s"),
+          "prolong_smooth": ("hbm", "GB/s")}
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -273,6 +275,8 @@ def main():
             bd = {}
             for kc in KCLASS:
                 _, st = timed_solves(h, cfg, prec, a.smoother, 1, 0, kc)
+                if st[0]["timed_kernel_units"] == 0:
+                    continue  # not launched in this configuration (fused away)
                 bd[kc] = dict(ms=round(st[0]["timed_kernel_ms"], 3), **roofline(
                     kc, st[0]["timed_kernel_ms"], st[0]["timed_kernel_bytes"], st[0]["timed_kernel_units"]))
             res[prec]["breakdown"] = bd

@@ -168,24 +168,33 @@ typedef struct {
  * on every level that runs as multi-block kernels (the levels below those run
  * inside the one-workgroup LDS tail and are not counted).  Each class is one
  * kernel symbol, so its average launch time is comparable with a profiler's.
+ * With the weighted-Jacobi smoother the cycle runs three fused kernels
+ * (SMOOTH_PAIR, RESTRICT_RES, PROLONG_SMOOTH) in place of the zero-start
+ * sweep, the first sweep, the residual, the restriction, the prolongation and
+ * the first post-sweep.
  * Algorithmic bytes per launch at a level with n rows, nnz nonzeros (ELL rows
  * of width W), m block columns, b = 4 (mixed) or 8 (FP64) bytes per correction
- * value, N = N_L, nz = n_c + m:
+ * value, n_prev rows on the next coarser level, N = N_L, nz = n_c + m:
  *   EIGRES    residual SpMM:  20 nnz + 8 N m (U) + b N m (R) + 8 N (D^-1)
  *   SPMM_AM   A and M SpMM:   20 nnz + 8 N m (U) + 16 N m (A U, M U)
- *   SMOOTH    Jacobi: one sweep from a nonzero iterate (the zero-start sweep
- *             is a different kernel and is not counted):
+ *   SMOOTH    Jacobi: one sweep from a nonzero iterate:
  *             (4 + b) nnz + 3 b n m   (S and columns; x, f read; y written);
  *             Gauss-Seidel: one colour pass over n_k rows:
  *             (4 + b) W n_k + b m (n + 2 n_k)   (its rows of S; x read once;
  *             f read and x written on its rows)
  *   RESIDUAL  (4 + b) nnz + 3 b n m;   RESTRICT  b n m + b n_prev m + 4 n_prev RW;
  *   PROLONG   b n_prev m + 2 b n m + 8 (n - n_prev);
+ *   SMOOTH_PAIR     (4 + b) nnz + 2 b n m            (f read, y written);
+ *   RESTRICT_RES    (4 + b) nnz + 2 b n m + b n_prev m + 4 n_prev RW
+ *                   (e, f read; the coarse right-hand side written);
+ *   PROLONG_SMOOTH  (4 + b) nnz + 3 b n m + b n_prev m + 8 (n - n_prev)
+ *                   (e, f read, y written; the coarse correction read);
  *   GRAM      8 N (nz + 2m) bytes, 4 N nz m flops;
  *   UPDATE    8 N nz + 8 N m bytes, 2 N nz m flops;   RITZ  one workgroup. */
 typedef enum {
   BMG_K_EIGRES = 0, BMG_K_SPMM_AM = 1, BMG_K_SMOOTH = 2, BMG_K_RESIDUAL = 3,
-  BMG_K_RESTRICT = 4, BMG_K_PROLONG = 5, BMG_K_GRAM = 6, BMG_K_UPDATE = 7, BMG_K_RITZ = 8
+  BMG_K_RESTRICT = 4, BMG_K_PROLONG = 5, BMG_K_GRAM = 6, BMG_K_UPDATE = 7, BMG_K_RITZ = 8,
+  BMG_K_SMOOTH_PAIR = 9, BMG_K_RESTRICT_RES = 10, BMG_K_PROLONG_SMOOTH = 11
 } bmg_kernel_class;
 
 /* Fill *o with the defaults listed above. */

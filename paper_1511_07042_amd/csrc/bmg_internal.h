@@ -178,6 +178,18 @@ int launch_jacobi(const DevLevel& L, const T* S, double omega, const T* x, const
 template <typename T>
 int launch_gs_colour(const DevLevel& L, const T* S, int colour, T* x, const T* f, int m,
                      hipStream_t s);
+// Fused cycle kernels (identical results to the unfused sequences):
+// two Jacobi sweeps from zero; residual + restriction; prolongation + one
+// Jacobi sweep.
+template <typename T>
+int launch_jacobi2z(const DevLevel& L, const T* S, double omega, const T* f, T* y, int m,
+                    hipStream_t s);
+template <typename T>
+int launch_resrestrict(const DevLevel& fine, const T* S, const T* e, const T* f, T* fc, int m,
+                       hipStream_t s);
+template <typename T>
+int launch_prolong_jacobi(const DevLevel& fine, const T* S, double omega, const T* e, const T* ec,
+                          const T* f, T* y, int m, hipStream_t s);
 template <typename T>
 int launch_restrict(const DevLevel& fine, const T* x, T* y, int m, hipStream_t s);
 template <typename T>

@@ -149,6 +149,186 @@ __global__ void __launch_bounds__(256) k_gs(int64_t cnt, const int* __restrict__
   }
 }
 
+// ---------------------------------------------------- fused cycle kernels --
+// Each computes, row by row, what a sequence of the kernels above computes,
+// with the same operations in the same order (so the results are identical
+// bit for bit), without writing the intermediate block to memory.
+
+// Two weighted-Jacobi sweeps from a zero iterate:
+//   y1 = omega f / d;  y = y1 + omega (f - S y1) / d,
+// with y1 at the neighbours formed on the fly from f and their diagonals.
+template <typename T, int WT>
+__global__ void __launch_bounds__(256) k_jacobi2z(int64_t n, int W, int m, int cpr, int rpb,
+                                                  const int* __restrict__ cols,
+                                                  const T* __restrict__ S, T omega,
+                                                  const T* __restrict__ f, T* __restrict__ y) {
+  constexpr int VW = Vec<T>::N;
+  constexpr int KM = WT > 0 ? WT : 1;
+  const int rloc = threadIdx.x / cpr;
+  const int ch = threadIdx.x - rloc * cpr;
+  if (rloc >= rpb) return;
+  const int off = ch * VW;
+  for (int64_t r = int64_t(blockIdx.x) * rpb + rloc; r < n; r += int64_t(gridDim.x) * rpb) {
+    const int64_t base = r * W;
+    const T d = S[base];
+    const Vec<T> fr = ld(f + r * m + off);
+    Vec<T> acc, xr;
+    for (int c = 0; c < VW; ++c) acc.v[c] = T(0);
+    if (WT > 0) {
+      int j[KM];
+      T sv[KM], dj[KM];
+      Vec<T> fv[KM];
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        j[k] = cols[base + k];
+        sv[k] = S[base + k];
+      }
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        dj[k] = S[int64_t(j[k]) * W];
+        fv[k] = ld(f + int64_t(j[k]) * m + off);
+      }
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        Vec<T> y1;
+        for (int c = 0; c < VW; ++c) y1.v[c] = omega * fv[k].v[c] / dj[k];
+        if (k == 0) xr = y1;
+        for (int c = 0; c < VW; ++c) acc.v[c] += sv[k] * y1.v[c];
+      }
+    } else {
+      for (int k = 0; k < W; ++k) {
+        const int jj = cols[base + k];
+        const T sk = S[base + k];
+        const T dk = S[int64_t(jj) * W];
+        const Vec<T> fk = ld(f + int64_t(jj) * m + off);
+        Vec<T> y1;
+        for (int c = 0; c < VW; ++c) y1.v[c] = omega * fk.v[c] / dk;
+        if (k == 0) xr = y1;
+        for (int c = 0; c < VW; ++c) acc.v[c] += sk * y1.v[c];
+      }
+    }
+    for (int c = 0; c < VW; ++c) acc.v[c] = fr.v[c] - acc.v[c];
+    for (int c = 0; c < VW; ++c) acc.v[c] = xr.v[c] + omega * acc.v[c] / d;
+    st(y + r * m + off, acc);
+  }
+}
+
+// Residual and restriction: fc[i] = r[i] + 1/2 sum_{children c of i} r[c],
+// r = f - S e on the fine rows (P^T of eq. proj-1 applied to the residual).
+template <typename T, int WT>
+__device__ __forceinline__ Vec<T> residual_row(const int* __restrict__ cols,
+                                               const T* __restrict__ S, int64_t r, int W,
+                                               const T* __restrict__ e, const T* __restrict__ f,
+                                               int m, int off) {
+  constexpr int VW = Vec<T>::N;
+  const Vec<T> fv = ld(f + r * m + off);
+  Vec<T> acc, xr;
+  row_gather<T, WT>(cols, S, r * W, W, e, m, off, acc, xr);
+  for (int c = 0; c < VW; ++c) acc.v[c] = fv.v[c] - acc.v[c];
+  return acc;
+}
+
+template <typename T, int WT>
+__global__ void __launch_bounds__(256) k_resrestrict(int64_t nc, int W, int RW, int m, int cpr,
+                                                     int rpb, const int* __restrict__ cols,
+                                                     const T* __restrict__ S,
+                                                     const int* __restrict__ rtab,
+                                                     const T* __restrict__ e,
+                                                     const T* __restrict__ f,
+                                                     T* __restrict__ fc) {
+  constexpr int VW = Vec<T>::N;
+  const int rloc = threadIdx.x / cpr;
+  const int ch = threadIdx.x - rloc * cpr;
+  if (rloc >= rpb) return;
+  const int off = ch * VW;
+  for (int64_t i = int64_t(blockIdx.x) * rpb + rloc; i < nc; i += int64_t(gridDim.x) * rpb) {
+    Vec<T> acc = residual_row<T, WT>(cols, S, i, W, e, f, m, off);
+    Vec<T> h;
+    for (int c = 0; c < VW; ++c) h.v[c] = T(0);
+    for (int k = 0; k < RW; ++k) {
+      const int j = rtab[i * RW + k];
+      if (j < 0) break;
+      const Vec<T> rv = residual_row<T, WT>(cols, S, j, W, e, f, m, off);
+      for (int c = 0; c < VW; ++c) h.v[c] += rv.v[c];
+    }
+    for (int c = 0; c < VW; ++c) acc.v[c] += T(0.5) * h.v[c];
+    st(fc + i * m + off, acc);
+  }
+}
+
+// Prolongation and one Jacobi sweep: with e' = e + P ec (P of eq. proj-1),
+// y = e' + omega (f - S e') / d; e' at the neighbours is formed on the fly.
+template <typename T>
+__device__ __forceinline__ Vec<T> prolonged(const T* __restrict__ e, const T* __restrict__ ec,
+                                            const int* __restrict__ parents, int64_t nc, int64_t j,
+                                            int m, int off) {
+  constexpr int VW = Vec<T>::N;
+  Vec<T> v;
+  if (j < nc) {
+    v = ld(ec + j * m + off);
+  } else {
+    const int64_t q = j - nc;
+    const Vec<T> xa = ld(ec + int64_t(parents[2 * q]) * m + off);
+    const Vec<T> xb = ld(ec + int64_t(parents[2 * q + 1]) * m + off);
+    for (int c = 0; c < VW; ++c) v.v[c] = T(0.5) * (xa.v[c] + xb.v[c]);
+  }
+  Vec<T> yv = ld(e + j * m + off);
+  for (int c = 0; c < VW; ++c) yv.v[c] += v.v[c];
+  return yv;
+}
+
+template <typename T, int WT>
+__global__ void __launch_bounds__(256) k_prolong_jacobi(int64_t n, int64_t nc, int W, int m,
+                                                        int cpr, int rpb,
+                                                        const int* __restrict__ cols,
+                                                        const T* __restrict__ S,
+                                                        const int* __restrict__ parents, T omega,
+                                                        const T* __restrict__ e,
+                                                        const T* __restrict__ ec,
+                                                        const T* __restrict__ f,
+                                                        T* __restrict__ y) {
+  constexpr int VW = Vec<T>::N;
+  constexpr int KM = WT > 0 ? WT : 1;
+  const int rloc = threadIdx.x / cpr;
+  const int ch = threadIdx.x - rloc * cpr;
+  if (rloc >= rpb) return;
+  const int off = ch * VW;
+  for (int64_t r = int64_t(blockIdx.x) * rpb + rloc; r < n; r += int64_t(gridDim.x) * rpb) {
+    const int64_t base = r * W;
+    const T d = S[base];
+    const Vec<T> fr = ld(f + r * m + off);
+    Vec<T> acc, xr;
+    for (int c = 0; c < VW; ++c) acc.v[c] = T(0);
+    if (WT > 0) {
+      int j[KM];
+      T sv[KM];
+      Vec<T> xv[KM];
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        j[k] = cols[base + k];
+        sv[k] = S[base + k];
+      }
+#pragma unroll
+      for (int k = 0; k < KM; ++k) xv[k] = prolonged<T>(e, ec, parents, nc, j[k], m, off);
+#pragma unroll
+      for (int k = 0; k < KM; ++k)
+        for (int c = 0; c < VW; ++c) acc.v[c] += sv[k] * xv[k].v[c];
+      xr = xv[0];
+    } else {
+      for (int k = 0; k < W; ++k) {
+        const int jj = cols[base + k];
+        const T sk = S[base + k];
+        const Vec<T> v = prolonged<T>(e, ec, parents, nc, jj, m, off);
+        if (k == 0) xr = v;
+        for (int c = 0; c < VW; ++c) acc.v[c] += sk * v.v[c];
+      }
+    }
+    for (int c = 0; c < VW; ++c) acc.v[c] = fr.v[c] - acc.v[c];
+    for (int c = 0; c < VW; ++c) acc.v[c] = xr.v[c] + omega * acc.v[c] / d;
+    st(y + r * m + off, acc);
+  }
+}
+
 // S = A - sigma M, elementwise over the ELL values, in precision T.
 template <typename T>
 __global__ void k_shift(int64_t cnt, const T* __restrict__ a, const T* __restrict__ mm, T sigma,
@@ -532,6 +712,34 @@ int launch_gs_colour(const DevLevel& L, const T* S, int colour, T* x, const T* f
   return check_launch();
 }
 
+template <typename T>
+int launch_jacobi2z(const DevLevel& L, const T* S, double omega, const T* f, T* y, int m,
+                    hipStream_t s) {
+  Geom g = row_geom<T>(L.n, m);
+  BMG_BY_WIDTH(L.W, (k_jacobi2z<T, 7>), (k_jacobi2z<T, 0>), g.grid, g.block, 0, s, L.n, L.W, m,
+               g.cpr, g.rpb, L.cols, S, T(omega), f, y);
+  return check_launch();
+}
+
+template <typename T>
+int launch_resrestrict(const DevLevel& fine, const T* S, const T* e, const T* f, T* fc, int m,
+                       hipStream_t s) {
+  Geom g = row_geom<T>(fine.n_prev, m);
+  BMG_BY_WIDTH(fine.W, (k_resrestrict<T, 7>), (k_resrestrict<T, 0>), g.grid, g.block, 0, s,
+               fine.n_prev, fine.W, fine.RW, m, g.cpr, g.rpb, fine.cols, S, fine.rtab, e, f, fc);
+  return check_launch();
+}
+
+template <typename T>
+int launch_prolong_jacobi(const DevLevel& fine, const T* S, double omega, const T* e, const T* ec,
+                          const T* f, T* y, int m, hipStream_t s) {
+  Geom g = row_geom<T>(fine.n, m);
+  BMG_BY_WIDTH(fine.W, (k_prolong_jacobi<T, 7>), (k_prolong_jacobi<T, 0>), g.grid, g.block, 0, s,
+               fine.n, fine.n_prev, fine.W, m, g.cpr, g.rpb, fine.cols, S, fine.parents, T(omega),
+               e, ec, f, y);
+  return check_launch();
+}
+
 int launch_spmm_am(const DevLevel& L, const double* x, double* ya, double* ym, int m,
                    hipStream_t s) {
   Geom g = row_geom<double>(L.n, m);
@@ -633,7 +841,13 @@ int launch_write_evecs(int64_t n, const double* U, int m, const int* sel, const 
   template int launch_dense_apply<T>(int, const T*, const T*, const T*, T*, int, hipStream_t);   \
   template int launch_fill<T>(T*, int64_t, T, hipStream_t);                                      \
   template int launch_add_to<T>(double*, const T*, int64_t, hipStream_t);                        \
-  template int launch_convert<T>(const double*, T*, int64_t, hipStream_t);
+  template int launch_convert<T>(const double*, T*, int64_t, hipStream_t);                       \
+  template int launch_jacobi2z<T>(const DevLevel&, const T*, double, const T*, T*, int,          \
+                                  hipStream_t);                                                   \
+  template int launch_resrestrict<T>(const DevLevel&, const T*, const T*, const T*, T*, int,     \
+                                     hipStream_t);                                                \
+  template int launch_prolong_jacobi<T>(const DevLevel&, const T*, double, const T*, const T*,   \
+                                        const T*, T*, int, hipStream_t);
 BMG_INST(double)
 BMG_INST(float)
 #undef BMG_INST

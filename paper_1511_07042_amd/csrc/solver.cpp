@@ -50,7 +50,7 @@ struct bmg_workspace {
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   double g_sigma = 0, g_omega = 0;
-  int g_smoother = -1, g_nu1 = -1, g_nu2 = -1, g_lc = -1, g_tail = -2, g_timed = -1;
+  int g_smoother = -1, g_nu1 = -1, g_nu2 = -1, g_lc = -1, g_tail = -2, g_timed = -1, g_fuse = -1;
   int nblk_res = 0, nblk_arg = 0;
   bmg::GramPlan gp{}, gpw{};
   std::vector<void*> allocs;
@@ -329,6 +329,7 @@ struct Cycle {
   int tail_hi = -1;  // levels l_c..tail_hi run in one workgroup, in LDS
   const TailArgs* tail_d = nullptr;
   int tail_lds = 0;
+  bool fuse_ok = std::getenv("BMG_NO_FUSE") == nullptr;  // fused Jacobi cycle kernels
 
   // Pack the LDS image of levels l_c..hi (the largest hi whose image and work
   // blocks fit the budget) and upload it with its descriptor.  phi0 and gh are
@@ -477,22 +478,60 @@ struct Cycle {
       for (int k = 0; k < 8; ++k) BMG_TRY(sweep(l, k % 2 == 0, k == 0));
       return BMG_OK;
     }
-    for (int k = 0; k < c.nu1; ++k) BMG_TRY(sweep(l, true, k == 0));
-    if (c.nu1 == 0) BMG_TRY(launch_fill<T>(e[l], D.n * c.m, T(0), s));
     const double b = sizeof(T);
     const double nnz = double(h->host[l].nnz), n = double(D.n), nc = double(D.n_prev);
-    int kc = kclass(BMG_K_RESIDUAL);
-    if (kt) kt->add(kc, (4 + b) * nnz + 3 * b * n * c.m, 1);
-    if (kt) BMG_TRY(kt->begin(kc));
-    BMG_TRY(launch_shifted<T>(D, S[l], ROW_RESIDUAL, e[l], f[l], t[l], c.m, s));
-    if (kt) BMG_TRY(kt->end(kc));
-    kc = kclass(BMG_K_RESTRICT);
-    if (kt) kt->add(kc, b * n * c.m + b * nc * c.m + 4.0 * nc * D.RW, 1);
-    if (kt) BMG_TRY(kt->begin(kc));
-    BMG_TRY(launch_restrict<T>(D, t[l], f[l - 1], c.m, s));
-    if (kt) BMG_TRY(kt->end(kc));
+    constexpr double kFuseMaxBlock = 24.0 * (1 << 20);
+    // weighted Jacobi: the zero-start pair of pre-sweeps, the residual with its
+    // restriction, and the prolongation with the first post-sweep each run as
+    // one fused kernel (same arithmetic, identical results).  Fusion saves
+    // launches and block round trips but recomputes residual rows and gathers
+    // the coarse correction per neighbour, so it pays while the level's blocks
+    // are small (launch- and latency-bound) and is skipped on levels whose
+    // blocks exceed kFuseMaxBlock bytes (bandwidth-bound).
+    const bool fuse = c.smoother == BMG_SMOOTH_JACOBI && fuse_ok &&
+                      double(D.n) * c.m * b <= kFuseMaxBlock;
+    int k0 = 0;
+    if (fuse && c.nu1 >= 2) {
+      const int kc = kclass(BMG_K_SMOOTH_PAIR);
+      if (kt) kt->add(kc, (4 + b) * nnz + 2 * b * n * c.m, 1);
+      if (kt) BMG_TRY(kt->begin(kc));
+      // reads only f, so it writes the iterate in place (no buffer swap)
+      BMG_TRY(launch_jacobi2z<T>(D, S[l], c.omega, f[l], e[l], c.m, s));
+      if (kt) BMG_TRY(kt->end(kc));
+      k0 = 2;
+    }
+    for (int k = k0; k < c.nu1; ++k) BMG_TRY(sweep(l, true, k == 0));
+    if (c.nu1 == 0) BMG_TRY(launch_fill<T>(e[l], D.n * c.m, T(0), s));
+    if (fuse) {
+      const int kc = kclass(BMG_K_RESTRICT_RES);
+      if (kt) kt->add(kc, (4 + b) * nnz + 2 * b * n * c.m + b * nc * c.m + 4.0 * nc * D.RW, 1);
+      if (kt) BMG_TRY(kt->begin(kc));
+      BMG_TRY(launch_resrestrict<T>(D, S[l], e[l], f[l], f[l - 1], c.m, s));
+      if (kt) BMG_TRY(kt->end(kc));
+    } else {
+      int kc = kclass(BMG_K_RESIDUAL);
+      if (kt) kt->add(kc, (4 + b) * nnz + 3 * b * n * c.m, 1);
+      if (kt) BMG_TRY(kt->begin(kc));
+      BMG_TRY(launch_shifted<T>(D, S[l], ROW_RESIDUAL, e[l], f[l], t[l], c.m, s));
+      if (kt) BMG_TRY(kt->end(kc));
+      kc = kclass(BMG_K_RESTRICT);
+      if (kt) kt->add(kc, b * n * c.m + b * nc * c.m + 4.0 * nc * D.RW, 1);
+      if (kt) BMG_TRY(kt->begin(kc));
+      BMG_TRY(launch_restrict<T>(D, t[l], f[l - 1], c.m, s));
+      if (kt) BMG_TRY(kt->end(kc));
+    }
     BMG_TRY(vcycle(l - 1));
-    kc = kclass(BMG_K_PROLONG);
+    if (fuse && c.nu2 >= 1) {
+      const int kc = kclass(BMG_K_PROLONG_SMOOTH);
+      if (kt) kt->add(kc, (4 + b) * nnz + 3 * b * n * c.m + b * nc * c.m + 8.0 * (n - nc), 1);
+      if (kt) BMG_TRY(kt->begin(kc));
+      BMG_TRY(launch_prolong_jacobi<T>(D, S[l], c.omega, e[l], e[l - 1], f[l], t[l], c.m, s));
+      if (kt) BMG_TRY(kt->end(kc));
+      std::swap(e[l], t[l]);
+      for (int k = 1; k < c.nu2; ++k) BMG_TRY(sweep(l, false, false));
+      return BMG_OK;
+    }
+    const int kc = kclass(BMG_K_PROLONG);
     if (kt) kt->add(kc, b * nc * c.m + 2 * b * n * c.m + 8.0 * (n - nc), 1);
     if (kt) BMG_TRY(kt->begin(kc));
     BMG_TRY(launch_prolong_add<T>(D, e[l - 1], e[l], c.m, s));
@@ -717,7 +756,7 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   const bool debug = std::getenv("BMG_DEBUG") != nullptr;
   if (use_graph && !(w->gexec && o.timed_kernel < 0 && w->g_timed < 0 && w->g_sigma == sigma && w->g_omega == o.omega &&
                      w->g_smoother == o.smoother && w->g_nu1 == o.nu1 && w->g_nu2 == o.nu2 &&
-                     w->g_lc == l_c && w->g_tail == cyc.tail_hi)) {
+                     w->g_lc == l_c && w->g_tail == cyc.tail_hi && w->g_fuse == int(cyc.fuse_ok))) {
     if (w->gexec) (void)hipGraphExecDestroy(w->gexec);
     if (w->graph) (void)hipGraphDestroy(w->graph);
     w->gexec = nullptr;
@@ -754,6 +793,7 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
       w->g_nu2 = o.nu2;
       w->g_lc = l_c;
       w->g_tail = cyc.tail_hi;
+      w->g_fuse = int(cyc.fuse_ok);
     }
     BMG_HIP(hipGraphLaunch(w->gexec, s));
     return BMG_OK;

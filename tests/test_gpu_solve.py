@@ -135,19 +135,21 @@ def test_c2_parity(lib, precision):
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_graph_tail_and_plain_launch_paths_identical(lib, smoother, precision, monkeypatch):
     # The cycle replayed as a HIP graph, the coarse levels fused in one
-    # workgroup, and plain per-kernel launches run the same arithmetic in the
-    # same order: results must agree bit for bit, over every replay of a solve.
+    # workgroup, the fused Jacobi cycle kernels and plain per-kernel launches
+    # run the same arithmetic in the same order: results must agree bit for
+    # bit, over every replay of a solve.
     h = lib.Hierarchy("sphere", 5)
     runs = {}
     for name, env in (("plain", {"BMG_NO_GRAPH": "1", "BMG_NO_TAIL": "1"}),
+                      ("unfused", {"BMG_NO_GRAPH": "1", "BMG_NO_TAIL": "1", "BMG_NO_FUSE": "1"}),
                       ("tail", {"BMG_NO_GRAPH": "1"}), ("graph", {}), ("graph2", {})):
-        for k in ("BMG_NO_GRAPH", "BMG_NO_TAIL"):
+        for k in ("BMG_NO_GRAPH", "BMG_NO_TAIL", "BMG_NO_FUSE"):
             monkeypatch.delenv(k, raising=False)
         for k, v in env.items():
             monkeypatch.setenv(k, v)
         runs[name] = h.solve(16, m=20, smoother=smoother, precision=precision)
     ev0, V0, s0 = runs["plain"]
-    for name in ("tail", "graph", "graph2"):
+    for name in ("unfused", "tail", "graph", "graph2"):
         ev, V, st = runs[name]
         assert st["cycles"] == s0["cycles"], name
         assert np.array_equal(ev, ev0), name
