@@ -169,7 +169,7 @@ __device__ __forceinline__ RotRec rot_params(const double* X, int p, int q, int 
 // and the (row, pair) items partition the changed entries of V, so the
 // updates are done in place: no element is read by one thread and written by
 // another within a round.
-__device__ int block_jacobi(double* X, double* V, int n, JacobiShared& sh, double rtol2) {
+__device__ __forceinline__ int block_jacobi(double* X, double* V, int n, JacobiShared& sh, double rtol2) {
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
   const int ne = n + (n & 1);
   const int half = ne / 2;
