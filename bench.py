@@ -6,11 +6,22 @@ finest-level pencil, iterated to the 1e-8 certificate (every row of the cycle:
 residual SpMM, correction V-cycle, Gram, Ritz, update).  The inputs (hierarchy
 and matrices) are resident in HBM before the timed region; the test vectors are
 drawn on the device from the step's seed.  `value` is converged eigenpairs per
-second of the FP32/FP64 mixed path; the plain FP64 GPU path is timed beside it.
+second of the FP32/FP64 mixed path on the sphere refined 6 times (k = 25,
+m = 32); the plain FP64 GPU path is timed beside it.
+
+Beside the timed solves the JSON line carries:
+  roofline      the dominant bandwidth-bound kernel of the mixed path, timed with
+                HIP events recorded at its own launches on the solve's stream;
+  breakdown     per kernel class (each timed in an extra solve);
+  c4            the sphere refined 8 times (655362 vertices, k = 64, m = 80),
+                where the sparse kernels are HBM-bound;
+  serving       a seeded request stream through the continuous-batching server;
+  cpu_baseline  the oracle (plain FP64 CPU implementation) on the same workload.
 
 Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -20,6 +31,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+# Kernel classes: bound and whether the library's figure counts bytes or flops.
+KCLASS = {"eigres": ("hbm", "GB/s"), "spmm_am": ("hbm", "GB/s"), "smooth": ("hbm", "GB/s"),
+          "residual": ("hbm", "GB/s"), "restrict": ("hbm", "GB/s"), "prolong": ("hbm", "GB/s"),
+          "gram": ("mfma", "TFLOP/s"), "update": ("mfma", "TFLOP/s"), "ritz": ("latency", "us"),
+          "smooth_pair": ("hbm", "GB/s"), "restrict_res": ("hbm", "GB/s"),
+          "prolong_smooth": ("hbm", "GB/s")}
+
+# Kernel symbols of the classes (template arguments of the mixed / FP64 paths).
+KSYMBOL = {"smooth": "k_rowop<{T}, 2, 7>", "residual": "k_rowop<{T}, 1, 7>",
+           "restrict": "k_restrict<{T}>", "prolong": "k_prolong_add<{T}>",
+           "smooth_pair": "k_jacobi2z<{T}, 7>", "restrict_res": "k_resrestrict<{T}, 7>",
+           "prolong_smooth": "k_prolong_jacobi<{T}, 7>", "eigres": "k_eigres<{T}, 7>",
+           "spmm_am": "k_spmm_am<7>", "gram": "k_gram + k_gram_reduce", "update": "k_update_zy",
+           "ritz": "k_ritz"}
+
+# Committed HBM-traffic summaries (two rocprofv3 --pmc passes each).
+TRAFFIC_FILES = {
+    ("restrict_res", "c2_sphere_ref6", "mixed"): "profiles/resrestrict_c2_sphere_ref6_traffic.txt",
+    ("smooth", "c4_sphere_ref8", "mixed"): "profiles/jacobi_sweep_c4_sphere_ref8_traffic.txt",
+}
 
 
 def parse():
@@ -29,15 +62,16 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2_sphere_ref6")
     ap.add_argument("--smoother", default="jacobi", choices=["gs", "jacobi"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default="both", choices=["both", "mixed", "fp64"])
-    ap.add_argument("--timed-kernel", default="smooth",
-                    help="kernel class timed with HIP events inside the timed region (roofline)")
-    ap.add_argument("--breakdown", action="store_true",
-                    help="after the timed region, time every kernel class in extra solves")
-    ap.add_argument("--serving", type=int, default=0, metavar="N",
-                    help="instead of the solve benchmark, serve a seeded stream of N requests "
-                         "(Poisson arrivals at 0.8x the measured capacity) and report latency")
+    ap.add_argument("--timed-kernel", default=None,
+                    help="kernel class for the roofline (default: the bandwidth-bound class "
+                         "with the largest total time in the mixed breakdown)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 655362-vertex section")
+    ap.add_argument("--serving", type=int, default=32, metavar="N",
+                    help="requests in the serving section (0: skip it)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving stream and print its JSON line")
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--serving-budget-gib", type=float, default=64.0)
     ap.add_argument("--serving-no-shift", action="store_true",
@@ -60,32 +94,17 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4, "launches": 5}))
 
 
-# Kernel classes: bound and whether the library's figure counts bytes or flops.
-KCLASS = {"eigres": ("hbm", "GB/s"), "spmm_am": ("hbm", "GB/s"), "smooth": ("hbm", "GB/s"),
-          "residual": ("hbm", "GB/s"), "restrict": ("hbm", "GB/s"), "prolong": ("hbm", "GB/s"),
-          "gram": ("mfma", "TFLOP/s"), "update": ("mfma", "TFLOP/s"), "ritz": ("latency", "us"),
-          "smooth_pair": ("hbm", "GB/s"), "restrict_res": ("hbm", "GB/s"),
-          "prolong_smooth": ("hbm", "GB/s")}
-FP64_PEAK_TFLOPS = 78.6
-
-
-TRAFFIC_FILES = {("smooth", "jacobi", "c2_sphere_ref6", "mixed"):
-                 "profiles/jacobi_sweep_c2_sphere_ref6_traffic.txt"}
-
-
 def kernel_source_hash():
-    """sha256 of the weighted-Jacobi row kernel's source text (its template)."""
-    import hashlib
-    import re
-    src = open(os.path.join(ROOT, "paper_1511_07042_amd", "csrc", "kernels_sparse.hip")).read()
-    m = re.search(r"template <typename T, int MODE, bool FUSE>\n__global__.*?\n}\n", src, re.S)
-    return hashlib.sha256(m.group(0).encode()).hexdigest() if m else None
+    """sha256 of the row-kernel source file: traffic summaries taken with other
+    kernel code are not reported."""
+    src = open(os.path.join(ROOT, "paper_1511_07042_amd", "csrc", "kernels_sparse.hip"), "rb").read()
+    return hashlib.sha256(src).hexdigest()
 
 
-def measured_traffic(kclass, smoother, workload, prec):
+def measured_traffic(kclass, workload, prec):
     """HBM bytes per launch from committed counter runs, or None when there are
-    none for this kernel and workload or the kernel changed since they were taken."""
-    rel = TRAFFIC_FILES.get((kclass, smoother, workload, prec))
+    none for this kernel and workload or the kernel source changed since."""
+    rel = TRAFFIC_FILES.get((kclass, workload, prec))
     if rel is None or not os.path.exists(os.path.join(ROOT, rel)):
         return None
     kv = {}
@@ -98,8 +117,11 @@ def measured_traffic(kclass, smoother, workload, prec):
     return float(kv["traffic_bytes_per_launch"])
 
 
-def roofline(kclass, ms, amount, units):
+def roofline(kclass, ms, amount, units, prec="mixed"):
     bound, unit = KCLASS[kclass]
+    name = KSYMBOL[kclass].format(T="float" if prec == "mixed" else "double")
+    if units == 0 or ms <= 0:
+        return None
     if bound == "hbm":
         achieved = amount / (ms * 1e-3) / 1e9
         peak = HBM_PEAK_GBS
@@ -107,14 +129,17 @@ def roofline(kclass, ms, amount, units):
         achieved = amount / (ms * 1e-3) / 1e12
         peak = FP64_PEAK_TFLOPS
     else:
-        return {"bound": "latency", "kernel": kclass, "avg_us": 1e3 * ms / max(units, 1)}
+        return {"bound": "latency", "kernel": name, "class": kclass, "units": int(units),
+                "avg_unit_us": round(1e3 * ms / units, 3)}
     return {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
-            "frac": round(achieved / peak, 4), "traffic": None, "kernel": kclass,
-            "units": int(units), "avg_unit_us": round(1e3 * ms / max(units, 1), 3),
-            "per_unit": round(amount / max(units, 1), 1)}
+            "frac": round(achieved / peak, 4), "traffic": None, "kernel": name, "class": kclass,
+            "units": int(units), "avg_unit_us": round(1e3 * ms / units, 3),
+            "per_unit": round(amount / units, 1)}
 
 
 def timed_solves(h, cfg, precision, smoother, steps, warmup, timed_kernel=None):
+    """W untimed warm-up solves, then exactly `steps` solves between two device
+    synchronisations.  Returns (seconds, per-solve stats)."""
     import torch
     kw = dict(m=cfg["m"], nu1=cfg["nu1"], nu2=cfg["nu2"], smoother=smoother, precision=precision,
               evecs=None, timed_kernel=timed_kernel)
@@ -132,26 +157,80 @@ def timed_solves(h, cfg, precision, smoother, steps, warmup, timed_kernel=None):
     return dt, stats
 
 
-def cpu_baseline(cfg, smoother):
-    """The oracle on the host cores: one solve of the same workload (seed 0)."""
+def breakdown(h, cfg, prec, smoother):
+    """Every kernel class timed with events in one extra solve (seed 0)."""
+    bd = {}
+    for kc in KCLASS:
+        _, st = timed_solves(h, cfg, prec, smoother, 1, 0, kc)
+        r = roofline(kc, st[0]["timed_kernel_ms"], st[0]["timed_kernel_bytes"],
+                     st[0]["timed_kernel_units"], prec)
+        if r is not None:  # classes fused away in this configuration are absent
+            bd[kc] = dict(ms_per_solve=round(st[0]["timed_kernel_ms"], 3), **r)
+    return bd
+
+
+def bench_workload(bmg, name, cfg, precs, steps, warmup, smoother, timed_kernel):
+    """Timed solves of one workload for each precision, the breakdown, and the
+    roofline of the dominant bandwidth-bound kernel."""
+    import torch
+    t0 = time.perf_counter()
+    h = bmg.Hierarchy(cfg["kind"], cfg["n_refine"], axes=cfg["axes"])
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    out = {"hierarchy_build_s": round(build_s, 3)}
+    for prec in precs:
+        dt, stats = timed_solves(h, cfg, prec, smoother, steps, warmup)
+        r = dict(value=round(steps * cfg["k"] / dt, 3), ms_per_step=round(1e3 * dt / steps, 3),
+                 cycles=[s["cycles"] for s in stats],
+                 t_solve_ms=[round(s["t_solve_ms"], 3) for s in stats],
+                 ritz_sweeps_max=max(s["ritz_sweeps_max"] for s in stats),
+                 ritz_fallbacks=sum(s["ritz_fallbacks"] for s in stats))
+        r["breakdown"] = breakdown(h, cfg, prec, smoother)
+        kc = timed_kernel
+        if kc is None:
+            hbm = [(v["ms_per_solve"], k) for k, v in r["breakdown"].items() if v["bound"] == "hbm"]
+            kc = max(hbm)[1]
+        # the roofline kernel: events around each of its launches, in solves of
+        # the same workload and seeds as the timed region
+        _, tst = timed_solves(h, cfg, prec, smoother, steps, 0, kc)
+        roof = roofline(kc, sum(s["timed_kernel_ms"] for s in tst),
+                        sum(s["timed_kernel_bytes"] for s in tst),
+                        sum(s["timed_kernel_units"] for s in tst), prec)
+        if roof is not None and "frac" in roof:
+            roof["traffic"] = measured_traffic(kc, name, prec)
+        r["roofline"] = roof
+        out[prec] = r
+        print(f"# {name} {prec}: {r['value']} eigenpairs/s, {r['ms_per_step']} ms/solve, "
+              f"roofline {roof}", file=sys.stderr, flush=True)
+    h.close()
+    return out
+
+
+def cpu_baseline(cfg, smoother, budget_s=10.0, max_solves=4):
+    """The oracle on the host cores: full solves of the same workload (seeds
+    0, 1, ...) until about budget_s seconds of CPU work."""
     import threadpoolctl
     from oracle import bmg as ob
     lv = ob.build_levels(cfg["kind"], cfg["n_refine"], axes=cfg["axes"])
     t0 = time.perf_counter()
-    ev, _, info = ob.solve(lv, cfg["k"], cfg["sigma"], cfg["tol"], m=cfg["m"], nu1=cfg["nu1"],
-                           nu2=cfg["nu2"], smoother=smoother)
+    n, cycles = 0, []
+    while n < max_solves and (n == 0 or time.perf_counter() - t0 < budget_s):
+        _, _, info = ob.solve(lv, cfg["k"], cfg["sigma"], cfg["tol"], m=cfg["m"], nu1=cfg["nu1"],
+                              nu2=cfg["nu2"], smoother=smoother, seed=n)
+        cycles.append(info["cycles"])
+        n += 1
     dt = time.perf_counter() - t0
     blas = max((p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()), default=1)
-    return dict(value=cfg["k"] / dt, unit="eigenpairs/s", cores=int(blas), kind="oracle",
-                sample=f"one full oracle solve of the same workload, seed 0 ({info['cycles']} cycles, "
-                       f"{dt:.1f} s; dense BLAS on {blas} threads, scipy.sparse products single-threaded)")
+    return dict(value=round(n * cfg["k"] / dt, 4), unit="eigenpairs/s", cores=int(blas), kind="oracle",
+                sample=f"{n} full oracle solves of the same workload, seeds 0..{n - 1} "
+                       f"({cycles} cycles, {dt:.1f} s); dense BLAS on {blas} threads, "
+                       f"scipy.sparse products single-threaded; host os.cpu_count() = {os.cpu_count()}")
 
 
-def _serve(bmg, reqs, slots, budget, rate=None, smoother="jacobi"):
-    """Submit the requests at their arrival times (all at once if rate is None)
+def _serve(bmg, reqs, slots, budget, timed, smoother):
+    """Submit the requests at their arrival times (all at once unless timed)
     and collect every result.  Returns (results, makespan_s)."""
-    import numpy as np
-    t_arr = [0.0] * len(reqs) if rate is None else [r["arrival_s"] for r in reqs]
+    t_arr = [r["arrival_s"] if timed else 0.0 for r in reqs]
     out = [None] * len(reqs)
     ids = {}
     with bmg.Server(budget, max_slots=slots) as srv:
@@ -173,59 +252,51 @@ def _serve(bmg, reqs, slots, budget, rate=None, smoother="jacobi"):
     return out, makespan
 
 
-def serving(a):
-    """Serving stream (seeded): surface, level, k and shift per request drawn as
-    in workloads.serving_stream; arrivals Poisson at 0.8x the capacity measured
-    on the same stream submitted all at once."""
+def serving(a, bmg):
+    """Seeded request stream (surface, level, k, shift per request as drawn by
+    workloads.serving_stream); Poisson arrivals at 0.8x the capacity measured
+    on the same requests submitted all at once."""
     import numpy as np
-    import torch
-    import paper_1511_07042_amd as bmg
     from workloads import serving_stream
-    torch.cuda.set_device(0)
     kinds = set(a.serving_kinds.split(","))
     full = serving_stream(4 * a.serving, seed=0, rate_per_s=1.0, sigma_positive=not a.serving_no_shift)
     reqs = [r for r in full if r["kind"] in kinds][:a.serving]
     budget = int(a.serving_budget_gib * (1 << 30))
-    # capacity: every request submitted at t = 0, hierarchies built on demand
-    res, span = _serve(bmg, reqs, a.serving_slots, budget, None, a.smoother)
+    _, span = _serve(bmg, reqs, a.serving_slots, budget, False, a.smoother)
     capacity = len(reqs) / span
     rate = 0.8 * capacity
-    print(f"# capacity {capacity:.2f} req/s over {span:.2f} s; serving at {rate:.2f} req/s",
-          file=sys.stderr, flush=True)
-    # timed run: Poisson arrivals (the stream's seeded exponential gaps, rescaled)
     gaps = np.diff([0.0] + [r["arrival_s"] for r in reqs])
-    t = np.cumsum(gaps / rate)
-    for r, ti in zip(reqs, t):
+    for r, ti in zip(reqs, np.cumsum(gaps / rate)):
         r["arrival_s"] = float(ti)
-    res, span = _serve(bmg, reqs, a.serving_slots, budget, rate, a.smoother)
+    res, span = _serve(bmg, reqs, a.serving_slots, budget, True, a.smoother)
     lat = np.array([r["latency_ms"] for r in res])
     ok = [r["status"] == 0 for r in res]
-    pairs = sum(q["k"] for q, good in zip(reqs, ok) if good)
-    status = {}
-    for r in res:
-        status[bmg.status_string(r["status"])] = status.get(bmg.status_string(r["status"]), 0) + 1
-    by_kind = {}
+    status, by_kind = {}, {}
     for q, r in zip(reqs, res):
+        s = bmg.status_string(r["status"])
+        status[s] = status.get(s, 0) + 1
         d = by_kind.setdefault(q["kind"] + ("/shift" if q["sigma"] else ""), {"n": 0, "ok": 0, "lat": []})
         d["n"] += 1
         d["ok"] += int(r["status"] == 0)
         d["lat"].append(r["latency_ms"])
     for d in by_kind.values():
         d["p50_ms"] = round(float(np.percentile(d.pop("lat"), 50)), 2)
-    out = {
+    okl = lat[np.array(ok)] if any(ok) else lat
+    return {
         "metric": "serving: converged eigenpairs/s and request latency (BMG, mixed precision)",
-        "value": round(pairs / span, 3), "unit": "eigenpairs/s", "n_gpus": 1,
+        "value": round(sum(q["k"] for q, g in zip(reqs, ok) if g) / span, 3), "unit": "eigenpairs/s",
         "p50_ms": round(float(np.percentile(lat, 50)), 2),
         "p99_ms": round(float(np.percentile(lat, 99)), 2),
+        "p50_ms_converged": round(float(np.percentile(okl, 50)), 2),
+        "p99_ms_converged": round(float(np.percentile(okl, 99)), 2),
         "requests": len(reqs), "converged": int(sum(ok)), "status": status, "by_kind": by_kind,
         "rate_req_s": round(rate, 3), "capacity_req_s": round(capacity, 3),
-        "makespan_s": round(span, 3), "slots": a.serving_slots,
-        "budget_gib": a.serving_budget_gib, "seed": 0, "data": "synthetic",
+        "makespan_s": round(span, 3), "slots": a.serving_slots, "budget_gib": a.serving_budget_gib,
+        "seed": 0, "data": "synthetic",
         "cycles_p50": float(np.percentile([r["stats"]["cycles"] for r in res], 50)),
         "config": {"workload": "c5_serving_stream", "kinds": sorted(kinds),
                    "shifts": not a.serving_no_shift, "smoother": a.smoother},
     }
-    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -234,73 +305,52 @@ def main():
         copy_calibration(a.copy_calibration)
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
-                          "n_gpus": a.gpus}))
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": a.gpus}))
         sys.exit(2)
-    if a.serving:
-        serving(a)
-        return
     import torch
+    torch.cuda.set_device(0)
     import paper_1511_07042_amd as bmg
     from workloads import CONFIGS
+    if a.serving_only:
+        print(json.dumps(serving(a, bmg)), flush=True)
+        return
+    precs = ["fp64", "mixed"] if a.only == "both" else [a.only]
     cfg = CONFIGS[a.workload]
-    torch.cuda.set_device(0)
-    t0 = time.perf_counter()
-    h = bmg.Hierarchy(cfg["kind"], cfg["n_refine"], axes=cfg["axes"])
-    torch.cuda.synchronize()
-    build_s = time.perf_counter() - t0
-    res = {}
-    roof = {}
-    for prec in (["fp64", "mixed"] if a.only == "both" else [a.only]):
-        # timed region: the production path (cycle replayed as a HIP graph)
-        dt, stats = timed_solves(h, cfg, prec, a.smoother, a.steps, a.warmup)
-        res[prec] = dict(value=a.steps * cfg["k"] / dt, ms_per_step=1e3 * dt / a.steps,
-                         cycles=[s["cycles"] for s in stats],
-                         t_solve_ms=[round(s["t_solve_ms"], 3) for s in stats],
-                         ritz_sweeps_max=max(s["ritz_sweeps_max"] for s in stats),
-                         ritz_fallbacks=sum(s["ritz_fallbacks"] for s in stats))
-        # roofline kernel: HIP events around each of its launches on the solve's
-        # stream, in solves of the same workload and seeds (plain launches)
-        _, tst = timed_solves(h, cfg, prec, a.smoother, a.steps, 0, a.timed_kernel)
-        roof[prec] = roofline(a.timed_kernel, sum(s["timed_kernel_ms"] for s in tst),
-                              sum(s["timed_kernel_bytes"] for s in tst),
-                              sum(s["timed_kernel_units"] for s in tst))
-        if "frac" in roof[prec]:
-            roof[prec]["traffic"] = measured_traffic(a.timed_kernel, a.smoother, a.workload, prec)
-            tb = "float" if prec == "mixed" else "double"
-            roof[prec]["kernel"] = (f"k_rowop<{tb}, 2, false> (weighted-Jacobi sweep, levels >= 3)"
-                                    if a.timed_kernel == "smooth" and a.smoother == "jacobi" else a.timed_kernel)
-        print(f"# {prec}: {res[prec]} roofline {roof[prec]}", file=sys.stderr, flush=True)
-        if a.breakdown:
-            bd = {}
-            for kc in KCLASS:
-                _, st = timed_solves(h, cfg, prec, a.smoother, 1, 0, kc)
-                if st[0]["timed_kernel_units"] == 0:
-                    continue  # not launched in this configuration (fused away)
-                bd[kc] = dict(ms=round(st[0]["timed_kernel_ms"], 3), **roofline(
-                    kc, st[0]["timed_kernel_ms"], st[0]["timed_kernel_bytes"], st[0]["timed_kernel_units"]))
-            res[prec]["breakdown"] = bd
-            print(f"# {prec} breakdown: {json.dumps(bd)}", file=sys.stderr, flush=True)
-    main_prec = "mixed" if "mixed" in res else a.only
+    main_res = bench_workload(bmg, a.workload, cfg, precs, a.steps, a.warmup, a.smoother,
+                              a.timed_kernel)
+    mp = "mixed" if "mixed" in main_res else a.only
     out = {
         "metric": "converged eigenpairs/s at 1e-8 rel (FP32/FP64 mixed BMG)",
-        "value": round(res[main_prec]["value"], 3),
+        "value": main_res[mp]["value"],
         "unit": "eigenpairs/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(res[main_prec]["ms_per_step"], 3),
+        "ms_per_step": main_res[mp]["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if main_prec == "mixed" else "f64",
+        "dtype": "f32+f64" if mp == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": a.workload, **{k: v for k, v in cfg.items()}, "smoother": a.smoother,
-                   "hierarchy_build_s": round(build_s, 3)},
-        "roofline": roof[main_prec],
-        "fp64_path": res.get("fp64"),
-        "mixed_path": res.get("mixed"),
+                   "hierarchy_build_s": main_res["hierarchy_build_s"]},
+        "roofline": main_res[mp]["roofline"],
+        "mixed_vs_fp64": (round(main_res["mixed"]["value"] / main_res["fp64"]["value"], 3)
+                          if a.only == "both" else None),
+        "fp64_path": main_res.get("fp64"),
+        "mixed_path": main_res.get("mixed"),
     }
+    if not a.no_c4 and a.workload != "c4_sphere_ref8":
+        c4 = bench_workload(bmg, "c4_sphere_ref8", CONFIGS["c4_sphere_ref8"], precs, 2, 1,
+                            a.smoother, "smooth")
+        out["c4"] = {"config": {"workload": "c4_sphere_ref8", **CONFIGS["c4_sphere_ref8"]},
+                     "value": c4[mp]["value"], "unit": "eigenpairs/s",
+                     "ms_per_step": c4[mp]["ms_per_step"], "roofline": c4[mp]["roofline"],
+                     "mixed_vs_fp64": (round(c4["mixed"]["value"] / c4["fp64"]["value"], 3)
+                                       if a.only == "both" else None),
+                     "fp64_path": c4.get("fp64"), "mixed_path": c4.get("mixed")}
+    if a.serving > 0:
+        out["serving"] = serving(a, bmg)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, a.smoother)
     print(json.dumps(out), flush=True)
