@@ -244,6 +244,7 @@ int launch_tail(const TailArgs* dev_args, int lds_bytes, hipStream_t s);
 struct RitzArgs {
   int n_c, m, nz;        // nz = n_c + m
   double sigma;
+  double rtol2;          // squared significance threshold of a Jacobi rotation
   const double* G;       // [nz][2m]: Z^T [A U | M U]
   const double* GW;      // [n_c][2 n_c]: W^T [A W | M W] (constant during a solve)
   double* Y;             // out [nz][m]
@@ -252,6 +253,14 @@ struct RitzArgs {
   int* status;           // out: 0 ok, 1 rank loss below m, 2 Jacobi did not converge
 };
 int launch_ritz(const RitzArgs& a, hipStream_t s);
+// Significance threshold (squared) of a rotation in the Ritz step.  An
+// off-diagonal a_pq left below 1e-11 of the diagonal scale moves a Ritz vector
+// by ~1e-11 relative and adds ~1e-11 ||C|| to its residual: far below what the
+// stopping certificate asks (rho / delta <= 1e-7) for the shifted Ritz
+// matrices of these problems (||C|| of order 1e2), and the certificate is
+// computed from the true residuals, so a looser threshold cannot pass a pair
+// that is not accurate.  Ritz values change at second order (~1e-22).
+constexpr double kRitzRtol2 = 1e-22;
 int launch_syev(int n, const double* A, double* w, double* V, int* status, hipStream_t s);
 int ritz_scratch_doubles(int nz);
 

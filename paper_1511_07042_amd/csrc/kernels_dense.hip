@@ -37,10 +37,6 @@ namespace bmg {
 namespace {
 
 constexpr int kMaxN = 96;
-// Significance threshold (squared) of a rotation in the Ritz step: a_pq below
-// 1e-13 of the diagonal scale changes the Ritz pairs by far less than the
-// residual certificate resolves (an eigenvector of C off by ~1e-13 relative).
-constexpr double kRitzRtol2 = 1e-26;
 constexpr int kMaxHalf = kMaxN / 2;
 constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
@@ -343,7 +339,7 @@ __device__ void select_nearest_zero(const double* X, int r, int mm, RitzShared& 
 
 // Global scratch: GA, GM (permuted order [U', W_c]), Bs = S (GA - sigma GM) S,
 // Lg (packed inverse Cholesky factor, or the SVQB basis T), W1 (SVQB only).
-__global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
+__global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma, double rtol2,
                                                    const double* __restrict__ G,
                                                    const double* __restrict__ GW, double* Y,
                                                    double* theta, double* scratch, int* status) {
@@ -567,7 +563,7 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
     __syncthreads();
   }
   ts[3] = wall_clock64();
-  const int sw = block_jacobi(cur, R0, r, sh.j, kRitzRtol2);
+  const int sw = block_jacobi(cur, R0, r, sh.j, rtol2);
   ts[4] = wall_clock64();
   const int mm = m < r ? m : r;
   select_nearest_zero(cur, r, mm, sh);
@@ -667,7 +663,7 @@ int launch_ritz(const RitzArgs& a, hipStream_t s) {
     return BMG_EINVAL;
   }
   set_lds_attr();
-  BMG_LAUNCH((k_ritz), 1, kThreads, lds_bytes(a.nz), s, a.n_c, a.m, a.sigma, a.G, a.GW, a.Y, a.theta,
+  BMG_LAUNCH((k_ritz), 1, kThreads, lds_bytes(a.nz), s, a.n_c, a.m, a.sigma, a.rtol2, a.G, a.GW, a.Y, a.theta,
                                               a.scratch, a.status);
   return check_launch();
 }

@@ -442,18 +442,25 @@ __global__ void __launch_bounds__(256) k_eigres(int64_t n, int W, int m, int cpr
     for (int c = threadIdx.x; c < m; c += blockDim.x) {
       double s = 0;
       for (int q = 0; q < rpb; ++q) s += sred[q * m + c];
-      part[int64_t(blockIdx.x) * m + c] = s;
+      part[int64_t(c) * gridDim.x + blockIdx.x] = s;  // column-major: [m][blocks]
     }
   }
 }
 
-// out[c] = sum_b part[b][c], one wavefront per column, fixed order.
-__global__ void k_colsum(const double* __restrict__ part, int nblk, int m, double* __restrict__ out) {
+// out[c] = sum_b part[c][b] (partials stored column-major), one 256-thread
+// block per column: each thread sums a fixed strided subset, then a fixed
+// reduction tree (deterministic).
+__global__ void __launch_bounds__(256) k_colsum(const double* __restrict__ part, int nblk, int m,
+                                                double* __restrict__ out) {
+  __shared__ double red[4];
   const int c = blockIdx.x;
+  const double* pc = part + int64_t(c) * nblk;
   double s = 0;
-  for (int b = threadIdx.x; b < nblk; b += 64) s += part[int64_t(b) * m + c];
+  for (int b = threadIdx.x; b < nblk; b += 256) s += pc[b];
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if (threadIdx.x == 0) out[c] = s;
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[c] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // --------------------------------------------------------------- transfers --
@@ -765,7 +772,7 @@ int launch_eigres(const DevLevel& L, const double* x, const double* theta, doubl
 }
 
 int launch_colsum(const double* part, int nblk, int m, double* out, hipStream_t s) {
-  k_colsum<<<m, 64, 0, s>>>(part, nblk, m, out);
+  k_colsum<<<m, 256, 0, s>>>(part, nblk, m, out);
   return check_launch();
 }
 

@@ -695,6 +695,8 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   ra.m = m;
   ra.nz = nz;
   ra.sigma = sigma;
+  ra.rtol2 = kRitzRtol2;
+  if (const char* e = std::getenv("BMG_RITZ_RTOL")) ra.rtol2 = std::atof(e) * std::atof(e);
   ra.G = w->G;
   ra.GW = w->GW;
   ra.Y = w->Y;
