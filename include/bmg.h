@@ -176,7 +176,9 @@ typedef struct {
  * of width W), m block columns, b = 4 (mixed) or 8 (FP64) bytes per correction
  * value, n_prev rows on the next coarser level, N = N_L, nz = n_c + m:
  *   EIGRES    residual SpMM:  20 nnz + 8 N m (U) + b N m (R) + 8 N (D^-1)
- *   SPMM_AM   A and M SpMM:   20 nnz + 8 N m (U) + 16 N m (A U, M U)
+ *   SPMM_AM   A and M SpMM:   20 nnz + 8 N m (U) + 16 N m (A U, M U); in a solve it
+ *             runs only at set-up (the products with W_c); the cycle's products
+ *             are formed inside the GRAM kernel
  *   SMOOTH    Jacobi: one sweep from a nonzero iterate:
  *             (4 + b) nnz + 3 b n m   (S and columns; x, f read; y written);
  *             Gauss-Seidel: one colour pass over n_k rows:
@@ -189,7 +191,8 @@ typedef struct {
  *                   (e, f read; the coarse right-hand side written);
  *   PROLONG_SMOOTH  (4 + b) nnz + 3 b n m + b n_prev m + 8 (n - n_prev)
  *                   (e, f read, y written; the coarse correction read);
- *   GRAM      8 N (nz + 2m) bytes, 4 N nz m flops;
+ *   GRAM      fused A U, M U and Z^T [A U | M U]: 4 N nz m flops (the products'
+ *             20 nnz + 8 N nz bytes read);
  *   UPDATE    8 N nz + 8 N m bytes, 2 N nz m flops;   RITZ  one workgroup. */
 typedef enum {
   BMG_K_EIGRES = 0, BMG_K_SPMM_AM = 1, BMG_K_SMOOTH = 2, BMG_K_RESIDUAL = 3,
@@ -261,9 +264,13 @@ typedef enum {
                             (column j = vector j); one-workgroup Jacobi, m <= 96 */
   BMG_OP_EIGRES = 12,    /* y = A_l x - (M_l x) diag(f), f: device [m] doubles;
                             (FP64 in, output in dtype)                           */
-  BMG_OP_UPDATE = 13     /* y [N_l][m] <- [x | y] f in place: x [N_l][m2] (NULL if
+  BMG_OP_UPDATE = 13,    /* y [N_l][m] <- [x | y] f in place: x [N_l][m2] (NULL if
                             m2 = 0), f = Y [m2 + m][m] row-major; the Ritz update
                             U <- [W_c, U'] Y (FP64, matrix cores, m2 + m <= 96)  */
+  BMG_OP_GRAM_AM = 14    /* y [m2 + m][2m] = [x | f]^T [A_l f | M_l f]: x [N_l][m2]
+                            (NULL if m2 = 0), f [N_l][m], m even; the Gram blocks
+                            of the enriched pencil with the products formed on the
+                            fly (FP64, matrix cores, m2 + m <= 96)               */
 } bmg_op;
 
 typedef struct {

@@ -211,6 +211,10 @@ struct GramPlan {
   int nz, ny, nzp, nyp, nblk;
 };
 GramPlan gram_plan(int64_t n, int nz, int ny);
+// G = [w | u]^T [A_L u | M_L u] with the products formed in LDS (fused SpMM
+// and Gram; w1 columns of w, m of u; plan for nz = w1 + m, ny = 2 m).
+int launch_gram_am(const GramPlan& p, const DevLevel& L, const double* w, int w1, const double* u,
+                   int m, double* part, double* G, hipStream_t s);
 int launch_gram(const GramPlan& p, int64_t n, const double* z1, int w1, const double* z2, int w2,
                 const double* y1, int v1, const double* y2, int v2, double* part, double* G,
                 hipStream_t s);

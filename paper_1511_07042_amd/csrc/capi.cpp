@@ -345,6 +345,19 @@ int bmg_apply(const bmg_hierarchy* hc, const bmg_apply_args* a, const void* x, c
       return f32 ? launch_eigres<float>(D, (const double*)x, (const double*)f, 1.0, (float*)y, nullptr, eigres_blocks(D, m), m, s)
                  : launch_eigres<double>(D, (const double*)x, (const double*)f, 1.0, (double*)y, nullptr, eigres_blocks(D, m), m, s);
     }
+    case BMG_OP_GRAM_AM: {
+      BMG_CHECK(f && !f32, "GRAM_AM takes FP64 blocks");
+      BMG_CHECK(m >= 2 && m % 2 == 0 && a->m2 >= 0 && a->m2 + m <= 96 && 2 * m <= 192 &&
+                    (a->m2 == 0 || x != nullptr),
+                "GRAM_AM needs even m, 0 <= m2, m2 + m <= 96, and x when m2 > 0");
+      GramPlan p = gram_plan(D.n, a->m2 + m, 2 * m);
+      double* part = nullptr;
+      BMG_HIP(hipMalloc(&part, sizeof(double) * p.nblk * p.nzp * p.nyp));
+      int st = launch_gram_am(p, D, (const double*)x, a->m2, (const double*)f, m, part, (double*)y, s);
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(part);
+      return st;
+    }
     case BMG_OP_UPDATE: {
       BMG_CHECK(f && !f32, "UPDATE takes FP64 blocks and an FP64 Y in f");
       BMG_CHECK(m >= 4 && m % 4 == 0 && m <= 96, "UPDATE needs m a multiple of 4 in [4, 96]");

@@ -91,6 +91,129 @@ __global__ void __launch_bounds__(256) k_gram(int64_t n, int64_t rows_per_block,
   }
 }
 
+constexpr int kGramAmChunk = 16;  // rows whose products share one LDS pass
+
+// Fused SpMM and Gram: G = Z^T [A U, M U] with Z = [W | U] (W: w1 columns,
+// U: m columns), the products A U and M U formed row chunk by row chunk in LDS
+// and contracted at once, so they never travel to or from HBM.  For each
+// 16-row chunk of its range a block (256 threads) first computes the chunk's
+// rows of A U and M U (FP64, one thread per row and column pair, the ELL row
+// gathered against U), then its four wavefronts run the chunk's MFMAs exactly
+// as k_gram does, with the B fragments read from LDS.  Partial sums per block
+// as in k_gram (reduced by k_gram_reduce in a fixed order).  A chunk is
+// kGramAmChunk rows: its products are formed in one pass (more gathers in
+// flight per barrier) and contracted 16 rows at a time.
+template <int TI, int TJW, int WT>
+__global__ void __launch_bounds__(256) k_gram_am(int64_t n, int64_t rows_per_block, int nzp, int nyp,
+                                                 const int* __restrict__ cols,
+                                                 const double* __restrict__ a,
+                                                 const double* __restrict__ mm, int W,
+                                                 const double* __restrict__ z1, int w1,
+                                                 const double* __restrict__ u, int m,
+                                                 double* __restrict__ part) {
+  constexpr int CH = kGramAmChunk;
+  extern __shared__ double ys[];  // [CH][nyp]: rows of [A U | M U] (zero padded)
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int TJ = nyp / 16;
+  const int li = lane & 15;
+  const int lk = lane >> 4;
+  const int cpr = m / 2;          // column pairs of U
+  const int items = CH * cpr;     // (row, pair) items of a chunk
+  d4 acc[TI][TJW];
+  for (int i = 0; i < TI; ++i)
+    for (int t = 0; t < TJW; ++t) acc[i][t] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int e = threadIdx.x; e < CH * nyp; e += blockDim.x) ys[e] = 0.0;
+  const int64_t rb = int64_t(blockIdx.x) * rows_per_block;
+  const int64_t re = rb + rows_per_block < n ? rb + rows_per_block : n;
+  for (int64_t r0 = rb; r0 < re; r0 += CH) {
+    // A fragments of the chunk's first 16 rows (global), issued before the products
+    double af[4][TI];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t r = r0 + 4 * q + lk;
+      const bool ok = r < re;
+#pragma unroll
+      for (int i = 0; i < TI; ++i) af[q][i] = ok ? zcol(z1, w1, u, m, r, 16 * i + li) : 0.0;
+    }
+    __syncthreads();  // the previous chunk's B fragments have been read
+    for (int e = threadIdx.x; e < items; e += blockDim.x) {
+      const int rl = e / cpr, ch = e - (e / cpr) * cpr;
+      const int64_t r = r0 + rl;
+      double a0 = 0.0, a1 = 0.0, m0 = 0.0, m1 = 0.0;
+      if (r < re) {
+        const int64_t base = r * W;
+        if (WT > 0) {
+          int j[WT > 0 ? WT : 1];
+          double av[WT > 0 ? WT : 1], mv[WT > 0 ? WT : 1];
+          double2 xv[WT > 0 ? WT : 1];
+#pragma unroll
+          for (int k = 0; k < WT; ++k) {
+            j[k] = cols[base + k];
+            av[k] = a[base + k];
+            mv[k] = mm[base + k];
+          }
+#pragma unroll
+          for (int k = 0; k < WT; ++k)
+            xv[k] = *reinterpret_cast<const double2*>(u + int64_t(j[k]) * m + 2 * ch);
+#pragma unroll
+          for (int k = 0; k < WT; ++k) {
+            a0 += av[k] * xv[k].x;
+            a1 += av[k] * xv[k].y;
+            m0 += mv[k] * xv[k].x;
+            m1 += mv[k] * xv[k].y;
+          }
+        } else {
+          for (int k = 0; k < W; ++k) {
+            const int jj = cols[base + k];
+            const double av = a[base + k], mv = mm[base + k];
+            const double2 xv = *reinterpret_cast<const double2*>(u + int64_t(jj) * m + 2 * ch);
+            a0 += av * xv.x;
+            a1 += av * xv.y;
+            m0 += mv * xv.x;
+            m1 += mv * xv.y;
+          }
+        }
+      }
+      double* yr = ys + rl * nyp;
+      yr[2 * ch] = a0;
+      yr[2 * ch + 1] = a1;
+      yr[m + 2 * ch] = m0;
+      yr[m + 2 * ch + 1] = m1;
+    }
+    __syncthreads();
+    for (int h = 0; h < CH / 16; ++h) {
+      if (h > 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t r = r0 + 16 * h + 4 * q + lk;
+          const bool ok = r < re;
+#pragma unroll
+          for (int i = 0; i < TI; ++i) af[q][i] = ok ? zcol(z1, w1, u, m, r, 16 * i + li) : 0.0;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int t = 0; t < TJW; ++t) {
+          const int tj = wave + 4 * t;
+          if (tj >= TJ) continue;
+          const double b = ys[(16 * h + 4 * q + lk) * nyp + 16 * tj + li];
+#pragma unroll
+          for (int i = 0; i < TI; ++i)
+            acc[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[q][i], b, acc[i][t], 0, 0, 0);
+        }
+    }
+  }
+  double* out = part + int64_t(blockIdx.x) * nzp * nyp;
+  for (int t = 0; t < TJW; ++t) {
+    const int tj = wave + 4 * t;
+    if (tj >= TJ) break;
+    for (int i = 0; i < TI; ++i)
+      for (int v = 0; v < 4; ++v) out[(16 * i + lk + 4 * v) * nyp + 16 * tj + li] = acc[i][t][v];
+  }
+}
+
 // G[i][j] = sum_b part[b][i][j] in a fixed order: each block covers 64
 // consecutive outputs with 16 segments of the partials (b = seg mod 16), then
 // adds the 16 segment sums in order.
@@ -246,6 +369,61 @@ int launch_gram(const GramPlan& p, int64_t n, const double* z1, int w1, const do
     case 6 * 4 + 3: GL(6, 3); break;
   }
 #undef GL
+  int st = check_launch();
+  if (st != BMG_OK) return st;
+  const int tot = p.nz * p.ny;
+  BMG_LAUNCH((k_gram_reduce), (tot + 63) / 64, 1024, 0, s, part, p.nblk, p.nzp, p.nyp, p.nz, p.ny, G);
+  return check_launch();
+}
+
+int launch_gram_am(const GramPlan& p, const DevLevel& L, const double* w, int w1, const double* u,
+                   int m, double* part, double* G, hipStream_t s) {
+  const int TI = p.nzp / 16;
+  const int TJ = p.nyp / 16;
+  const int TJW = (TJ + 3) / 4;
+  if (TI < 1 || TI > 6 || TJW < 1 || TJW > 3 || p.ny != 2 * m || p.nz != w1 + m || m % 2 != 0) {
+    set_error("gram_am: unsupported shape nz=%d ny=%d m=%d", p.nz, p.ny, m);
+    return BMG_EINVAL;
+  }
+  const int64_t n = L.n;
+  int64_t rpb = (n + p.nblk - 1) / p.nblk;
+  rpb = (rpb + kGramAmChunk - 1) / kGramAmChunk * kGramAmChunk;
+  const size_t shm = size_t(kGramAmChunk) * p.nyp * sizeof(double);
+  {
+    const LaunchEvents ev = g_launch_events;
+    g_launch_events = LaunchEvents{ev.start, nullptr};
+#define GA(a_, b_)                                                                                 \
+  do {                                                                                             \
+    if (L.W == 7)                                                                                  \
+      BMG_LAUNCH((k_gram_am<a_, b_, 7>), p.nblk, 256, shm, s, n, rpb, p.nzp, p.nyp, L.cols, L.a64, \
+                 L.m64, L.W, w, w1, u, m, part);                                                    \
+    else                                                                                           \
+      BMG_LAUNCH((k_gram_am<a_, b_, 0>), p.nblk, 256, shm, s, n, rpb, p.nzp, p.nyp, L.cols, L.a64, \
+                 L.m64, L.W, w, w1, u, m, part);                                                    \
+  } while (0)
+    switch (TI * 4 + TJW) {
+      case 1 * 4 + 1: GA(1, 1); break;
+      case 1 * 4 + 2: GA(1, 2); break;
+      case 1 * 4 + 3: GA(1, 3); break;
+      case 2 * 4 + 1: GA(2, 1); break;
+      case 2 * 4 + 2: GA(2, 2); break;
+      case 2 * 4 + 3: GA(2, 3); break;
+      case 3 * 4 + 1: GA(3, 1); break;
+      case 3 * 4 + 2: GA(3, 2); break;
+      case 3 * 4 + 3: GA(3, 3); break;
+      case 4 * 4 + 1: GA(4, 1); break;
+      case 4 * 4 + 2: GA(4, 2); break;
+      case 4 * 4 + 3: GA(4, 3); break;
+      case 5 * 4 + 1: GA(5, 1); break;
+      case 5 * 4 + 2: GA(5, 2); break;
+      case 5 * 4 + 3: GA(5, 3); break;
+      case 6 * 4 + 1: GA(6, 1); break;
+      case 6 * 4 + 2: GA(6, 2); break;
+      case 6 * 4 + 3: GA(6, 3); break;
+    }
+#undef GA
+    g_launch_events = LaunchEvents{nullptr, ev.stop};
+  }
   int st = check_launch();
   if (st != BMG_OK) return st;
   const int tot = p.nz * p.ny;

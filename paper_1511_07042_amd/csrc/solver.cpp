@@ -704,13 +704,10 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   ra.scratch = w->rscratch;
   ra.status = w->status;
   auto ritz_step = [&]() -> int {
-    kt.add(BMG_K_SPMM_AM, 20 * nnzL + 24 * Nd * m, 1);
-    BMG_TRY(kt.begin(BMG_K_SPMM_AM));
-    BMG_TRY(launch_spmm_am(DL, w->U, w->AU, w->MU, m, s));
-    BMG_TRY(kt.end(BMG_K_SPMM_AM));
+    // H4: A U', M U' and the Gram blocks of Z = [W_c, U'] in one fused pass
     kt.add(BMG_K_GRAM, 4.0 * Nd * nz * m, 1);
     BMG_TRY(kt.begin(BMG_K_GRAM));
-    BMG_TRY(launch_gram(w->gp, N, w->W, n_c, w->U, m, w->AU, m, w->MU, m, w->gpart, w->G, s));
+    BMG_TRY(launch_gram_am(w->gp, DL, w->W, n_c, w->U, m, w->gpart, w->G, s));
     BMG_TRY(kt.end(BMG_K_GRAM));
     kt.add(BMG_K_RITZ, 0.0, 1);
     BMG_TRY(kt.begin(BMG_K_RITZ));

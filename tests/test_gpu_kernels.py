@@ -267,3 +267,41 @@ def test_runtime_width_kernels(env):
     torch.cuda.synchronize()
     ref = A @ x - (M @ x) * th[None, :]
     assert _rel(_host(y), ref, abs(A) @ np.abs(x) + (abs(M) @ np.abs(x)) * th[None, :]) < 1e-14
+
+
+@pytest.mark.parametrize("level", [1, 4])
+@pytest.mark.parametrize("m2,m", [(0, 8), (12, 32), (12, 80), (32, 40), (4, 92)])
+def test_gram_fused_products(env, level, m2, m):
+    # [W | U]^T [A U | M U] with A U and M U formed inside the Gram kernel
+    torch, p, h, lv = env
+    L = lv[level]
+    rng = np.random.default_rng(7 * m + m2 + level)
+    W, U = rng.standard_normal((L.n, m2)), rng.standard_normal((L.n, m))
+    y = torch.zeros((m2 + m, 2 * m), dtype=torch.float64, device="cuda")
+    h.apply("gram_am", x=_dev(torch, W) if m2 else None, f=_dev(torch, U), y=y, m=m, m2=m2,
+            level=level)
+    torch.cuda.synchronize()
+    Z = np.hstack([W, U])
+    Y = np.hstack([L.A @ U, L.M @ U])
+    scale = np.abs(Z).T @ np.hstack([abs(L.A) @ np.abs(U), abs(L.M) @ np.abs(U)])
+    err = _rel(_host(y), Z.T @ Y, scale)
+    assert err < 1e-14, err
+
+
+def test_gram_fused_runtime_width(env):
+    torch, p, _, _ = env
+    from oracle import fem, mesh
+    xyz, tri = _bipyramid(8)
+    h = p.Hierarchy("custom", 3, xyz=xyz, tri=tri, project=mesh.project_sphere)
+    X, T = xyz, tri
+    for _ in range(3):
+        X, T, _par = mesh.refine(X, T, mesh.project_sphere)
+    A, M = fem.assemble(X, T)
+    rng = np.random.default_rng(5)
+    W, U = rng.standard_normal((A.shape[0], 10)), rng.standard_normal((A.shape[0], 12))
+    y = torch.zeros((22, 24), dtype=torch.float64, device="cuda")
+    h.apply("gram_am", x=_dev(torch, W), f=_dev(torch, U), y=y, m=12, m2=10)
+    torch.cuda.synchronize()
+    Z = np.hstack([W, U])
+    scale = np.abs(Z).T @ np.hstack([abs(A) @ np.abs(U), abs(M) @ np.abs(U)])
+    assert _rel(_host(y), Z.T @ np.hstack([A @ U, M @ U]), scale) < 1e-14
