@@ -220,8 +220,15 @@ def cpu_baseline(cfg, smoother, budget_s=10.0, max_solves=4):
         cycles.append(info["cycles"])
         n += 1
     dt = time.perf_counter() - t0
+    # second CPU reference: a library eigensolve of the same pencil (ARPACK
+    # shift-invert with SuperLU), timed once
+    from oracle import reference
+    t1 = time.perf_counter()
+    reference.discrete_eigs(lv[-1].A, lv[-1].M, cfg["k"], cfg["sigma"])
+    eigsh_s = time.perf_counter() - t1
     blas = max((p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()), default=1)
     return dict(value=round(n * cfg["k"] / dt, 4), unit="eigenpairs/s", cores=int(blas), kind="oracle",
+                library_eigsh_s=round(eigsh_s, 3),
                 sample=f"{n} full oracle solves of the same workload, seeds 0..{n - 1} "
                        f"({cycles} cycles, {dt:.1f} s); dense BLAS on {blas} threads, "
                        f"scipy.sparse products single-threaded; host os.cpu_count() = {os.cpu_count()}")
