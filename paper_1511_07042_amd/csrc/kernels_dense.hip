@@ -56,7 +56,6 @@ struct JacobiShared {
   // only): (c, s), t, and the pair (p, q)
   double2 cs[kWaves][kMaxHalf];
   double tt[kWaves][kMaxHalf];
-  int2 pq[kWaves][kMaxHalf];
   double red[2 * kWaves];
   double bcast[2];
   int sig[3];  // per sweep (mod 3): a significant rotation was applied
@@ -150,8 +149,9 @@ __device__ __forceinline__ RotRec rot_params(const double* X, int p, int q, int 
 }
 
 // Diagonalise the packed symmetric n x n matrix X (LDS) in place.  On return
-// X holds the diagonal form (eigenvalues on the diagonal, unsorted) and V (LDS,
-// n x n row-major) is orthogonal with X_in = V diag V^T.  A rotation is
+// X holds the diagonal form (eigenvalues on the diagonal, unsorted) and V (LDS)
+// holds the eigenvectors as rows: V[j * ldv + i] = component i of eigenvector
+// j, with ldv = n rounded up to even, so X_in = V^T diag V.  A rotation is
 // significant when a_pq^2 > rtol2 max(|a_pp a_qq|, (||X||_F / n)^2); sweeps
 // stop after a sweep without one.  Returns the sweeps used, or -1 if the limit
 // was hit.
@@ -159,24 +159,29 @@ __device__ __forceinline__ RotRec rot_params(const double* X, int p, int q, int 
 // A round costs two barriers (rotations computed, then updates done), and
 // nothing when none of its rotations is significant.  Every wave computes the
 // round's rotations (lane i: pair i) into its own LDS slot and keeps the
-// ballot of significant pairs in a scalar register: a thread touches a 2x2
-// block of X only if one of its two rotations is significant, and an
-// eigenvector item only if its rotation is.  The blocks of a round partition X
-// and the (row, pair) items partition the changed entries of V, so the
-// updates are done in place: no element is read by one thread and written by
-// another within a round.
-__device__ __forceinline__ int block_jacobi(double* X, double* V, int n, JacobiShared& sh, double rtol2) {
+// ballot of significant pairs in a scalar register; the pairs themselves are
+// recomputed from the round number (circle method) wherever they are needed.
+// A thread touches a 2x2 block of X only if one of its two rotations is
+// significant, and a 16-byte item of two rows of V only if its rotation is.
+// The blocks of a round partition X and the items partition the changed
+// entries of V, so the updates are done in place.
+__device__ __forceinline__ int block_jacobi(double* X, double* V, int n, JacobiShared& sh,
+                                            double rtol2) {
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
   const int ne = n + (n & 1);
+  const int ldv = ne;
   const int half = ne / 2;
   const int nb = half * (half + 1) / 2;  // blocks (t1 <= t2)
   constexpr int kNB = (kMaxHalf * (kMaxHalf + 1) / 2 + kThreads - 1) / kThreads;
+  constexpr int kVI = (kMaxHalf * kMaxHalf + kThreads - 1) / kThreads;
   double f2 = 0.0;
-  for (int e = tid; e < n * n; e += nt) {
-    const int i = e / n, j = e - (e / n) * n;
+  for (int e = tid; e < n * ldv; e += nt) {
+    const int i = e / ldv, j = e - (e / ldv) * ldv;
     V[e] = (i == j) ? 1.0 : 0.0;
-    const double x = X[sym(i, j)];
-    f2 += x * x;
+    if (j < n) {
+      const double x = X[sym(i, j)];
+      f2 += x * x;
+    }
   }
   if (tid == 0) {
     sh.sig[0] = 0;
@@ -202,14 +207,17 @@ __device__ __forceinline__ int block_jacobi(double* X, double* V, int n, JacobiS
     bt1[i] = t1;
     bt2[i] = t2;
   }
-  // eigenvector items: pair slot vt = tid mod half (threads below half * G),
-  // rows vr0, vr0 + G, ...  (G = nt / half row groups)
-  const int G = nt / half;
-  const int vt = tid % half, vr0 = tid / half;
-  const bool vlive = vr0 < G;
+  // eigenvector items: (pair slot vt, column pair vc) of the rows p and q of V
+  const int nvc = ne / 2;
+  int vt[kVI], vc[kVI];
+#pragma unroll
+  for (int i = 0; i < kVI; ++i) {
+    const int it = tid + i * nt;
+    vt[i] = it < half * nvc ? it / nvc : -1;
+    vc[i] = it < half * nvc ? it - (it / nvc) * nvc : 0;
+  }
   double2* cs = sh.cs[wave];
   double* tt = sh.tt[wave];
-  int2* pq = sh.pq[wave];
   int rounds = 0;  // thread 0: rounds with a significant rotation
   int ret = -1;
   for (int sweep = 0; sweep < 30 && ret < 0; ++sweep) {
@@ -224,7 +232,6 @@ __device__ __forceinline__ int block_jacobi(double* X, double* V, int n, JacobiS
         const RotRec r = rot_params(X, p, q, n, floor2, rtol2);
         cs[lane] = double2{r.c, r.s};
         tt[lane] = r.t;
-        pq[lane] = int2{p, q};
         sg = r.s != 0.0;
       }
       // identical in every wave: skip the round (no writes, no barrier)
@@ -242,20 +249,19 @@ __device__ __forceinline__ int block_jacobi(double* X, double* V, int n, JacobiS
         const int t1 = bt1[i], t2 = bt2[i];
         const bool g1 = (mask >> t1) & 1, g2 = (mask >> t2) & 1;
         if (!g1 && !g2) continue;
-        const int2 P2 = pq[t2];
+        int a1, b1, p2, q2;
+        rr_pair(t2, rd, ne, p2, q2);
         const double2 C2 = cs[t2];
         if (t1 == t2) {
-          const int p = P2.x, q = P2.y;  // significant: q < n
-          const double app = X[tri(p, p)], apq = X[tri(q, p)], aqq = X[tri(q, q)];
+          const double app = X[tri(p2, p2)], apq = X[tri(q2, p2)], aqq = X[tri(q2, q2)];
           const double t = tt[t2];
-          X[tri(p, p)] = app - t * apq;
-          X[tri(q, q)] = aqq + t * apq;
-          X[tri(q, p)] = 0.0;
+          X[tri(p2, p2)] = app - t * apq;
+          X[tri(q2, q2)] = aqq + t * apq;
+          X[tri(q2, p2)] = 0.0;
           continue;
         }
-        const int2 P1 = pq[t1];
+        rr_pair(t1, rd, ne, a1, b1);
         const double2 C1 = cs[t1];
-        const int a1 = P1.x, b1 = P1.y, p2 = P2.x, q2 = P2.y;
         const bool hq1 = b1 < n, hq2 = q2 < n;
         const double bpp = X[sym(a1, p2)];
         const double bpq = hq2 ? X[sym(a1, q2)] : 0.0;
@@ -269,16 +275,17 @@ __device__ __forceinline__ int block_jacobi(double* X, double* V, int n, JacobiS
         if (hq1) X[sym(b1, p2)] = c2 * lqp - s2 * lqq;
         if (hq1 && hq2) X[sym(b1, q2)] = s2 * lqp + c2 * lqq;
       }
-      if (vlive && ((mask >> vt) & 1)) {
-        const int2 P = pq[vt];
-        const double2 C = cs[vt];
-        constexpr int kVR = kMaxN;  // G >= 1 rows apart; at most n rows
-        for (int k = vr0; k < n && k < kVR; k += G) {
-          double* vr = V + k * n;
-          const double vp = vr[P.x], vq = vr[P.y];
-          vr[P.x] = C.x * vp - C.y * vq;
-          vr[P.y] = C.y * vp + C.x * vq;
-        }
+#pragma unroll
+      for (int i = 0; i < kVI; ++i) {
+        if (vt[i] < 0 || !((mask >> vt[i]) & 1)) continue;
+        int p, q;
+        rr_pair(vt[i], rd, ne, p, q);
+        const double2 C = cs[vt[i]];
+        double2* vp = reinterpret_cast<double2*>(V + p * ldv) + vc[i];
+        double2* vq = reinterpret_cast<double2*>(V + q * ldv) + vc[i];
+        const double2 a = *vp, b = *vq;
+        *vp = double2{C.x * a.x - C.y * b.x, C.x * a.y - C.y * b.y};
+        *vq = double2{C.y * a.x + C.x * b.x, C.y * a.y + C.x * b.y};
       }
       __syncthreads();
     }
@@ -299,12 +306,15 @@ struct RitzShared {
   int r;
 };
 
-constexpr int shared_doubles() { return int((sizeof(RitzShared) + 7) / 8); }
+// doubles before the matrices: even, so the eigenvector rows are 16-byte aligned
+constexpr int shared_doubles() { return int((sizeof(RitzShared) + 15) / 16) * 2; }
+// doubles of the eigenvector matrix: n rows of n rounded up to even
+__host__ __device__ constexpr int vsize(int n) { return n * (n + (n & 1)); }
 
 // LDS: [RitzShared][R0: n*n][Ra: n(n+1)/2][Rb: n(n+1)/2]
-size_t lds_bytes(int n) { return (size_t(shared_doubles()) + size_t(n) * n + size_t(n) * (n + 1)) * 8; }
+size_t lds_bytes(int n) { return (size_t(shared_doubles()) + size_t(vsize(n)) + size_t(n) * (n + 1)) * 8; }
 
-static_assert((shared_doubles() + kMaxN * kMaxN + kMaxN * (kMaxN + 1)) * 8 <= 160 * 1024,
+static_assert((shared_doubles() + vsize(kMaxN) + kMaxN * (kMaxN + 1)) * 8 <= 160 * 1024,
               "the Ritz kernel's LDS must fit one CU (160 KiB)");
 
 // Select the mm diagonal entries of the packed r x r matrix X nearest 0 (ties
@@ -347,8 +357,8 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
   RitzShared& sh = *reinterpret_cast<RitzShared*>(lds);
   const int nz = n_c + m;
   const int n = nz;
-  double* R0 = lds + shared_doubles();  // [nz][nz]
-  double* Ra = R0 + nz * nz;            // packed
+  double* R0 = lds + shared_doubles();  // [nz][nz] (eigenvectors: rows of even length)
+  double* Ra = R0 + vsize(nz);          // packed
   double* Rb = Ra + nz * (nz + 1) / 2;  // packed
   double* GA = scratch;
   double* GM = GA + nz * nz;
@@ -538,7 +548,7 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
     double* T = Lg;  // [nz][r]: basis coefficients
     for (int e = tid; e < nz * r; e += nt) {
       const int i = e / r, q = e - (e / r) * r;
-      T[e] = sh.sv[i] * R0[i * nz + sh.kk[q]] / sqrt(sh.d[q]);
+      T[e] = sh.sv[i] * R0[sh.kk[q] * (nz + (nz & 1)) + i] / sqrt(sh.d[q]);
     }
     __syncthreads();
     for (int e = tid; e < nz * r; e += nt) {
@@ -580,11 +590,11 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
       if (chol) {
         const int q = sh.dropmap[a];
         if (q >= 0) {
-          for (int b = q; b < r; ++b) acc += nxt[tri(b, q)] * R0[b * r + col];
+          for (int b = q; b < r; ++b) acc += nxt[tri(b, q)] * R0[col * (r + (r & 1)) + b];
           acc *= sh.sv[a];
         }
       } else {
-        for (int q = 0; q < r; ++q) acc += Lg[a * r + q] * R0[q * r + col];
+        for (int q = 0; q < r; ++q) acc += Lg[a * r + q] * R0[col * (r + (r & 1)) + q];
       }
     }
     Y[orig(a) * m + c] = acc;
@@ -607,7 +617,7 @@ __global__ void __launch_bounds__(kThreads) k_syev(int n, const double* __restri
   extern __shared__ double lds[];
   RitzShared& sh = *reinterpret_cast<RitzShared*>(lds);
   double* R0 = lds + shared_doubles();
-  double* cur = R0 + n * n;
+  double* cur = R0 + vsize(n);
   double* nxt = cur + n * (n + 1) / 2;
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int e = tid; e < n * n; e += nt) {
@@ -631,7 +641,7 @@ __global__ void __launch_bounds__(kThreads) k_syev(int n, const double* __restri
   for (int c = tid; c < n; c += nt) w[c] = sh.d[sh.sel[c]];
   for (int e = tid; e < n * n; e += nt) {
     const int i = e / n, c = e - (e / n) * n;
-    Vout[e] = R0[i * n + sh.sel[c]];
+    Vout[e] = R0[sh.sel[c] * (n + (n & 1)) + i];
   }
   if (tid == 0) *status = sw < 0 ? 2 : 0;
 }
