@@ -296,12 +296,47 @@ __device__ __forceinline__ int block_jacobi(double* X, double* V, int n, JacobiS
   return ret;
 }
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// C (M x N) = A (M x K) B (K x N) for small operands in LDS, on the FP64
+// matrix cores: the 16 x 16 output tiles are shared out over the workgroup's
+// wavefronts; a tile runs ceil(K / 4) v_mfma_f64_16x16x4f64 steps with the
+// fragments fetched through fa(i, k) and fb(k, j) (0 outside the operands), and
+// each output element is handed once to fo(i, j, value).  Lane layouts: A lane
+// l holds row l % 16 and k = l / 16; B lane l holds k = l / 16 and column l % 16;
+// result lane l holds column l % 16 of rows l / 16 + 4 v.  skip(ti, tj) drops
+// tiles whose outputs are not needed.
+template <class FA, class FB, class FO, class SK>
+__device__ __forceinline__ void lds_mfma_gemm(int M, int N, int K, FA fa, FB fb, FO fo, SK skip) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tm = (M + 15) / 16, tn = (N + 15) / 16;
+  for (int id = wave; id < tm * tn; id += nw) {
+    const int ti = id / tn, tj = id - (id / tn) * tn;
+    if (skip(ti, tj)) continue;
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+    const int i = 16 * ti + li, j = 16 * tj + li;
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int k = k0 + lk;
+      const double a = (i < M && k < K) ? fa(i, k) : 0.0;
+      const double b = (k < K && j < N) ? fb(k, j) : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * ti + lk + 4 * v;
+      if (row < M && j < N) fo(row, j, acc[v]);
+    }
+  }
+}
+
 struct RitzShared {
   JacobiShared j;
   double sv[kMaxN];
   double d[kMaxN];
   int kk[kMaxN];
   int sel[kMaxN];
+  int rank[kMaxN];     // selection scratch
   int dropmap[kMaxN];  // permuted column -> position among the kept ones, or -1
   int r;
 };
@@ -330,15 +365,15 @@ __device__ void select_nearest_zero(const double* X, int r, int mm, RitzShared& 
       const double mi = sh.d[i], ai = fabs(mi);
       if (ai < aj || (ai == aj && (mi < mj || (mi == mj && i < j)))) ++rank;
     }
-    sh.kk[j] = rank;
+    sh.rank[j] = rank;
   }
   __syncthreads();
   for (int j = tid; j < r; j += nt) {
-    if (sh.kk[j] >= mm) continue;
+    if (sh.rank[j] >= mm) continue;
     const double mj = sh.d[j];
     int pos = 0;
     for (int i = 0; i < r; ++i) {
-      if (sh.kk[i] >= mm) continue;
+      if (sh.rank[i] >= mm) continue;
       const double mi = sh.d[i];
       if (mi < mj || (mi == mj && i < j)) ++pos;
     }
@@ -483,43 +518,20 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
       if (b <= a) Rb[tri(a, b)] = Bs[sh.kk[a] * n + sh.kk[b]];
     }
     __syncthreads();
-    // W1 = Li Bk into R0 (r x r)
-    for (int e = tid; e < r * r; e += nt) {
-      const int i = e / r, j = e - (e / r) * r;
-      const double* li = Ra + tri(i, 0);
-      double a0 = 0.0, a1 = 0.0;
-      int k = 0;
-      for (; k + 1 <= i; k += 2) {
-        a0 += li[k] * Rb[sym(k, j)];
-        a1 += li[k + 1] * Rb[sym(k + 1, j)];
-      }
-      if (k <= i) a0 += li[k] * Rb[sym(k, j)];
-      R0[e] = a0 + a1;
-    }
+    // W1 = Li Bk into R0 (r x r), then C = W1 Li^T: only its lower triangle is
+    // kept (C is symmetric; the packed Jacobi matrix stores the lower part)
+    lds_mfma_gemm(
+        r, r, r, [&](int i, int k) { return k <= i ? Ra[tri(i, k)] : 0.0; },
+        [&](int k, int j) { return Rb[sym(k, j)]; },
+        [&](int i, int j, double v) { R0[i * r + j] = v; }, [](int, int) { return false; });
     __syncthreads();
-    // C = W1 Li^T, symmetrised, into Rb
-    for (int e = tid; e < r * r; e += nt) {
-      const int i = e / r, j = e - (e / r) * r;
-      if (j > i) continue;
-      const double* wi = R0 + i * r;
-      const double* wj = R0 + j * r;
-      const double* li = Ra + tri(i, 0);
-      const double* lj = Ra + tri(j, 0);
-      double a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0;
-      int k = 0;
-      for (; k + 1 <= j; k += 2) {
-        a1 += wi[k] * lj[k];
-        a3 += wi[k + 1] * lj[k + 1];
-      }
-      if (k <= j) a1 += wi[k] * lj[k];
-      k = 0;
-      for (; k + 1 <= i; k += 2) {
-        a2 += wj[k] * li[k];
-        a4 += wj[k + 1] * li[k + 1];
-      }
-      if (k <= i) a2 += wj[k] * li[k];
-      Rb[tri(i, j)] = 0.5 * ((a1 + a3) + (a2 + a4));
-    }
+    lds_mfma_gemm(
+        r, r, r, [&](int i, int k) { return R0[i * r + k]; },
+        [&](int k, int j) { return k <= j ? Ra[tri(j, k)] : 0.0; },
+        [&](int i, int j, double v) {
+          if (j <= i) Rb[tri(i, j)] = v;
+        },
+        [](int ti, int tj) { return tj > ti; });
     __syncthreads();
   } else {
     // ---- SVQB: eigendecompose the scaled Gram matrix, drop tiny directions
@@ -582,22 +594,32 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
     __syncthreads();
   }
   // Y (rows in the caller's order [W_c, U']) = basis coefficients of the selection
-  for (int e = tid; e < nz * m; e += nt) {
-    const int a = e / m, c = e - (e / m) * m;  // a: permuted row
-    double acc = 0.0;
-    if (c < mm) {
-      const int col = sh.sel[c];
-      if (chol) {
-        const int q = sh.dropmap[a];
-        if (q >= 0) {
-          for (int b = q; b < r; ++b) acc += nxt[tri(b, q)] * R0[col * (r + (r & 1)) + b];
-          acc *= sh.sv[a];
-        }
-      } else {
-        for (int q = 0; q < r; ++q) acc += Lg[a * r + q] * R0[col * (r + (r & 1)) + q];
-      }
+  const int ldv = r + (r & 1);
+  if (chol) {
+    // Y[kk[q]][c] = sv[kk[q]] (Li^T V_sel)[q][c] on the matrix cores; rows of
+    // dropped columns and columns beyond the selection are zero
+    lds_mfma_gemm(
+        r, mm, r, [&](int q, int b) { return b >= q ? nxt[tri(b, q)] : 0.0; },
+        [&](int b, int c) { return R0[sh.sel[c] * ldv + b]; },
+        [&](int q, int c, double v) {
+          const int a = sh.kk[q];
+          Y[orig(a) * m + c] = sh.sv[a] * v;
+        },
+        [](int, int) { return false; });
+    for (int e = tid; e < nz * m; e += nt) {
+      const int a = e / m, c = e - (e / m) * m;
+      if (sh.dropmap[a] < 0 || c >= mm) Y[orig(a) * m + c] = 0.0;
     }
-    Y[orig(a) * m + c] = acc;
+  } else {
+    for (int e = tid; e < nz * m; e += nt) {
+      const int a = e / m, c = e - (e / m) * m;  // a: permuted row
+      double acc = 0.0;
+      if (c < mm) {
+        const int col = sh.sel[c];
+        for (int q = 0; q < r; ++q) acc += Lg[a * r + q] * R0[col * ldv + q];
+      }
+      Y[orig(a) * m + c] = acc;
+    }
   }
   for (int c = tid; c < m; c += nt) theta[c] = c < mm ? sh.d[sh.sel[c]] + sigma : 0.0;
   ts[5] = wall_clock64();
