@@ -337,6 +337,8 @@ struct RitzShared {
   int kk[kMaxN];
   int sel[kMaxN];
   int rank[kMaxN];     // selection scratch
+  double f1[kMaxN];    // Cholesky: step-j multiplier of row j + 1 of each pair
+  double p1[kMaxN];    // and its pivot after step j
   int dropmap[kMaxN];  // permuted column -> position among the kept ones, or -1
   int r;
 };
@@ -455,12 +457,81 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
   // the span of the kept columns before it) is below 1e-10 is dropped: it
   // adds nothing to the enriched space.  With sigma = 0 this happens to the
   // constant vector of W_c once U' holds the converged constant mode.
-  for (int j = 0; j < n; ++j) {
+  // Columns are eliminated two at a time (one barrier per pair): every thread
+  // forms the second pivot and the first step's multipliers of the rows it
+  // touches from the values before the pair, so both steps land in one pass.
+  constexpr int kCW = 16, kCE = (kMaxN + kCW - 1) / kCW;
+  int j = 0;
+  for (; j + 1 < n; j += 2) {
+    const int j1 = j + 1;
+    const double p0 = Ra[tri(j, j)];
+    const bool k0 = p0 > 1e-10;  // uniform: every thread reads the same pivots
+    const double ip0 = k0 ? 1.0 / p0 : 0.0;
+    const double x10 = Ra[tri(j1, j)];
+    const double f1 = x10 * ip0;  // multiplier of row j + 1 in step j
+    const double p1 = Ra[tri(j1, j1)] - f1 * x10;
+    const bool k1 = p1 > 1e-10;
+    const double ip1 = k1 ? 1.0 / p1 : 0.0;
+    // row j + 1 takes step j only: its new pivot and its Z part are written
+    // after the last pair (every thread of this pass reads the old ones)
+    if (tid == 0) {
+      sh.f1[j1] = f1;
+      sh.p1[j1] = p1;
+    }
+    // rows i > j + 1: both steps
+    const int w = n - 2 - j;
+    for (int idx = tid; idx < w * kCW; idx += nt) {
+      const int i = j + 2 + idx / kCW, cl = idx % kCW;
+      const double fi = Ra[tri(i, j)] * ip0;
+      const double gi = (Ra[tri(i, j1)] - fi * x10) * ip1;
+      double out[kCE];
+#pragma unroll
+      for (int u = 0; u < kCE; ++u) {
+        const int c = cl + kCW * u;
+        out[u] = 0.0;
+        if (c <= i) {
+          if (c <= j) {
+            const double z1 = Rb[tri(j1, c)] - f1 * Rb[tri(j, c)];
+            out[u] = Rb[tri(i, c)] - fi * Rb[tri(j, c)] - gi * z1;
+          } else if (c == j1) {
+            out[u] = -gi;  // column j + 1 of Z: its identity entry is in row j + 1
+          } else {
+            const double xc0 = Ra[tri(c, j)];
+            const double xc1 = Ra[tri(c, j1)] - xc0 * ip0 * x10;
+            out[u] = Ra[tri(i, c)] - fi * xc0 - gi * xc1;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kCE; ++u) {
+        const int c = cl + kCW * u;
+        if (c <= i) {
+          if (c <= j1)
+            Rb[tri(i, c)] = out[u];
+          else
+            Ra[tri(i, c)] = out[u];
+        }
+      }
+    }
+    if (tid == 0) {
+      if (k0) sh.kk[sh.r++] = j;
+      if (k1) sh.kk[sh.r++] = j1;
+    }
+    __syncthreads();
+  }
+  // the deferred step j of each pair's second row: Z[j+1][c] -= f1 Z[j][c],
+  // c <= j (rows j and j+1 of Z no longer change)
+  for (int e = tid; e < (n / 2) * n; e += nt) {
+    const int jp = 2 * (e / n), c = e - (e / n) * n;
+    if (jp + 1 < n && c <= jp) Rb[tri(jp + 1, c)] -= sh.f1[jp + 1] * Rb[tri(jp, c)];
+    if (jp + 1 < n && c == jp + 1) Ra[tri(jp + 1, jp + 1)] = sh.p1[jp + 1];
+  }
+  __syncthreads();
+  for (; j < n; ++j) {  // a last single column
     const double piv = Ra[tri(j, j)];
-    if (piv > 1e-10) {  // uniform: every thread reads the same pivot
+    if (piv > 1e-10) {
       const int w = n - 1 - j;
       const double ip = 1.0 / piv;
-      constexpr int kCW = 16, kCE = (kMaxN + kCW - 1) / kCW;
       for (int idx = tid; idx < w * kCW; idx += nt) {
         const int i = j + 1 + idx / kCW, cl = idx % kCW;
         double src[kCE], dst[kCE];
