@@ -249,11 +249,12 @@ struct RitzArgs {
   int n_c, m, nz;        // nz = n_c + m
   double sigma;
   double rtol2;          // squared significance threshold of a Jacobi rotation
+  int warm;              // 1: start from the coarse-block basis the previous call left in scratch
   const double* G;       // [nz][2m]: Z^T [A U | M U]
   const double* GW;      // [n_c][2 n_c]: W^T [A W | M W] (constant during a solve)
   double* Y;             // out [nz][m]
   double* theta;         // out [m] ascending
-  double* scratch;       // [>= 6 nz nz + 4 nz] doubles
+  double* scratch;       // [ritz_scratch_doubles(nz)]; its tail persists between calls
   int* status;           // out: 0 ok, 1 rank loss below m, 2 Jacobi did not converge
 };
 int launch_ritz(const RitzArgs& a, hipStream_t s);

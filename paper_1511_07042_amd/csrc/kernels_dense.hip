@@ -38,6 +38,7 @@ namespace {
 
 constexpr int kMaxN = 96;
 constexpr int kMaxHalf = kMaxN / 2;
+constexpr int kWarmMax = 24;  // largest coarse block the Ritz step warm-starts
 constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
 
@@ -151,7 +152,10 @@ __device__ __forceinline__ RotRec rot_params(const double* X, int p, int q, int 
 // Diagonalise the packed symmetric n x n matrix X (LDS) in place.  On return
 // X holds the diagonal form (eigenvalues on the diagonal, unsorted) and V (LDS)
 // holds the eigenvectors as rows: V[j * ldv + i] = component i of eigenvector
-// j, with ldv = n rounded up to even, so X_in = V^T diag V.  A rotation is
+// j, with ldv = n rounded up to even, so X_in = V^T diag V.  With Q0 set, X is
+// taken to be T^T C T for T = diag(I_m0, Q0) (Q0: (n - m0)^2, row-major,
+// orthogonal, in LDS) and V starts from T^T, so that on return V holds the
+// eigenvectors of C instead.  A rotation is
 // significant when a_pq^2 > rtol2 max(|a_pp a_qq|, (||X||_F / n)^2); sweeps
 // stop after a sweep without one.  Returns the sweeps used, or -1 if the limit
 // was hit.
@@ -166,7 +170,7 @@ __device__ __forceinline__ RotRec rot_params(const double* X, int p, int q, int 
 // The blocks of a round partition X and the items partition the changed
 // entries of V, so the updates are done in place.
 __device__ __forceinline__ int block_jacobi(double* X, double* V, int n, JacobiShared& sh,
-                                            double rtol2) {
+                                            double rtol2, const double* Q0 = nullptr, int m0 = 0) {
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
   const int ne = n + (n & 1);
   const int ldv = ne;
@@ -175,9 +179,11 @@ __device__ __forceinline__ int block_jacobi(double* X, double* V, int n, JacobiS
   constexpr int kNB = (kMaxHalf * (kMaxHalf + 1) / 2 + kThreads - 1) / kThreads;
   constexpr int kVI = (kMaxHalf * kMaxHalf + kThreads - 1) / kThreads;
   double f2 = 0.0;
+  const int nw0 = n - m0;
   for (int e = tid; e < n * ldv; e += nt) {
     const int i = e / ldv, j = e - (e / ldv) * ldv;
-    V[e] = (i == j) ? 1.0 : 0.0;
+    V[e] = (Q0 != nullptr && i >= m0 && j >= m0 && j < n) ? Q0[(j - m0) * nw0 + (i - m0)]
+                                                           : ((i == j) ? 1.0 : 0.0);
     if (j < n) {
       const double x = X[sym(i, j)];
       f2 += x * x;
@@ -340,8 +346,22 @@ struct RitzShared {
   double f1[kMaxN];    // Cholesky: step-j multiplier of row j + 1 of each pair
   double p1[kMaxN];    // and its pivot after step j
   int dropmap[kMaxN];  // permuted column -> position among the kept ones, or -1
+  int wany[kWaves];    // block_any: per-wave votes
   int r;
 };
+
+// true in every thread if pred holds in any thread of the workgroup (two
+// barriers; a workgroup reduction of the device library would add static LDS,
+// and the kernel needs all 160 KiB as dynamic LDS)
+__device__ bool block_any(bool pred, RitzShared& sh) {
+  const uint64_t b = __ballot(pred);
+  if ((threadIdx.x & 63) == 0) sh.wany[threadIdx.x >> 6] = b != 0;
+  __syncthreads();
+  bool any = false;
+  for (int w = 0; w < int(blockDim.x >> 6); ++w) any = any || sh.wany[w] != 0;
+  __syncthreads();
+  return any;
+}
 
 // doubles before the matrices: even, so the eigenvector rows are 16-byte aligned
 constexpr int shared_doubles() { return int((sizeof(RitzShared) + 15) / 16) * 2; }
@@ -386,7 +406,7 @@ __device__ void select_nearest_zero(const double* X, int r, int mm, RitzShared& 
 
 // Global scratch: GA, GM (permuted order [U', W_c]), Bs = S (GA - sigma GM) S,
 // Lg (packed inverse Cholesky factor, or the SVQB basis T), W1 (SVQB only).
-__global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma, double rtol2,
+__global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma, double rtol2, int warm,
                                                    const double* __restrict__ G,
                                                    const double* __restrict__ GW, double* Y,
                                                    double* theta, double* scratch, int* status) {
@@ -655,8 +675,51 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
     }
     __syncthreads();
   }
+  // ---- warm start of the coarse block.  The previous call on this scratch
+  // left an orthonormal basis Q of the coarse (W_c) part that nearly
+  // diagonalises it, for the same kept columns: C is rotated to T^T C T,
+  // T = diag(I_m, Q), and Jacobi starts from V = T^T.  Q is only a change of
+  // basis of the same space, so the Ritz pairs are unchanged (up to rounding);
+  // Jacobi mostly has the U'-U' and U'-W_c couplings left, which the previous
+  // cycle's correction made small.
+  double* Qg = scratch + 5 * nz * nz;
+  int* whdr = reinterpret_cast<int*>(Qg + kWarmMax * kWarmMax);
+  const int nw = r - m;
+  const bool uprefix = chol && nw >= 1 && nw <= kWarmMax && nw * nw <= r * (r + 1) / 2;
+  bool use_warm = false;
+  if (uprefix && warm) {
+    const bool hdr_ok = whdr[0] == 1 && whdr[1] == r;
+    bool bad = false;
+    for (int q = tid; q < r; q += nt) bad = bad || whdr[4 + q] != sh.kk[q];
+    use_warm = hdr_ok && !block_any(bad, sh);
+  }
+  double* Qs = nxt;  // free: the inverse factor is also in Lg
+  if (use_warm) {
+    for (int e = tid; e < nw * nw; e += nt) Qs[e] = Qg[e];
+    __syncthreads();
+    // H = Q^T C[W rows, :] (nw x r) into R0 (free until Jacobi starts)
+    for (int e = tid; e < nw * r; e += nt) {
+      const int i = e / r, j = e - (e / r) * r;
+      double acc = 0.0;
+      for (int k = 0; k < nw; ++k) acc += Qs[k * nw + i] * cur[sym(m + k, j)];
+      R0[e] = acc;
+    }
+    __syncthreads();
+    // rows >= m of T^T C T, in place: [H_U | H_W Q]
+    for (int e = tid; e < nw * r; e += nt) {
+      const int i = e / r, j = e - (e / r) * r;
+      if (j < m) {
+        cur[tri(m + i, j)] = R0[e];
+      } else if (j - m <= i) {
+        double acc = 0.0;
+        for (int k = 0; k < nw; ++k) acc += R0[i * r + m + k] * Qs[k * nw + (j - m)];
+        cur[tri(m + i, j)] = acc;
+      }
+    }
+    __syncthreads();
+  }
   ts[3] = wall_clock64();
-  const int sw = block_jacobi(cur, R0, r, sh.j, rtol2);
+  const int sw = use_warm ? block_jacobi(cur, R0, r, sh.j, rtol2, Qs, m) : block_jacobi(cur, R0, r, sh.j, rtol2);
   ts[4] = wall_clock64();
   const int mm = m < r ? m : r;
   select_nearest_zero(cur, r, mm, sh);
@@ -693,13 +756,64 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
     }
   }
   for (int c = tid; c < m; c += nt) theta[c] = c < mm ? sh.d[sh.sel[c]] + sigma : 0.0;
+  // ---- the coarse-block basis for the next call: the W_c rows of the
+  // eigenvectors at the W_c positions, made orthonormal by Newton-Schulz
+  // steps P <- P (3 I - P^T P) / 2 (a sub-block of an orthogonal matrix, so
+  // its singular values are <= 1 and the steps cannot diverge); kept only if
+  // P^T P = I to 1e-13, else the next call starts cold.
+  bool made = false;
+  if (uprefix) {
+    __syncthreads();  // Li (nxt) and the eigenvectors (R0) have been read
+    double* P = nxt;
+    double* Gm = cur;
+    double* P2 = R0;
+    for (int e = tid; e < nw * nw; e += nt) {
+      const int k = e / nw, j = e - (e / nw) * nw;
+      P[e] = R0[(m + j) * ldv + (m + k)];
+    }
+    __syncthreads();
+    for (int it = 0; it < 3; ++it) {
+      for (int e = tid; e < nw * nw; e += nt) {
+        const int i = e / nw, j = e - (e / nw) * nw;
+        double acc = 0.0;
+        for (int k = 0; k < nw; ++k) acc += P[k * nw + i] * P[k * nw + j];
+        Gm[e] = acc;
+      }
+      __syncthreads();
+      for (int e = tid; e < nw * nw; e += nt) {
+        const int k = e / nw, j = e - (e / nw) * nw;
+        double acc = 0.0;
+        for (int i = 0; i < nw; ++i) acc += P[k * nw + i] * Gm[i * nw + j];
+        P2[e] = 1.5 * P[e] - 0.5 * acc;
+      }
+      __syncthreads();
+      double* t = P;
+      P = P2;
+      P2 = t;
+    }
+    bool bad = false;
+    for (int e = tid; e < nw * nw; e += nt) {
+      const int i = e / nw, j = e - (e / nw) * nw;
+      double acc = 0.0;
+      for (int k = 0; k < nw; ++k) acc += P[k * nw + i] * P[k * nw + j];
+      bad = bad || !(fabs(acc - (i == j ? 1.0 : 0.0)) <= 1e-13);
+    }
+    made = !block_any(bad, sh);
+    for (int e = tid; e < nw * nw; e += nt) Qg[e] = P[e];
+    for (int q = tid; q < r; q += nt) whdr[4 + q] = sh.kk[q];
+  }
   ts[5] = wall_clock64();
   if (tid == 0) {
+    whdr[0] = made ? 1 : 0;
+    whdr[1] = r;
+    whdr[2] = nw;
     status[0] = (r < m) ? 1 : (sw < 0 ? 2 : 0);
     status[1] = sw;
     status[2] = chol ? 0 : 1;
     status[3] = n - (chol ? r : n);
     status[9] = sh.j.rounds;
+    status[10] = use_warm ? 1 : 0;
+    status[11] = made ? 1 : 0;
     for (int i = 0; i < 5; ++i) status[4 + i] = int(ts[i + 1] - ts[i]);  // 100 MHz ticks
   }
 }
@@ -748,26 +862,36 @@ int check_launch() {
   return BMG_OK;
 }
 
-void set_lds_attr() {
+// Both kernels take up to 160 KiB of dynamic LDS (they have no static LDS).
+int set_lds_attr() {
   static bool done = false;
-  if (done) return;
-  (void)hipFuncSetAttribute((const void*)k_ritz, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  (void)hipFuncSetAttribute((const void*)k_syev, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (done) return BMG_OK;
+  for (const void* f : {(const void*)k_ritz, (const void*)k_syev}) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("cannot reserve 160 KiB of LDS for the Ritz kernels: %s", hipGetErrorString(e));
+      return BMG_EDEVICE;
+    }
+  }
   done = true;
+  return BMG_OK;
 }
 
 }  // namespace
 
-int ritz_scratch_doubles(int nz) { return 5 * nz * nz; }
+// GA, GM, Bs, Lg, W1 (nz^2 each), then the coarse-block basis kept between
+// calls (kWarmMax^2) and its header (valid, r, nw, -, kept columns: <= 128 ints)
+int ritz_scratch_doubles(int nz) { return 5 * nz * nz + kWarmMax * kWarmMax + 64; }
 
 int launch_ritz(const RitzArgs& a, hipStream_t s) {
   if (a.nz > kMaxN || a.nz != a.n_c + a.m) {
     set_error("ritz: nz = %d exceeds %d", a.nz, kMaxN);
     return BMG_EINVAL;
   }
-  set_lds_attr();
-  BMG_LAUNCH((k_ritz), 1, kThreads, lds_bytes(a.nz), s, a.n_c, a.m, a.sigma, a.rtol2, a.G, a.GW, a.Y, a.theta,
-                                              a.scratch, a.status);
+  BMG_TRY(set_lds_attr());
+  BMG_LAUNCH((k_ritz), 1, kThreads, lds_bytes(a.nz), s, a.n_c, a.m, a.sigma, a.rtol2, a.warm, a.G, a.GW, a.Y,
+                                              a.theta, a.scratch, a.status);
   return check_launch();
 }
 
@@ -776,7 +900,7 @@ int launch_syev(int n, const double* A, double* w, double* V, int* status, hipSt
     set_error("syev: n = %d outside [1, %d]", n, kMaxN);
     return BMG_EINVAL;
   }
-  set_lds_attr();
+  BMG_TRY(set_lds_attr());
   k_syev<<<1, kThreads, lds_bytes(n), s>>>(n, A, w, V, status);
   return check_launch();
 }

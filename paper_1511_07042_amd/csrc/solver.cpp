@@ -50,7 +50,7 @@ struct bmg_workspace {
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   double g_sigma = 0, g_omega = 0;
-  int g_smoother = -1, g_nu1 = -1, g_nu2 = -1, g_lc = -1, g_tail = -2, g_timed = -1, g_fuse = -1;
+  int g_smoother = -1, g_nu1 = -1, g_nu2 = -1, g_lc = -1, g_tail = -2, g_timed = -1, g_fuse = -1, g_warm = -1;
   int nblk_res = 0, nblk_arg = 0;
   bmg::GramPlan gp{}, gpw{};
   std::vector<void*> allocs;
@@ -697,6 +697,10 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   ra.sigma = sigma;
   ra.rtol2 = kRitzRtol2;
   if (const char* e = std::getenv("BMG_RITZ_RTOL")) ra.rtol2 = std::atof(e) * std::atof(e);
+  // the first Ritz step of a solve starts cold; later ones may reuse the
+  // coarse-block basis the previous step left (BMG_NO_WARM turns this off)
+  const int warm_ok = std::getenv("BMG_NO_WARM") ? 0 : 1;
+  ra.warm = 0;
   ra.G = w->G;
   ra.GW = w->GW;
   ra.Y = w->Y;
@@ -720,6 +724,7 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     return BMG_OK;
   };
   BMG_TRY(ritz_step());
+  ra.warm = warm_ok;
 
   Cycle<T> cyc;
   BMG_TRY(init_cycle<T>(cyc, h, w, CycleCfg{m, o.nu1, o.nu2, o.smoother, l_c, sigma, o.omega}, L, s));
@@ -755,7 +760,8 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   const bool debug = std::getenv("BMG_DEBUG") != nullptr;
   if (use_graph && !(w->gexec && o.timed_kernel < 0 && w->g_timed < 0 && w->g_sigma == sigma && w->g_omega == o.omega &&
                      w->g_smoother == o.smoother && w->g_nu1 == o.nu1 && w->g_nu2 == o.nu2 &&
-                     w->g_lc == l_c && w->g_tail == cyc.tail_hi && w->g_fuse == int(cyc.fuse_ok))) {
+                     w->g_lc == l_c && w->g_tail == cyc.tail_hi && w->g_fuse == int(cyc.fuse_ok) &&
+                     w->g_warm == ra.warm)) {
     if (w->gexec) (void)hipGraphExecDestroy(w->gexec);
     if (w->graph) (void)hipGraphDestroy(w->graph);
     w->gexec = nullptr;
@@ -793,6 +799,7 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
       w->g_lc = l_c;
       w->g_tail = cyc.tail_hi;
       w->g_fuse = int(cyc.fuse_ok);
+      w->g_warm = ra.warm;
     }
     BMG_HIP(hipGraphLaunch(w->gexec, s));
     return BMG_OK;
@@ -807,9 +814,9 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     int rs3[16] = {0};
     std::memcpy(rs3, w->hbuf + 2 * m, 16 * sizeof(int));
     if (debug) {
-      fprintf(stderr, "[bmg] cycle %d ritz: sweeps %d rounds %d fallback %d dropped %d | phases (us) assemble %.1f "
-              "chol %.1f products %.1f jacobi %.1f select %.1f\n", cycles, rs3[1], rs3[9], rs3[2], rs3[3],
-              rs3[4] * 0.01, rs3[5] * 0.01, rs3[6] * 0.01, rs3[7] * 0.01, rs3[8] * 0.01);
+      fprintf(stderr, "[bmg] cycle %d ritz: sweeps %d rounds %d fallback %d dropped %d warm %d/%d | phases (us) "
+              "assemble %.1f chol %.1f products %.1f jacobi %.1f select %.1f\n", cycles, rs3[1], rs3[9], rs3[2],
+              rs3[3], rs3[10], rs3[11], rs3[4] * 0.01, rs3[5] * 0.01, rs3[6] * 0.01, rs3[7] * 0.01, rs3[8] * 0.01);
     }
     const int rstat = rs3[0];
     ritz_sweeps_max = std::max(ritz_sweeps_max, rs3[1]);
