@@ -93,6 +93,50 @@ __global__ void __launch_bounds__(256) k_gram(int64_t n, int64_t rows_per_block,
 
 constexpr int kGramAmChunk = 16;  // rows whose products share one LDS pass
 
+// One (row, column pair) item of the products: rows r of A U and M U at
+// columns 2 ch, 2 ch + 1 (FP64), the ELL row gathered against U.  With a
+// compile-time width the item is straight-line code, so the items a thread
+// takes in one pass have their loads in flight together.  An invalid item
+// reads row r (a valid row) and returns zeros.
+template <int WT>
+__device__ __forceinline__ double4 am_item(int64_t r, bool valid, int W, const int* __restrict__ cols,
+                                           const double* __restrict__ a, const double* __restrict__ mm,
+                                           const double* __restrict__ u, int m, int ch) {
+  double a0 = 0.0, a1 = 0.0, m0 = 0.0, m1 = 0.0;
+  const int64_t base = r * W;
+  if (WT > 0) {
+    int j[WT > 0 ? WT : 1];
+    double av[WT > 0 ? WT : 1], mv[WT > 0 ? WT : 1];
+    double2 xv[WT > 0 ? WT : 1];
+#pragma unroll
+    for (int k = 0; k < WT; ++k) {
+      j[k] = cols[base + k];
+      av[k] = a[base + k];
+      mv[k] = mm[base + k];
+    }
+#pragma unroll
+    for (int k = 0; k < WT; ++k) xv[k] = *reinterpret_cast<const double2*>(u + int64_t(j[k]) * m + 2 * ch);
+#pragma unroll
+    for (int k = 0; k < WT; ++k) {
+      a0 += av[k] * xv[k].x;
+      a1 += av[k] * xv[k].y;
+      m0 += mv[k] * xv[k].x;
+      m1 += mv[k] * xv[k].y;
+    }
+  } else {
+    for (int k = 0; k < W; ++k) {
+      const int jj = cols[base + k];
+      const double av = a[base + k], mv = mm[base + k];
+      const double2 xv = *reinterpret_cast<const double2*>(u + int64_t(jj) * m + 2 * ch);
+      a0 += av * xv.x;
+      a1 += av * xv.y;
+      m0 += mv * xv.x;
+      m1 += mv * xv.y;
+    }
+  }
+  return valid ? double4{a0, a1, m0, m1} : double4{0.0, 0.0, 0.0, 0.0};
+}
+
 // Fused SpMM and Gram: G = Z^T [A U, M U] with Z = [W | U] (W: w1 columns,
 // U: m columns), the products A U and M U formed row chunk by row chunk in LDS
 // and contracted at once, so they never travel to or from HBM.  For each
@@ -137,49 +181,31 @@ __global__ void __launch_bounds__(256) k_gram_am(int64_t n, int64_t rows_per_blo
       for (int i = 0; i < TI; ++i) af[q][i] = ok ? zcol(z1, w1, u, m, r, 16 * i + li) : 0.0;
     }
     __syncthreads();  // the previous chunk's B fragments have been read
-    for (int e = threadIdx.x; e < items; e += blockDim.x) {
-      const int rl = e / cpr, ch = e - (e / cpr) * cpr;
-      const int64_t r = r0 + rl;
-      double a0 = 0.0, a1 = 0.0, m0 = 0.0, m1 = 0.0;
-      if (r < re) {
-        const int64_t base = r * W;
-        if (WT > 0) {
-          int j[WT > 0 ? WT : 1];
-          double av[WT > 0 ? WT : 1], mv[WT > 0 ? WT : 1];
-          double2 xv[WT > 0 ? WT : 1];
+    // with more than one item per thread (m > 32), three per pass with their
+    // loads in flight together
+    constexpr int NB = TJW > 1 ? 3 : 1;
+    for (int e0 = threadIdx.x; e0 < items; e0 += NB * 256) {
+      double4 y[NB];
 #pragma unroll
-          for (int k = 0; k < WT; ++k) {
-            j[k] = cols[base + k];
-            av[k] = a[base + k];
-            mv[k] = mm[base + k];
-          }
+      for (int k = 0; k < NB; ++k) {
+        const int e = e0 + k * 256;
+        const int rl = e / cpr, ch = e - (e / cpr) * cpr;
+        const int64_t r = r0 + rl;
+        const bool valid = e < items && r < re;
+        y[k] = am_item<WT>(valid ? r : r0, valid, W, cols, a, mm, u, m, ch);
+      }
 #pragma unroll
-          for (int k = 0; k < WT; ++k)
-            xv[k] = *reinterpret_cast<const double2*>(u + int64_t(j[k]) * m + 2 * ch);
-#pragma unroll
-          for (int k = 0; k < WT; ++k) {
-            a0 += av[k] * xv[k].x;
-            a1 += av[k] * xv[k].y;
-            m0 += mv[k] * xv[k].x;
-            m1 += mv[k] * xv[k].y;
-          }
-        } else {
-          for (int k = 0; k < W; ++k) {
-            const int jj = cols[base + k];
-            const double av = a[base + k], mv = mm[base + k];
-            const double2 xv = *reinterpret_cast<const double2*>(u + int64_t(jj) * m + 2 * ch);
-            a0 += av * xv.x;
-            a1 += av * xv.y;
-            m0 += mv * xv.x;
-            m1 += mv * xv.y;
-          }
+      for (int k = 0; k < NB; ++k) {
+        const int e = e0 + k * 256;
+        if (e < items) {
+          const int rl = e / cpr, ch = e - (e / cpr) * cpr;
+          double* yr = ys + rl * nyp;
+          yr[2 * ch] = y[k].x;
+          yr[2 * ch + 1] = y[k].y;
+          yr[m + 2 * ch] = y[k].z;
+          yr[m + 2 * ch + 1] = y[k].w;
         }
       }
-      double* yr = ys + rl * nyp;
-      yr[2 * ch] = a0;
-      yr[2 * ch + 1] = a1;
-      yr[m + 2 * ch] = m0;
-      yr[m + 2 * ch + 1] = m1;
     }
     __syncthreads();
     for (int h = 0; h < CH / 16; ++h) {
@@ -229,7 +255,19 @@ __global__ void __launch_bounds__(1024) k_gram_reduce(const double* __restrict__
     const int i = e / ny, j = e - (e / ny) * ny;
     const int64_t off = int64_t(i) * nyp + j;
     const int64_t stride = int64_t(nzp) * nyp;
-    for (int b = seg; b < nblk; b += 16) s += part[b * stride + off];
+    // eight loads in flight, added in the order b = seg, seg + 16, ...
+    constexpr int kU = 8;
+    for (int b0 = seg; b0 < nblk; b0 += 16 * kU) {
+      double v[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int b = b0 + 16 * u;
+        v[u] = b < nblk ? part[b * stride + off] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (b0 + 16 * u < nblk) s += v[u];
+    }
   }
   red[seg][el] = s;
   __syncthreads();
