@@ -364,9 +364,10 @@ GramPlan gram_plan(int64_t n, int nz, int ny) {
   p.nzp = (nz + 15) / 16 * 16;
   p.nyp = (ny + 15) / 16 * 16;
   // at least 64 rows per block, at most 1024 blocks, and partial sums of at
-  // most a quarter of the bytes the kernel reads
+  // most half the bytes the kernel reads (more blocks hide more of the
+  // gathers' latency; the partials cost a second pass)
   int64_t blocks = (n + 63) / 64;
-  const int64_t cap = int64_t(0.25 * double(n) * (nz + ny) / (double(p.nzp) * p.nyp));
+  const int64_t cap = int64_t(0.5 * double(n) * (nz + ny) / (double(p.nzp) * p.nyp));
   blocks = std::min<int64_t>(blocks, std::max<int64_t>(cap, 1));
   p.nblk = int(std::max<int64_t>(1, std::min<int64_t>(blocks, 1024)));
   return p;
