@@ -213,14 +213,19 @@ __device__ __forceinline__ int block_jacobi(double* X, double* V, int n, JacobiS
     bt1[i] = t1;
     bt2[i] = t2;
   }
-  // eigenvector items: (pair slot vt, column pair vc) of the rows p and q of V
+  // eigenvector items: (pair slot vt, column pair vc) of the rows p and q of V.
+  // When the blocks fit the first half of the threads (n <= 44), the items go
+  // to the second half, so no thread carries both a block and an item.
   const int nvc = ne / 2;
+  const bool split = nb <= nt / 2;
+  const int vbase = split ? nt / 2 : 0, vstride = split ? nt / 2 : nt;
   int vt[kVI], vc[kVI];
 #pragma unroll
   for (int i = 0; i < kVI; ++i) {
-    const int it = tid + i * nt;
-    vt[i] = it < half * nvc ? it / nvc : -1;
-    vc[i] = it < half * nvc ? it - (it / nvc) * nvc : 0;
+    const int it = (tid - vbase) + i * vstride;
+    const bool ok = tid >= vbase && it < half * nvc;
+    vt[i] = ok ? it / nvc : -1;
+    vc[i] = ok ? it - (it / nvc) * nvc : 0;
   }
   double2* cs = sh.cs[wave];
   double* tt = sh.tt[wave];
