@@ -233,6 +233,7 @@ struct TailLevel {  // byte offsets into the kernel's dynamic LDS
 };
 struct alignas(16) TailArgs {
   int lo, hi, m, smoother, nu1, nu2;
+  int m_full;  // columns of the global blocks; workgroup g takes columns [g m, (g + 1) m)
   double omega;
   const void* image;  // packed static arrays, copied to LDS offset 0
   int image_bytes;
@@ -242,7 +243,7 @@ struct alignas(16) TailArgs {
   TailLevel lv[kTailMaxLevels];
 };
 template <typename T>
-int launch_tail(const TailArgs* dev_args, int lds_bytes, hipStream_t s);
+int launch_tail(const TailArgs* dev_args, int lds_bytes, int groups, hipStream_t s);
 
 // One-workgroup Ritz step (see kernels_dense.hip).
 struct RitzArgs {

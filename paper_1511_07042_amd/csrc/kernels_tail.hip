@@ -1,9 +1,13 @@
-// The coarse end of the correction V-cycle, resident in LDS, in one workgroup.
+// The coarse end of the correction V-cycle, resident in LDS.
 //
 // On the smallest levels a smoothing pass, residual or transfer has only a few
 // hundred rows: a kernel launch costs more than the work.  This kernel runs
-// the whole V-cycle for levels lo..hi (lo = l_c) inside one 1024-thread
-// workgroup with every array of those levels in LDS: the shifted operator
+// the whole V-cycle for levels lo..hi (lo = l_c) inside 1024-thread
+// workgroups with every array of those levels in LDS.  The cycle acts on each
+// column of the block independently, so the columns are shared out: workgroup
+// g takes columns [g m, (g + 1) m) of the m_full-column blocks (m a multiple of
+// the 16-byte vector width), which lets a level whose full-width work arrays
+// would not fit LDS run here.  Each workgroup holds the shifted operator
 // S_l = A_l - sigma M_l (values and 16-bit column indices), the colour lists,
 // the parent and restriction tables, the level-0 spectral inverse, and the
 // work blocks e, f, t.  The operations and their order are those of the
@@ -159,10 +163,15 @@ __global__ void __launch_bounds__(1024) k_tail(const TailArgs* __restrict__ args
     int4* dst = reinterpret_cast<int4*>(lds);
     for (int i = tid; i < A.image_bytes / 16; i += nt) dst[i] = src[i];
     const LdsLevel<T> H = level<T>(A, lds, A.hi);
+    // this workgroup's columns of f (rows of m_full columns) into rows of m
     const int4* fs = reinterpret_cast<const int4*>(A.f_top);
     int4* fd = reinterpret_cast<int4*>(H.f);
-    const int nf = H.n * m * int(sizeof(T)) / 16;
-    for (int i = tid; i < nf; i += nt) fd[i] = fs[i];
+    const int c16 = m * int(sizeof(T)) / 16, f16 = A.m_full * int(sizeof(T)) / 16;
+    const int nf = H.n * c16;
+    for (int i = tid; i < nf; i += nt) {
+      const int r = i / c16, c = i - r * c16;
+      fd[i] = fs[r * f16 + blockIdx.x * c16 + c];
+    }
   }
   __syncthreads();
   // Jacobi buffer roles per level (bit l set: e and t exchanged), uniform
@@ -278,15 +287,19 @@ __global__ void __launch_bounds__(1024) k_tail(const TailArgs* __restrict__ args
     const LdsLevel<T> H = lev(A.hi);
     const int4* src = reinterpret_cast<const int4*>(H.e);
     int4* dst = reinterpret_cast<int4*>(A.e_top);
-    const int ne = H.n * m * int(sizeof(T)) / 16;
-    for (int i = tid; i < ne; i += nt) dst[i] = src[i];
+    const int c16 = m * int(sizeof(T)) / 16, f16 = A.m_full * int(sizeof(T)) / 16;
+    const int ne = H.n * c16;
+    for (int i = tid; i < ne; i += nt) {
+      const int r = i / c16, c = i - r * c16;
+      dst[r * f16 + blockIdx.x * c16 + c] = src[i];
+    }
   }
 }
 
 }  // namespace
 
 template <typename T>
-int launch_tail(const TailArgs* dev_args, int lds_bytes, hipStream_t s) {
+int launch_tail(const TailArgs* dev_args, int lds_bytes, int groups, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute((const void*)k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -295,7 +308,7 @@ int launch_tail(const TailArgs* dev_args, int lds_bytes, hipStream_t s) {
                               kTailLdsBudget);
     attr = true;
   }
-  k_tail<T><<<1, 1024, lds_bytes, s>>>(dev_args);
+  k_tail<T><<<groups, 1024, lds_bytes, s>>>(dev_args);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     set_error("tail kernel launch failed: %s", hipGetErrorString(e));
@@ -304,7 +317,7 @@ int launch_tail(const TailArgs* dev_args, int lds_bytes, hipStream_t s) {
   return BMG_OK;
 }
 
-template int launch_tail<float>(const TailArgs*, int, hipStream_t);
-template int launch_tail<double>(const TailArgs*, int, hipStream_t);
+template int launch_tail<float>(const TailArgs*, int, int, hipStream_t);
+template int launch_tail<double>(const TailArgs*, int, int, hipStream_t);
 
 }  // namespace bmg

@@ -329,6 +329,7 @@ struct Cycle {
   int tail_hi = -1;  // levels l_c..tail_hi run in one workgroup, in LDS
   const TailArgs* tail_d = nullptr;
   int tail_lds = 0;
+  int tail_groups = 1;  // workgroups of the tail (column groups)
   bool fuse_ok = std::getenv("BMG_NO_FUSE") == nullptr;  // fused Jacobi cycle kernels
 
   // Pack the LDS image of levels l_c..hi (the largest hi whose image and work
@@ -344,25 +345,47 @@ struct Cycle {
     const size_t vt = sizeof(T);
     const size_t n0 = size_t(h->n0);
     const bool spectral = c.l_c == 0;
-    size_t stat = spectral ? 2 * al(n0 * n0 * vt) + al(n0 * vt) : 0, work = 0;
-    int hi = -1;
-    for (int l = c.l_c; l < nl; ++l) {
-      const HostLevel& H = h->host[l];
-      if (H.n > 32767 || H.n_colours > kTailMaxColours) break;  // 16-bit tables
-      const size_t n = size_t(H.n), np = size_t(H.n_prev);
-      const size_t st = al(n * H.W * vt) + al(n * H.W * 2) + al(n * 2) + al((n - np) * 4) +
-                        al(np * H.RW * 2);
-      const size_t wk = 3 * al(n * c.m * vt);
-      if (stat + st + work + wk > size_t(kTailLdsBudget)) break;
-      stat += st;
-      work += wk;
-      hi = l;
+    const size_t stat0 = spectral ? 2 * al(n0 * n0 * vt) + al(n0 * vt) : 0;
+    // the highest level whose arrays fit LDS with mc columns per workgroup
+    auto top_level = [&](int mc, size_t& stat_out) {
+      size_t stat = stat0, work = 0;
+      int hi = -1;
+      for (int l = c.l_c; l < nl; ++l) {
+        const HostLevel& H = h->host[l];
+        if (H.n > 32767 || H.n_colours > kTailMaxColours) break;  // 16-bit tables
+        const size_t n = size_t(H.n), np = size_t(H.n_prev);
+        const size_t st = al(n * H.W * vt) + al(n * H.W * 2) + al(n * 2) + al((n - np) * 4) +
+                          al(np * H.RW * 2);
+        const size_t wk = 3 * al(n * size_t(mc) * vt);
+        if (stat + st + work + wk > size_t(kTailLdsBudget)) break;
+        stat += st;
+        work += wk;
+        hi = l;
+      }
+      stat_out = stat;
+      return hi;
+    };
+    // columns per workgroup: the fewest groups that reach the highest level
+    const int vw = int(16 / vt);
+    int hi = -1, groups = 1;
+    size_t stat = 0;
+    for (int g = 1; g <= c.m / vw; g *= 2) {
+      if (c.m % g != 0 || (c.m / g) % vw != 0) break;
+      size_t st_g = 0;
+      const int hg = top_level(c.m / g, st_g);
+      if (hg > hi) {
+        hi = hg;
+        groups = g;
+        stat = st_g;
+      }
     }
     if (hi < 0) return BMG_OK;
+    const int mc = c.m / groups;
     std::memset(th, 0, sizeof(TailArgs));
     th->lo = c.l_c;
     th->hi = hi;
-    th->m = c.m;
+    th->m = mc;
+    th->m_full = c.m;
     th->smoother = c.smoother;
     th->nu1 = c.nu1;
     th->nu2 = c.nu2;
@@ -409,7 +432,7 @@ struct Cycle {
     }
     th->image_bytes = int(pos);
     for (int l = c.l_c; l <= hi; ++l) {
-      const size_t b = al(size_t(h->host[l].n) * c.m * vt);
+      const size_t b = al(size_t(h->host[l].n) * mc * vt);
       TailLevel& t = th->lv[l];
       t.off_e = int(pos);
       pos += b;
@@ -430,6 +453,7 @@ struct Cycle {
     // img and th are host staging reused by the next solve
     BMG_HIP(hipStreamSynchronize(s));
     tail_hi = hi;
+    tail_groups = groups;
     tail_d = td;
     return BMG_OK;
   }
@@ -465,7 +489,7 @@ struct Cycle {
   // e[l] <- B_sigma f[l]
   int vcycle(int l) {
     const DevLevel& D = h->dev[l];
-    if (l == tail_hi) return launch_tail<T>(tail_d, tail_lds, s);
+    if (l == tail_hi) return launch_tail<T>(tail_d, tail_lds, tail_groups, s);
     if (l == c.l_c) {
       if (l == 0) {
         const int n0 = int(h->n0);

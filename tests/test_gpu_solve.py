@@ -156,6 +156,30 @@ def test_graph_tail_and_plain_launch_paths_identical(lib, smoother, precision, m
         assert np.array_equal(V, V0), name
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_tail_column_groups_identical(lib, precision, monkeypatch):
+    # With m = 32 the coarse-level tail shares the columns out over several
+    # workgroups (4 in FP32, 8 in FP64) and takes level 3 as well; the cycle
+    # acts on each column alone, so the result must equal the per-kernel
+    # launches bit for bit.
+    h = lib.Hierarchy("sphere", 5)
+    runs = {}
+    for name, env in (("plain", {"BMG_NO_GRAPH": "1", "BMG_NO_TAIL": "1"}),
+                      ("tail", {"BMG_NO_GRAPH": "1"}), ("graph", {})):
+        for k in ("BMG_NO_GRAPH", "BMG_NO_TAIL", "BMG_NO_FUSE"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        runs[name] = h.solve(25, m=32, smoother="jacobi", precision=precision)
+    ev0, V0, s0 = runs["plain"]
+    assert s0["converged"]
+    for name in ("tail", "graph"):
+        ev, V, st = runs[name]
+        assert st["cycles"] == s0["cycles"], name
+        assert np.array_equal(ev, ev0), name
+        assert np.array_equal(V, V0), name
+
+
 def _golden_eigs(name):
     import os
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
