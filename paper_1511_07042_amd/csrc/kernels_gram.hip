@@ -296,35 +296,57 @@ __global__ void __launch_bounds__(256) k_update_zy(int64_t n, const double* z1, 
   extern __shared__ double ys[];  // [ks * 4][TJ * 16]
   constexpr int MP = TJ * 16;
   const int nz = w1 + w2;
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t tiles = (n + 15) / 16;
+  const int64_t wstride = int64_t(gridDim.x) * (blockDim.x >> 6);
+  // this lane's A fragments of a tile: row l % 16 of the tile; k steps 2 s'
+  // and 2 s' + 1 take columns 8 s' + 2 j and 8 s' + 2 j + 1 of Z (j = l / 16),
+  // so a lane reads two adjacent columns with one 16-byte load (with w1 even;
+  // the B rows follow the same order)
+  auto load_a = [&](int64_t tile, double* a) {
+    const int64_t r = tile * 16 + li;
+    const bool live = tile < tiles && r < n;
+    const double* p1 = z1 + (live ? r : 0) * w1;
+    const double* p2 = z2 + (live ? r : 0) * w2 - w1;
+    if ((w1 & 1) == 0) {
+#pragma unroll
+      for (int s2 = 0; s2 < kUpdKMax / 2; ++s2) {
+        const int c = 8 * s2 + 2 * lk;
+        double2 v{0.0, 0.0};
+        if (live && c < nz)
+          v = c < w1 ? *reinterpret_cast<const double2*>(p1 + c) : *reinterpret_cast<const double2*>(p2 + c);
+        a[2 * s2] = v.x;
+        a[2 * s2 + 1] = v.y;
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < kUpdKMax; ++s) {
+        const int c = 8 * (s >> 1) + 2 * lk + (s & 1);
+        a[s] = (live && c < w1) ? p1[c] : ((live && c >= w1 && c < nz) ? p2[c] : 0.0);
+      }
+    }
+  };
+  int64_t tile = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  double a[kUpdKMax], an[kUpdKMax];
+  load_a(tile, a);  // in flight while Y is staged
+#pragma unroll 8
   for (int e = threadIdx.x; e < ks * 4 * MP; e += blockDim.x) {
     const int i = e / MP, c = e - (e / MP) * MP;
     ys[e] = (i < nz && c < m) ? Y[i * m + c] : 0.0;
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int li = lane & 15, lk = lane >> 4;
-  const int64_t tiles = (n + 15) / 16;
-  const int64_t wstride = int64_t(gridDim.x) * (blockDim.x >> 6);
-  for (int64_t tile = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); tile < tiles;
-       tile += wstride) {
-    const int64_t r = tile * 16 + li;
-    // this lane's row of z1 and of z2, indexed by the column c of Z
-    const double* p1 = z1 + (r < n ? r : 0) * w1;
-    const double* p2 = z2 + (r < n ? r : 0) * w2 - w1;
-    const bool live = r < n;
-    double a[kUpdKMax];
-#pragma unroll
-    for (int s = 0; s < kUpdKMax; ++s) {
-      const int c = 4 * s + lk;
-      a[s] = (live && c < w1) ? p1[c] : ((live && c >= w1 && c < nz) ? p2[c] : 0.0);
-    }
+  for (; tile < tiles; tile += wstride) {
+    // the next tile's fragments are loaded while this tile's MFMAs run (its
+    // rows are not written by this tile: tiles are disjoint)
+    load_a(tile + wstride, an);
     d4 acc[TJ];
 #pragma unroll
     for (int t = 0; t < TJ; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < kUpdKMax; ++s) {
       if (s < ks) {
-        const double* yrow = ys + (4 * s + lk) * MP + li;
+        const double* yrow = ys + (8 * (s >> 1) + 2 * lk + (s & 1)) * MP + li;
 #pragma unroll
         for (int t = 0; t < TJ; ++t)
           acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], yrow[16 * t], acc[t], 0, 0, 0);
@@ -340,6 +362,8 @@ __global__ void __launch_bounds__(256) k_update_zy(int64_t n, const double* z1, 
         if (row < n) U[row * m + c] = acc[t][v];
       }
     }
+#pragma unroll
+    for (int s = 0; s < kUpdKMax; ++s) a[s] = an[s];
   }
 }
 
@@ -473,7 +497,7 @@ int launch_gram_am(const GramPlan& p, const DevLevel& L, const double* w, int w1
 int launch_update_zy(int64_t n, const double* z1, int w1, const double* z2, int w2,
                      const double* Y, double* U, int m, hipStream_t s) {
   const int nz = w1 + w2;
-  const int ks = (nz + 3) / 4;
+  const int ks = (nz + 7) / 8 * 2;  // k steps of 4, in pairs (see the kernel's A fragments)
   const int TJ = (m + 15) / 16;
   if (ks < 1 || ks > kUpdKMax || TJ < 1 || TJ > 6 || m % 4 != 0) {
     set_error("update: unsupported shape nz=%d m=%d", nz, m);
@@ -481,7 +505,8 @@ int launch_update_zy(int64_t n, const double* z1, int w1, const double* z2, int 
   }
   const size_t shm = size_t(ks) * 4 * TJ * 16 * sizeof(double);
   const int64_t tiles = (n + 15) / 16;
-  const int grid = int(std::min<int64_t>((tiles + 3) / 4, 512));
+  // up to 1024 blocks (each stages Y in LDS once)
+  const int grid = int(std::min<int64_t>((tiles + 3) / 4, 1024));
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute((const void*)k_update_zy<5>, hipFuncAttributeMaxDynamicSharedMemorySize,
