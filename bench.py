@@ -101,9 +101,11 @@ def kernel_source_hash():
     return hashlib.sha256(src).hexdigest()
 
 
-def measured_traffic(kclass, workload, prec):
+def measured_traffic(kclass, workload, prec, per_unit):
     """HBM bytes per launch from committed counter runs, or None when there are
-    none for this kernel and workload or the kernel source changed since."""
+    none for this kernel and workload, the kernel source changed since, or the
+    launches it averages over differ from this run's (their algorithmic bytes
+    per launch, per_unit, must match the recorded ones)."""
     rel = TRAFFIC_FILES.get((kclass, workload, prec))
     if rel is None or not os.path.exists(os.path.join(ROOT, rel)):
         return None
@@ -113,6 +115,9 @@ def measured_traffic(kclass, workload, prec):
             key, val = line.split("=", 1)
             kv[key.strip()] = val.strip()
     if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    algo = float(kv.get("algorithmic_bytes_per_launch", "nan"))
+    if not abs(algo - per_unit) <= 0.5:
         return None
     return float(kv["traffic_bytes_per_launch"])
 
@@ -197,7 +202,7 @@ def bench_workload(bmg, name, cfg, precs, steps, warmup, smoother, timed_kernel)
                         sum(s["timed_kernel_bytes"] for s in tst),
                         sum(s["timed_kernel_units"] for s in tst), prec)
         if roof is not None and "frac" in roof:
-            roof["traffic"] = measured_traffic(kc, name, prec)
+            roof["traffic"] = measured_traffic(kc, name, prec, roof["per_unit"])
         r["roofline"] = roof
         out[prec] = r
         print(f"# {name} {prec}: {r['value']} eigenpairs/s, {r['ms_per_step']} ms/solve, "
