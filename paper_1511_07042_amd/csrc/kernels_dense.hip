@@ -23,12 +23,14 @@
 // pairs (p, q) are rotated at once.  Each wave computes the round's rotations
 // (lane i: pair i) into its own LDS slot, so no barrier is needed to share
 // them; a round in which no rotation is significant is skipped by every wave
-// (the vote is identical in all of them).  The matrix is double-buffered:
-// every 2x2 block [p1 q1] x [p2 q2] is read from one buffer, rotated on both
-// sides and written to the other, so a round costs one barrier.  Only
-// significant rotations are applied, |a_pq| > 1e-15 max(sqrt|a_pp a_qq|,
-// ||A||_F / n), so rounding noise is not churned; sweeps stop after a sweep
-// without one.
+// (the vote is identical in all of them).  Otherwise the 2x2 blocks
+// [p1 q1] x [p2 q2] of the packed matrix and the rotated rows of the
+// eigenvector matrix are updated in place between two barriers.  Only
+// significant rotations are applied, a_pq^2 > rtol2 max(|a_pp a_qq|,
+// (||A||_F / n)^2) (rtol2 = 1e-22 in the Ritz step), so rounding noise is not
+// churned; sweeps stop after a sweep without one.  Across cycles the Ritz step
+// starts Jacobi from the previous cycle's basis of the coarse block (see
+// k_ritz), which leaves mostly the small couplings the correction introduced.
 #include <cmath>
 
 #include "bmg_internal.h"
