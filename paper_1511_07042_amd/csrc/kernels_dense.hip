@@ -350,8 +350,7 @@ struct RitzShared {
   int kk[kMaxN];
   int sel[kMaxN];
   int rank[kMaxN];     // selection scratch
-  double f1[kMaxN];    // Cholesky: step-j multiplier of row j + 1 of each pair
-  double p1[kMaxN];    // and its pivot after step j
+  double p1[kMaxN];    // Cholesky: pivots of the blocks' rows j + 1..j + 3
   int dropmap[kMaxN];  // permuted column -> position among the kept ones, or -1
   int wany[kWaves];    // block_any: per-wave votes
   int r;
@@ -484,75 +483,120 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
   // the span of the kept columns before it) is below 1e-10 is dropped: it
   // adds nothing to the enriched space.  With sigma = 0 this happens to the
   // constant vector of W_c once U' holds the converged constant mode.
-  // Columns are eliminated two at a time (one barrier per pair): every thread
-  // forms the second pivot and the first step's multipliers of the rows it
-  // touches from the values before the pair, so both steps land in one pass.
+  // Columns are eliminated four at a time (one barrier per block of four).
+  // Every thread factors the block's 4 x 4 pivot part (LDL^T: pivots p_t,
+  // multipliers l_kt) from the values before the block.  A trailing row i
+  // forms its multipliers f_t by forward substitution from its four block
+  // entries, and every entry it owns subtracts sum_t f_t y_t(c), where y_t(c),
+  // pivot row t's value at column c after the block's earlier steps, comes
+  // from the stored pivot rows by the same substitution
+  // (y_t = x_t - sum_{r<t} l_tr y_r; on Z the pivot rows start as the
+  // identity in the block's columns).  The pivot rows' own Z rows and pivots
+  // are written after the last block (every thread of a pass reads the old
+  // ones); the multipliers are kept in the Jacobi scratch, free until Jacobi.
   constexpr int kCW = 16, kCE = (kMaxN + kCW - 1) / kCW;
+  constexpr int kB = 4;
+  double* lblk = reinterpret_cast<double*>(sh.j.cs);  // [n][3]: l_{t,r} of pivot row j + t
+  static_assert(sizeof(sh.j.cs) >= sizeof(double) * kMaxN * 3, "block multipliers fit the Jacobi scratch");
   int j = 0;
-  for (; j + 1 < n; j += 2) {
-    const int j1 = j + 1;
-    const double p0 = Ra[tri(j, j)];
-    const bool k0 = p0 > 1e-10;  // uniform: every thread reads the same pivots
-    const double ip0 = k0 ? 1.0 / p0 : 0.0;
-    const double x10 = Ra[tri(j1, j)];
-    const double f1 = x10 * ip0;  // multiplier of row j + 1 in step j
-    const double p1 = Ra[tri(j1, j1)] - f1 * x10;
-    const bool k1 = p1 > 1e-10;
-    const double ip1 = k1 ? 1.0 / p1 : 0.0;
-    // row j + 1 takes step j only: its new pivot and its Z part are written
-    // after the last pair (every thread of this pass reads the old ones)
-    if (tid == 0) {
-      sh.f1[j1] = f1;
-      sh.p1[j1] = p1;
+  for (; j + kB - 1 < n; j += kB) {
+    // the pivot block (lower part, values before this block), factored
+    double a[kB][kB];
+#pragma unroll
+    for (int t = 0; t < kB; ++t)
+#pragma unroll
+      for (int u = 0; u <= t; ++u) a[t][u] = Ra[tri(j + t, j + u)];
+    double pv[kB], ip[kB], l[kB][kB];
+    bool kept[kB];
+#pragma unroll
+    for (int t = 0; t < kB; ++t) {
+      pv[t] = a[t][t];
+      kept[t] = pv[t] > 1e-10;  // uniform: every thread reads the same values
+      ip[t] = kept[t] ? 1.0 / pv[t] : 0.0;
+#pragma unroll
+      for (int k = t + 1; k < kB; ++k) {
+        l[k][t] = a[k][t] * ip[t];
+#pragma unroll
+        for (int u = t + 1; u <= k; ++u) a[k][u] -= l[k][t] * a[u][t];
+      }
     }
-    // rows i > j + 1: both steps
-    const int w = n - 2 - j;
+    if (tid == 0) {
+#pragma unroll
+      for (int t = 1; t < kB; ++t) {
+        sh.p1[j + t] = pv[t];
+#pragma unroll
+        for (int r = 0; r < t; ++r) lblk[(j + t) * 3 + r] = l[t][r];
+      }
+#pragma unroll
+      for (int t = 0; t < kB; ++t)
+        if (kept[t]) sh.kk[sh.r++] = j + t;
+    }
+    // trailing rows i > j + 3
+    const int jl = j + kB - 1;
+    const int w = n - 1 - jl;
     for (int idx = tid; idx < w * kCW; idx += nt) {
-      const int i = j + 2 + idx / kCW, cl = idx % kCW;
-      const double fi = Ra[tri(i, j)] * ip0;
-      const double gi = (Ra[tri(i, j1)] - fi * x10) * ip1;
+      const int i = jl + 1 + idx / kCW, cl = idx % kCW;
+      double f[kB];
+#pragma unroll
+      for (int t = 0; t < kB; ++t) {
+        double x = Ra[tri(i, j + t)];
+#pragma unroll
+        for (int r = 0; r < t; ++r) x -= f[r] * a[t][r];  // a[t][r]: pivot row r at column t, step r
+        f[t] = x * ip[t];
+      }
       double out[kCE];
 #pragma unroll
       for (int u = 0; u < kCE; ++u) {
         const int c = cl + kCW * u;
         out[u] = 0.0;
         if (c <= i) {
-          if (c <= j) {
-            const double z1 = Rb[tri(j1, c)] - f1 * Rb[tri(j, c)];
-            out[u] = Rb[tri(i, c)] - fi * Rb[tri(j, c)] - gi * z1;
-          } else if (c == j1) {
-            out[u] = -gi;  // column j + 1 of Z: its identity entry is in row j + 1
-          } else {
-            const double xc0 = Ra[tri(c, j)];
-            const double xc1 = Ra[tri(c, j1)] - xc0 * ip0 * x10;
-            out[u] = Ra[tri(i, c)] - fi * xc0 - gi * xc1;
+          double y[kB];
+          const bool zpart = c <= jl;
+#pragma unroll
+          for (int t = 0; t < kB; ++t) {
+            double v = zpart ? (c <= j + t ? Rb[tri(j + t, c)] : 0.0) : Ra[tri(c, j + t)];
+#pragma unroll
+            for (int r = 0; r < t; ++r) v -= l[t][r] * y[r];
+            y[t] = v;
           }
+          double acc = zpart ? (c < j ? Rb[tri(i, c)] : 0.0) : Ra[tri(i, c)];
+#pragma unroll
+          for (int t = 0; t < kB; ++t) acc -= f[t] * y[t];
+          out[u] = acc;
         }
       }
 #pragma unroll
       for (int u = 0; u < kCE; ++u) {
         const int c = cl + kCW * u;
         if (c <= i) {
-          if (c <= j1)
+          if (c <= jl)
             Rb[tri(i, c)] = out[u];
           else
             Ra[tri(i, c)] = out[u];
         }
       }
     }
-    if (tid == 0) {
-      if (k0) sh.kk[sh.r++] = j;
-      if (k1) sh.kk[sh.r++] = j1;
-    }
     __syncthreads();
   }
-  // the deferred step j of each pair's second row: Z[j+1][c] -= f1 Z[j][c],
-  // c <= j (rows j and j+1 of Z no longer change)
-  for (int e = tid; e < (n / 2) * n; e += nt) {
-    const int jp = 2 * (e / n), c = e - (e / n) * n;
-    if (jp + 1 < n && c <= jp) Rb[tri(jp + 1, c)] -= sh.f1[jp + 1] * Rb[tri(jp, c)];
-    if (jp + 1 < n && c == jp + 1) Ra[tri(jp + 1, jp + 1)] = sh.p1[jp + 1];
+  // the blocks' pivot rows t = 1..3: their Z rows take the block's earlier
+  // steps, z_t = z_t - sum_{r<t} l_tr z_r (columns c < j + t, rows j..j+t-1
+  // final), and their pivots are stored
+  for (int e = tid; e < (j / kB) * (j + kB); e += nt) {
+    const int jb = kB * (e / (j + kB)), c = e - (e / (j + kB)) * (j + kB);
+    if (c >= jb + kB - 1) continue;
+    double z[kB];
+    z[0] = c <= jb ? Rb[tri(jb, c)] : 0.0;
+#pragma unroll
+    for (int t = 1; t < kB; ++t) {
+      double v = c <= jb + t ? Rb[tri(jb + t, c)] : 0.0;
+#pragma unroll
+      for (int r = 0; r < t; ++r) v -= lblk[(jb + t) * 3 + r] * z[r];
+      z[t] = v;
+      if (c < jb + t) Rb[tri(jb + t, c)] = v;
+    }
   }
+  for (int e = tid; e < j; e += nt)
+    if (e % kB != 0) Ra[tri(e, e)] = sh.p1[e];
   __syncthreads();
   for (; j < n; ++j) {  // a last single column
     const double piv = Ra[tri(j, j)];
