@@ -365,7 +365,8 @@ struct Cycle {
       stat_out = stat;
       return hi;
     };
-    // columns per workgroup: the fewest groups that reach the highest level
+    // columns per workgroup: the most groups (each on its own CU, each phase
+    // with fewer items per thread) among those that reach the highest level
     const int vw = int(16 / vt);
     int hi = -1, groups = 1;
     size_t stat = 0;
@@ -373,7 +374,7 @@ struct Cycle {
       if (c.m % g != 0 || (c.m / g) % vw != 0) break;
       size_t st_g = 0;
       const int hg = top_level(c.m / g, st_g);
-      if (hg > hi) {
+      if (hg >= hi) {
         hi = hg;
         groups = g;
         stat = st_g;

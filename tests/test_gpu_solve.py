@@ -159,7 +159,7 @@ def test_graph_tail_and_plain_launch_paths_identical(lib, smoother, precision, m
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_tail_column_groups_identical(lib, precision, monkeypatch):
     # With m = 32 the coarse-level tail shares the columns out over several
-    # workgroups (4 in FP32, 8 in FP64) and takes level 3 as well; the cycle
+    # workgroups (8 in FP32, 16 in FP64) and takes level 3 as well; the cycle
     # acts on each column alone, so the result must equal the per-kernel
     # launches bit for bit.
     h = lib.Hierarchy("sphere", 5)
