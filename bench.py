@@ -38,7 +38,7 @@ KCLASS = {"eigres": ("hbm", "GB/s"), "spmm_am": ("hbm", "GB/s"), "smooth": ("hbm
           "residual": ("hbm", "GB/s"), "restrict": ("hbm", "GB/s"), "prolong": ("hbm", "GB/s"),
           "gram": ("mfma", "TFLOP/s"), "update": ("mfma", "TFLOP/s"), "ritz": ("latency", "us"),
           "smooth_pair": ("hbm", "GB/s"), "restrict_res": ("hbm", "GB/s"),
-          "prolong_smooth": ("hbm", "GB/s")}
+          "prolong_smooth": ("hbm", "GB/s"), "smooth_add": ("hbm", "GB/s")}
 
 # Kernel symbols of the classes (template arguments of the mixed / FP64 paths).
 KSYMBOL = {"smooth": "k_rowop<{T}, 2, 7>", "residual": "k_rowop<{T}, 1, 7>",
@@ -46,7 +46,7 @@ KSYMBOL = {"smooth": "k_rowop<{T}, 2, 7>", "residual": "k_rowop<{T}, 1, 7>",
            "smooth_pair": "k_jacobi2z<{T}, 7>", "restrict_res": "k_resrestrict<{T}, 7>",
            "prolong_smooth": "k_prolong_jacobi<{T}, 7>", "eigres": "k_eigres<{T}, 7>",
            "spmm_am": "k_spmm_am<7>", "gram": "k_gram_am + k_gram_reduce", "update": "k_update_zy",
-           "ritz": "k_ritz"}
+           "ritz": "k_ritz", "smooth_add": "k_rowop<{T}, 4, 7>"}
 
 # Committed HBM-traffic summaries (two rocprofv3 --pmc passes each).
 TRAFFIC_FILES = {

@@ -191,13 +191,17 @@ typedef struct {
  *                   (e, f read; the coarse right-hand side written);
  *   PROLONG_SMOOTH  (4 + b) nnz + 3 b n m + b n_prev m + 8 (n - n_prev)
  *                   (e, f read, y written; the coarse correction read);
+ *   SMOOTH_ADD      (4 + b) nnz + 2 b n m + 16 n m   (the cycle's last Jacobi
+ *                   sweep on the finest level: x, f read; its result added to
+ *                   the FP64 iterate U, read and written);
  *   GRAM      fused A U, M U and Z^T [A U | M U]: 4 N nz m flops (the products'
  *             20 nnz + 8 N nz bytes read);
  *   UPDATE    8 N nz + 8 N m bytes, 2 N nz m flops;   RITZ  one workgroup. */
 typedef enum {
   BMG_K_EIGRES = 0, BMG_K_SPMM_AM = 1, BMG_K_SMOOTH = 2, BMG_K_RESIDUAL = 3,
   BMG_K_RESTRICT = 4, BMG_K_PROLONG = 5, BMG_K_GRAM = 6, BMG_K_UPDATE = 7, BMG_K_RITZ = 8,
-  BMG_K_SMOOTH_PAIR = 9, BMG_K_RESTRICT_RES = 10, BMG_K_PROLONG_SMOOTH = 11
+  BMG_K_SMOOTH_PAIR = 9, BMG_K_RESTRICT_RES = 10, BMG_K_PROLONG_SMOOTH = 11,
+  BMG_K_SMOOTH_ADD = 12
 } bmg_kernel_class;
 
 /* Fill *o with the defaults listed above. */

@@ -25,7 +25,7 @@ EXPORTS = {"xyz": 0, "tri": 1, "parents": 2, "ell_cols": 3, "ell_a": 4, "ell_m":
            "lumped": 7, "coarse_eig": 8}
 KERNEL_CLASSES = {"eigres": 0, "spmm_am": 1, "smooth": 2, "residual": 3, "restrict": 4,
                   "prolong": 5, "gram": 6, "update": 7, "ritz": 8, "smooth_pair": 9,
-                  "restrict_res": 10, "prolong_smooth": 11}
+                  "restrict_res": 10, "prolong_smooth": 11, "smooth_add": 12}
 OPS = {"A": 0, "M": 1, "shifted": 2, "residual": 3, "smooth_fwd": 4, "smooth_bwd": 5,
        "restrict": 6, "prolong_add": 7, "vcycle": 8, "gaussian": 9, "gram": 10, "syev": 11,
        "eigres": 12, "update": 13, "gram_am": 14}

@@ -173,8 +173,11 @@ int eigres_blocks(const DevLevel& L, int m);
 int launch_colsum(const double* part, int nblk, int m, double* out, hipStream_t s);
 
 template <typename T>
+// u_add != nullptr: the sweep's result is added to the FP64 block u_add
+// (n x m) instead of being written to y (the cycle's last sweep of the finest
+// level adds its correction to the iterate directly).
 int launch_jacobi(const DevLevel& L, const T* S, double omega, const T* x, const T* f, T* y,
-                  bool x_is_zero, int m, hipStream_t s);
+                  bool x_is_zero, int m, hipStream_t s, double* u_add = nullptr);
 template <typename T>
 int launch_gs_colour(const DevLevel& L, const T* S, int colour, T* x, const T* f, int m,
                      hipStream_t s);

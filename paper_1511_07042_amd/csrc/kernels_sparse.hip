@@ -90,7 +90,7 @@ __device__ __forceinline__ void row_gather(const int* __restrict__ cols, const T
 }
 
 // ---------------------------------------------------------- shifted ops --
-enum { K_SHIFTED = 0, K_RESIDUAL = 1, K_JACOBI = 2, K_JACOBI0 = 3 };
+enum { K_SHIFTED = 0, K_RESIDUAL = 1, K_JACOBI = 2, K_JACOBI0 = 3, K_JACOBI_ADD = 4 };
 
 // MODE K_SHIFTED: y = S x; K_RESIDUAL: y = f - S x;
 // K_JACOBI: y = x + omega (f - S x) / d; K_JACOBI0: y = omega f / d  (x = 0),
@@ -101,7 +101,8 @@ __global__ void __launch_bounds__(256) k_rowop(int64_t n, int W, int m, int cpr,
                                                const int* __restrict__ cols,
                                                const T* __restrict__ S, T omega,
                                                const T* __restrict__ x,
-                                               const T* __restrict__ f, T* __restrict__ y) {
+                                               const T* __restrict__ f, T* __restrict__ y,
+                                               double* __restrict__ u) {
   constexpr int VW = Vec<T>::N;
   const int rloc = threadIdx.x / cpr;
   const int ch = threadIdx.x - rloc * cpr;
@@ -115,14 +116,21 @@ __global__ void __launch_bounds__(256) k_rowop(int64_t n, int W, int m, int cpr,
       for (int c = 0; c < VW; ++c) acc.v[c] = omega * fv.v[c] / d;
     } else {
       Vec<T> fv;
-      if (MODE == K_RESIDUAL || MODE == K_JACOBI) fv = ld(f + r * m + ch * VW);
+      constexpr bool kF = MODE == K_RESIDUAL || MODE == K_JACOBI || MODE == K_JACOBI_ADD;
+      if (kF) fv = ld(f + r * m + ch * VW);
       row_gather<T, WT>(cols, S, base, W, x, m, ch * VW, acc, xr);
-      if (MODE == K_RESIDUAL || MODE == K_JACOBI)
+      if (kF)
         for (int c = 0; c < VW; ++c) acc.v[c] = fv.v[c] - acc.v[c];
-      if (MODE == K_JACOBI)
+      if (MODE == K_JACOBI || MODE == K_JACOBI_ADD)
         for (int c = 0; c < VW; ++c) acc.v[c] = xr.v[c] + omega * acc.v[c] / d;
     }
-    st(y + r * m + ch * VW, acc);
+    if (MODE == K_JACOBI_ADD) {
+      // the sweep's result is the correction: added to the FP64 iterate
+      double* ur = u + r * m + ch * VW;
+      for (int c = 0; c < VW; ++c) ur[c] += double(acc.v[c]);
+    } else {
+      st(y + r * m + ch * VW, acc);
+    }
   }
 }
 
@@ -688,23 +696,26 @@ int launch_shifted(const DevLevel& L, const T* S, int mode, const T* x, const T*
   Geom g = row_geom<T>(L.n, m);
   if (mode == ROW_SHIFTED)
     BMG_BY_WIDTH(L.W, (k_rowop<T, K_SHIFTED, 7>), (k_rowop<T, K_SHIFTED, 0>), g.grid, g.block, 0, s,
-                 L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(0), x, f, y);
+                 L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(0), x, f, y, nullptr);
   else
     BMG_BY_WIDTH(L.W, (k_rowop<T, K_RESIDUAL, 7>), (k_rowop<T, K_RESIDUAL, 0>), g.grid, g.block, 0, s,
-                 L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(0), x, f, y);
+                 L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(0), x, f, y, nullptr);
   return check_launch();
 }
 
 template <typename T>
 int launch_jacobi(const DevLevel& L, const T* S, double omega, const T* x, const T* f, T* y,
-                  bool x_is_zero, int m, hipStream_t s) {
+                  bool x_is_zero, int m, hipStream_t s, double* u_add) {
   Geom g = row_geom<T>(L.n, m);
   if (x_is_zero)
     BMG_LAUNCH((k_rowop<T, K_JACOBI0, 0>), g.grid, g.block, 0, s, L.n, L.W, m, g.cpr, g.rpb, L.cols,
-               S, T(omega), x, f, y);
+               S, T(omega), x, f, y, nullptr);
+  else if (u_add != nullptr)
+    BMG_BY_WIDTH(L.W, (k_rowop<T, K_JACOBI_ADD, 7>), (k_rowop<T, K_JACOBI_ADD, 0>), g.grid, g.block, 0,
+                 s, L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(omega), x, f, y, u_add);
   else
     BMG_BY_WIDTH(L.W, (k_rowop<T, K_JACOBI, 7>), (k_rowop<T, K_JACOBI, 0>), g.grid, g.block, 0, s,
-                 L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(omega), x, f, y);
+                 L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(omega), x, f, y, nullptr);
   return check_launch();
 }
 
@@ -839,7 +850,7 @@ int launch_write_evecs(int64_t n, const double* U, int m, const int* sel, const 
   template int launch_shifted<T>(const DevLevel&, const T*, int, const T*, const T*, T*, int,   \
                                  hipStream_t);                                                   \
   template int launch_jacobi<T>(const DevLevel&, const T*, double, const T*, const T*, T*, bool, \
-                                int, hipStream_t);                                               \
+                                int, hipStream_t, double*);                                               \
   template int launch_gs_colour<T>(const DevLevel&, const T*, int, T*, const T*, int, hipStream_t); \
   template int launch_eigres<T>(const DevLevel&, const double*, const double*, double, T*,       \
                                 double*, int, int, hipStream_t);                                 \

@@ -330,6 +330,11 @@ struct Cycle {
   const TailArgs* tail_d = nullptr;
   int tail_lds = 0;
   int tail_groups = 1;  // workgroups of the tail (column groups)
+  // set by the caller: the final Jacobi post-sweep of level add_level adds its
+  // result to add_u (FP64 n x m); added reports whether that happened
+  double* add_u = nullptr;
+  int add_level = -1;
+  bool added = false;
   bool fuse_ok = std::getenv("BMG_NO_FUSE") == nullptr;  // fused Jacobi cycle kernels
 
   // Pack the LDS image of levels l_c..hi (the largest hi whose image and work
@@ -461,17 +466,25 @@ struct Cycle {
 
   int kclass(int k) const { return kt ? k : -2; }
 
-  int sweep(int l, bool forward, bool from_zero) {
+  // last: the cycle's final post-sweep on its top level, which (Jacobi, with
+  // add_u set) adds its result to add_u instead of writing e[l]
+  int sweep(int l, bool forward, bool from_zero, bool last = false) {
     const DevLevel& D = h->dev[l];
     const HostLevel& H = h->host[l];
     const double b = sizeof(T), n = double(D.n);
     if (c.smoother == BMG_SMOOTH_JACOBI) {
-      const int kc = from_zero ? -2 : kclass(BMG_K_SMOOTH);
-      if (kt) kt->add(kc, (4 + b) * double(H.nnz) + 3 * b * n * c.m, 1);
+      const bool fold = last && !from_zero && add_u != nullptr && l == add_level;
+      const int kc = from_zero ? -2 : kclass(fold ? BMG_K_SMOOTH_ADD : BMG_K_SMOOTH);
+      if (kt)
+        kt->add(kc, fold ? (4 + b) * double(H.nnz) + 2 * b * n * c.m + 16.0 * n * c.m
+                         : (4 + b) * double(H.nnz) + 3 * b * n * c.m, 1);
       if (kt) BMG_TRY(kt->begin(kc));
-      BMG_TRY(launch_jacobi<T>(D, S[l], c.omega, e[l], f[l], t[l], from_zero, c.m, s));
+      BMG_TRY(launch_jacobi<T>(D, S[l], c.omega, e[l], f[l], t[l], from_zero, c.m, s, fold ? add_u : nullptr));
       if (kt) BMG_TRY(kt->end(kc));
+      // the roles swap as after any sweep (with fold, e[l] then holds no
+      // result: the correction is in add_u), so a cycle's swaps stay even
       std::swap(e[l], t[l]);
+      if (fold) added = true;
       return BMG_OK;
     }
     if (from_zero) BMG_TRY(launch_fill<T>(e[l], D.n * c.m, T(0), s));
@@ -553,7 +566,7 @@ struct Cycle {
       BMG_TRY(launch_prolong_jacobi<T>(D, S[l], c.omega, e[l], e[l - 1], f[l], t[l], c.m, s));
       if (kt) BMG_TRY(kt->end(kc));
       std::swap(e[l], t[l]);
-      for (int k = 1; k < c.nu2; ++k) BMG_TRY(sweep(l, false, false));
+      for (int k = 1; k < c.nu2; ++k) BMG_TRY(sweep(l, false, false, k == c.nu2 - 1));
       return BMG_OK;
     }
     const int kc = kclass(BMG_K_PROLONG);
@@ -561,7 +574,7 @@ struct Cycle {
     if (kt) BMG_TRY(kt->begin(kc));
     BMG_TRY(launch_prolong_add<T>(D, e[l - 1], e[l], c.m, s));
     if (kt) BMG_TRY(kt->end(kc));
-    for (int k = 0; k < c.nu2; ++k) BMG_TRY(sweep(l, false, false));
+    for (int k = 0; k < c.nu2; ++k) BMG_TRY(sweep(l, false, false, k == c.nu2 - 1));
     return BMG_OK;
   }
 };
@@ -722,6 +735,8 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   ra.sigma = sigma;
   ra.rtol2 = kRitzRtol2;
   if (const char* e = std::getenv("BMG_RITZ_RTOL")) ra.rtol2 = std::atof(e) * std::atof(e);
+  // U += E in the cycle's last Jacobi sweep (BMG_NO_FUSE keeps it separate)
+  const bool fold_add = std::getenv("BMG_NO_FUSE") == nullptr;
   // the first Ritz step of a solve starts cold; later ones may reuse the
   // coarse-block basis the previous step left (BMG_NO_WARM turns this off)
   const int warm_ok = std::getenv("BMG_NO_WARM") ? 0 : 1;
@@ -771,8 +786,12 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   };
   // H2-H6 followed by the next H1: the same launches every cycle
   auto cycle_body = [&]() -> int {
+    // U += E: folded into the cycle's last sweep when that is a Jacobi sweep
+    cyc.add_u = fold_add ? w->U : nullptr;
+    cyc.add_level = L;
+    cyc.added = false;
     BMG_TRY(cyc.vcycle(L));
-    BMG_TRY(launch_add_to<T>(w->U, cyc.e[L], N * m, s));
+    if (!cyc.added) BMG_TRY(launch_add_to<T>(w->U, cyc.e[L], N * m, s));
     BMG_TRY(ritz_step());
     BMG_TRY(residual_step());
     return BMG_OK;
