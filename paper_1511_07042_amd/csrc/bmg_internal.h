@@ -170,7 +170,11 @@ template <typename T>
 int launch_eigres(const DevLevel& L, const double* x, const double* theta, double sgn, T* y,
                   double* rho2_part, int nblk, int m, hipStream_t s);
 int eigres_blocks(const DevLevel& L, int m);
-int launch_colsum(const double* part, int nblk, int m, double* out, hipStream_t s);
+// out[c] = sum_b part[c][b]; with mirror set (host-mapped [theta m][rho2 m][8
+// status words]) theta and the status words are copied from src (the device
+// buffer of that layout, out = src + m) and the sums written there as well.
+int launch_colsum(const double* part, int nblk, int m, double* out, hipStream_t s,
+                  const double* src = nullptr, double* mirror = nullptr);
 
 template <typename T>
 // u_add != nullptr: the sweep's result is added to the FP64 block u_add

@@ -458,8 +458,13 @@ __global__ void __launch_bounds__(256) k_eigres(int64_t n, int W, int m, int cpr
 // out[c] = sum_b part[c][b] (partials stored column-major), one 256-thread
 // block per column: each thread sums a fixed strided subset, then a fixed
 // reduction tree (deterministic).
+// With mirror set (a host-mapped buffer laid out like [theta m][rho2 m][8
+// status words], src = the device copy of that layout with out = src + m) the
+// kernel also writes theta, the sums and the status words there, so the host
+// reads a cycle's results without a separate copy.
 __global__ void __launch_bounds__(256) k_colsum(const double* __restrict__ part, int nblk, int m,
-                                                double* __restrict__ out) {
+                                                double* __restrict__ out, const double* src,
+                                                double* mirror) {
   __shared__ double red[4];
   const int c = blockIdx.x;
   const double* pc = part + int64_t(c) * nblk;
@@ -468,7 +473,15 @@ __global__ void __launch_bounds__(256) k_colsum(const double* __restrict__ part,
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) out[c] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) {
+    const double t = (red[0] + red[1]) + (red[2] + red[3]);
+    out[c] = t;
+    if (mirror != nullptr) {
+      mirror[c] = src[c];
+      mirror[m + c] = t;
+    }
+  }
+  if (mirror != nullptr && c == 0 && threadIdx.x < 8) mirror[2 * m + threadIdx.x] = src[2 * m + threadIdx.x];
 }
 
 // --------------------------------------------------------------- transfers --
@@ -782,8 +795,9 @@ int launch_eigres(const DevLevel& L, const double* x, const double* theta, doubl
   return check_launch();
 }
 
-int launch_colsum(const double* part, int nblk, int m, double* out, hipStream_t s) {
-  k_colsum<<<m, 256, 0, s>>>(part, nblk, m, out);
+int launch_colsum(const double* part, int nblk, int m, double* out, hipStream_t s, const double* src,
+                  double* mirror) {
+  k_colsum<<<m, 256, 0, s>>>(part, nblk, m, out, src, mirror);
   return check_launch();
 }
 

@@ -42,6 +42,7 @@ struct bmg_workspace {
   double *sign = nullptr, *argv = nullptr;
   int* argi = nullptr;
   double* hbuf = nullptr;  // pinned host: theta[m], rho2[m], status
+  double* hbuf_d = nullptr;  // its device-side address (written by k_colsum)
   bmg::TailArgs* tail_h = nullptr;  // pinned host staging of the tail descriptor
   bmg::TailArgs* tail_d = nullptr;  // device copy
   hipStream_t stream = nullptr;     // internal stream (capturable), joined to the caller's
@@ -172,6 +173,10 @@ int make_workspace(bmg_hierarchy* h, int m, int n_c, int prec, bmg_workspace** o
     free_workspace(w);
     set_error("hipHostMalloc failed");
     return BMG_ENOMEM;
+  }
+  if (hipHostGetDevicePointer(reinterpret_cast<void**>(&w->hbuf_d), w->hbuf, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    w->hbuf_d = nullptr;  // the results are then copied back instead
   }
   *out = w;
   return BMG_OK;
@@ -781,7 +786,7 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     BMG_TRY(kt.begin(BMG_K_EIGRES));
     BMG_TRY(launch_eigres<T>(DL, w->U, w->theta, -1.0, cyc.f[L], w->rho2part, w->nblk_res, m, s));
     BMG_TRY(kt.end(BMG_K_EIGRES));
-    BMG_TRY(launch_colsum(w->rho2part, w->nblk_res, m, w->rho2, s));
+    BMG_TRY(launch_colsum(w->rho2part, w->nblk_res, m, w->rho2, s, w->theta, w->hbuf_d));
     return BMG_OK;
   };
   // H2-H6 followed by the next H1: the same launches every cycle
@@ -850,7 +855,10 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   };
   BMG_TRY(residual_step());
   for (;;) {
-    BMG_HIP(hipMemcpyAsync(w->hbuf, w->theta, sizeof(double) * (2 * m + 8), hipMemcpyDeviceToHost, s));
+    // theta, rho2 and the Ritz status words: written to the pinned host buffer
+    // by the cycle's last kernel (k_colsum), else copied back here
+    if (w->hbuf_d == nullptr)
+      BMG_HIP(hipMemcpyAsync(w->hbuf, w->theta, sizeof(double) * (2 * m + 8), hipMemcpyDeviceToHost, s));
     BMG_HIP(hipStreamSynchronize(s));
     kt.harvest(cycles > 0 && use_graph);
     std::memcpy(theta.data(), w->hbuf, sizeof(double) * m);
