@@ -469,7 +469,16 @@ __global__ void __launch_bounds__(256) k_colsum(const double* __restrict__ part,
   const int c = blockIdx.x;
   const double* pc = part + int64_t(c) * nblk;
   double s = 0;
-  for (int b = threadIdx.x; b < nblk; b += 256) s += pc[b];
+  // eight loads in flight, added in the order b = tid, tid + 256, ...
+  constexpr int kU = 8;
+  for (int b0 = threadIdx.x; b0 < nblk; b0 += 256 * kU) {
+    double v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) v[u] = b0 + 256 * u < nblk ? pc[b0 + 256 * u] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (b0 + 256 * u < nblk) s += v[u];
+  }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
