@@ -146,7 +146,8 @@ __device__ __forceinline__ double4 am_item(int64_t r, bool valid, int W, const i
 // as k_gram does, with the B fragments read from LDS.  Partial sums per block
 // as in k_gram (reduced by k_gram_reduce in a fixed order).  A chunk is
 // kGramAmChunk rows: its products are formed in one pass (more gathers in
-// flight per barrier) and contracted 16 rows at a time.
+// flight per barrier; with m > 32 a thread takes three items at once) and
+// contracted 16 rows at a time.
 template <int TI, int TJW, int WT>
 __global__ void __launch_bounds__(256) k_gram_am(int64_t n, int64_t rows_per_block, int nzp, int nyp,
                                                  const int* __restrict__ cols,
@@ -279,11 +280,13 @@ __global__ void __launch_bounds__(1024) k_gram_reduce(const double* __restrict__
 }
 
 // U[r][c] = sum_i Z[r][i] Y[i][c], Z = [z1 | z2] (nz <= 96 columns), on the
-// FP64 matrix cores.  Y (zero-padded to KS*4 rows and TJ*16 columns) is staged
-// in LDS once per block; each wavefront owns 16-row tiles of Z.  For one tile a
-// lane loads its A fragments for every k step (row l % 16, column 4 s + l / 16)
-// into registers, the wavefront runs KS x TJ MFMAs with B fragments read from
-// LDS, and then writes the tile's 16 x m outputs.  A tile is read completely
+// FP64 matrix cores.  Y (zero-padded to KS*4 rows, KS even, and TJ*16 columns)
+// is staged in LDS once per block; each wavefront owns 16-row tiles of Z.  For
+// one tile a lane loads its A fragments for every k step into registers (row
+// l % 16; steps 2 s' and 2 s' + 1 take columns 8 s' + 2 (l / 16) and the next
+// one, read together), the wavefront runs KS x TJ MFMAs with B fragments read
+// from LDS in the same row order, and then writes the tile's 16 x m outputs;
+// the next tile's fragments are loaded meanwhile.  A tile is read completely
 // before any of its outputs is written and no other wavefront touches its rows,
 // so U may alias z2 (the update is done in place).
 constexpr int kUpdKMax = 24;  // k steps of 4: nz <= 96
