@@ -241,40 +241,51 @@ __global__ void __launch_bounds__(256) k_gram_am(int64_t n, int64_t rows_per_blo
   }
 }
 
-// G[i][j] = sum_b part[b][i][j] in a fixed order: each block covers 64
-// consecutive outputs with 16 segments of the partials (b = seg mod 16), then
-// adds the 16 segment sums in order.
+// G[i][j] = sum_b part[b][i][j] in a fixed order.  A block covers 16
+// consecutive outputs with 64 segments of the partials (segment q takes
+// b = q, q + 64, ...; a wavefront reads four 128-byte runs per load); the
+// segment sums are then added in groups of four (q = 4g .. 4g + 3) and the 16
+// group sums in order.
 __global__ void __launch_bounds__(1024) k_gram_reduce(const double* __restrict__ part, int nblk,
                                                       int nzp, int nyp, int nz, int ny,
                                                       double* __restrict__ G) {
-  __shared__ double red[16][64];
-  const int el = threadIdx.x & 63, seg = threadIdx.x >> 6;
-  const int e = blockIdx.x * 64 + el;
+  constexpr int kOut = 16, kSeg = 64;
+  __shared__ double red[kSeg][kOut];
+  const int el = threadIdx.x & (kOut - 1), seg = threadIdx.x / kOut;
+  const int e = blockIdx.x * kOut + el;
   const int tot = nz * ny;
   double s = 0.0;
   if (e < tot) {
     const int i = e / ny, j = e - (e / ny) * ny;
     const int64_t off = int64_t(i) * nyp + j;
     const int64_t stride = int64_t(nzp) * nyp;
-    // eight loads in flight, added in the order b = seg, seg + 16, ...
+    // eight loads in flight, added in the order b = seg, seg + 64, ...
     constexpr int kU = 8;
-    for (int b0 = seg; b0 < nblk; b0 += 16 * kU) {
+    for (int b0 = seg; b0 < nblk; b0 += kSeg * kU) {
       double v[kU];
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
-        const int b = b0 + 16 * u;
+        const int b = b0 + kSeg * u;
         v[u] = b < nblk ? part[b * stride + off] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < kU; ++u)
-        if (b0 + 16 * u < nblk) s += v[u];
+        if (b0 + kSeg * u < nblk) s += v[u];
     }
   }
   red[seg][el] = s;
   __syncthreads();
-  if (seg == 0 && e < tot) {
+  double g = 0.0;
+  if (threadIdx.x < kOut * (kSeg / 4)) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) g += red[4 * seg + q][el];
+  }
+  __syncthreads();
+  if (threadIdx.x < kOut * (kSeg / 4)) red[seg][el] = g;
+  __syncthreads();
+  if (threadIdx.x < kOut && e < tot) {
     double t = 0.0;
-    for (int q = 0; q < 16; ++q) t += red[q][el];
+    for (int q = 0; q < kSeg / 4; ++q) t += red[q][el];
     G[e] = t;
   }
 }
@@ -438,7 +449,7 @@ int launch_gram(const GramPlan& p, int64_t n, const double* z1, int w1, const do
   int st = check_launch();
   if (st != BMG_OK) return st;
   const int tot = p.nz * p.ny;
-  BMG_LAUNCH((k_gram_reduce), (tot + 63) / 64, 1024, 0, s, part, p.nblk, p.nzp, p.nyp, p.nz, p.ny, G);
+  BMG_LAUNCH((k_gram_reduce), (tot + 15) / 16, 1024, 0, s, part, p.nblk, p.nzp, p.nyp, p.nz, p.ny, G);
   return check_launch();
 }
 
@@ -493,7 +504,7 @@ int launch_gram_am(const GramPlan& p, const DevLevel& L, const double* w, int w1
   int st = check_launch();
   if (st != BMG_OK) return st;
   const int tot = p.nz * p.ny;
-  BMG_LAUNCH((k_gram_reduce), (tot + 63) / 64, 1024, 0, s, part, p.nblk, p.nzp, p.nyp, p.nz, p.ny, G);
+  BMG_LAUNCH((k_gram_reduce), (tot + 15) / 16, 1024, 0, s, part, p.nblk, p.nzp, p.nyp, p.nz, p.ny, G);
   return check_launch();
 }
 
