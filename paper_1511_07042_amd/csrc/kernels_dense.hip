@@ -381,31 +381,43 @@ static_assert((shared_doubles() + vsize(kMaxN) + kMaxN * (kMaxN + 1)) * 8 <= 160
               "the Ritz kernel's LDS must fit one CU (160 KiB)");
 
 // Select the mm diagonal entries of the packed r x r matrix X nearest 0 (ties
-// by value, then index) and order them ascending into sh.sel[0..mm).
+// by value, then index) and order them ascending into sh.sel[0..mm).  The
+// wavefronts share out the entries j; a wavefront counts the entries ahead of
+// j with one ballot per 64 of them (lane l compares entry i0 + l).
 __device__ void select_nearest_zero(const double* X, int r, int mm, RitzShared& sh) {
   const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nwv = nt >> 6;
   for (int j = tid; j < r; j += nt) sh.d[j] = X[tri(j, j)];
   __syncthreads();
-  for (int j = tid; j < r; j += nt) {
+  for (int j = wave; j < r; j += nwv) {
     const double mj = sh.d[j], aj = fabs(mj);
     int rank = 0;
-    for (int i = 0; i < r; ++i) {
-      const double mi = sh.d[i], ai = fabs(mi);
-      if (ai < aj || (ai == aj && (mi < mj || (mi == mj && i < j)))) ++rank;
+    for (int i0 = 0; i0 < r; i0 += 64) {
+      const int i = i0 + lane;
+      bool ahead = false;
+      if (i < r) {
+        const double mi = sh.d[i], ai = fabs(mi);
+        ahead = ai < aj || (ai == aj && (mi < mj || (mi == mj && i < j)));
+      }
+      rank += __popcll(__ballot(ahead));
     }
-    sh.rank[j] = rank;
+    if (lane == 0) sh.rank[j] = rank;
   }
   __syncthreads();
-  for (int j = tid; j < r; j += nt) {
-    if (sh.rank[j] >= mm) continue;
+  for (int j = wave; j < r; j += nwv) {
+    if (sh.rank[j] >= mm) continue;  // the same j in every lane of the wavefront
     const double mj = sh.d[j];
     int pos = 0;
-    for (int i = 0; i < r; ++i) {
-      if (sh.rank[i] >= mm) continue;
-      const double mi = sh.d[i];
-      if (mi < mj || (mi == mj && i < j)) ++pos;
+    for (int i0 = 0; i0 < r; i0 += 64) {
+      const int i = i0 + lane;
+      bool ahead = false;
+      if (i < r && sh.rank[i] < mm) {
+        const double mi = sh.d[i];
+        ahead = mi < mj || (mi == mj && i < j);
+      }
+      pos += __popcll(__ballot(ahead));
     }
-    sh.sel[pos] = j;
+    if (lane == 0) sh.sel[pos] = j;
   }
   __syncthreads();
 }
