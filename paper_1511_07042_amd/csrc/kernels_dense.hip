@@ -318,7 +318,8 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // each output element is handed once to fo(i, j, value).  Lane layouts: A lane
 // l holds row l % 16 and k = l / 16; B lane l holds k = l / 16 and column l % 16;
 // result lane l holds column l % 16 of rows l / 16 + 4 v.  skip(ti, tj) drops
-// tiles whose outputs are not needed.
+// tiles whose outputs are not needed.  The fragments of eight k steps are
+// fetched before their MFMAs, so a tile waits on LDS once per 32 of K.
 template <class FA, class FB, class FO, class SK>
 __device__ __forceinline__ void lds_mfma_gemm(int M, int N, int K, FA fa, FB fb, FO fo, SK skip) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -329,11 +330,18 @@ __device__ __forceinline__ void lds_mfma_gemm(int M, int N, int K, FA fa, FB fb,
     if (skip(ti, tj)) continue;
     d4 acc = d4{0.0, 0.0, 0.0, 0.0};
     const int i = 16 * ti + li, j = 16 * tj + li;
-    for (int k0 = 0; k0 < K; k0 += 4) {
-      const int k = k0 + lk;
-      const double a = (i < M && k < K) ? fa(i, k) : 0.0;
-      const double b = (k < K && j < N) ? fb(k, j) : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    constexpr int kS = 8;
+    for (int k0 = 0; k0 < K; k0 += 4 * kS) {
+      double a[kS], b[kS];
+#pragma unroll
+      for (int t = 0; t < kS; ++t) {
+        const int k = k0 + 4 * t + lk;
+        a[t] = (i < M && k < K) ? fa(i, k) : 0.0;
+        b[t] = (k < K && j < N) ? fb(k, j) : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < kS; ++t)
+        if (k0 + 4 * t < K) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[t], acc, 0, 0, 0);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -422,8 +430,10 @@ __device__ void select_nearest_zero(const double* X, int r, int mm, RitzShared& 
   __syncthreads();
 }
 
-// Global scratch: GA, GM (permuted order [U', W_c]), Bs = S (GA - sigma GM) S,
-// Lg (packed inverse Cholesky factor, or the SVQB basis T), W1 (SVQB only).
+// Global scratch: GA, GM (permuted order [U', W_c]; read back by SVQB only),
+// an unused nz^2 slot, Lg (packed inverse Cholesky factor, or the SVQB basis
+// T), W1 (SVQB only).  The scaled shifted matrix S (GA - sigma GM) S stays in
+// LDS (packed, in R0) until the products.
 __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma, double rtol2, int warm,
                                                    const double* __restrict__ G,
                                                    const double* __restrict__ GW, double* Y,
@@ -437,8 +447,7 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
   double* Rb = Ra + nz * (nz + 1) / 2;  // packed
   double* GA = scratch;
   double* GM = GA + nz * nz;
-  double* Bs = GM + nz * nz;
-  double* Lg = Bs + nz * nz;
+  double* Lg = GM + 2 * nz * nz;
   double* W1 = Lg + nz * nz;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int m2 = 2 * m, nc2 = 2 * n_c;
@@ -466,23 +475,26 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
     }
     GA[e] = va;
     GM[e] = vm;
-    R0[e] = vm;
+    if (b <= a) {  // lower triangles (both blocks are symmetric) into LDS
+      Ra[tri(a, b)] = vm;
+      Rb[tri(a, b)] = va;
+    }
   }
   __syncthreads();
   for (int i = tid; i < nz; i += nt) {
-    const double dg = R0[i * nz + i];
+    const double dg = Ra[tri(i, i)];
     sh.sv[i] = dg > 0.0 ? 1.0 / sqrt(dg) : 0.0;
   }
   if (tid == 0) sh.r = 0;
   __syncthreads();
   for (int e = tid; e < nz * nz; e += nt) {
     const int i = e / nz, j = e - (e / nz) * nz;
+    if (j > i) continue;
     const double sij = sh.sv[i] * sh.sv[j];
-    if (j <= i) {
-      Ra[tri(i, j)] = R0[e] * sij;
-      Rb[tri(i, j)] = (i == j) ? 1.0 : 0.0;
-    }
-    Bs[e] = (GA[e] - sigma * R0[e]) * sij;
+    const double vm = Ra[tri(i, j)], va = Rb[tri(i, j)];
+    Ra[tri(i, j)] = vm * sij;
+    Rb[tri(i, j)] = (i == j) ? 1.0 : 0.0;
+    R0[tri(i, j)] = (va - sigma * vm) * sij;  // S (GA - sigma GM) S, packed
   }
   __syncthreads();
   ts[1] = wall_clock64();
@@ -644,7 +656,10 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
     }
     __syncthreads();
   }
-  for (int j = tid; j < n; j += nt) sh.d[j] = Ra[tri(j, j)];
+  for (int j = tid; j < n; j += nt) {
+    sh.d[j] = Ra[tri(j, j)];
+    sh.p1[j] = sqrt(sh.d[j]);  // kept pivots only are read (the blocks' pivots are no longer needed)
+  }
   __syncthreads();
   ts[2] = wall_clock64();
   int r = sh.r;
@@ -660,16 +675,17 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
       const int a = e / r, b = e - (e / r) * r;
       if (b <= a) {
         const int ka = sh.kk[a], kb = sh.kk[b];
-        const double v = Rb[tri(ka, kb)] / sqrt(sh.d[ka]);
+        const double v = Rb[tri(ka, kb)] / sh.p1[ka];
         Ra[tri(a, b)] = v;
         Lg[tri(a, b)] = v;
       }
     }
     __syncthreads();
-    // Bk = Bs on the kept rows and columns, packed, into Rb
+    // Bk = the scaled shifted matrix on the kept rows and columns (kk is
+    // increasing, so a >= b reads the lower triangle), packed, into Rb
     for (int e = tid; e < r * r; e += nt) {
       const int a = e / r, b = e - (e / r) * r;
-      if (b <= a) Rb[tri(a, b)] = Bs[sh.kk[a] * n + sh.kk[b]];
+      if (b <= a) Rb[tri(a, b)] = R0[tri(sh.kk[a], sh.kk[b])];
     }
     __syncthreads();
     // W1 = Li Bk into R0 (r x r), then C = W1 Li^T: only its lower triangle is
@@ -943,7 +959,7 @@ int set_lds_attr() {
 
 }  // namespace
 
-// GA, GM, Bs, Lg, W1 (nz^2 each), then the coarse-block basis kept between
+// GA, GM, an unused slot, Lg, W1 (nz^2 each), then the coarse-block basis kept between
 // calls (kWarmMax^2) and its header (valid, r, nw, -, kept columns: <= 128 ints)
 int ritz_scratch_doubles(int nz) { return 5 * nz * nz + kWarmMax * kWarmMax + 64; }
 
