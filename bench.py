@@ -68,6 +68,8 @@ def parse():
                          "with the largest total time in the mixed breakdown)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c4", action="store_true", help="skip the 655362-vertex section")
+    ap.add_argument("--no-concurrent", action="store_true",
+                    help="skip the 16 concurrent solves through the serving API")
     ap.add_argument("--serving", type=int, default=32, metavar="N",
                     help="requests in the serving section (0: skip it)")
     ap.add_argument("--serving-only", action="store_true",
@@ -372,7 +374,7 @@ def main():
         "fp64_path": main_res.get("fp64"),
         "mixed_path": main_res.get("mixed"),
     }
-    if a.only in ("both", "mixed"):
+    if a.only in ("both", "mixed") and not a.no_concurrent:
         out["concurrent"] = concurrent(bmg, cfg, a.smoother)
     if not a.no_c4 and a.workload != "c4_sphere_ref8":
         c4 = bench_workload(bmg, "c4_sphere_ref8", CONFIGS["c4_sphere_ref8"], precs, 2, 1,
