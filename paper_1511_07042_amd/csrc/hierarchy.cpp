@@ -1,6 +1,11 @@
 // Device-resident hierarchy: upload of the host levels, the level-0
 // eigendecomposition, sizes and export for inspection.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <utility>
+#include <vector>
 
 #include "bmg_internal.h"
 
@@ -21,12 +26,56 @@ int upload(T** dst, const T* src, size_t count, hipStream_t s, int64_t& bytes) {
   return BMG_OK;
 }
 
+// Rows ordered along a Morton (Z-order) curve through the vertex positions:
+// each coordinate is quantised to 21 bits over the level's bounding box and
+// the bits are interleaved; ties keep the index order.  Rows visited in this
+// order gather neighbour rows that were gathered a moment before, so a pass
+// over a level much larger than the caches fetches each row about once
+// instead of several times (the index order puts the coarse vertices first,
+// so every row's neighbours are also used half a pass away).
+std::vector<int32_t> morton_order(const HostLevel& H) {
+  const int64_t n = H.n;
+  double lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) lo[d] = hi[d] = n > 0 ? H.xyz[d] : 0.0;
+  for (int64_t i = 0; i < n; ++i)
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = std::min(lo[d], H.xyz[3 * i + d]);
+      hi[d] = std::max(hi[d], H.xyz[3 * i + d]);
+    }
+  constexpr int kBits = 21;
+  const double top = double((1u << kBits) - 1);
+  std::vector<std::pair<uint64_t, int32_t>> key(static_cast<size_t>(n));
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t code = 0;
+    uint32_t q[3];
+    for (int d = 0; d < 3; ++d) {
+      const double w = hi[d] > lo[d] ? (H.xyz[3 * i + d] - lo[d]) / (hi[d] - lo[d]) : 0.0;
+      q[d] = uint32_t(std::min(top, std::max(0.0, std::floor(w * top))));
+    }
+    for (int b = kBits - 1; b >= 0; --b)
+      for (int d = 0; d < 3; ++d) code = (code << 1) | ((q[d] >> b) & 1u);
+    key[size_t(i)] = {code, int32_t(i)};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int32_t> ord(static_cast<size_t>(n));
+  for (int64_t i = 0; i < n; ++i) ord[size_t(i)] = key[size_t(i)].second;
+  return ord;
+}
+
+// Levels with at least this many rows get a row order (smaller levels stay in
+// the caches in any order); BMG_ROW_ORDER_MIN_ROWS overrides it.
+int64_t row_order_min_rows() {
+  if (const char* e = std::getenv("BMG_ROW_ORDER_MIN_ROWS")) return std::atoll(e);
+  return 131072;
+}
+
 }  // namespace
 
 int upload_hierarchy(bmg_hierarchy* h, hipStream_t s) {
   const int nl = int(h->host.size());
   h->dev.resize(nl);
   std::vector<std::vector<float>> keep32;  // host staging must live until the stream syncs
+  const int64_t min_ordered = row_order_min_rows();
   for (int l = 0; l < nl; ++l) {
     const HostLevel& H = h->host[l];
     DevLevel& D = h->dev[l];
@@ -51,7 +100,12 @@ int upload_hierarchy(bmg_hierarchy* h, hipStream_t s) {
     BMG_TRY(upload(&D.parents, H.parents.data(), H.parents.size(), s, D.bytes));
     BMG_TRY(upload(&D.rtab, H.rtab.data(), H.rtab.size(), s, D.bytes));
     BMG_TRY(upload(&D.colour_rows, H.colour_rows.data(), H.colour_rows.size(), s, D.bytes));
-    BMG_HIP(hipStreamSynchronize(s));  // dinv is a local
+    std::vector<int32_t> ord;
+    if (H.n >= min_ordered) {
+      ord = morton_order(H);
+      BMG_TRY(upload(&D.row_order, ord.data(), ord.size(), s, D.bytes));
+    }
+    BMG_HIP(hipStreamSynchronize(s));  // dinv and ord are locals
   }
   // level-0 eigendecomposition on the device (FP64 and FP32, with transposes)
   const int64_t n0 = h->n0;
@@ -71,7 +125,7 @@ int upload_hierarchy(bmg_hierarchy* h, hipStream_t s) {
 
 void free_device(bmg_hierarchy* h) {
   for (auto& D : h->dev) {
-    void* ptrs[] = {D.cols, D.a64, D.m64, D.a32, D.m32, D.dinv, D.parents, D.rtab, D.colour_rows};
+    void* ptrs[] = {D.cols, D.a64, D.m64, D.a32, D.m32, D.dinv, D.parents, D.rtab, D.colour_rows, D.row_order};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     D = DevLevel();

@@ -95,19 +95,23 @@ enum { K_SHIFTED = 0, K_RESIDUAL = 1, K_JACOBI = 2, K_JACOBI0 = 3, K_JACOBI_ADD 
 // MODE K_SHIFTED: y = S x; K_RESIDUAL: y = f - S x;
 // K_JACOBI: y = x + omega (f - S x) / d; K_JACOBI0: y = omega f / d  (x = 0),
 // with S = A - sigma M (precomputed once per solve) and d = S_ii.
-// WT: ELL width when it is the built-in 7, else 0 (runtime W).
+// WT: ELL width when it is the built-in 7, else 0 (runtime W).  ord (or
+// null: rows in index order) is the order the rows are visited in: a
+// space-filling-curve order keeps the neighbour rows a pass gathers in cache
+// (every row's result is the same in any order).
 template <typename T, int MODE, int WT>
 __global__ void __launch_bounds__(256) k_rowop(int64_t n, int W, int m, int cpr, int rpb,
                                                const int* __restrict__ cols,
                                                const T* __restrict__ S, T omega,
                                                const T* __restrict__ x,
                                                const T* __restrict__ f, T* __restrict__ y,
-                                               double* __restrict__ u) {
+                                               double* __restrict__ u, const int* __restrict__ ord) {
   constexpr int VW = Vec<T>::N;
   const int rloc = threadIdx.x / cpr;
   const int ch = threadIdx.x - rloc * cpr;
   if (rloc >= rpb) return;
-  for (int64_t r = int64_t(blockIdx.x) * rpb + rloc; r < n; r += int64_t(gridDim.x) * rpb) {
+  for (int64_t i = int64_t(blockIdx.x) * rpb + rloc; i < n; i += int64_t(gridDim.x) * rpb) {
+    const int64_t r = ord != nullptr ? int64_t(ord[i]) : i;
     const int64_t base = r * W;
     Vec<T> acc, xr;
     const T d = S[base];
@@ -718,10 +722,10 @@ int launch_shifted(const DevLevel& L, const T* S, int mode, const T* x, const T*
   Geom g = row_geom<T>(L.n, m);
   if (mode == ROW_SHIFTED)
     BMG_BY_WIDTH(L.W, (k_rowop<T, K_SHIFTED, 7>), (k_rowop<T, K_SHIFTED, 0>), g.grid, g.block, 0, s,
-                 L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(0), x, f, y, nullptr);
+                 L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(0), x, f, y, nullptr, L.row_order);
   else
     BMG_BY_WIDTH(L.W, (k_rowop<T, K_RESIDUAL, 7>), (k_rowop<T, K_RESIDUAL, 0>), g.grid, g.block, 0, s,
-                 L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(0), x, f, y, nullptr);
+                 L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(0), x, f, y, nullptr, L.row_order);
   return check_launch();
 }
 
@@ -731,13 +735,13 @@ int launch_jacobi(const DevLevel& L, const T* S, double omega, const T* x, const
   Geom g = row_geom<T>(L.n, m);
   if (x_is_zero)
     BMG_LAUNCH((k_rowop<T, K_JACOBI0, 0>), g.grid, g.block, 0, s, L.n, L.W, m, g.cpr, g.rpb, L.cols,
-               S, T(omega), x, f, y, nullptr);
+               S, T(omega), x, f, y, nullptr, L.row_order);
   else if (u_add != nullptr)
     BMG_BY_WIDTH(L.W, (k_rowop<T, K_JACOBI_ADD, 7>), (k_rowop<T, K_JACOBI_ADD, 0>), g.grid, g.block, 0,
-                 s, L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(omega), x, f, y, u_add);
+                 s, L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(omega), x, f, y, u_add, L.row_order);
   else
     BMG_BY_WIDTH(L.W, (k_rowop<T, K_JACOBI, 7>), (k_rowop<T, K_JACOBI, 0>), g.grid, g.block, 0, s,
-                 L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(omega), x, f, y, nullptr);
+                 L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(omega), x, f, y, nullptr, L.row_order);
   return check_launch();
 }
 

@@ -180,6 +180,37 @@ def test_tail_column_groups_identical(lib, precision, monkeypatch):
         assert np.array_equal(V, V0), name
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_row_order_identical(lib, precision, monkeypatch):
+    # Levels of at least BMG_ROW_ORDER_MIN_ROWS rows visit their rows in a
+    # Morton order in the sweep / residual / shifted-product kernels (C4's two
+    # finest levels by default).  Every row's result is the same in any order,
+    # so a solve with every level ordered (threshold 0), on plain launches and
+    # on the graph replay, and with the unfused kernels, must equal the solve
+    # with none ordered bit for bit.
+    runs = {}
+    for name, thr, env in (("index", "1000000000", {"BMG_NO_GRAPH": "1"}),
+                           ("ordered", "0", {"BMG_NO_GRAPH": "1"}),
+                           ("ordered_graph", "0", {}),
+                           ("index_unfused", "1000000000", {"BMG_NO_FUSE": "1"}),
+                           ("ordered_unfused", "0", {"BMG_NO_FUSE": "1"})):
+        for k in ("BMG_NO_GRAPH", "BMG_NO_TAIL", "BMG_NO_FUSE"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        monkeypatch.setenv("BMG_ROW_ORDER_MIN_ROWS", thr)
+        h = lib.Hierarchy("sphere", 5)  # the threshold is read when the levels are uploaded
+        runs[name] = h.solve(25, m=32, smoother="jacobi", precision=precision)
+    for ref, other in (("index", "ordered"), ("index", "ordered_graph"),
+                       ("index_unfused", "ordered_unfused")):
+        ev0, V0, s0 = runs[ref]
+        ev, V, st = runs[other]
+        assert s0["converged"], ref
+        assert st["cycles"] == s0["cycles"], other
+        assert np.array_equal(ev, ev0), other
+        assert np.array_equal(V, V0), other
+
+
 def _golden_eigs(name):
     import os
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
