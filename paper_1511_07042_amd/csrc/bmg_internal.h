@@ -87,6 +87,7 @@ struct DevLevel {
   int32_t* rtab = nullptr;        // [n_prev][RW]
   int32_t* colour_rows = nullptr; // [n]
   int32_t* row_order = nullptr;   // [n] rows by Morton code of their vertex (large levels), else null
+  int32_t* chunk_order = nullptr; // [ceil(n / 16)] 16-row chunks by Morton code of their centroid (large levels), else null
   std::vector<int32_t> colour_ptr;
   int64_t bytes = 0;
 };

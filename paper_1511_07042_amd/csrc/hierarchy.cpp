@@ -33,14 +33,14 @@ int upload(T** dst, const T* src, size_t count, hipStream_t s, int64_t& bytes) {
 // over a level much larger than the caches fetches each row about once
 // instead of several times (the index order puts the coarse vertices first,
 // so every row's neighbours are also used half a pass away).
-std::vector<int32_t> morton_order(const HostLevel& H) {
-  const int64_t n = H.n;
+std::vector<int32_t> morton_order(const std::vector<double>& xyz) {
+  const int64_t n = int64_t(xyz.size() / 3);
   double lo[3], hi[3];
-  for (int d = 0; d < 3; ++d) lo[d] = hi[d] = n > 0 ? H.xyz[d] : 0.0;
+  for (int d = 0; d < 3; ++d) lo[d] = hi[d] = n > 0 ? xyz[d] : 0.0;
   for (int64_t i = 0; i < n; ++i)
     for (int d = 0; d < 3; ++d) {
-      lo[d] = std::min(lo[d], H.xyz[3 * i + d]);
-      hi[d] = std::max(hi[d], H.xyz[3 * i + d]);
+      lo[d] = std::min(lo[d], xyz[3 * i + d]);
+      hi[d] = std::max(hi[d], xyz[3 * i + d]);
     }
   constexpr int kBits = 21;
   const double top = double((1u << kBits) - 1);
@@ -49,7 +49,7 @@ std::vector<int32_t> morton_order(const HostLevel& H) {
     uint64_t code = 0;
     uint32_t q[3];
     for (int d = 0; d < 3; ++d) {
-      const double w = hi[d] > lo[d] ? (H.xyz[3 * i + d] - lo[d]) / (hi[d] - lo[d]) : 0.0;
+      const double w = hi[d] > lo[d] ? (xyz[3 * i + d] - lo[d]) / (hi[d] - lo[d]) : 0.0;
       q[d] = uint32_t(std::min(top, std::max(0.0, std::floor(w * top))));
     }
     for (int b = kBits - 1; b >= 0; --b)
@@ -61,6 +61,25 @@ std::vector<int32_t> morton_order(const HostLevel& H) {
   for (int64_t i = 0; i < n; ++i) ord[size_t(i)] = key[size_t(i)].second;
   return ord;
 }
+
+// The same order over 16-row chunks (the fused Gram kernel's unit), each
+// placed at the centroid of its vertices.
+std::vector<int32_t> chunk_morton_order(const HostLevel& H) {
+  constexpr int64_t kChunk = 16;
+  const int64_t nch = (H.n + kChunk - 1) / kChunk;
+  std::vector<double> cxyz(static_cast<size_t>(3 * nch), 0.0);
+  for (int64_t c = 0; c < nch; ++c) {
+    const int64_t r0 = c * kChunk, r1 = std::min(H.n, r0 + kChunk);
+    for (int64_t r = r0; r < r1; ++r)
+      for (int d = 0; d < 3; ++d) cxyz[size_t(3 * c + d)] += H.xyz[size_t(3 * r + d)];
+    for (int d = 0; d < 3; ++d) cxyz[size_t(3 * c + d)] /= double(r1 - r0);
+  }
+  return morton_order(cxyz);
+}
+
+// The Gram kernel's chunk order changes which rows a block's partial sums
+// cover (and so their rounding): it is used on levels this large only.
+constexpr int64_t kChunkOrderMinRows = 131072;
 
 // Levels with at least this many rows get a row order (smaller levels stay in
 // the caches in any order); BMG_ROW_ORDER_MIN_ROWS overrides it.
@@ -102,10 +121,15 @@ int upload_hierarchy(bmg_hierarchy* h, hipStream_t s) {
     BMG_TRY(upload(&D.colour_rows, H.colour_rows.data(), H.colour_rows.size(), s, D.bytes));
     std::vector<int32_t> ord;
     if (H.n >= min_ordered) {
-      ord = morton_order(H);
+      ord = morton_order(H.xyz);
       BMG_TRY(upload(&D.row_order, ord.data(), ord.size(), s, D.bytes));
     }
-    BMG_HIP(hipStreamSynchronize(s));  // dinv and ord are locals
+    std::vector<int32_t> cord;
+    if (H.n >= kChunkOrderMinRows) {
+      cord = chunk_morton_order(H);
+      BMG_TRY(upload(&D.chunk_order, cord.data(), cord.size(), s, D.bytes));
+    }
+    BMG_HIP(hipStreamSynchronize(s));  // dinv, ord and cord are locals
   }
   // level-0 eigendecomposition on the device (FP64 and FP32, with transposes)
   const int64_t n0 = h->n0;
@@ -125,7 +149,7 @@ int upload_hierarchy(bmg_hierarchy* h, hipStream_t s) {
 
 void free_device(bmg_hierarchy* h) {
   for (auto& D : h->dev) {
-    void* ptrs[] = {D.cols, D.a64, D.m64, D.a32, D.m32, D.dinv, D.parents, D.rtab, D.colour_rows, D.row_order};
+    void* ptrs[] = {D.cols, D.a64, D.m64, D.a32, D.m32, D.dinv, D.parents, D.rtab, D.colour_rows, D.row_order, D.chunk_order};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     D = DevLevel();

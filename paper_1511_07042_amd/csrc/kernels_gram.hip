@@ -92,6 +92,7 @@ __global__ void __launch_bounds__(256) k_gram(int64_t n, int64_t rows_per_block,
 }
 
 constexpr int kGramAmChunk = 16;  // rows whose products share one LDS pass
+static_assert(kGramAmChunk == 16, "the levels' chunk order (DevLevel::chunk_order) is built over 16-row chunks");
 
 // One (row, column pair) item of the products: rows r of A U and M U at
 // columns 2 ch, 2 ch + 1 (FP64), the ELL row gathered against U.  With a
@@ -155,7 +156,8 @@ __global__ void __launch_bounds__(256) k_gram_am(int64_t n, int64_t rows_per_blo
                                                  const double* __restrict__ mm, int W,
                                                  const double* __restrict__ z1, int w1,
                                                  const double* __restrict__ u, int m,
-                                                 double* __restrict__ part) {
+                                                 double* __restrict__ part,
+                                                 const int* __restrict__ corder) {
   constexpr int CH = kGramAmChunk;
   extern __shared__ double ys[];  // [CH][nyp]: rows of [A U | M U] (zero padded)
   const int lane = threadIdx.x & 63;
@@ -171,13 +173,19 @@ __global__ void __launch_bounds__(256) k_gram_am(int64_t n, int64_t rows_per_blo
   for (int e = threadIdx.x; e < CH * nyp; e += blockDim.x) ys[e] = 0.0;
   const int64_t rb = int64_t(blockIdx.x) * rows_per_block;
   const int64_t re = rb + rows_per_block < n ? rb + rows_per_block : n;
-  for (int64_t r0 = rb; r0 < re; r0 += CH) {
+  for (int64_t c0 = rb; c0 < re; c0 += CH) {
+    // logical chunk c0 / CH is the matrix rows [r0, r1): in index order the
+    // same rows, else the chunk the level's chunk order puts there (16
+    // consecutive rows, so the rows of Z are still read as one piece, while
+    // the gathers of consecutive chunks stay close on the surface)
+    const int64_t r0 = corder != nullptr ? int64_t(corder[c0 / CH]) * CH : c0;
+    const int64_t r1 = r0 + CH < n ? r0 + CH : n;
     // A fragments of the chunk's first 16 rows (global), issued before the products
     double af[4][TI];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int64_t r = r0 + 4 * q + lk;
-      const bool ok = r < re;
+      const bool ok = r < r1;
 #pragma unroll
       for (int i = 0; i < TI; ++i) af[q][i] = ok ? zcol(z1, w1, u, m, r, 16 * i + li) : 0.0;
     }
@@ -192,7 +200,7 @@ __global__ void __launch_bounds__(256) k_gram_am(int64_t n, int64_t rows_per_blo
         const int e = e0 + k * 256;
         const int rl = e / cpr, ch = e - (e / cpr) * cpr;
         const int64_t r = r0 + rl;
-        const bool valid = e < items && r < re;
+        const bool valid = e < items && r < r1;
         y[k] = am_item<WT>(valid ? r : r0, valid, W, cols, a, mm, u, m, ch);
       }
 #pragma unroll
@@ -214,7 +222,7 @@ __global__ void __launch_bounds__(256) k_gram_am(int64_t n, int64_t rows_per_blo
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int64_t r = r0 + 16 * h + 4 * q + lk;
-          const bool ok = r < re;
+          const bool ok = r < r1;
 #pragma unroll
           for (int i = 0; i < TI; ++i) af[q][i] = ok ? zcol(z1, w1, u, m, r, 16 * i + li) : 0.0;
         }
@@ -473,10 +481,10 @@ int launch_gram_am(const GramPlan& p, const DevLevel& L, const double* w, int w1
   do {                                                                                             \
     if (L.W == 7)                                                                                  \
       BMG_LAUNCH((k_gram_am<a_, b_, 7>), p.nblk, 256, shm, s, n, rpb, p.nzp, p.nyp, L.cols, L.a64, \
-                 L.m64, L.W, w, w1, u, m, part);                                                    \
+                 L.m64, L.W, w, w1, u, m, part, L.chunk_order);                                     \
     else                                                                                           \
       BMG_LAUNCH((k_gram_am<a_, b_, 0>), p.nblk, 256, shm, s, n, rpb, p.nzp, p.nyp, L.cols, L.a64, \
-                 L.m64, L.W, w, w1, u, m, part);                                                    \
+                 L.m64, L.W, w, w1, u, m, part, L.chunk_order);                                     \
   } while (0)
     switch (TI * 4 + TJW) {
       case 1 * 4 + 1: GA(1, 1); break;
