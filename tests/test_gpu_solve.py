@@ -45,6 +45,23 @@ def test_c1_parity(lib, c1, precision, smoother):
     assert abs(st["cycles"] - info["cycles"]) <= max(3, info["cycles"] // 5)
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_cold_ritz_start_parity(lib, c1, precision, monkeypatch):
+    # BMG_NO_WARM: every Ritz step's Jacobi starts from the identity instead of
+    # the previous step's basis of the coarse block.  That basis is only a
+    # change of basis of the same space, so both paths meet the oracle's pairs
+    # and agree with each other up to rounding.
+    h, lv, ref_ev, ref_U = c1
+    monkeypatch.setenv("BMG_NO_WARM", "1")
+    ev0, U0, s0 = h.solve(9, 0.0, 1e-8, m=12, smoother="jacobi", precision=precision)
+    monkeypatch.delenv("BMG_NO_WARM")
+    ev1, U1, s1 = h.solve(9, 0.0, 1e-8, m=12, smoother="jacobi", precision=precision)
+    assert s0["converged"] == 1 and s1["converged"] == 1
+    _check_pairs(ev0, U0, lv, ref_ev, ref_U, 9)
+    assert abs(s0["cycles"] - s1["cycles"]) <= 1
+    assert np.max(np.abs(ev0 - ev1) / np.maximum(np.abs(ev1), 1.0)) < 1e-9
+
+
 def test_seeded_block_equals_initial_block(lib, c1):
     h, lv, ref_ev, ref_U = c1
     from oracle import rng
