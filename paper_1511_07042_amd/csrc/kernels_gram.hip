@@ -308,9 +308,9 @@ __global__ void __launch_bounds__(1024) k_gram_reduce(const double* __restrict__
 // the next tile's fragments are loaded meanwhile.  A tile is read completely
 // before any of its outputs is written and no other wavefront touches its rows,
 // so U may alias z2 (the update is done in place).
-constexpr int kUpdKMax = 24;  // k steps of 4: nz <= 96
+constexpr int kUpdKMax = 24;  // k steps of 4: nz <= 96 (KM: 12 when nz <= 48, else 24)
 
-template <int TJ>
+template <int TJ, int KM>
 __global__ void __launch_bounds__(256) k_update_zy(int64_t n, const double* z1, int w1,
                                                    const double* z2, int w2,
                                                    const double* __restrict__ Y, int m, int ks,
@@ -333,7 +333,7 @@ __global__ void __launch_bounds__(256) k_update_zy(int64_t n, const double* z1, 
     const double* p2 = z2 + (live ? r : 0) * w2 - w1;
     if ((w1 & 1) == 0) {
 #pragma unroll
-      for (int s2 = 0; s2 < kUpdKMax / 2; ++s2) {
+      for (int s2 = 0; s2 < KM / 2; ++s2) {
         const int c = 8 * s2 + 2 * lk;
         double2 v{0.0, 0.0};
         if (live && c < nz)
@@ -343,14 +343,14 @@ __global__ void __launch_bounds__(256) k_update_zy(int64_t n, const double* z1, 
       }
     } else {
 #pragma unroll
-      for (int s = 0; s < kUpdKMax; ++s) {
+      for (int s = 0; s < KM; ++s) {
         const int c = 8 * (s >> 1) + 2 * lk + (s & 1);
         a[s] = (live && c < w1) ? p1[c] : ((live && c >= w1 && c < nz) ? p2[c] : 0.0);
       }
     }
   };
   int64_t tile = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  double a[kUpdKMax], an[kUpdKMax];
+  double a[KM], an[KM];
   load_a(tile, a);  // in flight while Y is staged
 #pragma unroll 8
   for (int e = threadIdx.x; e < ks * 4 * MP; e += blockDim.x) {
@@ -366,7 +366,7 @@ __global__ void __launch_bounds__(256) k_update_zy(int64_t n, const double* z1, 
 #pragma unroll
     for (int t = 0; t < TJ; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int s = 0; s < kUpdKMax; ++s) {
+    for (int s = 0; s < KM; ++s) {
       if (s < ks) {
         const double* yrow = ys + (8 * (s >> 1) + 2 * lk + (s & 1)) * MP + li;
 #pragma unroll
@@ -385,7 +385,7 @@ __global__ void __launch_bounds__(256) k_update_zy(int64_t n, const double* z1, 
       }
     }
 #pragma unroll
-    for (int s = 0; s < kUpdKMax; ++s) a[s] = an[s];
+    for (int s = 0; s < KM; ++s) a[s] = an[s];
   }
 }
 
@@ -531,13 +531,20 @@ int launch_update_zy(int64_t n, const double* z1, int w1, const double* z2, int 
   const int grid = int(std::min<int64_t>((tiles + 3) / 4, 1024));
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_update_zy<5>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)k_update_zy<5, 24>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               96 * 1024);
-    (void)hipFuncSetAttribute((const void*)k_update_zy<6>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)k_update_zy<6, 24>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               96 * 1024);
     attr_set = true;
   }
-#define UL(tj) BMG_LAUNCH((k_update_zy<tj>), grid, 256, shm, s, n, z1, w1, z2, w2, Y, m, ks, U)
+  // fragment registers for 12 k steps when they suffice (nz <= 48), else 24
+#define UL(tj)                                                                                    \
+  do {                                                                                            \
+    if (ks <= 12)                                                                                 \
+      BMG_LAUNCH((k_update_zy<tj, 12>), grid, 256, shm, s, n, z1, w1, z2, w2, Y, m, ks, U);       \
+    else                                                                                          \
+      BMG_LAUNCH((k_update_zy<tj, 24>), grid, 256, shm, s, n, z1, w1, z2, w2, Y, m, ks, U);       \
+  } while (0)
   switch (TJ) {
     case 1: UL(1); break;
     case 2: UL(2); break;
