@@ -153,7 +153,7 @@ typedef struct {
   int32_t n_c;        /* level-0 eigenvectors in the enrichment; 0 -> min(N_0, 32) */
   int32_t l_c;        /* coarsest level of the correction cycle; -1 -> the coarsest
                          l with N_l >= 8 |Gamma_h| sigma / (4 pi) */
-  double omega;       /* Jacobi weight (2/3) */
+  double omega;       /* Jacobi weight (default 0.85) */
   double angle_tol;   /* Davis-Kahan stopping bound on rho_i / delta_i (1e-7) */
   uint64_t seed;      /* test vectors: element (i,j) ~ N(0,1) from SplitMix64
                          counters 2c, 2c+1 with c = i m + j, Box-Muller */

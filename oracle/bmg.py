@@ -21,7 +21,7 @@ What is computed (paper Sec. 4, Alg. 2 and Alg. 3, with Remark 3.2):
     V(nu1, nu2) cycle for the rediscretised operators A_l - sigma M_l on
     levels L down to l_c, with P^T as restriction and P as prolongation
     (Sec. 3), smoothing by multicolour symmetric Gauss-Seidel (Sec. 5.3,
-    method 4; Remark 4.2) or weighted Jacobi.
+    method 4; Remark 4.2) or weighted Jacobi (weight 0.85 unless given).
  4. M-orthonormalisation of Z = [W_c, U'] (Alg. 2 step 3, "orthogonalize with
     respect to b_h") by SVQB, then the Ritz eigenproblem of the enriched
     pencil (eq. pb-c-aux-mat) shifted by sigma; the m Ritz pairs nearest sigma
@@ -38,7 +38,11 @@ its own words): n_c = min(N_0, 32); l_c is the coarsest level with
 N_l >= 8 n_W(sigma), n_W(sigma) = |Gamma_h| sigma / (4 pi) (Weyl count); at
 l_c = 0 the coarse operator is inverted on its spectrum with the modes within
 1e-2 max(1, |sigma|) of sigma dropped, otherwise 8 smoothing sweeps are used;
-Ritz values whose relative gap is below 1e-2 form one cluster.
+Ritz values whose relative gap is below 1e-2 form one cluster; the
+weighted-Jacobi weight is 0.85 (local Fourier analysis of the P1 stiffness
+stencil on a regular triangle lattice: D^-1 A maps the frequencies that the
+coarse grid cannot represent into [2/3, 3/2], whose best damping weight is
+2 / (2/3 + 3/2) = 12/13; 0.85 keeps a margin for irregular meshes).
 """
 import math
 
@@ -114,7 +118,7 @@ class Smoother:
 class BMG:
     """The BMG cycle on a fixed hierarchy and shift (see module docstring)."""
 
-    def __init__(self, levels, sigma, m, nu1=2, nu2=2, smoother="gs", omega=2.0 / 3.0,
+    def __init__(self, levels, sigma, m, nu1=2, nu2=2, smoother="gs", omega=0.85,
                  n_c=None, l_c=None):
         self.levels = levels
         self.sigma = float(sigma)
@@ -227,7 +231,7 @@ def default_m(k, sigma):
 
 
 def solve(levels, k, sigma=0.0, tol=1e-8, m=None, nu1=2, nu2=2, smoother="gs",
-          omega=2.0 / 3.0, max_cycles=200, seed=0, angle_tol=1e-7, U0=None,
+          omega=0.85, max_cycles=200, seed=0, angle_tol=1e-7, U0=None,
           n_c=None, l_c=None, history=False):
     """The k eigenpairs of (A_L, M_L) nearest sigma by BMG.
 

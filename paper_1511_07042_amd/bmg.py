@@ -217,7 +217,7 @@ class Hierarchy:
         return arr
 
     def solve(self, k, sigma=0.0, tol=1e-8, m=0, nu1=2, nu2=2, smoother="gs", precision="fp64",
-              max_cycles=200, n_c=0, l_c=-1, omega=2.0 / 3.0, angle_tol=1e-7, seed=0,
+              max_cycles=200, n_c=0, l_c=-1, omega=0.85, angle_tol=1e-7, seed=0,
               initial_block=None, evecs="host", stream=None, allow_noconv=False, timed_kernel=None):
         """Returns (evals [k], evecs [N, k] or None, stats dict).
 
@@ -260,7 +260,7 @@ class Hierarchy:
         return evals, V, stats
 
     def apply(self, op, x=None, f=None, y=None, level=None, m=None, m2=0, dtype=None, sigma=0.0,
-              smoother="gs", nu1=2, nu2=2, l_c=-1, omega=2.0 / 3.0, seed=0, stream=None):
+              smoother="gs", nu1=2, nu2=2, l_c=-1, omega=0.85, seed=0, stream=None):
         """Enqueue one operator on torch.cuda tensors (see bmg_op in include/bmg.h)."""
         import torch
         a = ApplyArgs()
@@ -300,7 +300,7 @@ def finest_vertices(kind="sphere", n_refine=0, nu=64, nv=32, n_vert=0, n_tri=0):
 
 
 def _opts(m=0, nu1=2, nu2=2, smoother="jacobi", precision="mixed", max_cycles=200, n_c=0, l_c=-1,
-          omega=2.0 / 3.0, angle_tol=1e-7, seed=0):
+          omega=0.85, angle_tol=1e-7, seed=0):
     o = SolveOpts()
     _lib.bmg_solve_opts_default(C.byref(o))
     o.m, o.nu1, o.nu2 = int(m), int(nu1), int(nu2)

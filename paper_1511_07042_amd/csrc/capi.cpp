@@ -80,7 +80,7 @@ void bmg_solve_opts_default(bmg_solve_opts* o) {
   o->max_cycles = 200;
   o->n_c = 0;
   o->l_c = -1;
-  o->omega = 2.0 / 3.0;
+  o->omega = 0.85;
   o->angle_tol = 1e-7;
   o->seed = 0;
   o->initial_block = nullptr;

@@ -81,7 +81,8 @@ def test_smoothing_sweep(env, smoother, forward, level):
         h.apply(op, f=fd, y=y, level=level, sigma=2.0, smoother="gs")
     else:
         y = torch.zeros((L.n, 8), dtype=torch.float64, device="cuda")
-        h.apply(op, x=_dev(torch, e), f=fd, y=y, level=level, sigma=2.0, smoother="jacobi")
+        h.apply(op, x=_dev(torch, e), f=fd, y=y, level=level, sigma=2.0, smoother="jacobi",
+                omega=2.0 / 3.0)
     torch.cuda.synchronize()
     assert np.max(np.abs(_host(y) - ref)) < 1e-11 * max(1.0, np.max(np.abs(ref)))
 
@@ -125,7 +126,8 @@ def test_vcycle(env, smoother, sigma):
     for dt_name, tol in (("f64", 1e-10), ("f32", 2e-4)):
         dt = torch.float64 if dt_name == "f64" else torch.float32
         y = torch.zeros((lv[-1].n, m), dtype=dt, device="cuda")
-        h.apply("vcycle", x=_dev(torch, f, dt), y=y, sigma=sigma, smoother=smoother, l_c=bm.l_c)
+        h.apply("vcycle", x=_dev(torch, f, dt), y=y, sigma=sigma, smoother=smoother, l_c=bm.l_c,
+                omega=2.0 / 3.0)
         torch.cuda.synchronize()
         err = np.max(np.abs(_host(y) - ref)) / np.max(np.abs(ref))
         assert err < tol, (dt_name, err)
@@ -258,7 +260,8 @@ def test_runtime_width_kernels(env):
     torch.cuda.synchronize()
     assert _rel(_host(y), f - S @ x, scale) < 1e-14
     d = S.diagonal()
-    h.apply("smooth_fwd", x=_dev(torch, x), f=_dev(torch, f), y=y, sigma=sigma, smoother="jacobi")
+    h.apply("smooth_fwd", x=_dev(torch, x), f=_dev(torch, f), y=y, sigma=sigma, smoother="jacobi",
+            omega=2.0 / 3.0)
     torch.cuda.synchronize()
     ref = x + (2.0 / 3.0) * (f - S @ x) / d[:, None]
     assert _rel(_host(y), ref, np.abs(x) + scale / np.abs(d)[:, None]) < 1e-13
