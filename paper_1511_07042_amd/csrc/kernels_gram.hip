@@ -307,8 +307,10 @@ __global__ void __launch_bounds__(1024) k_gram_reduce(const double* __restrict__
 // from LDS in the same row order, and then writes the tile's 16 x m outputs;
 // the next tile's fragments are loaded meanwhile.  A tile is read completely
 // before any of its outputs is written and no other wavefront touches its rows,
-// so U may alias z2 (the update is done in place).
-constexpr int kUpdKMax = 24;  // k steps of 4: nz <= 96 (KM: 12 when nz <= 48, else 24)
+// so U may alias z2 (the update is done in place).  The fragment registers
+// hold KM k steps, a template parameter: 12 when nz <= 48, else 24, so a
+// narrow block keeps fewer registers and more wavefronts per SIMD.
+constexpr int kUpdKMax = 24;  // k steps of 4: nz <= 96
 
 template <int TJ, int KM>
 __global__ void __launch_bounds__(256) k_update_zy(int64_t n, const double* z1, int w1,
