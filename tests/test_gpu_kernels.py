@@ -201,7 +201,10 @@ def test_eigen_residual(env, dt_name):
 
 
 @pytest.mark.parametrize("level", [0, 2, 4])
-@pytest.mark.parametrize("m2,m", [(12, 12), (12, 32), (0, 8), (12, 80), (16, 80), (32, 40), (4, 92)])
+# nz = m2 + m = 48 and 49 sit on either side of the kernel's 12 / 24 k-step
+# register variants (49 also has an odd W width)
+@pytest.mark.parametrize("m2,m", [(12, 12), (12, 32), (0, 8), (12, 80), (16, 80), (32, 40), (4, 92),
+                                  (16, 32), (17, 32)])
 def test_update_in_place(env, level, m2, m):
     # U <- [W | U] Y in place: the Ritz update of the iterate block
     torch, p, h, lv = env
