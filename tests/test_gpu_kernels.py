@@ -145,7 +145,9 @@ def test_gaussian_block(env):
 
 
 @pytest.mark.parametrize("level", [0, 1, 4])
-@pytest.mark.parametrize("wx,wf", [(1, 1), (20, 40), (44, 64), (92, 160), (96, 192)])
+# 13 x 7 and 45 x 33: output counts that leave a ragged last block of the
+# partial-sum reduction (16 outputs per block)
+@pytest.mark.parametrize("wx,wf", [(1, 1), (20, 40), (44, 64), (92, 160), (96, 192), (13, 7), (45, 33)])
 def test_gram_mfma(env, level, wx, wf):
     torch, p, h, lv = env
     n = lv[level].n
@@ -276,7 +278,7 @@ def test_runtime_width_kernels(env):
 
 
 @pytest.mark.parametrize("level", [1, 4])
-@pytest.mark.parametrize("m2,m", [(0, 8), (12, 32), (12, 80), (32, 40), (4, 92)])
+@pytest.mark.parametrize("m2,m", [(0, 8), (12, 32), (12, 80), (32, 40), (4, 92), (5, 6)])
 def test_gram_fused_products(env, level, m2, m):
     # [W | U]^T [A U | M U] with A U and M U formed inside the Gram kernel
     torch, p, h, lv = env
