@@ -18,7 +18,7 @@ Beside the timed solves the JSON line carries:
   serving       a seeded request stream through the continuous-batching server;
   cpu_baseline  the oracle (plain FP64 CPU implementation) on the same workload.
 
-Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus N > 1 is refused: the library runs on one GPU.
 """
 import argparse
 import hashlib
@@ -339,7 +339,7 @@ def main():
         copy_calibration(a.copy_calibration)
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": a.gpus}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1", "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
