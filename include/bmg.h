@@ -139,9 +139,33 @@ int bmg_hierarchy_export(const bmg_hierarchy* h, int32_t level, int32_t what, vo
 typedef enum { BMG_SMOOTH_GS = 0, BMG_SMOOTH_JACOBI = 1 } bmg_smoother;
 typedef enum { BMG_FP64 = 0, BMG_MIXED = 1 } bmg_precision;
 
+/* Iteration schemes.
+ * BMG_SCHEME_ENRICHED: fixed shift; the n_c level-0 eigenvectors nearest sigma,
+ *   prolongated to level L, stay in every Rayleigh-Ritz step beside the block
+ *   (the enriched coarse space V_H + X_h of Alg. 2 step 4); the correction's
+ *   coarsest level follows the Weyl rule of l_c below.  Meant for the lower end
+ *   of the spectrum.
+ * BMG_SCHEME_SHIFTED: interior shifts (Sec. 5.2, Remark 4.1, Alg. 3 step 4,
+ *   Alg. 4 step 1).  All eigenpairs of one coarse level l_c are computed once
+ *   per hierarchy (dense, kept with it); l_c is the coarsest level with
+ *   N_l >= pi n_W^2 / m, n_W = |Gamma_h| sigma / (4 pi), capped at 12288
+ *   vertices (m is then raised when it was not given, at most 96).  The block
+ *   starts from the m level-l_c eigenvectors nearest the level's shift,
+ *   prolongated and relaxed once on the source problem of eq. pb-f-aux-mat;
+ *   each level l_c <= l < L of the correction uses A_l - sigma_l M_l with the
+ *   adaptive shift sigma_l = sigma + mean over the block of (the Rayleigh
+ *   quotient of its values at the level-l vertices on level l - its Ritz
+ *   value), recomputed before every correction (and once between two starts);
+ *   the coarse solve at l_c is the truncated spectral inverse (modes within
+ *   1e-2 max(1, |sigma|) of sigma_lc dropped); the Ritz step uses the span of
+ *   the block alone.  seed and n_c are not used.
+ * BMG_SCHEME_AUTO: SHIFTED when sigma > 0, else ENRICHED. */
+typedef enum { BMG_SCHEME_AUTO = 0, BMG_SCHEME_ENRICHED = 1, BMG_SCHEME_SHIFTED = 2 } bmg_scheme;
+
 typedef struct {
   int32_t m;          /* test vectors; 0 -> 4 ceil(1.25 k / 4) (sigma = 0) or
-                         4 ceil(1.5 k / 4) (sigma != 0); must be a multiple of 4 */
+                         4 ceil(1.5 k / 4) (sigma != 0), raised by the
+                         shifted scheme's coarse-level cap; a multiple of 4 */
   int32_t nu1, nu2;   /* pre- and post-smoothing sweeps per level (2, 2) */
   int32_t smoother;   /* bmg_smoother: multicolour symmetric Gauss-Seidel (colours
                          ascending before, descending after the coarse correction)
@@ -150,9 +174,11 @@ typedef struct {
                          (values and accumulation); residuals, Gram matrices, the
                          Ritz problem and the iterate stay FP64 */
   int32_t max_cycles; /* 200 */
-  int32_t n_c;        /* level-0 eigenvectors in the enrichment; 0 -> min(N_0, 32) */
-  int32_t l_c;        /* coarsest level of the correction cycle; -1 -> the coarsest
-                         l with N_l >= 8 |Gamma_h| sigma / (4 pi) */
+  int32_t n_c;        /* level-0 eigenvectors in the enrichment; 0 -> min(N_0, 32)
+                         rounded down to even (ENRICHED scheme only) */
+  int32_t l_c;        /* coarsest level of the correction cycle; -1 -> ENRICHED:
+                         the coarsest l with N_l >= 8 |Gamma_h| sigma / (4 pi);
+                         SHIFTED: the rule of bmg_scheme */
   double omega;       /* Jacobi weight (default 0.85) */
   double angle_tol;   /* Davis-Kahan stopping bound on rho_i / delta_i (1e-7) */
   uint64_t seed;      /* test vectors: element (i,j) ~ N(0,1) from SplitMix64
@@ -160,7 +186,7 @@ typedef struct {
   const double* initial_block; /* optional host [N_L][m] block replacing the seeded one */
   int32_t timed_kernel; /* bmg_kernel_class to bracket with HIP events on `stream`,
                            or -1; see bmg_solve_stats */
-  int32_t reserved;
+  int32_t scheme;       /* bmg_scheme (BMG_SCHEME_AUTO) */
 } bmg_solve_opts;
 
 /* Kernel classes that bmg_solve can time.  EIGRES, SPMM_AM, GRAM, UPDATE and
@@ -223,6 +249,11 @@ typedef struct {
   int64_t timed_kernel_units; /* launches */
   int32_t ritz_sweeps_max;    /* most Jacobi sweeps of one Ritz step */
   int32_t ritz_fallbacks;     /* Ritz steps that needed SVQB instead of Cholesky */
+  int32_t scheme;             /* bmg_scheme used (ENRICHED or SHIFTED) */
+  int32_t reserved2;
+  double coarse_eig_ms;       /* SHIFTED: wall time of the level-l_c eigensolve when it
+                                 was built (never part of t_solve_ms) */
+  double lc_shift;            /* SHIFTED: final adaptive shift of level l_c; else sigma */
 } bmg_solve_stats;
 
 /* The k eigenpairs of (A_L, M_L) nearest sigma on the finest level L.
@@ -238,8 +269,13 @@ typedef struct {
  * stop when rho_i^2 / delta_i <= 0.1 tol max(|theta_i|, 1) and
  * rho_i / delta_i <= angle_tol for every returned pair.
  * Errors: BMG_EINVAL if k < 1, m < k, m % 4 != 0, m > N_L / 2, n_c + m > 96,
- * tol <= 0 or NaN, sigma not finite; BMG_ENOCONV when max_cycles is reached
- * (evals, evecs and stats still hold the current pairs); BMG_ENOMEM.
+ * tol <= 0 or NaN, sigma not finite, an unknown scheme, or (SHIFTED) a level
+ * l_c above 12288 vertices; BMG_ENOCONV when max_cycles is reached (evals,
+ * evecs and stats still hold the current pairs) or when the Ritz step finds
+ * fewer than m independent directions (evals and evecs are then not written);
+ * BMG_ENOMEM.
+ * The first SHIFTED solve on a hierarchy also computes the level-l_c
+ * eigendecomposition, before t_solve_ms starts (its time is coarse_eig_ms).
  * The call blocks until the result is on the host (evals) / in evecs.
  * Concurrent calls on one hierarchy are allowed on different streams. */
 int bmg_solve(bmg_hierarchy* h, int32_t k, double sigma, double tol, const bmg_solve_opts* opts,

@@ -43,6 +43,43 @@ weighted-Jacobi weight is 0.85 (local Fourier analysis of the P1 stiffness
 stencil on a regular triangle lattice: D^-1 A maps the frequencies that the
 coarse grid cannot represent into [2/3, 3/2], whose best damping weight is
 2 / (2/3 + 3/2) = 12/13; 0.85 keeps a margin for irregular meshes).
+
+Interior shifts (sigma > 0; scheme "shifted").  The fixed-shift cycle above
+stalls when sigma lies inside the spectrum: coarse levels misplace the
+eigenvalues near sigma by O(sigma^2 h_l^2) (the a priori estimate of Sec. 2.3),
+so the coarse correction acts like shift-and-invert about a wrong shift, and
+prolongated coarse eigenvectors kept in the Ritz space add Ritz values with
+large residuals right next to sigma.  The shifted scheme follows the paper's
+own route to interior eigenvalues instead (Sec. 5.2; Remark 4.1; Alg. 3
+step 4; Alg. 4 step 1):
+
+ 1. Coarse eigensolve (Alg. 2 step 1, Alg. 4 step 1) of every pair of the
+    level l_c, the coarsest level with N_l >= pi n_W(sigma)^2 / m (the coarse
+    level must place the eigenvalues near sigma, O(sigma^2 |Gamma| / N_l) off,
+    within the window of half-width ~ 2 pi m / |Gamma| that m vectors cover),
+    but at most the finest level with N_l <= 12288 vertices; when that cap
+    binds below level L and m was not given, m is raised to the multiple of 4
+    that meets the rule (at most 96).  When l_c = L the coarse eigensolve is
+    the fine one and the start already returns the exact pairs.
+ 2. Start (Alg. 2 steps 2-4): the m level-l_c eigenvectors nearest the level's
+    shift, prolongated to level L, relaxed once on the source problem of
+    eq. (pb-f-aux-mat) with their coarse eigenvalues as Theta, then a
+    Rayleigh-Ritz step in their span (no fixed coarse vectors).
+ 3. Adaptive shifts (Remark 4.1, Sec. 5.2: the coarse shift moves by the mean
+    of Rayleigh quotients, compensating the drift of the discrete spectra
+    between levels): on each level l_c <= l < L the correction operator is
+    A_l - sigma_l M_l with sigma_l = sigma + Delta_l, Delta_l the mean over the
+    block of (Rayleigh quotient on level l of the vector's values at the
+    level-l vertices) - (its Ritz value).  Vertices of level l are the first
+    N_l vertices of every finer level, so this is nodal injection.  The
+    offsets are estimated after the first start, which is then repeated once
+    with the coarse pairs nearest sigma + Delta_{l_c} (coarse eigenvalues
+    shifted back by Delta_{l_c} as Theta); afterwards they are recomputed from
+    the current block before every correction.
+ 4. Cycles: the V(nu1, nu2) correction of step 3 above with the per-level
+    shifts, the truncated spectral inverse of A_{l_c} - sigma_{l_c} M_{l_c}
+    as the coarse solve, and the Rayleigh-Ritz step in the span of the block
+    alone; stopping rule and output as in step 5 above.
 """
 import math
 
@@ -232,11 +269,19 @@ def default_m(k, sigma):
 
 def solve(levels, k, sigma=0.0, tol=1e-8, m=None, nu1=2, nu2=2, smoother="gs",
           omega=0.85, max_cycles=200, seed=0, angle_tol=1e-7, U0=None,
-          n_c=None, l_c=None, history=False):
+          n_c=None, l_c=None, history=False, scheme="auto"):
     """The k eigenpairs of (A_L, M_L) nearest sigma by BMG.
 
+    scheme: "enriched" (fixed shift, coarse vectors in every Ritz step),
+    "shifted" (the interior-shift scheme of the module docstring) or "auto"
+    (shifted when sigma > 0).
     Returns (evals ascending, M-orthonormal evecs N_L x k, info dict).
     """
+    if scheme == "auto":
+        scheme = "shifted" if sigma > 0 else "enriched"
+    if scheme == "shifted":
+        return solve_shifted(levels, k, sigma, tol, m, nu1, nu2, smoother, omega, max_cycles,
+                             angle_tol, l_c, history)
     m = default_m(k, sigma) if m is None else m
     bmg = BMG(levels, sigma, m, nu1, nu2, smoother, omega, n_c, l_c)
     lv = levels[-1]
@@ -268,4 +313,162 @@ def solve(levels, k, sigma=0.0, tol=1e-8, m=None, nu1=2, nu2=2, smoother="gs",
     evecs = normalise_signs(U[:, order])
     info = dict(cycles=cycles, converged=converged, rho=rho, delta=delta, m=m,
                 l_c=bmg.l_c, n_c=bmg.n_c, history=hist)
+    return evals, evecs, info
+
+
+# ---------------------------------------------------------------- interior --
+
+MAX_COARSE_EIG_VERTICES = 12288
+
+
+def shifted_coarse_level(levels, sigma, m, m_given=True):
+    """(l_c, m) for the shifted scheme: coarsest l with N_l >= pi n_W^2 / m,
+    capped at the finest level with N_l <= 12288; when the cap binds below the
+    finest level and m was not given, m is raised to meet the rule (multiple
+    of 4, at most 96).  At l_c = L the coarse solve is exact."""
+    n_w = levels[-1].area * max(sigma, 0.0) / (4.0 * math.pi)
+    need = math.pi * n_w * n_w / m
+    cap = 0
+    for l, lv in enumerate(levels):
+        if lv.n <= MAX_COARSE_EIG_VERTICES:
+            cap = l
+    for l, lv in enumerate(levels):
+        if lv.n >= need:
+            if l <= cap:
+                return l, m
+            break
+    if not m_given and cap < len(levels) - 1:
+        m = min(96, max(m, 4 * int(math.ceil(math.pi * n_w * n_w / levels[cap].n / 4.0))))
+    return cap, m
+
+
+def injected_rayleigh_offsets(levels, U, theta, l_c):
+    """Delta_l = mean_i (RQ_l(U_i restricted to the level-l vertices) - theta_i)."""
+    L = len(levels) - 1
+    off = np.zeros(L + 1)
+    for l in range(l_c, L):
+        lv = levels[l]
+        X = U[:lv.n]
+        rq = np.einsum("ij,ij->j", X, lv.A @ X) / np.einsum("ij,ij->j", X, lv.M @ X)
+        off[l] = float(np.mean(rq - theta))
+    return off
+
+
+class ShiftedBMG:
+    """The interior-shift cycle (module docstring, steps 1-4)."""
+
+    def __init__(self, levels, sigma, m, l_c, nu1=2, nu2=2, smoother="gs", omega=0.85):
+        self.levels = levels
+        self.sigma = float(sigma)
+        self.m = m
+        self.l_c = l_c
+        self.nu1, self.nu2 = nu1, nu2
+        self.kind = smoother
+        self.omega = omega
+        self.L = len(levels) - 1
+        lc = levels[l_c]
+        # coarse eigensolve of level l_c (Alg. 2 step 1, Alg. 4 step 1)
+        self.lam, self.phi = sla.eigh(lc.A.toarray(), lc.M.toarray())
+        self.set_offsets(np.zeros(self.L + 1))
+
+    def set_offsets(self, off):
+        """Per-level shifts sigma_l = sigma + off[l] (Remark 4.1)."""
+        self.off = np.array(off, dtype=np.float64)
+        self.smoothers = {}
+        for l in range(self.l_c + 1, self.L + 1):
+            self.smoothers[l] = Smoother(self.levels[l], self.sigma + self.off[l], self.kind,
+                                         self.omega)
+        x = self.lam - (self.sigma + self.off[self.l_c])
+        keep = np.abs(x) >= 1e-2 * max(1.0, abs(self.sigma))
+        self.g = np.where(keep, 1.0 / np.where(keep, x, 1.0), 0.0)
+
+    def vcycle(self, l, f):
+        if l == self.l_c:
+            return self.phi @ (self.g[:, None] * (self.phi.T @ f))
+        sm = self.smoothers[l]
+        e = np.zeros_like(f)
+        for _ in range(self.nu1):
+            e = sm.sweep(e, f, forward=True)
+        r = f - sm.S @ e
+        P = self.levels[l].P
+        e = e + P @ self.vcycle(l - 1, P.T @ r)
+        for _ in range(self.nu2):
+            e = sm.sweep(e, f, forward=False)
+        return e
+
+    def rayleigh_ritz(self, U):
+        """Exact Rayleigh-Ritz in span(U); the m pairs nearest sigma."""
+        lv = self.levels[self.L]
+        GA = U.T @ (lv.A @ U)
+        GM = U.T @ (lv.M @ U)
+        GA = 0.5 * (GA + GA.T)
+        GM = 0.5 * (GM + GM.T)
+        s = 1.0 / np.sqrt(np.diag(GM))
+        d, V = np.linalg.eigh(GM * s[:, None] * s[None, :])
+        keep = d > 1e-12 * d.max()
+        T = (s[:, None] * V[:, keep]) / np.sqrt(d[keep])[None, :]
+        C = T.T @ (GA - self.sigma * GM) @ T
+        mu, Q = np.linalg.eigh(0.5 * (C + C.T))
+        if len(mu) < self.m:
+            raise RuntimeError("block lost rank below m")
+        sel = nearest_indices(mu, 0.0, self.m)
+        sel = sel[np.argsort(mu[sel], kind="stable")]
+        return U @ (T @ Q[:, sel]), mu[sel] + self.sigma
+
+    def start(self):
+        """Prolongated coarse pairs nearest the level-l_c shift, one source
+        relaxation (eq. pb-f-aux-mat) and a Ritz step (Alg. 2 steps 2-4)."""
+        lv = self.levels[self.L]
+        sel = np.sort(nearest_indices(self.lam, self.sigma + self.off[self.l_c], self.m))
+        U = self.phi[:, sel]
+        for l in range(self.l_c + 1, self.L + 1):
+            U = self.levels[l].P @ U
+        theta0 = self.lam[sel] - self.off[self.l_c]
+        if self.l_c < self.L:
+            R = lv.A @ U - (lv.M @ U) * theta0[None, :]
+            U = U + self.vcycle(self.L, -R)
+        return self.rayleigh_ritz(U)
+
+
+def solve_shifted(levels, k, sigma, tol=1e-8, m=None, nu1=2, nu2=2, smoother="gs", omega=0.85,
+                  max_cycles=200, angle_tol=1e-7, l_c=None, history=False):
+    """The k eigenpairs nearest an interior shift sigma (module docstring, steps 1-4)."""
+    m_given = m is not None
+    m = default_m(k, sigma) if m is None else m
+    if l_c is None:
+        l_c, m = shifted_coarse_level(levels, sigma, m, m_given)
+    bmg = ShiftedBMG(levels, sigma, m, l_c, nu1, nu2, smoother, omega)
+    lv = levels[-1]
+    U, theta = bmg.start()
+    if l_c < bmg.L:
+        bmg.set_offsets(injected_rayleigh_offsets(levels, U, theta, l_c))
+        U, theta = bmg.start()
+    cert = BMG.certificates
+    hist = []
+    cycles = 0
+    converged = False
+    while True:
+        R = lv.A @ U - (lv.M @ U) * theta[None, :]
+        ret = nearest_indices(theta, sigma, k)
+        rho, delta = cert(bmg, R, theta, ret)
+        th = theta[ret]
+        ok_kt = np.all(rho ** 2 / delta <= 0.1 * tol * np.maximum(np.abs(th), 1.0))
+        ok_dk = np.max(rho / delta) <= angle_tol
+        if history:
+            hist.append((theta.copy(), rho.copy(), delta.copy()))
+        if ok_kt and ok_dk:
+            converged = True
+            break
+        if cycles >= max_cycles:
+            break
+        if l_c < bmg.L:
+            bmg.set_offsets(injected_rayleigh_offsets(levels, U, theta, l_c))
+        U, theta = bmg.rayleigh_ritz(U + bmg.vcycle(bmg.L, -R))
+        cycles += 1
+    ret = np.sort(nearest_indices(theta, sigma, k))
+    order = ret[np.argsort(theta[ret], kind="stable")]
+    evals = theta[order]
+    evecs = normalise_signs(U[:, order])
+    info = dict(cycles=cycles, converged=converged, rho=rho, delta=delta, m=m, l_c=l_c, n_c=0,
+                offsets=bmg.off.copy(), history=hist, scheme="shifted")
     return evals, evecs, info

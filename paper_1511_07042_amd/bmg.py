@@ -21,6 +21,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EBUSY, ECANCELED = 0, -1, -2, -3, -4, -5, 
 KINDS = {"sphere": 0, "ellipsoid": 1, "torus": 2, "custom": 3}
 SMOOTHERS = {"gs": 0, "jacobi": 1}
 PRECISIONS = {"fp64": 0, "mixed": 1}
+SCHEMES = {"auto": 0, "enriched": 1, "shifted": 2}
 EXPORTS = {"xyz": 0, "tri": 1, "parents": 2, "ell_cols": 3, "ell_a": 4, "ell_m": 5, "colours": 6,
            "lumped": 7, "coarse_eig": 8}
 KERNEL_CLASSES = {"eigres": 0, "spmm_am": 1, "smooth": 2, "residual": 3, "restrict": 4,
@@ -51,7 +52,7 @@ class SolveOpts(C.Structure):
                 ("precision", C.c_int32), ("max_cycles", C.c_int32), ("n_c", C.c_int32),
                 ("l_c", C.c_int32), ("omega", C.c_double), ("angle_tol", C.c_double),
                 ("seed", C.c_uint64), ("initial_block", C.POINTER(C.c_double)),
-                ("timed_kernel", C.c_int32), ("reserved", C.c_int32)]
+                ("timed_kernel", C.c_int32), ("scheme", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -61,7 +62,9 @@ class SolveStats(C.Structure):
                 ("max_kato_temple", C.c_double), ("rho", C.POINTER(C.c_double)),
                 ("delta", C.POINTER(C.c_double)), ("timed_kernel_ms", C.c_double),
                 ("timed_kernel_bytes", C.c_double), ("timed_kernel_units", C.c_int64),
-                ("ritz_sweeps_max", C.c_int32), ("ritz_fallbacks", C.c_int32)]
+                ("ritz_sweeps_max", C.c_int32), ("ritz_fallbacks", C.c_int32),
+                ("scheme", C.c_int32), ("reserved2", C.c_int32), ("coarse_eig_ms", C.c_double),
+                ("lc_shift", C.c_double)]
 
 
 class ApplyArgs(C.Structure):
@@ -218,7 +221,8 @@ class Hierarchy:
 
     def solve(self, k, sigma=0.0, tol=1e-8, m=0, nu1=2, nu2=2, smoother="gs", precision="fp64",
               max_cycles=200, n_c=0, l_c=-1, omega=0.85, angle_tol=1e-7, seed=0,
-              initial_block=None, evecs="host", stream=None, allow_noconv=False, timed_kernel=None):
+              initial_block=None, evecs="host", stream=None, allow_noconv=False, timed_kernel=None,
+              scheme="auto"):
         """Returns (evals [k], evecs [N, k] or None, stats dict).
 
         evecs: "host" -> numpy array, "device" -> torch.cuda tensor view, None.
@@ -231,6 +235,7 @@ class Hierarchy:
         o.max_cycles, o.n_c, o.l_c = int(max_cycles), int(n_c), int(l_c)
         o.omega, o.angle_tol, o.seed = float(omega), float(angle_tol), int(seed)
         o.timed_kernel = -1 if timed_kernel is None else KERNEL_CLASSES[timed_kernel]
+        o.scheme = SCHEMES[scheme]
         keep = None
         if initial_block is not None:
             keep = np.ascontiguousarray(initial_block, dtype=np.float64)
@@ -300,7 +305,7 @@ def finest_vertices(kind="sphere", n_refine=0, nu=64, nv=32, n_vert=0, n_tri=0):
 
 
 def _opts(m=0, nu1=2, nu2=2, smoother="jacobi", precision="mixed", max_cycles=200, n_c=0, l_c=-1,
-          omega=0.85, angle_tol=1e-7, seed=0):
+          omega=0.85, angle_tol=1e-7, seed=0, scheme="auto"):
     o = SolveOpts()
     _lib.bmg_solve_opts_default(C.byref(o))
     o.m, o.nu1, o.nu2 = int(m), int(nu1), int(nu2)
@@ -308,6 +313,7 @@ def _opts(m=0, nu1=2, nu2=2, smoother="jacobi", precision="mixed", max_cycles=20
     o.precision = PRECISIONS[precision]
     o.max_cycles, o.n_c, o.l_c = int(max_cycles), int(n_c), int(l_c)
     o.omega, o.angle_tol, o.seed = float(omega), float(angle_tol), int(seed)
+    o.scheme = SCHEMES[scheme]
     return o
 
 

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libbmg.so")
 
 SOURCES = ["mesh.cpp", "assemble.cpp", "dense_host.cpp", "hierarchy.cpp", "solver.cpp",
            "capi.cpp", "server.cpp", "dense_device.cpp", "kernels_sparse.hip", "kernels_gram.hip",
-           "kernels_dense.hip", "kernels_tail.hip"]
+           "kernels_dense.hip", "kernels_tail.hip", "kernels_coarse.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -7,6 +7,7 @@
 
 #include <atomic>
 #include <cstdint>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -92,6 +93,21 @@ struct DevLevel {
   int64_t bytes = 0;
 };
 
+// All generalized eigenpairs of one level (Alg. 2 step 1 taken at a finer
+// coarse level; the interior-shift scheme's coarse solve and start block).
+// Built on first use and kept with the hierarchy: it does not depend on the
+// shift.  Eigenvectors one per row: phi[j][i] = x_j(i), M_l-orthonormal.
+struct LevelEig {
+  int level = -1;
+  int n = 0;
+  std::vector<double> lam;   // host [n] ascending
+  double* d_lam = nullptr;   // [n]
+  double* d_phi64 = nullptr; // [n][n]
+  float* d_phi32 = nullptr;  // [n][n]
+  int64_t bytes = 0;
+  double setup_ms = 0.0;     // wall time of the eigensolve and upload
+};
+
 }  // namespace bmg
 
 struct bmg_hierarchy {
@@ -108,6 +124,9 @@ struct bmg_hierarchy {
   float* d_phi0t_32 = nullptr;
   std::mutex ws_mutex;
   std::vector<struct bmg_workspace*> ws_pool;
+  // per-level eigendecompositions of the interior-shift scheme (by level)
+  std::mutex eig_mutex;
+  std::vector<std::unique_ptr<bmg::LevelEig>> level_eig;
 };
 
 namespace bmg {
@@ -118,6 +137,15 @@ constexpr int kHostEigMax = 1024;
 constexpr int kDeviceEigMax = 4096;
 int device_sygv(int n, const std::vector<double>& A, const std::vector<double>& M,
                 std::vector<double>& lam, std::vector<double>& X, hipStream_t s);
+// The same solve leaving the eigenvectors on the device: *vecs [n][n] with
+// row j the M-orthonormal eigenvector j (the caller frees it with hipFree).
+int device_sygv_keep(int n, const std::vector<double>& A, const std::vector<double>& M,
+                     std::vector<double>& lam, double** vecs, hipStream_t s);
+// Largest level the interior-shift scheme eigendecomposes densely.
+constexpr int kLevelEigMax = 12288;
+// The eigendecomposition of level l (built on first use; thread-safe).
+int level_eig(bmg_hierarchy* h, int l, hipStream_t s, const LevelEig** out);
+void free_level_eigs(bmg_hierarchy* h);
 int upload_hierarchy(bmg_hierarchy* h, hipStream_t s);
 void free_device(bmg_hierarchy* h);
 // Solve workspaces pooled per hierarchy (solver.cpp): bytes held by the idle
@@ -125,6 +153,9 @@ void free_device(bmg_hierarchy* h);
 void free_workspaces(bmg_hierarchy* h);
 int64_t idle_workspace_bytes(bmg_hierarchy* h);
 void trim_idle_workspaces(bmg_hierarchy* h);
+// Defaults shared by the solver and the server's footprint estimates.
+int default_block_width(int k, double sigma);
+int default_coarse_vectors(const bmg_hierarchy* h);
 int solve(bmg_hierarchy* h, int k, double sigma, double tol, const bmg_solve_opts* opts,
           double* evals, double* evecs, int64_t ld, int evecs_on_device, void* stream,
           bmg_solve_stats* stats);
@@ -278,6 +309,29 @@ int launch_ritz(const RitzArgs& a, hipStream_t s);
 constexpr double kRitzRtol2 = 1e-22;
 int launch_syev(int n, const double* A, double* w, double* V, int* status, hipStream_t s);
 int ritz_scratch_doubles(int nz);
+
+// Interior-shift scheme (kernels_coarse.hip).
+// e = Phi^T diag(g) Phi f with phi [n][n] (row j = eigenvector j), f, e [n][m];
+// t [n][m] and part [spec_slices(n)][n][m] are scratch.
+int spec_slices(int n);
+template <typename T>
+int launch_spec_apply(int n, const T* phi, const T* g, const T* f, T* t, T* part, T* e, int m,
+                      hipStream_t s);
+// g[i] = 1 / (lam[i] - *shift), 0 where |lam[i] - *shift| < tau
+template <typename T>
+int launch_spec_g(int n, const double* lam, const double* shift, double tau, T* g, hipStream_t s);
+// S = A - (*shift) M, the shift read from device memory
+template <typename T>
+int launch_shift_dev(const DevLevel& L, const double* shift, T* S, hipStream_t s);
+// blk [n][m]: blk[i][c] = phi[sel[c]][i]
+int launch_gather_rows(int n, int m, const double* phi, const int* sel, double* blk, hipStream_t s);
+// Per-level shifts from the block U (FP64 [N_top][m]) and its Ritz values
+// theta: shifts[l] = sigma + mean_c(U_c^T A_l U_c / U_c^T M_l U_c - theta_c)
+// over the first N_l rows, lo <= l < top; shifts[top] = sigma.  part holds
+// [top][kRqBlocks][2m] doubles.
+constexpr int kRqBlocks = 64;
+int launch_offsets(const std::vector<DevLevel>& dev, int lo, int top, const double* U, int m,
+                   double sigma, const double* theta, double* part, double* shifts, hipStream_t s);
 
 // column-wise argmax |U[:, sel_j]| (lowest row on ties) and output writer
 int launch_signs(int64_t n, const double* U, int m, const int* sel, int k, double* sign_out,

@@ -85,6 +85,7 @@ void bmg_solve_opts_default(bmg_solve_opts* o) {
   o->seed = 0;
   o->initial_block = nullptr;
   o->timed_kernel = -1;
+  o->scheme = BMG_SCHEME_AUTO;
 }
 
 static int build_impl(const bmg_surface_desc* desc, int32_t n_refine, void* stream,

@@ -1,7 +1,7 @@
 // Setup-time generalized symmetric-definite eigensolver for coarse meshes too
 // large for the host Jacobi solver (the 64 x 32 torus grid has 2048
-// vertices): A_0 x = lambda M_0 x (Alg. 2 step 1) with rocSOLVER's dsygvd on
-// the device.  It runs once per hierarchy, outside every solve.  The library
+// vertices): A_l x = lambda M_l x (Alg. 2 step 1) with rocSOLVER's dsygvd on
+// the device.  It runs once per hierarchy and level, outside every cycle.  The library
 // is opened on first use (dlopen), so processes whose coarse meshes are small
 // never load it.
 #include <dlfcn.h>
@@ -57,10 +57,12 @@ const Solver& solver() {
 
 }  // namespace
 
-// lam ascending [n]; X row-major [n][n] with column j the M-orthonormal
-// eigenvector of lam[j].  A and M are dense row-major (symmetric).
-int device_sygv(int n, const std::vector<double>& A, const std::vector<double>& M,
-                std::vector<double>& lam, std::vector<double>& X, hipStream_t s) {
+// lam ascending [n]; *vecs (device, [n][n]) with row j the M-orthonormal
+// eigenvector of lam[j] (rocSOLVER's column-major result read row by row).
+// A and M are dense row-major (symmetric).
+int device_sygv_keep(int n, const std::vector<double>& A, const std::vector<double>& M,
+                     std::vector<double>& lam, double** vecs, hipStream_t s) {
+  *vecs = nullptr;
   const Solver& so = solver();
   if (!so.ok) {
     set_error("coarse eigensolve of %d vertices needs rocSOLVER: %s", n, so.why.c_str());
@@ -91,29 +93,49 @@ int device_sygv(int n, const std::vector<double>& A, const std::vector<double>& 
   if (st == BMG_OK && so.sygvd(hdl, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_lower, n,
                                dA, n, dB, n, dD, dE, dinfo) != rocblas_status_success)
     fail("rocsolver_dsygvd");
-  std::vector<double> colmajor;
   if (st == BMG_OK) {
     lam.assign(n, 0.0);
-    colmajor.assign(nn, 0.0);
     if (hipMemcpyAsync(lam.data(), dD, size_t(n) * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(colmajor.data(), dA, nn * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipMemcpyAsync(&info, dinfo, sizeof(rocblas_int), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       fail("download");
   }
   if (hdl) (void)so.destroy(hdl);
   (void)hipStreamSynchronize(s);
-  for (void* p : {(void*)dA, (void*)dB, (void*)dD, (void*)dE, (void*)dinfo})
+  for (void* p : {(void*)dB, (void*)dD, (void*)dE, (void*)dinfo})
     if (p) (void)hipFree(p);
-  if (st != BMG_OK) return st;
-  if (info != 0) {
+  if (st == BMG_OK && info != 0) {
     set_error("coarse eigensolve: dsygvd info = %d (mass matrix not positive definite?)", info);
-    return BMG_EINVAL;
+    st = BMG_EINVAL;
   }
-  // column j of the column-major result is eigenvector j: transpose to row-major
+  if (st != BMG_OK) {
+    if (dA) (void)hipFree(dA);
+    return st;
+  }
+  *vecs = dA;
+  return BMG_OK;
+}
+
+// lam ascending [n]; X row-major [n][n] with column j the M-orthonormal
+// eigenvector of lam[j].
+int device_sygv(int n, const std::vector<double>& A, const std::vector<double>& M,
+                std::vector<double>& lam, std::vector<double>& X, hipStream_t s) {
+  double* d = nullptr;
+  BMG_TRY(device_sygv_keep(n, A, M, lam, &d, s));
+  const size_t nn = size_t(n) * n;
+  std::vector<double> rows(nn);
+  const hipError_t e1 = hipMemcpyAsync(rows.data(), d, nn * 8, hipMemcpyDeviceToHost, s);
+  const hipError_t e2 = hipStreamSynchronize(s);
+  (void)hipFree(d);
+  if (e1 != hipSuccess || e2 != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("coarse eigensolve: download failed");
+    return BMG_EDEVICE;
+  }
+  // row j is eigenvector j: transpose to column j
   X.assign(nn, 0.0);
   for (int j = 0; j < n; ++j)
-    for (int i = 0; i < n; ++i) X[size_t(i) * n + j] = colmajor[size_t(j) * n + i];
+    for (int i = 0; i < n; ++i) X[size_t(i) * n + j] = rows[size_t(j) * n + i];
   return BMG_OK;
 }
 

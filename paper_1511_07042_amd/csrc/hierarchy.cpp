@@ -1,6 +1,7 @@
 // Device-resident hierarchy: upload of the host levels, the level-0
 // eigendecomposition, sizes and export for inspection.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -147,7 +148,74 @@ int upload_hierarchy(bmg_hierarchy* h, hipStream_t s) {
   return BMG_OK;
 }
 
+int level_eig(bmg_hierarchy* h, int l, hipStream_t s, const LevelEig** out) {
+  std::lock_guard<std::mutex> g(h->eig_mutex);
+  const int nl = int(h->host.size());
+  BMG_CHECK(l >= 0 && l < nl, "level %d out of range", l);
+  if (h->level_eig.size() < size_t(nl)) h->level_eig.resize(nl);
+  if (h->level_eig[l]) {
+    *out = h->level_eig[l].get();
+    return BMG_OK;
+  }
+  const HostLevel& H = h->host[l];
+  const int n = int(H.n);
+  BMG_CHECK(H.n <= kLevelEigMax, "level %d has %lld vertices; the dense eigensolve takes at most %d", l,
+            (long long)H.n, kLevelEigMax);
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<double> A(size_t(n) * n, 0.0), M(size_t(n) * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < H.W; ++k) {
+      const int j = H.cols[size_t(i) * H.W + k];
+      A[size_t(i) * n + j] += H.a[size_t(i) * H.W + k];
+      M[size_t(i) * n + j] += H.mm[size_t(i) * H.W + k];
+    }
+  auto e = std::make_unique<LevelEig>();
+  e->level = l;
+  e->n = n;
+  const size_t nn = size_t(n) * n;
+  if (n <= kHostEigMax) {
+    std::vector<double> X;
+    BMG_TRY(dense_sygv(n, A, M, e->lam, X));
+    std::vector<double> rows(nn);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) rows[size_t(j) * n + i] = X[size_t(i) * n + j];
+    BMG_TRY(upload(&e->d_phi64, rows.data(), nn, s, e->bytes));
+    BMG_HIP(hipStreamSynchronize(s));  // rows is a local
+  } else {
+    A.shrink_to_fit();
+    BMG_TRY(device_sygv_keep(n, A, M, e->lam, &e->d_phi64, s));
+    e->bytes += int64_t(nn * sizeof(double));
+  }
+  BMG_TRY(upload(&e->d_lam, e->lam.data(), size_t(n), s, e->bytes));
+  if (hipMalloc(reinterpret_cast<void**>(&e->d_phi32), nn * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(e->d_phi64);
+    (void)hipFree(e->d_lam);
+    set_error("hipMalloc of %zu bytes failed", nn * sizeof(float));
+    return BMG_ENOMEM;
+  }
+  e->bytes += int64_t(nn * sizeof(float));
+  BMG_TRY(launch_convert<float>(e->d_phi64, e->d_phi32, int64_t(nn), s));
+  BMG_HIP(hipStreamSynchronize(s));  // lam is uploaded from the object itself; keep it simple
+  e->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  h->level_eig[l] = std::move(e);
+  *out = h->level_eig[l].get();
+  return BMG_OK;
+}
+
+void free_level_eigs(bmg_hierarchy* h) {
+  std::lock_guard<std::mutex> g(h->eig_mutex);
+  for (auto& e : h->level_eig) {
+    if (!e) continue;
+    for (void* p : {(void*)e->d_lam, (void*)e->d_phi64, (void*)e->d_phi32})
+      if (p) (void)hipFree(p);
+    e.reset();
+  }
+  h->level_eig.clear();
+}
+
 void free_device(bmg_hierarchy* h) {
+  free_level_eigs(h);
   for (auto& D : h->dev) {
     void* ptrs[] = {D.cols, D.a64, D.m64, D.a32, D.m32, D.dinv, D.parents, D.rtab, D.colour_rows, D.row_order, D.chunk_order};
     for (void* p : ptrs)

@@ -54,6 +54,16 @@ struct bmg_workspace {
   int g_smoother = -1, g_nu1 = -1, g_nu2 = -1, g_lc = -1, g_tail = -2, g_timed = -1, g_fuse = -1, g_warm = -1;
   int nblk_res = 0, nblk_arg = 0;
   bmg::GramPlan gp{}, gpw{};
+  // interior-shift scheme: per-level shifts, the quadratic-form partials they
+  // come from, and the coarse solve's scratch (sized for sh_n coarse rows)
+  int g_scheme = -1;
+  int64_t sh_n = -1;
+  double* shifts = nullptr;   // [nl]
+  double* rqpart = nullptr;   // [nl][kRqBlocks][2m]
+  void* spec_g = nullptr;     // [sh_n] correction precision
+  void* spec_t = nullptr;     // [sh_n][m]
+  void* spec_part = nullptr;  // [spec_slices(sh_n)][sh_n][m]
+  int* csel = nullptr;        // [m] coarse eigenvectors of the start block
   std::vector<void*> allocs;
   int64_t bytes = 0;  // device bytes held by allocs
 };
@@ -341,6 +351,13 @@ struct Cycle {
   int add_level = -1;
   bool added = false;
   bool fuse_ok = std::getenv("BMG_NO_FUSE") == nullptr;  // fused Jacobi cycle kernels
+  // coarse solve at l_c by the truncated spectral inverse of a dense level
+  // (the interior-shift scheme): eigenvectors one per row, inverse spectrum g
+  const T* lc_phi = nullptr;
+  const T* lc_g = nullptr;
+  T* lc_t = nullptr;
+  T* lc_part = nullptr;
+  int lc_n = 0;
 
   // Pack the LDS image of levels l_c..hi (the largest hi whose image and work
   // blocks fit the budget) and upload it with its descriptor.  phi0 and gh are
@@ -510,6 +527,7 @@ struct Cycle {
     const DevLevel& D = h->dev[l];
     if (l == tail_hi) return launch_tail<T>(tail_d, tail_lds, tail_groups, s);
     if (l == c.l_c) {
+      if (lc_phi) return launch_spec_apply<T>(lc_n, lc_phi, lc_g, f[l], lc_t, lc_part, e[l], c.m, s);
       if (l == 0) {
         const int n0 = int(h->n0);
         const T* pt = std::is_same<T, float>::value ? (const T*)h->d_phi0t_32 : (const T*)h->d_phi0t_64;
@@ -600,7 +618,7 @@ std::vector<double> coarse_inverse(const bmg_hierarchy* h, double sigma) {
 // level up to `top`, upload the level-0 inverse and set up the LDS tail.
 template <typename T>
 int init_cycle(Cycle<T>& cyc, bmg_hierarchy* h, bmg_workspace* w, const CycleCfg& cfg, int top,
-               hipStream_t s) {
+               hipStream_t s, bool allow_tail = true) {
   const int nl = int(h->dev.size());
   cyc.h = h;
   cyc.c = cfg;
@@ -621,9 +639,46 @@ int init_cycle(Cycle<T>& cyc, bmg_hierarchy* h, bmg_workspace* w, const CycleCfg
   const std::vector<double> gh = coarse_inverse(h, cfg.sigma);
   std::vector<T> g(gh.begin(), gh.end());
   BMG_HIP(hipMemcpyAsync(w->gco, g.data(), sizeof(T) * g.size(), hipMemcpyHostToDevice, s));
-  BMG_TRY(cyc.setup_tail(w->tail_h, w->tail_d, w->tail_img, w->tail_host, h->phi0, gh, top));
+  if (allow_tail) BMG_TRY(cyc.setup_tail(w->tail_h, w->tail_d, w->tail_img, w->tail_host, h->phi0, gh, top));
   BMG_HIP(hipStreamSynchronize(s));  // g is a host local
   return BMG_OK;
+}
+
+int default_block_width(int k, double sigma) {
+  const double fac = sigma == 0.0 ? 1.25 : 1.5;
+  return 4 * int(std::ceil(fac * k / 4.0));
+}
+
+int default_coarse_vectors(const bmg_hierarchy* h) { return int(std::min<int64_t>(h->n0, 32)) & ~1; }
+
+// Coarse level of the interior-shift scheme: the coarsest l with
+// N_l >= pi n_W(sigma)^2 / m, n_W = |Gamma_h| sigma / (4 pi) the Weyl count of
+// eigenvalues below sigma.  The P1 eigenvalues near sigma on level l are off
+// by O(sigma^2 h_l^2) ~ sigma^2 |Gamma| / N_l (Sec. 2.3), and a block of m
+// vectors spans a window of half-width ~ 2 pi m / |Gamma| about sigma; the
+// level must place the eigenvalues within a fraction of that window, which
+// gives N_l ~ n_W^2 / m (the constant pi was measured on the ellipsoid
+// (1, 1.5, 2) at sigma = 50 and 100).  Levels above kLevelEigMax vertices are
+// not eigendecomposed: if the rule needs one, the finest level within the
+// cap is used and, when m was not given, m is raised to meet the rule
+// (a multiple of 4, at most 96).
+int shifted_coarse_level(const bmg_hierarchy* h, double sigma, int& m, bool m_given) {
+  const int nl = int(h->host.size());
+  const double nw = h->host[nl - 1].area * std::max(sigma, 0.0) / (4.0 * M_PI);
+  const double need = M_PI * nw * nw / m;
+  int cap = 0;
+  for (int l = 0; l < nl; ++l)
+    if (h->host[l].n <= kLevelEigMax) cap = l;
+  for (int l = 0; l < nl; ++l)
+    if (double(h->host[l].n) >= need) {
+      if (l <= cap) return l;
+      break;
+    }
+  if (!m_given && cap < nl - 1) {
+    const int want = 4 * int(std::ceil(M_PI * nw * nw / double(h->host[cap].n) / 4.0));
+    m = std::min(96, std::max(m, want));
+  }
+  return cap;
 }
 
 int weyl_coarsest(const bmg_hierarchy* h, double sigma) {
@@ -689,21 +744,37 @@ Cert certify(const std::vector<double>& theta, const std::vector<double>& rho2, 
 
 template <typename T>
 int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double tol,
-              const bmg_solve_opts& o, int l_c, double* evals, double* evecs, int64_t ld,
-              int evecs_on_device, hipStream_t s, bmg_solve_stats* stats) {
+              const bmg_solve_opts& o, int l_c, const LevelEig* lce, double* evals, double* evecs,
+              int64_t ld, int evecs_on_device, hipStream_t s, bmg_solve_stats* stats) {
   const int nl = int(h->dev.size());
   const int L = nl - 1;
   const DevLevel& DL = h->dev[L];
   const int64_t N = DL.n;
   const int m = o.m, n_c = o.n_c, nz = n_c + m;
   const int64_t n0 = h->n0;
+  // interior-shift scheme: no fixed coarse vectors, per-level shifts, the
+  // spectral inverse of level l_c as the coarse solve, coarse start block
+  const bool shifted = lce != nullptr;
   hipEvent_t ev0, ev1;
   BMG_HIP(hipEventCreate(&ev0));
   BMG_HIP(hipEventCreate(&ev1));
   BMG_HIP(hipEventRecord(ev0, s));
+  if (shifted && w->sh_n < lce->n) {
+    // scratch of the coarse solve and the shift estimates (kept by the
+    // workspace for later solves)
+    const size_t vb = sizeof(T);
+    const size_t n = size_t(lce->n);
+    if (dalloc(w, reinterpret_cast<void**>(&w->shifts), sizeof(double) * nl) != BMG_OK ||
+        dalloc(w, reinterpret_cast<void**>(&w->rqpart), sizeof(double) * nl * kRqBlocks * 2 * m) != BMG_OK ||
+        dalloc(w, &w->spec_g, vb * n) != BMG_OK || dalloc(w, &w->spec_t, vb * n * m) != BMG_OK ||
+        dalloc(w, &w->spec_part, vb * n * m * spec_slices(int(n))) != BMG_OK ||
+        dalloc(w, reinterpret_cast<void**>(&w->csel), sizeof(int) * m) != BMG_OK)
+      return BMG_ENOMEM;
+    w->sh_n = lce->n;
+  }
 
   // ---- S2: W_c = P_{0->L} Phi_c, its Gram blocks, and the level-0 inverse
-  {
+  if (!shifted) {
     std::vector<int> idx = nearest(h->lam0, sigma, n_c);
     std::sort(idx.begin(), idx.end());
     std::vector<double> phic(size_t(n0) * n_c);
@@ -719,13 +790,16 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     }
     BMG_HIP(hipStreamSynchronize(s));  // phic is a host local
   }
-  BMG_TRY(launch_spmm_am(DL, w->W, w->AW, w->MW, n_c, s));
-  BMG_TRY(launch_gram(w->gpw, N, w->W, n_c, nullptr, 0, w->AW, n_c, w->MW, n_c, w->gpart, w->GW, s));
+  if (!shifted) {
+    BMG_TRY(launch_spmm_am(DL, w->W, w->AW, w->MW, n_c, s));
+    BMG_TRY(launch_gram(w->gpw, N, w->W, n_c, nullptr, 0, w->AW, n_c, w->MW, n_c, w->gpart, w->GW, s));
+  }
 
-  // ---- S3: test vectors and the first Rayleigh-Ritz step
+  // ---- S3: test vectors and the first Rayleigh-Ritz step (the interior
+  // scheme starts from coarse eigenvectors further below unless a block is given)
   if (o.initial_block)
     BMG_HIP(hipMemcpyAsync(w->U, o.initial_block, sizeof(double) * N * m, hipMemcpyHostToDevice, s));
-  else
+  else if (!shifted)
     BMG_TRY(launch_gaussian(w->U, N, m, o.seed, s));
 
   KTimer kt;
@@ -768,13 +842,79 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     BMG_TRY(kt.end(BMG_K_UPDATE));
     return BMG_OK;
   };
-  BMG_TRY(ritz_step());
+  if (!shifted || o.initial_block) BMG_TRY(ritz_step());
   ra.warm = warm_ok;
 
   Cycle<T> cyc;
-  BMG_TRY(init_cycle<T>(cyc, h, w, CycleCfg{m, o.nu1, o.nu2, o.smoother, l_c, sigma, o.omega}, L, s));
+  BMG_TRY(init_cycle<T>(cyc, h, w, CycleCfg{m, o.nu1, o.nu2, o.smoother, l_c, sigma, o.omega}, L, s,
+                        !shifted));
   cyc.kt = o.timed_kernel >= 0 ? &kt : nullptr;
   cyc.L = L;
+  // truncation of the coarse inverse spectrum (as at level 0)
+  const double spec_tau = 1e-2 * std::max(1.0, std::fabs(sigma));
+  if (shifted) {
+    cyc.lc_phi = std::is_same<T, float>::value ? reinterpret_cast<const T*>(lce->d_phi32)
+                                               : reinterpret_cast<const T*>(lce->d_phi64);
+    cyc.lc_g = static_cast<const T*>(w->spec_g);
+    cyc.lc_t = static_cast<T*>(w->spec_t);
+    cyc.lc_part = static_cast<T*>(w->spec_part);
+    cyc.lc_n = lce->n;
+  }
+  // shifts of levels l_c..L from the current block (Remark 4.1), the shifted
+  // operators and the coarse inverse spectrum that depend on them
+  auto adapt_shifts = [&]() -> int {
+    BMG_TRY(launch_offsets(h->dev, l_c, L, w->U, m, sigma, w->theta, w->rqpart, w->shifts, s));
+    for (int l = l_c + 1; l <= L; ++l)
+      BMG_TRY(launch_shift_dev<T>(h->dev[l], w->shifts + l, static_cast<T*>(w->S[l]), s));
+    BMG_TRY(launch_spec_g<T>(lce->n, lce->d_lam, w->shifts + l_c, spec_tau, static_cast<T*>(w->spec_g), s));
+    return BMG_OK;
+  };
+  std::vector<double> shifts_h(nl, sigma);
+  if (shifted) {
+    BMG_HIP(hipMemcpyAsync(w->shifts, shifts_h.data(), sizeof(double) * nl, hipMemcpyHostToDevice, s));
+    BMG_TRY(launch_spec_g<T>(lce->n, lce->d_lam, w->shifts + l_c, spec_tau, static_cast<T*>(w->spec_g), s));
+    BMG_HIP(hipStreamSynchronize(s));  // shifts_h is read by the copy
+  }
+  // Start of the interior scheme (Alg. 2 steps 2-4, Alg. 4 step 1): the m
+  // level-l_c eigenvectors nearest sigma + off (off: the level's offset),
+  // prolongated to level L, one relaxation of the source problem with their
+  // eigenvalues shifted back by off as Theta, and a Ritz step in their span.
+  std::vector<double> theta0(m);
+  std::vector<int> csel;
+  auto start = [&](double off) -> int {
+    csel = nearest(lce->lam, sigma + off, m);
+    std::sort(csel.begin(), csel.end());
+    for (int j = 0; j < m; ++j) theta0[j] = lce->lam[csel[j]] - off;
+    BMG_HIP(hipMemcpyAsync(w->csel, csel.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
+    BMG_HIP(hipMemcpyAsync(w->theta, theta0.data(), sizeof(double) * m, hipMemcpyHostToDevice, s));
+    double* cur = ((L - l_c) % 2 == 0) ? w->U : w->AU;  // ping-pong so the last lands in U
+    BMG_TRY(launch_gather_rows(lce->n, m, lce->d_phi64, w->csel, cur, s));
+    for (int l = l_c + 1; l <= L; ++l) {
+      double* nxt = (cur == w->U) ? w->AU : w->U;
+      BMG_TRY(launch_fill<double>(nxt, h->dev[l].n * m, 0.0, s));
+      BMG_TRY(launch_prolong_add<double>(h->dev[l], cur, nxt, m, s));
+      cur = nxt;
+    }
+    if (l_c < L) {
+      BMG_TRY(launch_eigres<T>(DL, w->U, w->theta, -1.0, cyc.f[L], w->rho2part, w->nblk_res, m, s));
+      cyc.add_u = nullptr;
+      cyc.added = false;
+      BMG_TRY(cyc.vcycle(L));
+      BMG_TRY(launch_add_to<T>(w->U, cyc.e[L], N * m, s));
+    }
+    BMG_TRY(ritz_step());
+    BMG_HIP(hipStreamSynchronize(s));  // csel and theta0 are read by the copies
+    return BMG_OK;
+  };
+  if (shifted && !o.initial_block) {
+    BMG_TRY(start(0.0));
+    if (l_c < L) {
+      BMG_TRY(adapt_shifts());
+      BMG_HIP(hipMemcpyAsync(shifts_h.data(), w->shifts, sizeof(double) * nl, hipMemcpyDeviceToHost, s));
+      BMG_HIP(hipStreamSynchronize(s));
+      BMG_TRY(start(shifts_h[l_c] - sigma));
+    }
+  }
 
   std::vector<double> theta(m), rho2(m);
   Cert cert;
@@ -791,6 +931,7 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   };
   // H2-H6 followed by the next H1: the same launches every cycle
   auto cycle_body = [&]() -> int {
+    if (shifted) BMG_TRY(adapt_shifts());
     // U += E: folded into the cycle's last sweep when that is a Jacobi sweep
     cyc.add_u = fold_add ? w->U : nullptr;
     cyc.add_level = L;
@@ -807,7 +948,8 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   // recorded per launch)
   bool use_graph = o.timed_kernel < 0 && !std::getenv("BMG_NO_GRAPH");
   const bool debug = std::getenv("BMG_DEBUG") != nullptr;
-  if (use_graph && !(w->gexec && o.timed_kernel < 0 && w->g_timed < 0 && w->g_sigma == sigma && w->g_omega == o.omega &&
+  if (use_graph && !(w->gexec && o.timed_kernel < 0 && w->g_timed < 0 && w->g_sigma == sigma &&
+                     w->g_scheme == int(shifted) && w->g_omega == o.omega &&
                      w->g_smoother == o.smoother && w->g_nu1 == o.nu1 && w->g_nu2 == o.nu2 &&
                      w->g_lc == l_c && w->g_tail == cyc.tail_hi && w->g_fuse == int(cyc.fuse_ok) &&
                      w->g_warm == ra.warm)) {
@@ -849,6 +991,7 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
       w->g_tail = cyc.tail_hi;
       w->g_fuse = int(cyc.fuse_ok);
       w->g_warm = ra.warm;
+      w->g_scheme = int(shifted);
     }
     BMG_HIP(hipGraphLaunch(w->gexec, s));
     return BMG_OK;
@@ -874,8 +1017,10 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     ritz_sweeps_max = std::max(ritz_sweeps_max, rs3[1]);
     ritz_fallbacks += rs3[2];
     if (rstat == 1) {
-      set_error("enriched space lost rank below m");
+      // no m pairs exist: nothing is certified and no pair is written
+      set_error("enriched space lost rank below m after %d cycles", cycles);
       status = BMG_ENOCONV;
+      cert = Cert();
       break;
     }
     bool finite = true;
@@ -902,11 +1047,14 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     ++cycles;
   }
 
-  // ---- output: k pairs nearest sigma, ascending, signs normalised
+  // ---- output: k pairs nearest sigma, ascending, signs normalised (none
+  // when the Ritz step lost rank: evals and evecs are then left untouched)
   std::vector<int> sel = cert.ret;
   std::sort(sel.begin(), sel.end());  // theta is ascending
-  for (int j = 0; j < k; ++j) evals[j] = theta[sel[j]];
-  if (evecs) {
+  const bool have_pairs = int(sel.size()) == k;
+  if (have_pairs)
+    for (int j = 0; j < k; ++j) evals[j] = theta[sel[j]];
+  if (evecs && have_pairs) {
     BMG_HIP(hipMemcpyAsync(w->sel, sel.data(), sizeof(int) * k, hipMemcpyHostToDevice, s));
     BMG_TRY(launch_signs(N, w->U, m, w->sel, k, w->sign, w->argv, w->argi, w->nblk_arg, s));
     if (evecs_on_device) {
@@ -937,6 +1085,17 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     stats->timed_kernel_units = kt.units;
     stats->ritz_sweeps_max = ritz_sweeps_max;
     stats->ritz_fallbacks = ritz_fallbacks;
+    stats->scheme = shifted ? BMG_SCHEME_SHIFTED : BMG_SCHEME_ENRICHED;
+    stats->coarse_eig_ms = shifted ? lce->setup_ms : 0.0;
+    stats->lc_shift = shifted ? shifts_h[l_c] : sigma;
+    if (shifted && l_c < L) {
+      // final shift of level l_c (the adaptive shift after the last cycle)
+      double v = sigma;
+      if (hipMemcpy(&v, w->shifts + l_c, sizeof(double), hipMemcpyDeviceToHost) == hipSuccess)
+        stats->lc_shift = v;
+      else
+        (void)hipGetLastError();
+    }
     // report in the output order (ascending)
     for (int j = 0; j < k && j < int(cert.ret.size()); ++j) {
       const int pos = int(std::find(cert.ret.begin(), cert.ret.end(), sel[j]) - cert.ret.begin());
@@ -961,15 +1120,23 @@ int solve(bmg_hierarchy* h, int k, double sigma, double tol, const bmg_solve_opt
   BMG_CHECK(k >= 1, "k must be >= 1");
   BMG_CHECK(std::isfinite(sigma), "sigma must be finite");
   BMG_CHECK(tol > 0 && std::isfinite(tol), "tol must be positive and finite");
-  if (o.m <= 0) {
-    const double fac = sigma == 0.0 ? 1.25 : 1.5;
-    o.m = 4 * int(std::ceil(fac * k / 4.0));
+  BMG_CHECK(o.scheme >= BMG_SCHEME_AUTO && o.scheme <= BMG_SCHEME_SHIFTED, "unknown scheme %d", o.scheme);
+  const bool shifted = o.scheme == BMG_SCHEME_SHIFTED || (o.scheme == BMG_SCHEME_AUTO && sigma > 0.0);
+  const bool m_given = o.m > 0;
+  if (o.m <= 0) o.m = default_block_width(k, sigma);
+  int l_c = o.l_c;
+  if (shifted) {
+    if (l_c < 0) l_c = shifted_coarse_level(h, sigma, o.m, m_given);
+    o.n_c = 0;
+  } else {
+    if (o.n_c <= 0) o.n_c = default_coarse_vectors(h);
+    if (l_c < 0) l_c = weyl_coarsest(h, sigma);
   }
-  if (o.n_c <= 0) o.n_c = int(std::min<int64_t>(h->n0, 32)) & ~1;
   BMG_CHECK(o.m % 4 == 0, "m = %d must be a multiple of 4", o.m);
   BMG_CHECK(o.m >= k, "m = %d must be >= k = %d", o.m, k);
   BMG_CHECK(int64_t(o.m) <= N / 2, "m = %d must be <= N_L / 2", o.m);
-  BMG_CHECK(o.n_c % 2 == 0 && o.n_c >= 2 && o.n_c <= h->n0, "n_c must be even and in [2, N_0]");
+  if (!shifted)
+    BMG_CHECK(o.n_c % 2 == 0 && o.n_c >= 2 && o.n_c <= h->n0, "n_c must be even and in [2, N_0]");
   BMG_CHECK(o.n_c + o.m <= 96, "n_c + m = %d exceeds 96", o.n_c + o.m);
   BMG_CHECK(o.nu1 >= 0 && o.nu2 >= 0 && o.nu1 <= 64 && o.nu2 <= 64, "nu1, nu2 must be in [0, 64]");
   BMG_CHECK(o.smoother == BMG_SMOOTH_GS || o.smoother == BMG_SMOOTH_JACOBI, "unknown smoother");
@@ -978,9 +1145,13 @@ int solve(bmg_hierarchy* h, int k, double sigma, double tol, const bmg_solve_opt
   BMG_CHECK(o.omega > 0 && o.omega < 2, "omega must be in (0, 2)");
   BMG_CHECK(o.angle_tol > 0, "angle_tol must be positive");
   BMG_CHECK(evecs == nullptr || ld >= N, "ld must be >= N_L");
-  const int l_c = o.l_c < 0 ? weyl_coarsest(h, sigma) : o.l_c;
   BMG_CHECK(l_c >= 0 && l_c < nl, "l_c out of range");
+  if (shifted)
+    BMG_CHECK(h->host[l_c].n <= kLevelEigMax, "l_c = %d has %lld vertices; the interior scheme's dense "
+              "eigensolve takes at most %d", l_c, (long long)h->host[l_c].n, kLevelEigMax);
   BMG_HIP(hipSetDevice(h->device));
+  const LevelEig* lce = nullptr;
+  if (shifted) BMG_TRY(level_eig(h, l_c, static_cast<hipStream_t>(stream), &lce));
   bmg_workspace* w = nullptr;
   BMG_TRY(acquire_workspace(h, o.m, o.n_c, o.precision, &w));
   // work runs on the workspace's own stream, ordered after the caller's
@@ -993,8 +1164,8 @@ int solve(bmg_hierarchy* h, int k, double sigma, double tol, const bmg_solve_opt
     st = BMG_EDEVICE;
   } else {
     st = (o.precision == BMG_MIXED)
-             ? run_solve<float>(h, w, k, sigma, tol, o, l_c, evals, evecs, ld, evecs_on_device, s, stats)
-             : run_solve<double>(h, w, k, sigma, tol, o, l_c, evals, evecs, ld, evecs_on_device, s, stats);
+             ? run_solve<float>(h, w, k, sigma, tol, o, l_c, lce, evals, evecs, ld, evecs_on_device, s, stats)
+             : run_solve<double>(h, w, k, sigma, tol, o, l_c, lce, evals, evecs, ld, evecs_on_device, s, stats);
   }
   (void)hipStreamSynchronize(s);
   if (hipEventRecord(w->ev_out, s) == hipSuccess) (void)hipStreamWaitEvent(cs, w->ev_out, 0);
@@ -1009,7 +1180,7 @@ int apply_vcycle(bmg_hierarchy* h, int level, int dtype, int m, double sigma, in
   BMG_CHECK(lc >= 0 && lc <= level, "l_c must be in [0, level]");
   bmg_workspace* w = nullptr;
   const int prec = dtype == 1 ? BMG_MIXED : BMG_FP64;
-  const int n_c = int(std::min<int64_t>(h->n0, 32)) & ~1;
+  const int n_c = default_coarse_vectors(h);
   BMG_TRY(make_workspace(h, m, n_c, prec, &w));
   const size_t vb = dtype == 1 ? sizeof(float) : sizeof(double);
   int st = BMG_OK;
