@@ -307,10 +307,22 @@ typedef enum {
   BMG_OP_UPDATE = 13,    /* y [N_l][m] <- [x | y] f in place: x [N_l][m2] (NULL if
                             m2 = 0), f = Y [m2 + m][m] row-major; the Ritz update
                             U <- [W_c, U'] Y (FP64, matrix cores, m2 + m <= 96)  */
-  BMG_OP_GRAM_AM = 14    /* y [m2 + m][2m] = [x | f]^T [A_l f | M_l f]: x [N_l][m2]
+  BMG_OP_GRAM_AM = 14,   /* y [m2 + m][2m] = [x | f]^T [A_l f | M_l f]: x [N_l][m2]
                             (NULL if m2 = 0), f [N_l][m], m even; the Gram blocks
                             of the enriched pencil with the products formed on the
                             fly (FP64, matrix cores, m2 + m <= 96)               */
+  BMG_OP_COARSE_SOLVE = 15, /* y [N_l][m] = Phi diag(g) Phi^T x: the SHIFTED scheme's
+                            coarse solve, the truncated spectral inverse of
+                            A_l - sigma M_l (g = 1 / (lambda - sigma), 0 within
+                            1e-2 max(1, |sigma|)); builds (and keeps) the level's
+                            eigendecomposition on first use; N_l <= 12288, m a
+                            multiple of 4 up to 96 (dtype)                       */
+  BMG_OP_SHIFT_OFFSETS = 16 /* y [level + 1] doubles: y[j] = sigma + mean_c(x_c^T A_j
+                            x_c / x_c^T M_j x_c - f_c) over the first N_j rows of
+                            x, for l_c <= j < level, and y[level] = sigma (the
+                            SHIFTED scheme's adaptive shifts); x FP64 [N_level][m],
+                            f device [m] Ritz values, m even up to 96; other
+                            entries of y are not written                         */
 } bmg_op;
 
 typedef struct {

@@ -369,15 +369,20 @@ class ShiftedBMG:
         lc = levels[l_c]
         # coarse eigensolve of level l_c (Alg. 2 step 1, Alg. 4 step 1)
         self.lam, self.phi = sla.eigh(lc.A.toarray(), lc.M.toarray())
+        self.smoothers = {}
         self.set_offsets(np.zeros(self.L + 1))
 
     def set_offsets(self, off):
         """Per-level shifts sigma_l = sigma + off[l] (Remark 4.1)."""
         self.off = np.array(off, dtype=np.float64)
-        self.smoothers = {}
         for l in range(self.l_c + 1, self.L + 1):
-            self.smoothers[l] = Smoother(self.levels[l], self.sigma + self.off[l], self.kind,
-                                         self.omega)
+            lv, sig = self.levels[l], self.sigma + self.off[l]
+            if l not in self.smoothers:
+                self.smoothers[l] = Smoother(lv, sig, self.kind, self.omega)
+            else:
+                sm = self.smoothers[l]
+                sm.S = (lv.A - sig * lv.M).tocsr()
+                sm.d = sm.S.diagonal()
         x = self.lam - (self.sigma + self.off[self.l_c])
         keep = np.abs(x) >= 1e-2 * max(1.0, abs(self.sigma))
         self.g = np.where(keep, 1.0 / np.where(keep, x, 1.0), 0.0)

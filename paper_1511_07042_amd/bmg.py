@@ -29,7 +29,7 @@ KERNEL_CLASSES = {"eigres": 0, "spmm_am": 1, "smooth": 2, "residual": 3, "restri
                   "restrict_res": 10, "prolong_smooth": 11, "smooth_add": 12}
 OPS = {"A": 0, "M": 1, "shifted": 2, "residual": 3, "smooth_fwd": 4, "smooth_bwd": 5,
        "restrict": 6, "prolong_add": 7, "vcycle": 8, "gaussian": 9, "gram": 10, "syev": 11,
-       "eigres": 12, "update": 13, "gram_am": 14}
+       "eigres": 12, "update": 13, "gram_am": 14, "coarse_solve": 15, "shift_offsets": 16}
 
 PROJECT_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.c_void_p)
 

@@ -367,6 +367,54 @@ int bmg_apply(const bmg_hierarchy* hc, const bmg_apply_args* a, const void* x, c
       return launch_update_zy(D.n, (const double*)x, a->m2, (const double*)y, m, (const double*)f,
                               (double*)y, m, s);
     }
+    case BMG_OP_COARSE_SOLVE: {
+      BMG_CHECK(x != nullptr, "x required");
+      BMG_CHECK(m >= 4 && m % 4 == 0 && m <= 96, "COARSE_SOLVE needs m a multiple of 4 in [4, 96]");
+      BMG_CHECK(std::isfinite(a->sigma), "sigma must be finite");
+      const LevelEig* e = nullptr;
+      BMG_TRY(level_eig(h, l, s, &e));
+      const int n = e->n;
+      const size_t vb = f32 ? sizeof(float) : sizeof(double);
+      void *g = nullptr, *t = nullptr, *part = nullptr;
+      double* sh = nullptr;
+      int st = BMG_OK;
+      if (hipMalloc(&g, vb * n) != hipSuccess || hipMalloc(&t, vb * n * m) != hipSuccess ||
+          hipMalloc(&part, vb * n * m * spec_slices(n)) != hipSuccess ||
+          hipMalloc(reinterpret_cast<void**>(&sh), sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc failed");
+        st = BMG_ENOMEM;
+      }
+      const double tau = 1e-2 * std::max(1.0, std::fabs(a->sigma));
+      if (st == BMG_OK && hipMemcpyAsync(sh, &a->sigma, sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess) {
+        set_error("copy failed");
+        st = BMG_EDEVICE;
+      }
+      if (st == BMG_OK)
+        st = f32 ? launch_spec_g<float>(n, e->d_lam, sh, tau, (float*)g, s)
+                 : launch_spec_g<double>(n, e->d_lam, sh, tau, (double*)g, s);
+      if (st == BMG_OK)
+        st = f32 ? launch_spec_apply<float>(n, e->d_phi32, (const float*)g, (const float*)x, (float*)t,
+                                            (float*)part, (float*)y, m, s)
+                 : launch_spec_apply<double>(n, e->d_phi64, (const double*)g, (const double*)x,
+                                             (double*)t, (double*)part, (double*)y, m, s);
+      (void)hipStreamSynchronize(s);
+      for (void* p : {g, t, part, (void*)sh})
+        if (p) (void)hipFree(p);
+      return st;
+    }
+    case BMG_OP_SHIFT_OFFSETS: {
+      BMG_CHECK(x && f && !f32, "SHIFT_OFFSETS takes an FP64 block x and FP64 theta in f");
+      BMG_CHECK(m >= 2 && m % 2 == 0 && m <= 96, "SHIFT_OFFSETS needs even m in [2, 96]");
+      BMG_CHECK(a->l_c >= 0 && a->l_c <= l, "SHIFT_OFFSETS needs 0 <= l_c <= level");
+      double* part = nullptr;
+      BMG_HIP(hipMalloc(&part, sizeof(double) * (l + 1) * kRqBlocks * 2 * m));
+      int st = launch_offsets(h->dev, a->l_c, l, (const double*)x, m, a->sigma, (const double*)f, part,
+                              (double*)y, s);
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(part);
+      return st;
+    }
     default:
       BMG_CHECK(false, "unknown op %d", a->op);
   }

@@ -20,6 +20,14 @@ REQUESTS = [
          smoother="jacobi", seed=4),
     dict(kind="sphere", n_refine=3, k=9, sigma=0.0, m=12, precision="mixed", smoother="jacobi", seed=5),
     dict(kind="sphere", n_refine=5, k=25, sigma=0.0, m=32, precision="mixed", smoother="jacobi", seed=6),
+    # interior shifts (the shifted scheme) on the three surfaces, and a torus at sigma = 0
+    dict(kind="torus", n_refine=1, k=12, sigma=60.0, precision="mixed", smoother="jacobi", seed=7),
+    dict(kind="ellipsoid", n_refine=5, k=16, sigma=50.0, axes=(1.0, 1.5, 2.0), precision="mixed",
+         smoother="jacobi", seed=8),
+    dict(kind="torus", n_refine=1, k=8, sigma=0.0, precision="fp64", smoother="gs", seed=9),
+    dict(kind="sphere", n_refine=4, k=10, sigma=150.0, precision="fp64", smoother="jacobi", seed=10),
+    dict(kind="ellipsoid", n_refine=4, k=20, sigma=120.0, axes=(1.3, 1.9, 1.1), precision="mixed",
+         smoother="gs", seed=11),
 ]
 
 SURF = ("kind", "n_refine", "axes")
