@@ -32,6 +32,7 @@
 // starts Jacobi from the previous cycle's basis of the coarse block (see
 // k_ritz), which leaves mostly the small couplings the correction introduced.
 #include <cmath>
+#include <mutex>
 
 #include "bmg_internal.h"
 
@@ -942,18 +943,25 @@ int check_launch() {
 }
 
 // Both kernels take up to 160 KiB of dynamic LDS (they have no static LDS).
+// Set once per process (std::call_once: solves on several threads may reach
+// here together); the outcome is kept and every later call returns it.
 int set_lds_attr() {
-  static bool done = false;
-  if (done) return BMG_OK;
-  for (const void* f : {(const void*)k_ritz, (const void*)k_syev}) {
-    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      set_error("cannot reserve 160 KiB of LDS for the Ritz kernels: %s", hipGetErrorString(e));
-      return BMG_EDEVICE;
+  static std::once_flag once;
+  static hipError_t err = hipSuccess;
+  std::call_once(once, [] {
+    for (const void* f : {(const void*)k_ritz, (const void*)k_syev}) {
+      const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        err = e;
+        return;
+      }
     }
+  });
+  if (err != hipSuccess) {
+    set_error("cannot reserve 160 KiB of LDS for the Ritz kernels: %s", hipGetErrorString(err));
+    return BMG_EDEVICE;
   }
-  done = true;
   return BMG_OK;
 }
 

@@ -14,6 +14,8 @@
 // Update: U = Z Y for a small Y (the new Ritz vectors U <- [W_c, U'] Y).
 #include <algorithm>
 
+#include <mutex>
+
 #include "bmg_internal.h"
 
 namespace bmg {
@@ -531,14 +533,13 @@ int launch_update_zy(int64_t n, const double* z1, int w1, const double* z2, int 
   const int64_t tiles = (n + 15) / 16;
   // up to 1024 blocks (each stages Y in LDS once)
   const int grid = int(std::min<int64_t>((tiles + 3) / 4, 1024));
-  static bool attr_set = false;
-  if (!attr_set) {
+  static std::once_flag once;  // solves on several threads may arrive together
+  std::call_once(once, [] {
     (void)hipFuncSetAttribute((const void*)k_update_zy<5, 24>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               96 * 1024);
     (void)hipFuncSetAttribute((const void*)k_update_zy<6, 24>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               96 * 1024);
-    attr_set = true;
-  }
+  });
   // fragment registers for 12 k steps when they suffice (nz <= 48), else 24
 #define UL(tj)                                                                                    \
   do {                                                                                            \

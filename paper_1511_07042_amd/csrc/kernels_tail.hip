@@ -16,6 +16,8 @@
 // with workgroup barriers in place of kernel boundaries.  The host packs the
 // static part once per solve into one contiguous image; a call copies the
 // image and f[hi] into LDS and writes e[hi] back.
+#include <mutex>
+
 #include "bmg_internal.h"
 
 namespace bmg {
@@ -300,14 +302,13 @@ __global__ void __launch_bounds__(1024) k_tail(const TailArgs* __restrict__ args
 
 template <typename T>
 int launch_tail(const TailArgs* dev_args, int lds_bytes, int groups, hipStream_t s) {
-  static bool attr = false;
-  if (!attr) {
+  static std::once_flag once;  // solves on several threads may arrive together
+  std::call_once(once, [] {
     (void)hipFuncSetAttribute((const void*)k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kTailLdsBudget);
     (void)hipFuncSetAttribute((const void*)k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kTailLdsBudget);
-    attr = true;
-  }
+  });
   k_tail<T><<<groups, 1024, lds_bytes, s>>>(dev_args);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
