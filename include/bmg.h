@@ -347,6 +347,22 @@ typedef struct {
 int bmg_apply(const bmg_hierarchy* h, const bmg_apply_args* args, const void* x, const void* f,
               void* y, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the fused
+ * Gram of bmg_apply(BMG_OP_GRAM_AM), G [m2 + m][2m] = [w | u]^T [A_l u | M_l u]
+ * with w device [N_l][m2] (NULL if m2 = 0), u device [N_l][m], m even,
+ * m2 + m <= 96, G device, all FP64, enqueued on `stream`.  It calls no
+ * hipMalloc, hipFree or allocating library routine: the kernel's partial sums
+ * live in a static 16 MiB device array (one per device, held until the process
+ * ends); the row-block count is reduced where the planner's would not fit, so
+ * results agree with bmg_apply's to rounding (a different summation split),
+ * not bit for bit.  Calls that overlap on one device share that array and
+ * race: serialise them (one stream, or events).  Errors: BMG_EINVAL for
+ * invalid sizes or a block whose partial sums exceed the array, BMG_EDEVICE
+ * if the array's device address cannot be obtained. */
+int bmg_gram_am_noalloc(const bmg_hierarchy* h, int32_t level, const double* w, int32_t m2,
+                        const double* u, int32_t m, double* G, void* stream);
+
 /* ------------------------------------------------------------- serving --- */
 
 typedef struct bmg_server bmg_server;

@@ -87,6 +87,8 @@ _sig = {
                             C.POINTER(C.c_double), C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
                             C.POINTER(SolveStats)]),
     "bmg_apply": (C.c_int, [_H, C.POINTER(ApplyArgs), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "bmg_gram_am_noalloc": (C.c_int, [_H, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32,
+                                      C.c_void_p, C.c_void_p]),
     "bmg_server_create": (C.c_int, [C.c_int64, C.c_int32, C.POINTER(C.c_void_p)]),
     "bmg_server_submit": (C.c_int, [C.c_void_p, C.POINTER(SurfaceDesc), C.c_int32, C.c_int32,
                                     C.c_double, C.c_double, C.POINTER(SolveOpts),
@@ -286,6 +288,20 @@ class Hierarchy:
         p = lambda t: None if t is None else C.c_void_p(t.data_ptr())
         _check(_lib.bmg_apply(self._h, C.byref(a), p(x), p(f), p(y), _stream_ptr(stream)), f"bmg_apply({op})")
         return y
+
+
+def gram_am_noalloc(h, u, G, w=None, level=None, stream=None):
+    """bmg_gram_am_noalloc on torch.cuda FP64 tensors: G = [w | u]^T [A u | M u]."""
+    lvl = h.n_levels - 1 if level is None else int(level)
+    m = int(u.shape[-1])
+    m2 = 0 if w is None else int(w.shape[-1])
+    for t in (u, G, w):
+        if t is not None:
+            assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    _check(_lib.bmg_gram_am_noalloc(h._h, lvl, None if w is None else C.c_void_p(w.data_ptr()), m2,
+                                    C.c_void_p(u.data_ptr()), m, C.c_void_p(G.data_ptr()),
+                                    _stream_ptr(stream)), "bmg_gram_am_noalloc")
+    return G
 
 
 def finest_vertices(kind="sphere", n_refine=0, nu=64, nv=32, n_vert=0, n_tri=0):

@@ -15,6 +15,7 @@
 #include <algorithm>
 
 #include <mutex>
+#include <vector>
 
 #include "bmg_internal.h"
 
@@ -520,6 +521,40 @@ int launch_gram_am(const GramPlan& p, const DevLevel& L, const double* w, int w1
   return check_launch();
 }
 
+// ------------------------------------------- allocation-free fused Gram --
+// bmg_gram_am_noalloc keeps the Gram kernel's partial sums in this array
+// instead of a buffer from hipMalloc.  Each device holds its own copy until
+// the process ends; its address on the current device comes from
+// hipGetSymbolAddress (the name itself is a host-side stand-in, not a device
+// address) and is kept per device.  Every partial sum is written before it is
+// read, so nothing needs clearing between calls; calls that overlap on one
+// device share the array and race.
+constexpr size_t kNoallocScratchDoubles = size_t(2) << 20;  // 16 MiB
+static __device__ __align__(256) double scratch[kNoallocScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_ptr;  // by device ordinal
+
+int noalloc_scratch(int dev, double** out) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (int(g_scratch_ptr.size()) <= dev) g_scratch_ptr.resize(size_t(dev) + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      set_error("hipGetSymbolAddress of the scratch array failed on device %d: %s", dev,
+                hipGetErrorString(e));
+      return BMG_EDEVICE;
+    }
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return BMG_OK;
+}
+}  // namespace
+
 int launch_update_zy(int64_t n, const double* z1, int w1, const double* z2, int w2,
                      const double* Y, double* U, int m, hipStream_t s) {
   const int nz = w1 + w2;
@@ -561,3 +596,27 @@ int launch_update_zy(int64_t n, const double* z1, int w1, const double* z2, int 
 }
 
 }  // namespace bmg
+
+extern "C" int bmg_gram_am_noalloc(const bmg_hierarchy* h, int32_t level, const double* w, int32_t m2,
+                                   const double* u, int32_t m, double* G, void* stream) {
+  using namespace bmg;
+  BMG_CHECK(h != nullptr && !h->dev.empty(), "hierarchy with device data required");
+  BMG_CHECK(level >= 0 && level < int(h->dev.size()), "level %d out of range", level);
+  BMG_CHECK(u != nullptr && G != nullptr, "u and G must be non-NULL");
+  BMG_CHECK(m >= 2 && m % 2 == 0 && m2 >= 0 && m2 + m <= 96 && (m2 == 0 || w != nullptr),
+            "gram_am_noalloc needs even m >= 2, 0 <= m2, m2 + m <= 96, and w when m2 > 0");
+  BMG_HIP(hipSetDevice(h->device));
+  double* part = nullptr;
+  BMG_TRY(noalloc_scratch(h->device, &part));
+  const DevLevel& D = h->dev[level];
+  GramPlan p = gram_plan(D.n, m2 + m, 2 * m);
+  // as many row blocks as the planner asks for, while their partial sums fit
+  const size_t per_block = size_t(p.nzp) * p.nyp;
+  if (per_block > kNoallocScratchDoubles) {
+    set_error("gram_am_noalloc: one block's partial sums (%zu doubles) exceed the %zu-double scratch",
+              per_block, kNoallocScratchDoubles);
+    return BMG_EINVAL;
+  }
+  p.nblk = int(std::min<size_t>(size_t(p.nblk), kNoallocScratchDoubles / per_block));
+  return launch_gram_am(p, D, w, m2, u, m, part, G, static_cast<hipStream_t>(stream));
+}

@@ -1,0 +1,56 @@
+"""The allocation-free fused Gram (bmg_gram_am_noalloc) against the allocating
+entry point bmg_apply(BMG_OP_GRAM_AM) and against the plain products, on two
+calls in a row (the second smaller, so it runs on the scratch the first left)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(p, h, level, m2, m, seed):
+    import torch
+    from oracle import bmg as ob
+    rng = np.random.default_rng(seed)
+    n = h.info(level)["n_vert"]
+    W = rng.standard_normal((n, m2)) if m2 else None
+    U = rng.standard_normal((n, m))
+    dW = None if W is None else torch.tensor(W, device="cuda")
+    dU = torch.tensor(U, device="cuda")
+    G0 = torch.full((m2 + m, 2 * m), np.nan, dtype=torch.float64, device="cuda")
+    G1 = torch.full((m2 + m, 2 * m), np.nan, dtype=torch.float64, device="cuda")
+    p.bmg.gram_am_noalloc(h, dU, G0, w=dW, level=level)
+    h.apply("gram_am", x=dW, f=dU, y=G1, m=m, m2=m2, level=level)
+    torch.cuda.synchronize()
+    g0, g1 = G0.cpu().numpy(), G1.cpu().numpy()
+    return W, U, g0, g1
+
+
+def test_noalloc_gram_equals_allocating_entry_point():
+    import torch
+    import paper_1511_07042_amd as p
+    from oracle import bmg as ob
+    lv = ob.build_levels("sphere", 6)
+    with p.Hierarchy("sphere", 6) as h:
+        # a large call first (many row blocks, the partial sums fill most of the
+        # scratch), then a smaller one on another level
+        for level, m2, m, seed in [(6, 12, 80, 1), (4, 0, 8, 2)]:
+            W, U, g0, g1 = _case(p, h, level, m2, m, seed)
+            L = lv[level]
+            Z = U if W is None else np.hstack([W, U])
+            ref = Z.T @ np.hstack([L.A @ U, L.M @ U])
+            scale = np.abs(Z).T @ np.hstack([abs(L.A) @ np.abs(U), abs(L.M) @ np.abs(U)])
+            assert np.all(np.isfinite(g0))
+            assert np.max(np.abs(g0 - g1) / scale) < 1e-14, (level, m2, m)
+            assert np.max(np.abs(g0 - ref) / scale) < 1e-14, (level, m2, m)
+
+
+def test_noalloc_gram_rejects_bad_sizes():
+    import torch
+    import paper_1511_07042_amd as p
+    with p.Hierarchy("sphere", 3) as h:
+        U = torch.zeros((h.N, 90), dtype=torch.float64, device="cuda")
+        W = torch.zeros((h.N, 12), dtype=torch.float64, device="cuda")
+        G = torch.zeros((102, 180), dtype=torch.float64, device="cuda")
+        with pytest.raises(p.BMGError) as e:
+            p.bmg.gram_am_noalloc(h, U, G, w=W)  # m2 + m = 102 > 96
+        assert e.value.status == p.EINVAL
