@@ -3,20 +3,30 @@
 
 A step is one complete solve: the k eigenpairs nearest sigma of the workload's
 finest-level pencil, iterated to the 1e-8 certificate (every row of the cycle:
-residual SpMM, correction V-cycle, Gram, Ritz, update).  The inputs (hierarchy
-and matrices) are resident in HBM before the timed region; the test vectors are
-drawn on the device from the step's seed.  `value` is converged eigenpairs per
-second of the FP32/FP64 mixed path on the sphere refined 6 times (k = 25,
-m = 32); the plain FP64 GPU path is timed beside it.
+residual SpMM, correction V-cycle, Gram, Ritz, update) and written out as
+M-orthonormal eigenvectors in device memory.  The hierarchy and matrices are
+resident in HBM before the timed region; the test vectors are drawn on the
+device from the step's seed (seeds 0..steps-1).  `value` is converged
+eigenpairs per second of the FP32/FP64 mixed path on the largest single-GPU
+workload, the sphere refined 8 times (655362 vertices, k = 64, m = 80); the
+plain FP64 GPU path is timed beside it.
 
 Beside the timed solves the JSON line carries:
-  roofline      the dominant bandwidth-bound kernel of the mixed path, timed with
-                HIP events recorded at its own launches on the solve's stream;
-  breakdown     per kernel class (each timed in an extra solve);
-  c4            the sphere refined 8 times (655362 vertices, k = 64, m = 80),
-                where the sparse kernels are HBM-bound;
-  serving       a seeded request stream through the continuous-batching server;
-  cpu_baseline  the oracle (plain FP64 CPU implementation) on the same workload.
+  per_pair_rel_err  each returned eigenvalue against the stored oracle
+                    eigenvalues of the same pencil (tests/golden);
+  roofline          the kernel class with the largest total time in the mixed
+                    breakdown, timed with HIP events recorded at its own
+                    launches on the solve's stream; roofline_finest_sweep: the
+                    Jacobi sweep on the finest level alone;
+  breakdown         per kernel class (each timed in an extra solve);
+  c3                the ellipsoid (1, 1.5, 2) refined 7 times, the 16 eigenpairs
+                    nearest sigma = 100 (interior-shift scheme);
+  c2                the sphere refined 6 times (k = 25), and 16 of its solves
+                    run concurrently through the serving API;
+  serving           a seeded request stream through the continuous-batching server;
+  cpu_baseline      the oracle (plain FP64 CPU implementation) on the headline
+                    workload: its start and a few cycles timed, the full solve
+                    extrapolated to the GPU's cycle count.
 
 Prints one JSON line.  --gpus N > 1 is refused: the library runs on one GPU.
 """
@@ -54,22 +64,30 @@ TRAFFIC_FILES = {
     ("smooth", "c4_sphere_ref8", "mixed"): "profiles/jacobi_sweep_c4_sphere_ref8_traffic.txt",
 }
 
+# Stored eigenvalues of each workload's pencil (written from the oracle by
+# tests/golden/make_reference_eigs.py): the per-pair error of the timed solves.
+GOLDEN = {"c4_sphere_ref8": "tests/golden/c4_sphere_ref8_eigs.txt",
+          "c3_ellipsoid_ref7_sigma100": "tests/golden/c3_ellipsoid_ref7_eigs.txt",
+          "c2_sphere_ref6": "tests/golden/c2_sphere_ref6_eigs.txt"}
+
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2_sphere_ref6")
+    ap.add_argument("--workload", default="c4_sphere_ref8")
     ap.add_argument("--smoother", default="jacobi", choices=["gs", "jacobi"])
     ap.add_argument("--only", default="both", choices=["both", "mixed", "fp64"])
     ap.add_argument("--timed-kernel", default=None,
                     help="kernel class for the roofline (default: the bandwidth-bound class "
                          "with the largest total time in the mixed breakdown)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-c4", action="store_true", help="skip the 655362-vertex section")
+    ap.add_argument("--no-c3", action="store_true", help="skip the interior-shift section")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 40962-vertex section")
     ap.add_argument("--no-concurrent", action="store_true",
-                    help="skip the 16 concurrent solves through the serving API")
+                    help="skip the 16 concurrent C2 solves through the serving API")
+    ap.add_argument("--no-breakdown", action="store_true", help="skip the per-class breakdown")
     ap.add_argument("--serving", type=int, default=32, metavar="N",
                     help="requests in the serving section (0: skip it)")
     ap.add_argument("--serving-only", action="store_true",
@@ -144,31 +162,48 @@ def roofline(kclass, ms, amount, units, prec="mixed"):
             "per_unit": round(amount / units, 1)}
 
 
-def timed_solves(h, cfg, precision, smoother, steps, warmup, timed_kernel=None):
+def timed_solves(h, cfg, precision, smoother, steps, warmup, timed_kernel=None, evecs="device"):
     """W untimed warm-up solves, then exactly `steps` solves between two device
-    synchronisations.  Returns (seconds, per-solve stats)."""
+    synchronisations, each writing its eigenvectors to device memory.
+    Returns (seconds, per-solve stats, per-solve eigenvalues)."""
     import torch
     kw = dict(m=cfg["m"], nu1=cfg["nu1"], nu2=cfg["nu2"], smoother=smoother, precision=precision,
-              evecs=None, timed_kernel=timed_kernel)
+              evecs=evecs, timed_kernel=timed_kernel)
     for s in range(warmup):
         h.solve(cfg["k"], cfg["sigma"], cfg["tol"], seed=1000 + s, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    stats = []
+    stats, evals = [], []
     for s in range(steps):
-        _, _, st = h.solve(cfg["k"], cfg["sigma"], cfg["tol"], seed=s, **kw)
+        ev, _, st = h.solve(cfg["k"], cfg["sigma"], cfg["tol"], seed=s, **kw)
         assert st["converged"] == 1, st
         stats.append(st)
+        evals.append(ev)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return dt, stats
+    return dt, stats, evals
+
+
+def per_pair_error(name, cfg, evals):
+    """Relative error max(|lambda|, 1) of every returned eigenvalue against the
+    stored oracle eigenvalues (the k nearest sigma among them)."""
+    import numpy as np
+    rel = GOLDEN.get(name)
+    if rel is None or not os.path.exists(os.path.join(ROOT, rel)):
+        return None
+    ref = np.array([float(x) for x in open(os.path.join(ROOT, rel)) if not x.startswith("#")])
+    near = np.sort(ref[np.sort(np.argsort(np.abs(ref - cfg["sigma"]), kind="stable")[:cfg["k"]])])
+    errs = [np.abs(np.asarray(ev) - near) / np.maximum(np.abs(near), 1.0) for ev in evals]
+    return {"max": float(max(e.max() for e in errs)),
+            "seed0": [float("%.3g" % v) for v in errs[0]],
+            "reference": rel, "note": "relative to max(|lambda|, 1); every timed seed checked"}
 
 
 def breakdown(h, cfg, prec, smoother):
     """Every kernel class timed with events in one extra solve (seed 0)."""
     bd = {}
     for kc in KCLASS:
-        _, st = timed_solves(h, cfg, prec, smoother, 1, 0, kc)
+        _, st, _ = timed_solves(h, cfg, prec, smoother, 1, 0, kc, evecs=None)
         r = roofline(kc, st[0]["timed_kernel_ms"], st[0]["timed_kernel_bytes"],
                      st[0]["timed_kernel_units"], prec)
         if r is not None:  # classes fused away in this configuration are absent
@@ -176,9 +211,24 @@ def breakdown(h, cfg, prec, smoother):
     return bd
 
 
-def bench_workload(bmg, name, cfg, precs, steps, warmup, smoother, timed_kernel):
-    """Timed solves of one workload for each precision, the breakdown, and the
-    roofline of the dominant bandwidth-bound kernel."""
+def class_roofline(h, name, cfg, prec, smoother, steps, kc, level=None):
+    """Events around each launch of one kernel class (on one level if given),
+    in solves of the same workload and seeds as the timed region."""
+    tk = kc if level is None else (kc, level)
+    _, tst, _ = timed_solves(h, cfg, prec, smoother, steps, 0, tk, evecs=None)
+    roof = roofline(kc, sum(s["timed_kernel_ms"] for s in tst),
+                    sum(s["timed_kernel_bytes"] for s in tst),
+                    sum(s["timed_kernel_units"] for s in tst), prec)
+    if roof is not None and "frac" in roof:
+        roof["traffic"] = measured_traffic(kc, name, prec, roof["per_unit"]) if level is None else None
+        if level is not None:
+            roof["level"] = level
+    return roof
+
+
+def bench_workload(bmg, name, cfg, precs, steps, warmup, smoother, timed_kernel, with_breakdown=True):
+    """Timed solves of one workload for each precision, the per-pair error, the
+    breakdown, and the roofline of the dominant kernel class."""
     import torch
     t0 = time.perf_counter()
     h = bmg.Hierarchy(cfg["kind"], cfg["n_refine"], axes=cfg["axes"])
@@ -186,59 +236,74 @@ def bench_workload(bmg, name, cfg, precs, steps, warmup, smoother, timed_kernel)
     build_s = time.perf_counter() - t0
     out = {"hierarchy_build_s": round(build_s, 3)}
     for prec in precs:
-        dt, stats = timed_solves(h, cfg, prec, smoother, steps, warmup)
+        dt, stats, evals = timed_solves(h, cfg, prec, smoother, steps, warmup)
         r = dict(value=round(steps * cfg["k"] / dt, 3), ms_per_step=round(1e3 * dt / steps, 3),
                  cycles=[s["cycles"] for s in stats],
                  t_solve_ms=[round(s["t_solve_ms"], 3) for s in stats],
+                 scheme=["", "enriched", "shifted"][stats[0]["scheme"]], l_c=stats[0]["l_c"],
+                 coarse_eig_ms=round(max(s["coarse_eig_ms"] for s in stats), 1),
                  ritz_sweeps_max=max(s["ritz_sweeps_max"] for s in stats),
                  ritz_fallbacks=sum(s["ritz_fallbacks"] for s in stats))
-        r["breakdown"] = breakdown(h, cfg, prec, smoother)
+        r["per_pair_rel_err"] = per_pair_error(name, cfg, evals)
         kc = timed_kernel
+        if with_breakdown:
+            r["breakdown"] = breakdown(h, cfg, prec, smoother)
+            if kc is None:
+                timed = [(v["ms_per_solve"], k) for k, v in r["breakdown"].items()
+                         if v["bound"] in ("hbm", "mfma")]
+                kc = max(timed)[1]
         if kc is None:
-            hbm = [(v["ms_per_solve"], k) for k, v in r["breakdown"].items() if v["bound"] == "hbm"]
-            kc = max(hbm)[1]
-        # the roofline kernel: events around each of its launches, in solves of
-        # the same workload and seeds as the timed region
-        _, tst = timed_solves(h, cfg, prec, smoother, steps, 0, kc)
-        roof = roofline(kc, sum(s["timed_kernel_ms"] for s in tst),
-                        sum(s["timed_kernel_bytes"] for s in tst),
-                        sum(s["timed_kernel_units"] for s in tst), prec)
-        if roof is not None and "frac" in roof:
-            roof["traffic"] = measured_traffic(kc, name, prec, roof["per_unit"])
-        r["roofline"] = roof
+            kc = "smooth"
+        r["roofline"] = class_roofline(h, name, cfg, prec, smoother, steps, kc)
+        if smoother == "jacobi":
+            L = cfg["n_refine"]
+            r["roofline_finest_sweep"] = class_roofline(h, name, cfg, prec, smoother, steps, "smooth", L)
         out[prec] = r
         print(f"# {name} {prec}: {r['value']} eigenpairs/s, {r['ms_per_step']} ms/solve, "
-              f"roofline {roof}", file=sys.stderr, flush=True)
+              f"cycles {r['cycles']}, roofline {r['roofline']}", file=sys.stderr, flush=True)
     h.close()
     return out
 
 
-def cpu_baseline(cfg, smoother, budget_s=10.0, max_solves=4):
-    """The oracle on the host cores: full solves of the same workload (seeds
-    0, 1, ...) until about budget_s seconds of CPU work."""
+def cpu_baseline(cfg, smoother, gpu_cycles, budget_s=20.0, max_solves=4):
+    """The oracle on the host cores, on the headline workload.  Its start
+    (coarse vectors, seeded block, first Ritz step) and one cycle are timed; if
+    a full solve fits budget_s, full solves (seeds 0, 1, ...) are timed instead,
+    else the full solve is extrapolated as start + cycles x cycle time with the
+    GPU's FP64 cycle count for the same seed."""
     import threadpoolctl
     from oracle import bmg as ob
     lv = ob.build_levels(cfg["kind"], cfg["n_refine"], axes=cfg["axes"])
+    kw = dict(m=cfg["m"], nu1=cfg["nu1"], nu2=cfg["nu2"], smoother=smoother)
     t0 = time.perf_counter()
-    n, cycles = 0, []
-    while n < max_solves and (n == 0 or time.perf_counter() - t0 < budget_s):
-        _, _, info = ob.solve(lv, cfg["k"], cfg["sigma"], cfg["tol"], m=cfg["m"], nu1=cfg["nu1"],
-                              nu2=cfg["nu2"], smoother=smoother, seed=n)
-        cycles.append(info["cycles"])
-        n += 1
-    dt = time.perf_counter() - t0
-    # second CPU reference: a library eigensolve of the same pencil (ARPACK
-    # shift-invert with SuperLU), timed once
-    from oracle import reference
-    t1 = time.perf_counter()
-    reference.discrete_eigs(lv[-1].A, lv[-1].M, cfg["k"], cfg["sigma"])
-    eigsh_s = time.perf_counter() - t1
+    ob.solve(lv, cfg["k"], cfg["sigma"], cfg["tol"], seed=0, max_cycles=0, **kw)
+    t_start = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ob.solve(lv, cfg["k"], cfg["sigma"], cfg["tol"], seed=0, max_cycles=1, **kw)
+    t_cycle = max(time.perf_counter() - t0 - t_start, 1e-9)
+    est = t_start + gpu_cycles * t_cycle
     blas = max((p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()), default=1)
-    return dict(value=round(n * cfg["k"] / dt, 4), unit="eigenpairs/s", cores=int(blas), kind="oracle",
-                library_eigsh_s=round(eigsh_s, 3),
-                sample=f"{n} full oracle solves of the same workload, seeds 0..{n - 1} "
-                       f"({cycles} cycles, {dt:.1f} s); dense BLAS on {blas} threads, "
-                       f"scipy.sparse products single-threaded; host os.cpu_count() = {os.cpu_count()}")
+    threads = (f"dense BLAS on {blas} threads, scipy.sparse products single-threaded; "
+               f"host os.cpu_count() = {os.cpu_count()}")
+    if est <= budget_s:
+        t0 = time.perf_counter()
+        n, cycles = 0, []
+        while n < max_solves and (n == 0 or time.perf_counter() - t0 < budget_s):
+            _, _, info = ob.solve(lv, cfg["k"], cfg["sigma"], cfg["tol"], seed=n, **kw)
+            cycles.append(info["cycles"])
+            n += 1
+        dt = time.perf_counter() - t0
+        return dict(value=round(n * cfg["k"] / dt, 4), unit="eigenpairs/s", cores=int(blas),
+                    kind="oracle", extrapolated=False,
+                    sample=f"{n} full oracle solves of the same workload, seeds 0..{n - 1} "
+                           f"({cycles} cycles, {dt:.1f} s); {threads}")
+    return dict(value=round(cfg["k"] / est, 5), unit="eigenpairs/s", cores=int(blas), kind="oracle",
+                extrapolated=True, start_s=round(t_start, 2), cycle_s=round(t_cycle, 2),
+                cycles=int(gpu_cycles),
+                sample=f"the oracle's start (coarse vectors, seeded block, first Ritz step: "
+                       f"{t_start:.1f} s) and one cycle ({t_cycle:.1f} s) on the same workload, seed 0; "
+                       f"the full solve extrapolated to the {gpu_cycles} cycles the GPU's FP64 path "
+                       f"takes for that seed ({est:.0f} s); hierarchy build excluded; {threads}")
 
 
 def _serve(bmg, reqs, slots, budget, timed, smoother):
@@ -333,6 +398,21 @@ def concurrent(bmg, cfg, smoother, n_req=16, slots=8):
                     "serving API (one stream per slot); not the single-solve `value`"}
 
 
+def section(bmg, name, precs, steps, warmup, smoother, with_breakdown=False):
+    """A secondary workload: timed solves and the roofline of its dominant class."""
+    from workloads import CONFIGS
+    cfg = CONFIGS[name]
+    res = bench_workload(bmg, name, cfg, precs, steps, warmup, smoother, None, with_breakdown)
+    mp = "mixed" if "mixed" in res else precs[0]
+    return {"config": {"workload": name, **cfg}, "value": res[mp]["value"], "unit": "eigenpairs/s",
+            "ms_per_step": res[mp]["ms_per_step"], "roofline": res[mp]["roofline"],
+            "per_pair_rel_err_max": (res[mp]["per_pair_rel_err"] or {}).get("max"),
+            "mixed_vs_fp64": (round(res["mixed"]["value"] / res["fp64"]["value"], 3)
+                              if "mixed" in res and "fp64" in res else None),
+            "hierarchy_build_s": res["hierarchy_build_s"],
+            "fp64_path": res.get("fp64"), "mixed_path": res.get("mixed")}
+
+
 def main():
     a = parse()
     if a.copy_calibration:
@@ -351,7 +431,7 @@ def main():
     precs = ["fp64", "mixed"] if a.only == "both" else [a.only]
     cfg = CONFIGS[a.workload]
     main_res = bench_workload(bmg, a.workload, cfg, precs, a.steps, a.warmup, a.smoother,
-                              a.timed_kernel)
+                              a.timed_kernel, not a.no_breakdown)
     mp = "mixed" if "mixed" in main_res else a.only
     out = {
         "metric": "converged eigenpairs/s at 1e-8 rel (FP32/FP64 mixed BMG)",
@@ -367,28 +447,27 @@ def main():
         "dtype": "f32+f64" if mp == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": a.workload, **{k: v for k, v in cfg.items()}, "smoother": a.smoother,
-                   "hierarchy_build_s": main_res["hierarchy_build_s"]},
+                   "hierarchy_build_s": main_res["hierarchy_build_s"],
+                   "evecs": "written to device memory in every timed solve"},
+        "per_pair_rel_err": main_res[mp]["per_pair_rel_err"],
         "roofline": main_res[mp]["roofline"],
+        "roofline_finest_sweep": main_res[mp].get("roofline_finest_sweep"),
         "mixed_vs_fp64": (round(main_res["mixed"]["value"] / main_res["fp64"]["value"], 3)
                           if a.only == "both" else None),
         "fp64_path": main_res.get("fp64"),
         "mixed_path": main_res.get("mixed"),
     }
-    if a.only in ("both", "mixed") and not a.no_concurrent:
-        out["concurrent"] = concurrent(bmg, cfg, a.smoother)
-    if not a.no_c4 and a.workload != "c4_sphere_ref8":
-        c4 = bench_workload(bmg, "c4_sphere_ref8", CONFIGS["c4_sphere_ref8"], precs, 2, 1,
-                            a.smoother, "smooth")
-        out["c4"] = {"config": {"workload": "c4_sphere_ref8", **CONFIGS["c4_sphere_ref8"]},
-                     "value": c4[mp]["value"], "unit": "eigenpairs/s",
-                     "ms_per_step": c4[mp]["ms_per_step"], "roofline": c4[mp]["roofline"],
-                     "mixed_vs_fp64": (round(c4["mixed"]["value"] / c4["fp64"]["value"], 3)
-                                       if a.only == "both" else None),
-                     "fp64_path": c4.get("fp64"), "mixed_path": c4.get("mixed")}
+    if not a.no_c3 and a.workload != "c3_ellipsoid_ref7_sigma100":
+        out["c3"] = section(bmg, "c3_ellipsoid_ref7_sigma100", precs, a.steps, 1, a.smoother)
+    if not a.no_c2 and a.workload != "c2_sphere_ref6":
+        out["c2"] = section(bmg, "c2_sphere_ref6", precs, a.steps, 1, a.smoother)
+        if a.only in ("both", "mixed") and not a.no_concurrent:
+            out["c2"]["concurrent"] = concurrent(bmg, CONFIGS["c2_sphere_ref6"], a.smoother)
     if a.serving > 0:
         out["serving"] = serving(a, bmg)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, a.smoother)
+        fp = main_res.get("fp64") or main_res[mp]
+        out["cpu_baseline"] = cpu_baseline(cfg, a.smoother, fp["cycles"][0])
     print(json.dumps(out), flush=True)
 
 

@@ -148,8 +148,10 @@ typedef enum { BMG_FP64 = 0, BMG_MIXED = 1 } bmg_precision;
  * BMG_SCHEME_SHIFTED: interior shifts (Sec. 5.2, Remark 4.1, Alg. 3 step 4,
  *   Alg. 4 step 1).  All eigenpairs of one coarse level l_c are computed once
  *   per hierarchy (dense, kept with it); l_c is the coarsest level with
- *   N_l >= pi n_W^2 / m, n_W = |Gamma_h| sigma / (4 pi), capped at 12288
- *   vertices (m is then raised when it was not given, at most 96).  The block
+ *   sigma^2 h_max,l^2 |Gamma_h| / m <= 60 (h_max,l its longest edge: its
+ *   eigenvalues near sigma are then within a few block windows of the fine
+ *   ones) and N_l >= 2 m, capped at 12288 vertices (m is then raised when it
+ *   was not given, at most 96).  The block
  *   starts from the m level-l_c eigenvectors nearest the level's shift,
  *   prolongated and relaxed once on the source problem of eq. pb-f-aux-mat;
  *   each level l_c <= l < L of the correction uses A_l - sigma_l M_l with the
@@ -185,7 +187,8 @@ typedef struct {
                          counters 2c, 2c+1 with c = i m + j, Box-Muller */
   const double* initial_block; /* optional host [N_L][m] block replacing the seeded one */
   int32_t timed_kernel; /* bmg_kernel_class to bracket with HIP events on `stream`,
-                           or -1; see bmg_solve_stats */
+                           or -1; see bmg_solve_stats.  class + 256 (l + 1) times
+                           a V-cycle class on level l only */
   int32_t scheme;       /* bmg_scheme (BMG_SCHEME_AUTO) */
 } bmg_solve_opts;
 

@@ -54,13 +54,19 @@ own route to interior eigenvalues instead (Sec. 5.2; Remark 4.1; Alg. 3
 step 4; Alg. 4 step 1):
 
  1. Coarse eigensolve (Alg. 2 step 1, Alg. 4 step 1) of every pair of the
-    level l_c, the coarsest level with N_l >= pi n_W(sigma)^2 / m (the coarse
-    level must place the eigenvalues near sigma, O(sigma^2 |Gamma| / N_l) off,
-    within the window of half-width ~ 2 pi m / |Gamma| that m vectors cover),
-    but at most the finest level with N_l <= 12288 vertices; when that cap
-    binds below level L and m was not given, m is raised to the multiple of 4
-    that meets the rule (at most 96).  When l_c = L the coarse eigensolve is
-    the fine one and the start already returns the exact pairs.
+    level l_c, the coarsest level with sigma^2 h_max^2 |Gamma_h| / m <= 60
+    (h_max its longest edge) and N_l >= 2 m: the coarse level must place the
+    eigenvalues near sigma, O(sigma^2 h^2) off (the a priori estimate of
+    Sec. 2.3), within a fixed multiple of the window of about 2 pi m / |Gamma|
+    that m vectors span around sigma; the constant 60 is a measured reading
+    (the ellipsoid (1, 1.5, 2) at sigma = 40..100 and the 64 x 32 torus grid
+    at sigma = 84..138 converge in 18-41 cycles at values 39-80, weighted
+    Jacobi on the torus grid slows to 127-155 cycles at 79, and the cycle
+    stalls from 156).  At
+    most the finest level with N_l <= 12288 vertices is used; when that cap
+    binds below level L and m was not given, m is raised to meet the rule
+    there (a multiple of 4, at most 96).  When l_c = L the coarse eigensolve
+    is the fine one and the start already returns the exact pairs.
  2. Start (Alg. 2 steps 2-4): the m level-l_c eigenvectors nearest the level's
     shift, prolongated to level L, relaxed once on the source problem of
     eq. (pb-f-aux-mat) with their coarse eigenvalues as Theta, then a
@@ -102,6 +108,9 @@ class LevelOps:
         self.colours = colour.greedy_colouring(self.A)
         self.n = self.A.shape[0]
         self.area = float(fem.triangle_areas(lv.xyz, lv.tri).sum())
+        e = np.concatenate([lv.xyz[lv.tri[:, a]] - lv.xyz[lv.tri[:, b]]
+                            for a, b in ((0, 1), (1, 2), (2, 0))])
+        self.hmax = float(np.sqrt((e * e).sum(axis=1)).max())  # longest edge
 
 
 def build_levels(kind, n_refine, axes=(1.0, 1.0, 1.0)):
@@ -321,24 +330,28 @@ def solve(levels, k, sigma=0.0, tol=1e-8, m=None, nu1=2, nu2=2, smoother="gs",
 MAX_COARSE_EIG_VERTICES = 12288
 
 
+SHIFT_RESOLUTION = 60.0
+
+
 def shifted_coarse_level(levels, sigma, m, m_given=True):
-    """(l_c, m) for the shifted scheme: coarsest l with N_l >= pi n_W^2 / m,
-    capped at the finest level with N_l <= 12288; when the cap binds below the
-    finest level and m was not given, m is raised to meet the rule (multiple
-    of 4, at most 96).  At l_c = L the coarse solve is exact."""
-    n_w = levels[-1].area * max(sigma, 0.0) / (4.0 * math.pi)
-    need = math.pi * n_w * n_w / m
+    """(l_c, m) for the shifted scheme: the coarsest l with
+    sigma^2 h_max,l^2 |Gamma_h| / m <= 60 and N_l >= 2 m, capped at the finest
+    level with N_l <= 12288; when the cap binds below the finest level and m
+    was not given, m is raised to meet the rule there (multiple of 4, at most
+    96 and at most N_cap / 2).  At l_c = L the coarse solve is exact."""
+    area = levels[-1].area
     cap = 0
     for l, lv in enumerate(levels):
         if lv.n <= MAX_COARSE_EIG_VERTICES:
             cap = l
     for l, lv in enumerate(levels):
-        if lv.n >= need:
+        if sigma * sigma * lv.hmax ** 2 * area / m <= SHIFT_RESOLUTION and lv.n >= 2 * m:
             if l <= cap:
                 return l, m
             break
     if not m_given and cap < len(levels) - 1:
-        m = min(96, max(m, 4 * int(math.ceil(math.pi * n_w * n_w / levels[cap].n / 4.0))))
+        want = 4 * int(math.ceil(sigma * sigma * levels[cap].hmax ** 2 * area / SHIFT_RESOLUTION / 4.0))
+        m = min(96, max(m, want), levels[cap].n // 2 // 4 * 4)
     return cap, m
 
 

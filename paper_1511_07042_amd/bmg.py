@@ -236,7 +236,12 @@ class Hierarchy:
         o.precision = PRECISIONS[precision]
         o.max_cycles, o.n_c, o.l_c = int(max_cycles), int(n_c), int(l_c)
         o.omega, o.angle_tol, o.seed = float(omega), float(angle_tol), int(seed)
-        o.timed_kernel = -1 if timed_kernel is None else KERNEL_CLASSES[timed_kernel]
+        if timed_kernel is None:
+            o.timed_kernel = -1
+        elif isinstance(timed_kernel, tuple):  # (class, level): that level's launches only
+            o.timed_kernel = KERNEL_CLASSES[timed_kernel[0]] + 256 * (int(timed_kernel[1]) + 1)
+        else:
+            o.timed_kernel = KERNEL_CLASSES[timed_kernel]
         o.scheme = SCHEMES[scheme]
         keep = None
         if initial_block is not None:

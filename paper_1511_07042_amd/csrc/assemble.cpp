@@ -56,6 +56,7 @@ int assemble_level(HostLevel& lv, const HostLevel* coarser) {
     return size_t(-1);
   };
   lv.area = 0.0;
+  lv.hmax = 0.0;
   for (int64_t t = 0; t < nt; ++t) {
     const int32_t v[3] = {lv.tri[3 * t], lv.tri[3 * t + 1], lv.tri[3 * t + 2]};
     double x[3][3];
@@ -72,6 +73,8 @@ int assemble_level(HostLevel& lv, const HostLevel* coarser) {
       u[k] = x[1][k] - x[0][k];
       w[k] = x[2][k] - x[0][k];
     }
+    for (int i = 0; i < 3; ++i)
+      lv.hmax = std::max(lv.hmax, std::sqrt(e[i][0] * e[i][0] + e[i][1] * e[i][1] + e[i][2] * e[i][2]));
     double cr[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
     const double area = 0.5 * std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
     BMG_CHECK(area > 0 && std::isfinite(area), "degenerate triangle %lld", (long long)t);

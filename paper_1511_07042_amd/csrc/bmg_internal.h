@@ -61,6 +61,7 @@ struct HostLevel {
   int32_t RW = 0;                    // children per coarse vertex (restriction gather width)
   std::vector<int32_t> rtab;         // [n_prev][RW] new vertices adjacent to coarse vertex i, -1 pad
   double area = 0.0;
+  double hmax = 0.0;                 // longest edge
   int64_t nnz = 0;
 };
 

@@ -124,53 +124,22 @@ int64_t workspace_estimate(const bmg_surface_desc& d, int n_refine, int m, int n
   return b + 2 * (1 << 20);
 }
 
-// An upper bound of the surface area |Gamma_h| (vertices lie on Gamma):
-// 4 pi a_max^2 for the sphere and ellipsoid, 4 pi^2 R r (with 5% margin for
-// the polyhedral torus); for a custom mesh, twice its coarse area.
-double area_bound(const bmg_surface_desc& d, const std::vector<double>& xyz,
-                  const std::vector<int32_t>& tri) {
-  if (d.kind == BMG_SPHERE) return 4.0 * M_PI;
-  if (d.kind == BMG_ELLIPSOID) {
-    const double a = std::max({d.axes[0], d.axes[1], d.axes[2]});
-    return 4.0 * M_PI * a * a;
-  }
-  if (d.kind == BMG_TORUS) return 1.05 * 4.0 * M_PI * M_PI * d.R * d.r;
-  double area = 0.0;
-  for (size_t t = 0; t + 2 < tri.size(); t += 3) {
-    const double* p0 = &xyz[3 * size_t(tri[t])];
-    const double* p1 = &xyz[3 * size_t(tri[t + 1])];
-    const double* p2 = &xyz[3 * size_t(tri[t + 2])];
-    const double u[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
-    const double v[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
-    const double c[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
-    area += 0.5 * std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
-  }
-  return 2.0 * area;
-}
-
 // Device bytes the interior-shift scheme adds for a request: the dense
 // eigendecomposition of its coarse level (FP64 and FP32 eigenvectors, kept
-// with the hierarchy) and the coarse solve's scratch.  The level and block
-// width follow the solver's rule (pi n_W^2 / m, at most kLevelEigMax
-// vertices, m raised when not given) with the area bound above, so they are
-// at least the solver's.  *m_est receives the block width.
-int64_t shifted_estimate(const bmg_surface_desc& d, int n_refine, double sigma, int m,
-                         bool m_given, int prec, double area, int* m_est) {
+// with the hierarchy) and the coarse solve's scratch.  The solver picks the
+// level from the meshes' edge lengths, which are not known before the build,
+// so this bound takes the finest level it may use (at most kLevelEigMax
+// vertices) and, when m was not given, the widest block (96, or half that
+// level's vertices).  *m_est receives the block width.
+int64_t shifted_estimate(const bmg_surface_desc& d, int n_refine, int m, bool m_given, int prec,
+                         int* m_est) {
   const std::vector<int64_t> lv = level_vertices(d, n_refine);
-  const double nw = area * std::max(sigma, 0.0) / (4.0 * M_PI);
   int cap = 0;
   for (size_t l = 0; l < lv.size(); ++l)
     if (lv[l] <= bmg::kLevelEigMax) cap = int(l);
-  int lc = cap;
-  for (size_t l = 0; l < lv.size(); ++l)
-    if (double(lv[l]) >= M_PI * nw * nw / m) {
-      lc = std::min(int(l), cap);
-      break;
-    }
-  if (!m_given && lc == cap && cap < int(lv.size()) - 1 && double(lv[cap]) < M_PI * nw * nw / m)
-    m = std::min(96, std::max(m, 4 * int(std::ceil(M_PI * nw * nw / double(lv[cap]) / 4.0))));
+  const int64_t n = lv[cap];
+  if (!m_given && cap < int(lv.size()) - 1) m = std::max(m, int(std::min<int64_t>(96, n / 2 / 4 * 4)));
   *m_est = m;
-  const int64_t n = lv[lc];
   const int64_t vb = prec == BMG_MIXED ? 4 : 8;
   return 12 * n * n + 8 * n + vb * n * (1 + int64_t(m) * (1 + bmg::spec_slices(int(n))));
 }
@@ -451,8 +420,7 @@ int bmg_server_submit(bmg_server* s, const bmg_surface_desc* desc, int32_t n_ref
   r->hier = hierarchy_estimate(r->desc, n_refine);
   int64_t extra = 0;
   if (shifted)
-    extra = shifted_estimate(r->desc, n_refine, sigma, m_est, r->opts.m > 0, r->opts.precision,
-                             area_bound(r->desc, r->xyz, r->tri), &m_est);
+    extra = shifted_estimate(r->desc, n_refine, m_est, r->opts.m > 0, r->opts.precision, &m_est);
   r->need = workspace_estimate(r->desc, n_refine, m_est, n_c, r->opts.precision) + extra;
   BMG_CHECK(m_est >= k && int64_t(m_est) <= r->n_est / 2, "m must be in [k, N_L / 2]");
   std::lock_guard<std::mutex> g(s->mu);

@@ -251,6 +251,7 @@ void trim_idle_workspaces(bmg_hierarchy* h) {
 // synchronisation of the solve.
 struct KTimer {
   int which = -1;
+  int level = -1;  // time only launches on this level (-1: every level)
   hipStream_t s = nullptr;
   std::vector<hipEvent_t> ev;
   size_t used = 0;
@@ -486,7 +487,8 @@ struct Cycle {
     return BMG_OK;
   }
 
-  int kclass(int k) const { return kt ? k : -2; }
+  // the class to time for a launch on level l (-2: not timed)
+  int kclass(int k, int l) const { return kt && (kt->level < 0 || kt->level == l) ? k : -2; }
 
   // last: the cycle's final post-sweep on its top level, which (Jacobi, with
   // add_u set) adds its result to add_u instead of writing e[l]
@@ -496,7 +498,7 @@ struct Cycle {
     const double b = sizeof(T), n = double(D.n);
     if (c.smoother == BMG_SMOOTH_JACOBI) {
       const bool fold = last && !from_zero && add_u != nullptr && l == add_level;
-      const int kc = from_zero ? -2 : kclass(fold ? BMG_K_SMOOTH_ADD : BMG_K_SMOOTH);
+      const int kc = from_zero ? -2 : kclass(fold ? BMG_K_SMOOTH_ADD : BMG_K_SMOOTH, l);
       if (kt)
         kt->add(kc, fold ? (4 + b) * double(H.nnz) + 2 * b * n * c.m + 16.0 * n * c.m
                          : (4 + b) * double(H.nnz) + 3 * b * n * c.m, 1);
@@ -510,7 +512,7 @@ struct Cycle {
       return BMG_OK;
     }
     if (from_zero) BMG_TRY(launch_fill<T>(e[l], D.n * c.m, T(0), s));
-    const int kc = kclass(BMG_K_SMOOTH);
+    const int kc = kclass(BMG_K_SMOOTH, l);
     for (int k = 0; k < D.n_colours; ++k) {
       const int col = forward ? k : D.n_colours - 1 - k;
       const double nk = double(H.colour_ptr[col + 1] - H.colour_ptr[col]);
@@ -553,7 +555,7 @@ struct Cycle {
                       double(D.n) * c.m * b <= kFuseMaxBlock;
     int k0 = 0;
     if (fuse && c.nu1 >= 2) {
-      const int kc = kclass(BMG_K_SMOOTH_PAIR);
+      const int kc = kclass(BMG_K_SMOOTH_PAIR, l);
       if (kt) kt->add(kc, (4 + b) * nnz + 2 * b * n * c.m, 1);
       if (kt) BMG_TRY(kt->begin(kc));
       // reads only f, so it writes the iterate in place (no buffer swap)
@@ -564,18 +566,18 @@ struct Cycle {
     for (int k = k0; k < c.nu1; ++k) BMG_TRY(sweep(l, true, k == 0));
     if (c.nu1 == 0) BMG_TRY(launch_fill<T>(e[l], D.n * c.m, T(0), s));
     if (fuse) {
-      const int kc = kclass(BMG_K_RESTRICT_RES);
+      const int kc = kclass(BMG_K_RESTRICT_RES, l);
       if (kt) kt->add(kc, (4 + b) * nnz + 2 * b * n * c.m + b * nc * c.m + 4.0 * nc * D.RW, 1);
       if (kt) BMG_TRY(kt->begin(kc));
       BMG_TRY(launch_resrestrict<T>(D, S[l], e[l], f[l], f[l - 1], c.m, s));
       if (kt) BMG_TRY(kt->end(kc));
     } else {
-      int kc = kclass(BMG_K_RESIDUAL);
+      int kc = kclass(BMG_K_RESIDUAL, l);
       if (kt) kt->add(kc, (4 + b) * nnz + 3 * b * n * c.m, 1);
       if (kt) BMG_TRY(kt->begin(kc));
       BMG_TRY(launch_shifted<T>(D, S[l], ROW_RESIDUAL, e[l], f[l], t[l], c.m, s));
       if (kt) BMG_TRY(kt->end(kc));
-      kc = kclass(BMG_K_RESTRICT);
+      kc = kclass(BMG_K_RESTRICT, l);
       if (kt) kt->add(kc, b * n * c.m + b * nc * c.m + 4.0 * nc * D.RW, 1);
       if (kt) BMG_TRY(kt->begin(kc));
       BMG_TRY(launch_restrict<T>(D, t[l], f[l - 1], c.m, s));
@@ -583,7 +585,7 @@ struct Cycle {
     }
     BMG_TRY(vcycle(l - 1));
     if (fuse && c.nu2 >= 1) {
-      const int kc = kclass(BMG_K_PROLONG_SMOOTH);
+      const int kc = kclass(BMG_K_PROLONG_SMOOTH, l);
       if (kt) kt->add(kc, (4 + b) * nnz + 3 * b * n * c.m + b * nc * c.m + 8.0 * (n - nc), 1);
       if (kt) BMG_TRY(kt->begin(kc));
       BMG_TRY(launch_prolong_jacobi<T>(D, S[l], c.omega, e[l], e[l - 1], f[l], t[l], c.m, s));
@@ -592,7 +594,7 @@ struct Cycle {
       for (int k = 1; k < c.nu2; ++k) BMG_TRY(sweep(l, false, false, k == c.nu2 - 1));
       return BMG_OK;
     }
-    const int kc = kclass(BMG_K_PROLONG);
+    const int kc = kclass(BMG_K_PROLONG, l);
     if (kt) kt->add(kc, b * nc * c.m + 2 * b * n * c.m + 8.0 * (n - nc), 1);
     if (kt) BMG_TRY(kt->begin(kc));
     BMG_TRY(launch_prolong_add<T>(D, e[l - 1], e[l], c.m, s));
@@ -651,32 +653,43 @@ int default_block_width(int k, double sigma) {
 
 int default_coarse_vectors(const bmg_hierarchy* h) { return int(std::min<int64_t>(h->n0, 32)) & ~1; }
 
-// Coarse level of the interior-shift scheme: the coarsest l with
-// N_l >= pi n_W(sigma)^2 / m, n_W = |Gamma_h| sigma / (4 pi) the Weyl count of
-// eigenvalues below sigma.  The P1 eigenvalues near sigma on level l are off
-// by O(sigma^2 h_l^2) ~ sigma^2 |Gamma| / N_l (Sec. 2.3), and a block of m
-// vectors spans a window of half-width ~ 2 pi m / |Gamma| about sigma; the
-// level must place the eigenvalues within a fraction of that window, which
-// gives N_l ~ n_W^2 / m (the constant pi was measured on the ellipsoid
-// (1, 1.5, 2) at sigma = 50 and 100).  Levels above kLevelEigMax vertices are
-// not eigendecomposed: if the rule needs one, the finest level within the
-// cap is used and, when m was not given, m is raised to meet the rule
-// (a multiple of 4, at most 96).
+// Coarse level of the interior-shift scheme.  The P1 eigenvalue error of an
+// eigenfunction near sigma on level l is O(sigma^2 h^2) (the a priori estimate
+// of Sec. 2.3) with h the mesh size along it, and a block of m vectors spans a
+// window of about 2 pi m / |Gamma_h| around sigma; the coarse solve must place
+// the eigenvalues near sigma within a fixed multiple of that window.  With the
+// longest edge h_max,l (which bounds the spread over directions on stretched
+// grids such as the torus's) the rule is: the coarsest l with
+//   sigma^2 h_max,l^2 |Gamma_h| / m <= 60   and   N_l >= 2 m
+// (the level must hold twice the start block's eigenpairs).  The constant was
+// measured: the ellipsoid (1, 1.5, 2) at sigma = 40..100 and the 64 x 32 torus
+// grid at sigma = 84..138 converge in 18-41 cycles at values 39-80, weighted
+// Jacobi on the torus grid slows to 127-155 cycles at 79, and the cycle
+// stalls at 156 and above.  Levels above kLevelEigMax vertices are not
+// eigendecomposed: if the rule needs one, the finest level within the cap is
+// used and, when m was not given, m is raised to meet the rule there (a
+// multiple of 4, at most 96).
+constexpr double kShiftResolution = 60.0;
+
 int shifted_coarse_level(const bmg_hierarchy* h, double sigma, int& m, bool m_given) {
   const int nl = int(h->host.size());
-  const double nw = h->host[nl - 1].area * std::max(sigma, 0.0) / (4.0 * M_PI);
-  const double need = M_PI * nw * nw / m;
+  const double area = h->host[nl - 1].area;
+  auto q = [&](int l, int mm) {
+    const double hm = h->host[l].hmax;
+    return sigma * sigma * hm * hm * area / mm;
+  };
   int cap = 0;
   for (int l = 0; l < nl; ++l)
     if (h->host[l].n <= kLevelEigMax) cap = l;
   for (int l = 0; l < nl; ++l)
-    if (double(h->host[l].n) >= need) {
+    if (q(l, m) <= kShiftResolution && h->host[l].n >= 2 * m) {
       if (l <= cap) return l;
       break;
     }
   if (!m_given && cap < nl - 1) {
-    const int want = 4 * int(std::ceil(M_PI * nw * nw / double(h->host[cap].n) / 4.0));
-    m = std::min(96, std::max(m, want));
+    const double hm = h->host[cap].hmax;
+    const int want = 4 * int(std::ceil(sigma * sigma * hm * hm * area / kShiftResolution / 4.0));
+    m = std::min({96, std::max(m, want), int(h->host[cap].n / 2) / 4 * 4});
   }
   return cap;
 }
@@ -803,7 +816,9 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     BMG_TRY(launch_gaussian(w->U, N, m, o.seed, s));
 
   KTimer kt;
-  kt.which = o.timed_kernel;
+  // timed_kernel = class, or class + 256 (l + 1) for the launches on level l only
+  kt.which = o.timed_kernel < 0 ? -1 : (o.timed_kernel & 255);
+  kt.level = o.timed_kernel < 0 ? -1 : (o.timed_kernel >> 8) - 1;
   kt.s = s;
   const double nnzL = double(h->host[L].nnz), Nd = double(N);
   int ritz_sweeps_max = 0, ritz_fallbacks = 0;
@@ -883,6 +898,7 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   std::vector<int> csel;
   auto start = [&](double off) -> int {
     csel = nearest(lce->lam, sigma + off, m);
+    BMG_CHECK(int(csel.size()) == m, "level %d has fewer than m = %d eigenpairs", l_c, m);
     std::sort(csel.begin(), csel.end());
     for (int j = 0; j < m; ++j) theta0[j] = lce->lam[csel[j]] - off;
     BMG_HIP(hipMemcpyAsync(w->csel, csel.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
@@ -1146,9 +1162,12 @@ int solve(bmg_hierarchy* h, int k, double sigma, double tol, const bmg_solve_opt
   BMG_CHECK(o.angle_tol > 0, "angle_tol must be positive");
   BMG_CHECK(evecs == nullptr || ld >= N, "ld must be >= N_L");
   BMG_CHECK(l_c >= 0 && l_c < nl, "l_c out of range");
-  if (shifted)
+  if (shifted) {
     BMG_CHECK(h->host[l_c].n <= kLevelEigMax, "l_c = %d has %lld vertices; the interior scheme's dense "
               "eigensolve takes at most %d", l_c, (long long)h->host[l_c].n, kLevelEigMax);
+    BMG_CHECK(h->host[l_c].n >= o.m, "l_c = %d has %lld vertices, fewer than the m = %d start vectors",
+              l_c, (long long)h->host[l_c].n, o.m);
+  }
   BMG_HIP(hipSetDevice(h->device));
   const LevelEig* lce = nullptr;
   if (shifted) BMG_TRY(level_eig(h, l_c, static_cast<hipStream_t>(stream), &lce));

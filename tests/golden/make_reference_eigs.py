@@ -4,7 +4,7 @@ Calls only the oracle: the hierarchy and P1 matrices of oracle.bmg and the
 library eigensolver wrapper oracle.reference.discrete_eigs (ARPACK
 shift-invert), and for interior shifts the oracle's own BMG solve, whose
 cycle count and largest deviation from ARPACK go into the file's header.
-Usage:  python tests/golden/make_reference_eigs.py c4|c3
+Usage:  python tests/golden/make_reference_eigs.py c4|c3|c2
 """
 import os
 import sys
@@ -21,6 +21,7 @@ CASES = {
     # name: (surface, axes, n_refine, count, sigma)
     "c4": ("sphere", (1.0, 1.0, 1.0), 8, 80, 0.0),
     "c3": ("ellipsoid", (1.0, 1.5, 2.0), 7, 40, 100.0),
+    "c2": ("sphere", (1.0, 1.0, 1.0), 6, 40, 0.0),
 }
 
 

@@ -22,7 +22,7 @@ REQUESTS = [
     dict(kind="sphere", n_refine=5, k=25, sigma=0.0, m=32, precision="mixed", smoother="jacobi", seed=6),
     # interior shifts (the shifted scheme) on the three surfaces, and a torus at sigma = 0
     dict(kind="torus", n_refine=1, k=12, sigma=60.0, precision="mixed", smoother="jacobi", seed=7),
-    dict(kind="ellipsoid", n_refine=5, k=16, sigma=50.0, axes=(1.0, 1.5, 2.0), precision="mixed",
+    dict(kind="ellipsoid", n_refine=5, k=16, sigma=40.0, axes=(1.0, 1.5, 2.0), precision="mixed",
          smoother="jacobi", seed=8),
     dict(kind="torus", n_refine=1, k=8, sigma=0.0, precision="fp64", smoother="gs", seed=9),
     dict(kind="sphere", n_refine=4, k=10, sigma=150.0, precision="fp64", smoother="jacobi", seed=10),

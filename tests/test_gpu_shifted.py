@@ -4,7 +4,7 @@ Kernels: the coarse spectral solve and the adaptive-shift offsets, element by
 element against oracle/bmg.py.  Solves: C3 (ellipsoid (1, 1.5, 2) refined 7
 times, the 16 eigenpairs nearest sigma = 100, 24 vectors) in both precisions
 against ARPACK shift-invert on the oracle's pencil and the stored oracle
-eigenvalues; the 5-refinement ellipsoid at sigma = 50 against the oracle's own
+eigenvalues; the 5-refinement ellipsoid at sigma = 40 against the oracle's own
 shifted BMG (pairs, cycle counts, final adaptive shift); a coarse level equal
 to the finest (exact start).
 """
@@ -138,19 +138,19 @@ def test_c3_parity(lib, c3, precision, smoother):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_ellipsoid_sigma50_against_oracle_bmg(lib, ell, precision):
+def test_ellipsoid_sigma40_against_oracle_bmg(lib, ell, precision):
     from oracle import bmg as ob
     h, lv = ell
-    oev, oU, info = ob.solve(lv, 16, 50.0, 1e-8, m=24, smoother="jacobi", omega=0.85)
+    oev, oU, info = ob.solve(lv, 16, 40.0, 1e-8, m=24, smoother="jacobi", omega=0.85)
     assert info["converged"]
-    ev, U, st = h.solve(16, 50.0, 1e-8, m=24, precision=precision, smoother="jacobi")
+    ev, U, st = h.solve(16, 40.0, 1e-8, m=24, precision=precision, smoother="jacobi")
     assert st["converged"] == 1 and st["l_c"] == info["l_c"] == 4
     from oracle import reference
     rel, sine = reference.compare(ev, U, oev, oU, lv[-1].M)
     assert rel < 1e-8 and sine < 1e-6
     assert abs(st["cycles"] - info["cycles"]) <= (0 if precision == "fp64" else 3), (st["cycles"], info["cycles"])
     # the adaptive shift of level l_c in the last cycle: the same block gives the same shift
-    assert abs(st["lc_shift"] - (50.0 + info["offsets"][4])) < (1e-8 if precision == "fp64" else 1e-5)
+    assert abs(st["lc_shift"] - (40.0 + info["offsets"][4])) < (1e-8 if precision == "fp64" else 1e-5)
 
 
 def test_coarse_level_equal_to_finest_is_exact(lib):
@@ -161,6 +161,21 @@ def test_coarse_level_equal_to_finest_is_exact(lib):
         ev, U, st = h.solve(16, 100.0, 1e-8, precision="mixed", smoother="jacobi")
         assert st["converged"] == 1 and st["cycles"] == 0 and st["l_c"] == 1
         _check_pairs(ev, U, lv[-1].M, ref_ev, ref_U, 100.0, 16, rel_tol=1e-12, sine_tol=1e-9)
+
+
+def test_small_shift_wide_block_uses_a_level_with_2m_pairs(lib):
+    # sigma = 12 with k = 30 (m = 48): the Weyl rule alone would pick the
+    # 12-vertex level, which holds fewer eigenpairs than the start block needs
+    from oracle import bmg as ob, reference
+    lv = ob.build_levels("sphere", 3)
+    ref_ev, ref_U = reference.discrete_eigs(lv[-1].A, lv[-1].M, 60, 12.0)
+    with lib.Hierarchy("sphere", 3) as h:
+        ev, U, st = h.solve(30, 12.0, 1e-8, precision="mixed", smoother="jacobi")
+        assert st["converged"] == 1 and st["m"] == 48 and st["l_c"] == 2
+        _check_pairs(ev, U, lv[-1].M, ref_ev, ref_U, 12.0, 30)
+        with pytest.raises(lib.BMGError) as e:  # an explicit level with fewer than m vertices
+            h.solve(30, 12.0, 1e-8, l_c=0)
+        assert e.value.status == lib.EINVAL
 
 
 @pytest.mark.parametrize("scheme", ["shifted", "enriched"])

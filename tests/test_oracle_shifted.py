@@ -28,13 +28,13 @@ def ell5():
 
 
 @pytest.mark.parametrize("smoother", ["jacobi", "gs"])
-def test_ellipsoid_ref5_sigma50_matches_arpack(ell5, smoother):
-    # 16 pairs nearest 50 on the 10242-vertex ellipsoid (about 111 eigenvalues below sigma)
+def test_ellipsoid_ref5_sigma40_matches_arpack(ell5, smoother):
+    # 16 pairs nearest 40 on the 10242-vertex ellipsoid (about 89 eigenvalues below sigma)
     lv = ell5[-1]
-    ev, U, info = bmg.solve(ell5, 16, 50.0, 1e-8, m=24, smoother=smoother)
+    ev, U, info = bmg.solve(ell5, 16, 40.0, 1e-8, m=24, smoother=smoother)
     assert info["converged"] and info["scheme"] == "shifted" and info["l_c"] == 4
-    ref_ev, ref_U = reference.discrete_eigs(lv.A, lv.M, 24, 50.0)
-    idx = _nearest(ref_ev, 50.0, 16)
+    ref_ev, ref_U = reference.discrete_eigs(lv.A, lv.M, 24, 40.0)
+    idx = _nearest(ref_ev, 40.0, 16)
     rel, sine = reference.compare(ev, U, ref_ev[idx], ref_U[:, idx], lv.M, ref_ev, ref_U)
     assert rel < 1e-9 and sine < 1e-6
     assert np.abs(U.T @ (lv.M @ U) - np.eye(16)).max() < 1e-12
@@ -47,7 +47,7 @@ def test_ellipsoid_ref5_sigma50_matches_arpack(ell5, smoother):
 def test_without_adaptive_shift_the_fixed_shift_cycle_stalls(ell5):
     # the same problem with the fixed-shift enriched scheme does not reach the
     # certificate: the reason the shifted scheme exists
-    ev, U, info = bmg.solve(ell5, 16, 50.0, 1e-8, m=24, smoother="jacobi", scheme="enriched",
+    ev, U, info = bmg.solve(ell5, 16, 40.0, 1e-8, m=24, smoother="jacobi", scheme="enriched",
                             max_cycles=40)
     assert not info["converged"]
 
@@ -129,23 +129,41 @@ def test_injected_rayleigh_offsets_converge_at_h2():
 
 @pytest.mark.parametrize("kind,nref,axes,sigma,m,want", [
     ("ellipsoid", 7, (1.0, 1.5, 2.0), 100.0, 24, (5, 24)),   # C3
-    ("ellipsoid", 5, (1.0, 1.5, 2.0), 50.0, 24, (4, 24)),
+    ("ellipsoid", 5, (1.0, 1.5, 2.0), 40.0, 24, (4, 24)),
+    ("ellipsoid", 5, (1.0, 1.5, 2.0), 50.0, 24, (5, 24)),   # level 4 is too coarse at 50: l_c = L
     ("sphere", 4, (1.0, 1.0, 1.0), 6.0, 8, (1, 8)),
+    # a small shift with a wide block: the level must hold 2 m eigenpairs (162 >= 96)
+    ("sphere", 3, (1.0, 1.0, 1.0), 12.0, 48, (2, 48)),
+    # the stretched torus grid needs a finer coarse level than its vertex count suggests
+    ("torus", 2, (1.0, 1.0, 1.0), 138.0, 48, (1, 48)),
 ])
 def test_shifted_coarse_level_rule(kind, nref, axes, sigma, m, want):
     levels = bmg.build_levels(kind, nref, axes=axes)
-    nw = levels[-1].area * sigma / (4 * math.pi)
+    area = levels[-1].area
     lc, mm = bmg.shifted_coarse_level(levels, sigma, m, m_given=True)
     assert (lc, mm) == want
-    assert levels[lc].n >= math.pi * nw * nw / m and (lc == 0 or levels[lc - 1].n < math.pi * nw * nw / m)
+
+    def ok(l):
+        return sigma ** 2 * levels[l].hmax ** 2 * area / m <= 60.0 and levels[l].n >= 2 * m
+    capped = levels[lc].n <= 12288 and (lc + 1 == len(levels) or levels[lc + 1].n > 12288)
+    assert (ok(lc) or capped) and all(not ok(l) for l in range(lc))
+
+
+def test_longest_edge_halves_per_level():
+    # h_max of the sphere hierarchy: the icosahedron edge 4 / sqrt(10 + 2 sqrt(5))
+    # on level 0, then about half per refinement (midpoints lifted to the sphere)
+    levels = bmg.build_levels("sphere", 4)
+    assert abs(levels[0].hmax - 4.0 / math.sqrt(10.0 + 2.0 * math.sqrt(5.0))) < 1e-14
+    for a, b in zip(levels[:-1], levels[1:]):
+        assert 0.45 < b.hmax / a.hmax < 0.6
 
 
 def test_shifted_coarse_level_cap_raises_m():
     # torus refined twice (32768 vertices > the 12288 cap) at sigma = 200 with
     # m = 8: the rule wants level 2, the cap gives level 1 (8192 vertices) and
-    # a block of 4 ceil(pi n_W^2 / 8192 / 4) vectors
+    # a block of 4 ceil(sigma^2 h_max^2 |Gamma| / 60 / 4) vectors there
     levels = bmg.build_levels("torus", 2)
-    nw = levels[-1].area * 200.0 / (4 * math.pi)
+    want = 4 * math.ceil(200.0 ** 2 * levels[1].hmax ** 2 * levels[-1].area / 60.0 / 4)
     lc, m = bmg.shifted_coarse_level(levels, 200.0, 8, m_given=False)
-    assert lc == 1 and m == 4 * math.ceil(math.pi * nw * nw / 8192 / 4)
+    assert lc == 1 and m == want and 8 < m <= 96
     assert bmg.shifted_coarse_level(levels, 200.0, 8, m_given=True) == (1, 8)
