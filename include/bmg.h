@@ -190,6 +190,22 @@ typedef struct {
                            or -1; see bmg_solve_stats.  class + 256 (l + 1) times
                            a V-cycle class on level l only */
   int32_t scheme;       /* bmg_scheme (BMG_SCHEME_AUTO) */
+  /* Level ramp (BFMG, Alg. 4): with ramp_cycles > 0 the solve starts on level
+   * l0 from that level's exact eigenpairs nearest sigma (Alg. 4 step 1; all
+   * its pairs are computed once per hierarchy and level, at most 12288
+   * vertices) and visits every level l0 < l < L with the block prolongated
+   * from the level below, a Rayleigh-Ritz step and ramp_cycles cycles of that
+   * level's own BMG cycle (its finest level is l), before continuing on level L
+   * as usual (max_cycles, certificate).  The k values nearest sigma after each
+   * level go to stats->ramp_evals.  With max_cycles = ramp_cycles this is the
+   * one-pass BFMG of the paper's Table 1 (every level gets the same number
+   * of cycles; the solve then ends with BMG_ENOCONV unless the certificate
+   * held).  ramp_level: l0 in [l_c, L], or -1 for the coarsest level at or
+   * above l_c with at least 2 m vertices (BMG_EINVAL outside that range or
+   * above 12288 vertices).  ramp_cycles at most 64.  seed and initial_block
+   * are not used by a ramp; the Ritz warm start is off during the ramp. */
+  int32_t ramp_cycles;  /* 0 */
+  int32_t ramp_level;   /* -1 */
 } bmg_solve_opts;
 
 /* Kernel classes that bmg_solve can time.  EIGRES, SPMM_AM, GRAM, UPDATE and
@@ -257,6 +273,12 @@ typedef struct {
   double coarse_eig_ms;       /* SHIFTED: wall time of the level-l_c eigensolve when it
                                  was built (never part of t_solve_ms) */
   double lc_shift;            /* SHIFTED: final adaptive shift of level l_c; else sigma */
+  double* ramp_evals;         /* nullable host [n_levels][k]: with a level ramp, row l holds
+                                 the k eigenvalue approximations nearest sigma (ascending)
+                                 after level l (l0 <= l < L) and row L the returned ones;
+                                 rows below l0 are not written */
+  int32_t ramp_start;         /* l0 of the ramp, or -1 */
+  int32_t reserved3;
 } bmg_solve_stats;
 
 /* The k eigenpairs of (A_L, M_L) nearest sigma on the finest level L.

@@ -46,7 +46,7 @@ coarse grid cannot represent into [2/3, 3/2], whose best damping weight is
 
 Interior shifts (sigma > 0; scheme "shifted").  The fixed-shift cycle above
 stalls when sigma lies inside the spectrum: coarse levels misplace the
-eigenvalues near sigma by O(sigma^2 h_l^2) (the a priori estimate of Sec. 2.3),
+eigenvalues near sigma by O(sigma^2 h_l^2) (the a priori estimate of Sec. 2.2, Lemma 2.2),
 so the coarse correction acts like shift-and-invert about a wrong shift, and
 prolongated coarse eigenvectors kept in the Ritz space add Ritz values with
 large residuals right next to sigma.  The shifted scheme follows the paper's
@@ -57,7 +57,7 @@ step 4; Alg. 4 step 1):
     level l_c, the coarsest level with sigma^2 h_max^2 |Gamma_h| / m <= 60
     (h_max its longest edge) and N_l >= 2 m: the coarse level must place the
     eigenvalues near sigma, O(sigma^2 h^2) off (the a priori estimate of
-    Sec. 2.3), within a fixed multiple of the window of about 2 pi m / |Gamma|
+    Sec. 2.2, Lemma 2.2), within a fixed multiple of the window of about 2 pi m / |Gamma|
     that m vectors span around sigma; the constant 60 is a measured reading
     (the ellipsoid (1, 1.5, 2) at sigma = 40..100 and the 64 x 32 torus grid
     at sigma = 84..138 converge in 18-41 cycles at values 39-80, weighted
@@ -86,6 +86,21 @@ step 4; Alg. 4 step 1):
     shifts, the truncated spectral inverse of A_{l_c} - sigma_{l_c} M_{l_c}
     as the coarse solve, and the Rayleigh-Ritz step in the span of the block
     alone; stopping rule and output as in step 5 above.
+
+Level ramp (BFMG, Alg. 4; both schemes, ramp_cycles > 0).  Instead of the
+seeded block (or the shifted start), the solve begins on a level l0 >= l_c
+(default: the coarsest such level with N_l >= 2 m) with the m eigenpairs of
+(A_l0, M_l0) nearest sigma (Alg. 4 step 1, a direct eigensolve), then for
+every level l0 < l < L: the block prolongated from level l - 1, a
+Rayleigh-Ritz step on level l, and ramp_cycles cycles of the scheme's own
+cycle on the hierarchy cut at level l (Alg. 4 step 2: the V-cycle between the
+coarse end and level l; the enriched scheme takes W_c = P_{0->l} Phi_c, the
+shifted one its adaptive shifts relative to level l).  After each level the k
+Ritz values nearest sigma are recorded (Alg. 4 step 3, the eigenvalue
+approximation of that level).  On level L the block is prolongated, one
+Rayleigh-Ritz step follows and the solve continues as usual.  With
+max_cycles = ramp_cycles every level gets the same number of cycles: the
+one-pass run behind the rates of Table 1.
 """
 import math
 
@@ -276,25 +291,77 @@ def default_m(k, sigma):
     return 4 * int(math.ceil(f * k / 4.0))
 
 
+def ramp_start_level(levels, m, l_c):
+    """Default first level of a ramp: the coarsest l >= l_c with N_l >= 2 m."""
+    for l in range(l_c, len(levels)):
+        if levels[l].n >= 2 * m:
+            return l
+    return len(levels) - 1
+
+
+def level_ramp(levels, k, sigma, m, l0, ramp_cycles, cycle_on):
+    """The level ramp of the module docstring up to level L - 1.
+
+    cycle_on(l) gives the scheme's cycle object on the hierarchy cut at
+    level l; it must offer rayleigh_ritz(U), vcycle(l, f) and adapt(U, theta)
+    (the shifts before a correction; nothing for the enriched scheme).
+    Returns (U on level L - 1 or l0, row of recorded values per level).
+    """
+    L = len(levels) - 1
+    rows = np.full((L + 1, k), np.nan)
+    lv0 = levels[l0]
+    lam, phi = sla.eigh(lv0.A.toarray(), lv0.M.toarray())
+    U = phi[:, np.sort(nearest_indices(lam, sigma, m))]
+    for lev in range(l0, L):
+        lv = levels[lev]
+        if lev > l0:
+            U = lv.P @ U
+        cyc = cycle_on(lev)
+        U, theta = cyc.rayleigh_ritz(U)
+        for _ in range(ramp_cycles if lev > l0 else 0):
+            cyc.adapt(U, theta)
+            R = lv.A @ U - (lv.M @ U) * theta[None, :]
+            U, theta = cyc.rayleigh_ritz(U + cyc.vcycle(lev, -R))
+        rows[lev] = theta[np.sort(nearest_indices(theta, sigma, k))]
+    if l0 < L:
+        U = levels[L].P @ U
+    return U, rows
+
+
 def solve(levels, k, sigma=0.0, tol=1e-8, m=None, nu1=2, nu2=2, smoother="gs",
           omega=0.85, max_cycles=200, seed=0, angle_tol=1e-7, U0=None,
-          n_c=None, l_c=None, history=False, scheme="auto"):
+          n_c=None, l_c=None, history=False, scheme="auto", ramp_cycles=0, ramp_level=None):
     """The k eigenpairs of (A_L, M_L) nearest sigma by BMG.
 
     scheme: "enriched" (fixed shift, coarse vectors in every Ritz step),
     "shifted" (the interior-shift scheme of the module docstring) or "auto"
-    (shifted when sigma > 0).
-    Returns (evals ascending, M-orthonormal evecs N_L x k, info dict).
+    (shifted when sigma > 0).  ramp_cycles > 0: start with the level ramp
+    (BFMG) from ramp_level (None: the default of ramp_start_level).
+    Returns (evals ascending, M-orthonormal evecs N_L x k, info dict); with a
+    ramp, info["ramp_evals"] holds the recorded values per level (row L: the
+    returned ones) and info["ramp_start"] the first level.
     """
     if scheme == "auto":
         scheme = "shifted" if sigma > 0 else "enriched"
     if scheme == "shifted":
         return solve_shifted(levels, k, sigma, tol, m, nu1, nu2, smoother, omega, max_cycles,
-                             angle_tol, l_c, history)
+                             angle_tol, l_c, history, ramp_cycles, ramp_level)
     m = default_m(k, sigma) if m is None else m
     bmg = BMG(levels, sigma, m, nu1, nu2, smoother, omega, n_c, l_c)
     lv = levels[-1]
-    U = rng.gaussian_block(lv.n, m, seed) if U0 is None else np.array(U0, dtype=np.float64)
+    rows = None
+    if ramp_cycles > 0:
+        l0 = ramp_start_level(levels, m, bmg.l_c) if ramp_level is None else ramp_level
+        if not bmg.l_c <= l0 < len(levels):
+            raise ValueError("ramp level outside [l_c, L]")
+
+        def cycle_on(lev):
+            c = BMG(levels[:lev + 1], sigma, m, nu1, nu2, smoother, omega, bmg.n_c, bmg.l_c)
+            c.adapt = lambda U, theta: None
+            return c
+        U, rows = level_ramp(levels, k, sigma, m, l0, ramp_cycles, cycle_on)
+    else:
+        U = rng.gaussian_block(lv.n, m, seed) if U0 is None else np.array(U0, dtype=np.float64)
     U, theta = bmg.rayleigh_ritz(U)
     hist = []
     cycles = 0
@@ -322,6 +389,9 @@ def solve(levels, k, sigma=0.0, tol=1e-8, m=None, nu1=2, nu2=2, smoother="gs",
     evecs = normalise_signs(U[:, order])
     info = dict(cycles=cycles, converged=converged, rho=rho, delta=delta, m=m,
                 l_c=bmg.l_c, n_c=bmg.n_c, history=hist)
+    if rows is not None:
+        rows[-1] = evals
+        info.update(ramp_evals=rows, ramp_start=l0)
     return evals, evecs, info
 
 
@@ -449,7 +519,8 @@ class ShiftedBMG:
 
 
 def solve_shifted(levels, k, sigma, tol=1e-8, m=None, nu1=2, nu2=2, smoother="gs", omega=0.85,
-                  max_cycles=200, angle_tol=1e-7, l_c=None, history=False):
+                  max_cycles=200, angle_tol=1e-7, l_c=None, history=False, ramp_cycles=0,
+                  ramp_level=None):
     """The k eigenpairs nearest an interior shift sigma (module docstring, steps 1-4)."""
     m_given = m is not None
     m = default_m(k, sigma) if m is None else m
@@ -457,10 +528,24 @@ def solve_shifted(levels, k, sigma, tol=1e-8, m=None, nu1=2, nu2=2, smoother="gs
         l_c, m = shifted_coarse_level(levels, sigma, m, m_given)
     bmg = ShiftedBMG(levels, sigma, m, l_c, nu1, nu2, smoother, omega)
     lv = levels[-1]
-    U, theta = bmg.start()
-    if l_c < bmg.L:
-        bmg.set_offsets(injected_rayleigh_offsets(levels, U, theta, l_c))
+    rows = None
+    if ramp_cycles > 0:
+        l0 = ramp_start_level(levels, m, l_c) if ramp_level is None else ramp_level
+        if not l_c <= l0 < len(levels):
+            raise ValueError("ramp level outside [l_c, L]")
+
+        def cycle_on(lev):
+            c = ShiftedBMG(levels[:lev + 1], sigma, m, l_c, nu1, nu2, smoother, omega)
+            c.adapt = lambda U, theta: c.set_offsets(
+                injected_rayleigh_offsets(levels[:lev + 1], U, theta, l_c))
+            return c
+        U, rows = level_ramp(levels, k, sigma, m, l0, ramp_cycles, cycle_on)
+        U, theta = bmg.rayleigh_ritz(U)
+    else:
         U, theta = bmg.start()
+        if l_c < bmg.L:
+            bmg.set_offsets(injected_rayleigh_offsets(levels, U, theta, l_c))
+            U, theta = bmg.start()
     cert = BMG.certificates
     hist = []
     cycles = 0
@@ -489,4 +574,7 @@ def solve_shifted(levels, k, sigma, tol=1e-8, m=None, nu1=2, nu2=2, smoother="gs
     evecs = normalise_signs(U[:, order])
     info = dict(cycles=cycles, converged=converged, rho=rho, delta=delta, m=m, l_c=l_c, n_c=0,
                 offsets=bmg.off.copy(), history=hist, scheme="shifted")
+    if rows is not None:
+        rows[-1] = evals
+        info.update(ramp_evals=rows, ramp_start=l0)
     return evals, evecs, info

@@ -52,7 +52,8 @@ class SolveOpts(C.Structure):
                 ("precision", C.c_int32), ("max_cycles", C.c_int32), ("n_c", C.c_int32),
                 ("l_c", C.c_int32), ("omega", C.c_double), ("angle_tol", C.c_double),
                 ("seed", C.c_uint64), ("initial_block", C.POINTER(C.c_double)),
-                ("timed_kernel", C.c_int32), ("scheme", C.c_int32)]
+                ("timed_kernel", C.c_int32), ("scheme", C.c_int32), ("ramp_cycles", C.c_int32),
+                ("ramp_level", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -64,7 +65,8 @@ class SolveStats(C.Structure):
                 ("timed_kernel_bytes", C.c_double), ("timed_kernel_units", C.c_int64),
                 ("ritz_sweeps_max", C.c_int32), ("ritz_fallbacks", C.c_int32),
                 ("scheme", C.c_int32), ("reserved2", C.c_int32), ("coarse_eig_ms", C.c_double),
-                ("lc_shift", C.c_double)]
+                ("lc_shift", C.c_double), ("ramp_evals", C.POINTER(C.c_double)),
+                ("ramp_start", C.c_int32), ("reserved3", C.c_int32)]
 
 
 class ApplyArgs(C.Structure):
@@ -224,7 +226,7 @@ class Hierarchy:
     def solve(self, k, sigma=0.0, tol=1e-8, m=0, nu1=2, nu2=2, smoother="gs", precision="fp64",
               max_cycles=200, n_c=0, l_c=-1, omega=0.85, angle_tol=1e-7, seed=0,
               initial_block=None, evecs="host", stream=None, allow_noconv=False, timed_kernel=None,
-              scheme="auto"):
+              scheme="auto", ramp_cycles=0, ramp_level=-1):
         """Returns (evals [k], evecs [N, k] or None, stats dict).
 
         evecs: "host" -> numpy array, "device" -> torch.cuda tensor view, None.
@@ -243,6 +245,7 @@ class Hierarchy:
         else:
             o.timed_kernel = KERNEL_CLASSES[timed_kernel]
         o.scheme = SCHEMES[scheme]
+        o.ramp_cycles, o.ramp_level = int(ramp_cycles), int(ramp_level)
         keep = None
         if initial_block is not None:
             keep = np.ascontiguousarray(initial_block, dtype=np.float64)
@@ -253,6 +256,8 @@ class Hierarchy:
         st = SolveStats()
         st.rho = rho.ctypes.data_as(C.POINTER(C.c_double))
         st.delta = delta.ctypes.data_as(C.POINTER(C.c_double))
+        ramp = np.full((self.n_levels, k), np.nan)
+        st.ramp_evals = ramp.ctypes.data_as(C.POINTER(C.c_double))
         out = None
         ptr, on_dev = None, 0
         if evecs == "host":
@@ -266,8 +271,9 @@ class Hierarchy:
                                 evals.ctypes.data_as(C.POINTER(C.c_double)), ptr, int(self.N),
                                 on_dev, _stream_ptr(stream) if self.device else None, C.byref(st))
         _check(status, "bmg_solve", allow=(ENOCONV,) if allow_noconv else ())
-        stats = {f: getattr(st, f) for f, _ in SolveStats._fields_ if f not in ("rho", "delta")}
-        stats.update(rho=rho, delta=delta, status=status)
+        stats = {f: getattr(st, f) for f, _ in SolveStats._fields_
+                 if f not in ("rho", "delta", "ramp_evals")}
+        stats.update(rho=rho, delta=delta, status=status, ramp_evals=ramp)
         V = None if out is None else out.T
         return evals, V, stats
 
@@ -378,7 +384,8 @@ class Server:
         if status == EBUSY:
             return None
         del self._n[rid]
-        stats = {f: getattr(st, f) for f, _ in SolveStats._fields_ if f not in ("rho", "delta")}
+        stats = {f: getattr(st, f) for f, _ in SolveStats._fields_
+                 if f not in ("rho", "delta", "ramp_evals")}
         stats.update(rho=rho, delta=delta)
         err = _lib.bmg_last_error().decode(errors="replace") if status != OK else ""
         return dict(status=status, evals=evals, evecs=None if V is None else V.T, stats=stats,

@@ -86,6 +86,8 @@ void bmg_solve_opts_default(bmg_solve_opts* o) {
   o->initial_block = nullptr;
   o->timed_kernel = -1;
   o->scheme = BMG_SCHEME_AUTO;
+  o->ramp_cycles = 0;
+  o->ramp_level = -1;
 }
 
 static int build_impl(const bmg_surface_desc* desc, int32_t n_refine, void* stream,

@@ -464,9 +464,11 @@ int bmg_server_poll(bmg_server* s, uint64_t request_id, double* evals, double* e
   if (stats) {
     double* rho = stats->rho;
     double* delta = stats->delta;
+    double* ramp = stats->ramp_evals;
     *stats = r->stats;
     stats->rho = rho;
     stats->delta = delta;
+    stats->ramp_evals = ramp;  // not kept by the server: left untouched
     if (rho && !r->rho.empty()) std::memcpy(rho, r->rho.data(), sizeof(double) * r->k);
     if (delta && !r->delta.empty()) std::memcpy(delta, r->delta.data(), sizeof(double) * r->k);
   }

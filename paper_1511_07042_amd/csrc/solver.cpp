@@ -655,7 +655,7 @@ int default_coarse_vectors(const bmg_hierarchy* h) { return int(std::min<int64_t
 
 // Coarse level of the interior-shift scheme.  The P1 eigenvalue error of an
 // eigenfunction near sigma on level l is O(sigma^2 h^2) (the a priori estimate
-// of Sec. 2.3) with h the mesh size along it, and a block of m vectors spans a
+// of Sec. 2.2, Lemma 2.2) with h the mesh size along it, and a block of m vectors spans a
 // window of about 2 pi m / |Gamma_h| around sigma; the coarse solve must place
 // the eigenvalues near sigma within a fixed multiple of that window.  With the
 // longest edge h_max,l (which bounds the spread over directions on stretched
@@ -757,8 +757,8 @@ Cert certify(const std::vector<double>& theta, const std::vector<double>& rho2, 
 
 template <typename T>
 int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double tol,
-              const bmg_solve_opts& o, int l_c, const LevelEig* lce, double* evals, double* evecs,
-              int64_t ld, int evecs_on_device, hipStream_t s, bmg_solve_stats* stats) {
+              const bmg_solve_opts& o, int l_c, const LevelEig* lce, const LevelEig* lre, double* evals,
+              double* evecs, int64_t ld, int evecs_on_device, hipStream_t s, bmg_solve_stats* stats) {
   const int nl = int(h->dev.size());
   const int L = nl - 1;
   const DevLevel& DL = h->dev[L];
@@ -786,34 +786,41 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     w->sh_n = lce->n;
   }
 
-  // ---- S2: W_c = P_{0->L} Phi_c, its Gram blocks, and the level-0 inverse
-  if (!shifted) {
+  // ---- S2: W_c = P_{0->top} Phi_c and its Gram blocks on level top (top = L
+  // but for the levels of a ramp)
+  auto build_wc = [&](int top) -> int {
     std::vector<int> idx = nearest(h->lam0, sigma, n_c);
     std::sort(idx.begin(), idx.end());
     std::vector<double> phic(size_t(n0) * n_c);
     for (int64_t i = 0; i < n0; ++i)
       for (int j = 0; j < n_c; ++j) phic[size_t(i) * n_c + j] = h->phi0[size_t(i) * n0 + idx[j]];
-    double* cur = (L % 2 == 0) ? w->W : w->AW;  // ping-pong so the last lands in W
+    double* cur = (top % 2 == 0) ? w->W : w->AW;  // ping-pong so the last lands in W
     BMG_HIP(hipMemcpyAsync(cur, phic.data(), sizeof(double) * phic.size(), hipMemcpyHostToDevice, s));
-    for (int l = 1; l <= L; ++l) {
+    for (int l = 1; l <= top; ++l) {
       double* nxt = (cur == w->W) ? w->AW : w->W;
       BMG_TRY(launch_fill<double>(nxt, h->dev[l].n * n_c, 0.0, s));
       BMG_TRY(launch_prolong_add<double>(h->dev[l], cur, nxt, n_c, s));
       cur = nxt;
     }
+    const DevLevel& D = h->dev[top];
+    BMG_TRY(launch_spmm_am(D, w->W, w->AW, w->MW, n_c, s));
+    const GramPlan gpw = top == L ? w->gpw : gram_plan(D.n, n_c, 2 * n_c);
+    BMG_TRY(launch_gram(gpw, D.n, w->W, n_c, nullptr, 0, w->AW, n_c, w->MW, n_c, w->gpart, w->GW, s));
     BMG_HIP(hipStreamSynchronize(s));  // phic is a host local
-  }
-  if (!shifted) {
-    BMG_TRY(launch_spmm_am(DL, w->W, w->AW, w->MW, n_c, s));
-    BMG_TRY(launch_gram(w->gpw, N, w->W, n_c, nullptr, 0, w->AW, n_c, w->MW, n_c, w->gpart, w->GW, s));
-  }
+    return BMG_OK;
+  };
+  const bool ramp = lre != nullptr;
+  if (!shifted && !ramp) BMG_TRY(build_wc(L));
 
   // ---- S3: test vectors and the first Rayleigh-Ritz step (the interior
   // scheme starts from coarse eigenvectors further below unless a block is given)
-  if (o.initial_block)
+  if (ramp) {
+    // the ramp below fills U
+  } else if (o.initial_block) {
     BMG_HIP(hipMemcpyAsync(w->U, o.initial_block, sizeof(double) * N * m, hipMemcpyHostToDevice, s));
-  else if (!shifted)
+  } else if (!shifted) {
     BMG_TRY(launch_gaussian(w->U, N, m, o.seed, s));
+  }
 
   KTimer kt;
   // timed_kernel = class, or class + 256 (l + 1) for the launches on level l only
@@ -857,7 +864,7 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     BMG_TRY(kt.end(BMG_K_UPDATE));
     return BMG_OK;
   };
-  if (!shifted || o.initial_block) BMG_TRY(ritz_step());
+  if (!ramp && (!shifted || o.initial_block)) BMG_TRY(ritz_step());
   ra.warm = warm_ok;
 
   Cycle<T> cyc;
@@ -922,7 +929,97 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     BMG_HIP(hipStreamSynchronize(s));  // csel and theta0 are read by the copies
     return BMG_OK;
   };
-  if (shifted && !o.initial_block) {
+  // ---- Level ramp (BFMG, Alg. 4): the exact pairs of level l0 nearest sigma
+  // (step 1), then on every level l0 < lev < L the block prolongated from the
+  // level below, a Ritz step and ramp_cycles cycles of the level's own cycle
+  // (step 2: the V-cycle between level lev and the coarse end), recording the
+  // k values nearest sigma after each level (step 3); level L then continues
+  // as the solve's own loop.  Plain launches; the Ritz warm start is off.
+  std::vector<double> ramp_rows;
+  int ramp_l0 = -1;
+  if (ramp) {
+    ramp_l0 = lre->level;
+    ramp_rows.assign(size_t(nl) * k, std::nan(""));
+    const int warm_saved = ra.warm;
+    ra.warm = 0;
+    auto ritz_on = [&](int lev) -> int {
+      const DevLevel& D = h->dev[lev];
+      const GramPlan gp = lev == L ? w->gp : gram_plan(D.n, nz, 2 * m);
+      BMG_TRY(launch_gram_am(gp, D, w->W, n_c, w->U, m, w->gpart, w->G, s));
+      BMG_TRY(launch_ritz(ra, s));
+      BMG_TRY(launch_update_zy(D.n, w->W, n_c, w->U, m, w->Y, w->U, m, s));
+      return BMG_OK;
+    };
+    auto record = [&](int lev) -> int {
+      std::vector<double> buf(2 * m + 8);
+      BMG_HIP(hipMemcpyAsync(buf.data(), w->theta, sizeof(double) * buf.size(), hipMemcpyDeviceToHost, s));
+      BMG_HIP(hipStreamSynchronize(s));
+      int rs0 = 0;
+      std::memcpy(&rs0, buf.data() + 2 * m, sizeof(int));
+      if (rs0 == 1) {
+        set_error("the block lost rank below m on level %d of the ramp", lev);
+        return BMG_ENOCONV;
+      }
+      std::vector<double> th(buf.begin(), buf.begin() + m);
+      std::vector<int> sel = nearest(th, sigma, k);
+      std::sort(sel.begin(), sel.end());
+      for (int j = 0; j < k && j < int(sel.size()); ++j) ramp_rows[size_t(lev) * k + j] = th[sel[j]];
+      return BMG_OK;
+    };
+    // step 1: level l0's own eigenpairs nearest sigma
+    {
+      std::vector<int> sel = nearest(lre->lam, sigma, m);
+      BMG_CHECK(int(sel.size()) == m, "level %d has fewer than m = %d eigenpairs", ramp_l0, m);
+      std::sort(sel.begin(), sel.end());
+      BMG_HIP(hipMemcpyAsync(w->sel, sel.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
+      BMG_TRY(launch_gather_rows(lre->n, m, lre->d_phi64, w->sel, w->U, s));
+      BMG_HIP(hipStreamSynchronize(s));  // sel is a host local
+    }
+    for (int lev = ramp_l0; lev < L; ++lev) {
+      const DevLevel& D = h->dev[lev];
+      if (lev > ramp_l0) {
+        // prolongate the block from level lev - 1
+        BMG_TRY(launch_fill<double>(w->AU, D.n * m, 0.0, s));
+        BMG_TRY(launch_prolong_add<double>(D, w->U, w->AU, m, s));
+        BMG_HIP(hipMemcpyAsync(w->U, w->AU, sizeof(double) * D.n * m, hipMemcpyDeviceToDevice, s));
+      }
+      if (!shifted) BMG_TRY(build_wc(lev));
+      BMG_TRY(ritz_on(lev));
+      for (int c = 0; lev > ramp_l0 && c < o.ramp_cycles; ++c) {
+        if (shifted) {
+          BMG_TRY(launch_offsets(h->dev, l_c, lev, w->U, m, sigma, w->theta, w->rqpart, w->shifts, s));
+          for (int l = l_c + 1; l <= lev; ++l)
+            BMG_TRY(launch_shift_dev<T>(h->dev[l], w->shifts + l, static_cast<T*>(w->S[l]), s));
+          BMG_TRY(launch_spec_g<T>(lce->n, lce->d_lam, w->shifts + l_c, spec_tau, static_cast<T*>(w->spec_g), s));
+        }
+        BMG_TRY(launch_eigres<T>(D, w->U, w->theta, -1.0, cyc.f[lev], w->rho2part, eigres_blocks(D, m), m, s));
+        cyc.add_u = fold_add ? w->U : nullptr;
+        cyc.add_level = lev;
+        cyc.added = false;
+        BMG_TRY(cyc.vcycle(lev));
+        if (!cyc.added) BMG_TRY(launch_add_to<T>(w->U, cyc.e[lev], D.n * m, s));
+        BMG_TRY(ritz_on(lev));
+      }
+      BMG_TRY(record(lev));
+    }
+    // on to level L: prolongate, the fine coarse vectors, a Ritz step
+    if (ramp_l0 < L) {
+      BMG_TRY(launch_fill<double>(w->AU, N * m, 0.0, s));
+      BMG_TRY(launch_prolong_add<double>(DL, w->U, w->AU, m, s));
+      BMG_HIP(hipMemcpyAsync(w->U, w->AU, sizeof(double) * N * m, hipMemcpyDeviceToDevice, s));
+    }
+    if (!shifted) BMG_TRY(build_wc(L));
+    if (shifted) {
+      // the shifts and operators of the finest level's cycles start from sigma again
+      BMG_HIP(hipMemcpyAsync(w->shifts, shifts_h.data(), sizeof(double) * nl, hipMemcpyHostToDevice, s));
+      for (int l = l_c + 1; l <= L; ++l)
+        BMG_TRY(launch_shift_dev<T>(h->dev[l], w->shifts + l, static_cast<T*>(w->S[l]), s));
+      BMG_TRY(launch_spec_g<T>(lce->n, lce->d_lam, w->shifts + l_c, spec_tau, static_cast<T*>(w->spec_g), s));
+      BMG_HIP(hipStreamSynchronize(s));
+    }
+    BMG_TRY(ritz_step());
+    ra.warm = warm_saved;
+  } else if (shifted && !o.initial_block) {
     BMG_TRY(start(0.0));
     if (l_c < L) {
       BMG_TRY(adapt_shifts());
@@ -1102,6 +1199,12 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     stats->ritz_sweeps_max = ritz_sweeps_max;
     stats->ritz_fallbacks = ritz_fallbacks;
     stats->scheme = shifted ? BMG_SCHEME_SHIFTED : BMG_SCHEME_ENRICHED;
+    stats->ramp_start = ramp_l0;
+    if (ramp && stats->ramp_evals) {
+      for (int j = 0; j < k; ++j) ramp_rows[size_t(L) * k + j] = have_pairs ? evals[j] : std::nan("");
+      for (int l = ramp_l0; l <= L; ++l)
+        for (int j = 0; j < k; ++j) stats->ramp_evals[size_t(l) * k + j] = ramp_rows[size_t(l) * k + j];
+    }
     stats->coarse_eig_ms = shifted ? lce->setup_ms : 0.0;
     stats->lc_shift = shifted ? shifts_h[l_c] : sigma;
     if (shifted && l_c < L) {
@@ -1168,9 +1271,25 @@ int solve(bmg_hierarchy* h, int k, double sigma, double tol, const bmg_solve_opt
     BMG_CHECK(h->host[l_c].n >= o.m, "l_c = %d has %lld vertices, fewer than the m = %d start vectors",
               l_c, (long long)h->host[l_c].n, o.m);
   }
+  BMG_CHECK(o.ramp_cycles >= 0 && o.ramp_cycles <= 64, "ramp_cycles must be in [0, 64]");
+  int ramp_l0 = -1;
+  if (o.ramp_cycles > 0) {
+    ramp_l0 = o.ramp_level;
+    if (ramp_l0 < 0) {
+      // the coarsest level at or above l_c that holds 2 m eigenpairs
+      ramp_l0 = nl - 1;
+      for (int l = nl - 1; l >= l_c; --l)
+        if (h->host[l].n >= 2 * int64_t(o.m)) ramp_l0 = l;
+    }
+    BMG_CHECK(ramp_l0 >= l_c && ramp_l0 < nl, "ramp_level %d outside [l_c = %d, %d]", ramp_l0, l_c, nl - 1);
+    BMG_CHECK(h->host[ramp_l0].n >= o.m && h->host[ramp_l0].n <= kLevelEigMax,
+              "the ramp's first level needs between m and %d vertices", kLevelEigMax);
+  }
   BMG_HIP(hipSetDevice(h->device));
   const LevelEig* lce = nullptr;
   if (shifted) BMG_TRY(level_eig(h, l_c, static_cast<hipStream_t>(stream), &lce));
+  const LevelEig* lre = nullptr;
+  if (ramp_l0 >= 0) BMG_TRY(level_eig(h, ramp_l0, static_cast<hipStream_t>(stream), &lre));
   bmg_workspace* w = nullptr;
   BMG_TRY(acquire_workspace(h, o.m, o.n_c, o.precision, &w));
   // work runs on the workspace's own stream, ordered after the caller's
@@ -1183,8 +1302,8 @@ int solve(bmg_hierarchy* h, int k, double sigma, double tol, const bmg_solve_opt
     st = BMG_EDEVICE;
   } else {
     st = (o.precision == BMG_MIXED)
-             ? run_solve<float>(h, w, k, sigma, tol, o, l_c, lce, evals, evecs, ld, evecs_on_device, s, stats)
-             : run_solve<double>(h, w, k, sigma, tol, o, l_c, lce, evals, evecs, ld, evecs_on_device, s, stats);
+             ? run_solve<float>(h, w, k, sigma, tol, o, l_c, lce, lre, evals, evecs, ld, evecs_on_device, s, stats)
+             : run_solve<double>(h, w, k, sigma, tol, o, l_c, lce, lre, evals, evecs, ld, evecs_on_device, s, stats);
   }
   (void)hipStreamSynchronize(s);
   if (hipEventRecord(w->ev_out, s) == hipSuccess) (void)hipStreamWaitEvent(cs, w->ev_out, 0);
