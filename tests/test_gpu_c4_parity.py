@@ -1,0 +1,214 @@
+"""Parity at the full C4 size (sphere refined 8 times: 655362 vertices).
+
+Kernels at levels 7 (163842 rows) and 8 with the solve's block width m = 80
+(and 12 coarse columns where the solve has them), element by element against
+the oracle's own pencil and transfers.  At these sizes the row kernels wrap
+their grids (more than 8192 row groups), the Gram kernel visits row chunks in
+Morton order (levels of 131072 rows and more), and the V-cycle's Jacobi
+levels whose blocks exceed 24 MiB run as separate (unfused) kernels.
+
+Solves: the certified C4 eigenpairs (mixed and FP64, Jacobi and Gauss-Seidel)
+in the oracle's pencil: M-orthonormality in the oracle's M, per-pair
+eigenvalues against the stored oracle values, and per cluster the
+Davis-Kahan bound ||sin Theta||_F <= ||R||_{M^-1} / delta from the residual in
+the oracle's (A, M), with delta the distance to the nearest stored eigenvalue
+outside the cluster, which bounds the angle to the oracle's exact eigenspace.
+"""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def c4():
+    import torch
+    import paper_1511_07042_amd as p
+    from oracle import bmg as ob
+    print("building the oracle's sphere hierarchy, 8 refinements", flush=True)
+    lv = ob.build_levels("sphere", 8)
+    h = p.Hierarchy("sphere", 8)
+    yield torch, p, h, lv
+    h.close()
+
+
+def _dev(torch, x, dt=None):
+    return torch.tensor(np.ascontiguousarray(x), dtype=dt or torch.float64, device="cuda")
+
+
+def _host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _rel(got, ref, scale):
+    return float(np.max(np.abs(got - ref) / scale))
+
+
+def _asm_tol(L):
+    # The library and the oracle assemble A and M independently.  Their
+    # entries come from edge vectors x_j - x_i of length ~h between vertices of
+    # norm ~1, so each assembly rounds them to about eps / h relative: the two
+    # differ by 1.3e-14 (level 7) and 3.1e-14 (level 8) of a row's largest
+    # entry, measured on the host build.  Products against the oracle's
+    # matrices are held to 2e-15 / h_max relative to |A| |x| (2.4e-14 on
+    # level 4, 1.9e-13 on level 7, 3.9e-13 on level 8).
+    return max(1e-14, 2e-15 / L.hmax)
+
+
+# ----------------------------------------------------------------- kernels --
+
+@pytest.mark.parametrize("level", [7, 8])
+def test_products_and_residuals(c4, level):
+    torch, p, h, lv = c4
+    L = lv[level]
+    m = 80
+    rng = np.random.default_rng(level)
+    x, f = rng.standard_normal((L.n, m)), rng.standard_normal((L.n, m))
+    xd = _dev(torch, x)
+    for op, Mat in (("A", L.A), ("M", L.M)):
+        y = torch.zeros((L.n, m), dtype=torch.float64, device="cuda")
+        h.apply(op, x=xd, y=y, level=level)
+        torch.cuda.synchronize()
+        assert _rel(_host(y), Mat @ x, abs(Mat) @ np.abs(x) + 1e-300) < _asm_tol(L), op
+    sigma = 5.0
+    S = (L.A - sigma * L.M).tocsr()
+    scale = (abs(L.A) + sigma * abs(L.M)) @ np.abs(x) + np.abs(f)
+    for dt, tol in ((torch.float64, _asm_tol(L)), (torch.float32, 3e-6)):
+        xt, ft = _dev(torch, x, dt), _dev(torch, f, dt)
+        y = torch.zeros_like(xt)
+        h.apply("residual", x=xt, f=ft, y=y, level=level, sigma=sigma)
+        torch.cuda.synchronize()
+        assert _rel(_host(y), _host(ft) - S @ _host(xt), scale) < tol, dt
+    th = np.sort(rng.uniform(0, 60, m))
+    ref = L.A @ x - (L.M @ x) * th[None, :]
+    esc = abs(L.A) @ np.abs(x) + (abs(L.M) @ np.abs(x)) * th[None, :]
+    for dt, code, tol in ((torch.float64, 0, _asm_tol(L)), (torch.float32, 1, 1e-7)):
+        y = torch.zeros((L.n, m), dtype=dt, device="cuda")
+        h.apply("eigres", x=xd, f=_dev(torch, th), y=y, level=level, dtype=code)
+        torch.cuda.synchronize()
+        assert _rel(_host(y), ref, esc) < tol, dt
+
+
+@pytest.mark.parametrize("level", [7, 8])
+def test_sweeps_and_transfers(c4, level):
+    torch, p, h, lv = c4
+    from oracle import bmg as ob
+    L = lv[level]
+    m = 80
+    rng = np.random.default_rng(10 + level)
+    e, f = rng.standard_normal((L.n, m)), rng.standard_normal((L.n, m))
+    sm = ob.Smoother(L, 2.0, "jacobi", 0.85)
+    ref = sm.sweep(e, f)
+    for dt, tol in ((torch.float64, 1e-11), (torch.float32, 1e-5)):
+        y = torch.zeros((L.n, m), dtype=dt, device="cuda")
+        h.apply("smooth_fwd", x=_dev(torch, e, dt), f=_dev(torch, f, dt), y=y, level=level,
+                sigma=2.0, smoother="jacobi", omega=0.85)
+        torch.cuda.synchronize()
+        assert np.max(np.abs(_host(y) - ref)) < tol * max(1.0, np.max(np.abs(ref))), dt
+    gs = ob.Smoother(L, 2.0, "gs", 0.85)
+    for forward in (True, False):
+        ref = gs.sweep(e, f, forward=forward)
+        y = _dev(torch, e)
+        h.apply("smooth_fwd" if forward else "smooth_bwd", f=_dev(torch, f), y=y, level=level,
+                sigma=2.0, smoother="gs")
+        torch.cuda.synchronize()
+        assert np.max(np.abs(_host(y) - ref)) < 1e-11 * max(1.0, np.max(np.abs(ref))), forward
+    P = L.P
+    nf, nc = P.shape
+    for dt, tol in ((torch.float64, 1e-15), (torch.float32, 1e-6)):
+        xf = _dev(torch, e, dt)
+        y = torch.zeros((nc, m), dtype=dt, device="cuda")
+        h.apply("restrict", x=xf, y=y, level=level)
+        torch.cuda.synchronize()
+        ref = P.T @ _host(xf)
+        assert np.max(np.abs(_host(y) - ref)) < 8 * tol * np.max(np.abs(ref)), dt
+        xc = _dev(torch, f[:nc], dt)
+        yf = _dev(torch, e, dt)
+        h.apply("prolong_add", x=xc, y=yf, level=level)
+        torch.cuda.synchronize()
+        ref = _host(_dev(torch, e, dt)) + P @ _host(xc)
+        assert np.max(np.abs(_host(yf) - ref)) < 8 * tol * np.max(np.abs(ref)), dt
+
+
+@pytest.mark.parametrize("level", [7, 8])
+def test_fused_gram_and_update(c4, level):
+    # the Ritz step's two MFMA kernels at the solve's shape: [W | U]^T [A U | M U]
+    # (chunk-ordered at these sizes) and U <- [W | U] Y in place
+    torch, p, h, lv = c4
+    L = lv[level]
+    m2, m = 12, 80
+    rng = np.random.default_rng(20 + level)
+    W, U = rng.standard_normal((L.n, m2)), rng.standard_normal((L.n, m))
+    Wd, Ud = _dev(torch, W), _dev(torch, U)
+    y = torch.zeros((m2 + m, 2 * m), dtype=torch.float64, device="cuda")
+    h.apply("gram_am", x=Wd, f=Ud, y=y, m=m, m2=m2, level=level)
+    torch.cuda.synchronize()
+    Z = np.hstack([W, U])
+    AU, MU = L.A @ U, L.M @ U
+    scale = np.abs(Z).T @ np.hstack([abs(L.A) @ np.abs(U), abs(L.M) @ np.abs(U)])
+    assert _rel(_host(y), Z.T @ np.hstack([AU, MU]), scale) < _asm_tol(L)
+    Y = rng.standard_normal((m2 + m, m))
+    h.apply("update", x=Wd, f=_dev(torch, Y), y=Ud, m=m, m2=m2, level=level)
+    torch.cuda.synchronize()
+    assert _rel(_host(Ud), Z @ Y, np.abs(Z) @ np.abs(Y)) < 1e-14
+
+
+@pytest.mark.parametrize("smoother", ["jacobi", "gs"])
+def test_vcycle_full_depth(c4, smoother):
+    # one V(2, 2) cycle from level 8 to the level-0 spectral inverse: the
+    # FP32 Jacobi levels 7 and 8 (blocks of 52 and 210 MB) run unfused
+    torch, p, h, lv = c4
+    from oracle import bmg as ob
+    m = 80
+    bm = ob.BMG(lv, 0.0, m, 2, 2, smoother, 0.85)
+    f = np.random.default_rng(5).standard_normal((lv[-1].n, m))
+    ref = bm.vcycle(len(lv) - 1, f)
+    for dt, tol in ((torch.float64, 1e-10), (torch.float32, 2e-4)):
+        y = torch.zeros((lv[-1].n, m), dtype=dt, device="cuda")
+        h.apply("vcycle", x=_dev(torch, f, dt), y=y, sigma=0.0, smoother=smoother, l_c=bm.l_c,
+                omega=0.85)
+        torch.cuda.synchronize()
+        err = np.max(np.abs(_host(y) - ref)) / np.max(np.abs(ref))
+        assert err < tol, (dt, err)
+
+
+# ------------------------------------------------------------------ solves --
+
+def _clusters(vals, gap=1e-2):
+    out, start = [], 0
+    for j in range(1, len(vals) + 1):
+        if j == len(vals) or vals[j] - vals[j - 1] >= gap * max(abs(vals[j]), abs(vals[j - 1]), 1.0):
+            out.append((start, j))
+            start = j
+    return out
+
+
+@pytest.mark.parametrize("precision,smoother", [("mixed", "jacobi"), ("fp64", "gs"), ("mixed", "gs")])
+def test_c4_eigenspaces_in_the_oracle_pencil(c4, precision, smoother):
+    torch, p, h, lv = c4
+    gold = np.array([float(x) for x in open(os.path.join(GOLDEN, "c4_sphere_ref8_eigs.txt"))
+                     if not x.startswith("#")])
+    ev, U, st = h.solve(64, 0.0, 1e-8, m=80, precision=precision, smoother=smoother)
+    assert st["converged"] == 1
+    print(f"C4 {precision} {smoother}: {st['cycles']} cycles, {st['t_solve_ms']:.1f} ms", flush=True)
+    L = lv[-1]
+    rel = np.abs(ev - gold[:64]) / np.maximum(np.abs(gold[:64]), 1.0)
+    assert rel.max() < 1e-8, rel.max()
+    MU = L.M @ U
+    assert np.max(np.abs(U.T @ MU - np.eye(64))) < 1e-10
+    R = L.A @ U - MU * ev[None, :]
+    D = np.asarray(L.M.sum(axis=1)).ravel()  # 1/4 D <= M <= D: ||r||_{M^-1} <= 2 ||r||_{D^-1}
+    rn2 = 4.0 * np.sum(R * R / D[:, None], axis=0)
+    worst = 0.0
+    for a, b in _clusters(gold[:64]):
+        lo, hi = gold[a], gold[b - 1]
+        outside = np.concatenate([gold[:a], gold[b:]])
+        delta = np.min(np.minimum(np.abs(outside[:, None] - ev[None, a:b]), np.inf))
+        bound = np.sqrt(rn2[a:b].sum()) / delta
+        worst = max(worst, bound)
+        assert bound < 1e-6, (a, b, lo, hi, bound)
+    print(f"  largest Davis-Kahan sine bound per cluster: {worst:.1e}", flush=True)
