@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libbmg.so")
 
-SOURCES = ["mesh.cpp", "assemble.cpp", "dense_host.cpp", "hierarchy.cpp", "solver.cpp",
+SOURCES = ["mesh.cpp", "assemble.cpp", "dense_host.cpp", "order.cpp", "hierarchy.cpp", "solver.cpp",
            "capi.cpp", "server.cpp", "dense_device.cpp", "kernels_sparse.hip", "kernels_gram.hip",
            "kernels_dense.hip", "kernels_tail.hip", "kernels_coarse.hip"]
 
@@ -47,7 +47,8 @@ def build(verbose=False, jobs=8):
         raise RuntimeError("compilation failed: " + ", ".join(s for s, _ in errs))
     objs = [o for _, o, _, _ in results]
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-ldl"]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + \
+        ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-ldl"]
     p = subprocess.run(cmd, capture_output=True, text=True)
     if p.returncode != 0:
         raise RuntimeError("link failed:\n" + p.stdout + p.stderr)

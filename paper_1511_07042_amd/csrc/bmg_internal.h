@@ -16,6 +16,18 @@
 
 namespace bmg {
 
+// ------------------------------------------------------------------ tracing --
+// A named host-time range for rocprofv3's marker trace (roctx): open while the
+// object lives.  The solve, its level ramp, its start, its cycle loop, a
+// hierarchy build and a level's dense eigendecomposition are marked.
+class TraceRange {
+ public:
+  explicit TraceRange(const char* name);
+  ~TraceRange();
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
+
 // ------------------------------------------------------------------ errors --
 void set_error(const char* fmt, ...);
 const char* get_error();
@@ -74,6 +86,11 @@ int assemble_level(HostLevel& lv, const HostLevel* coarser);
 // X^T M X = I.  Cholesky reduction + cyclic Jacobi.
 int dense_sygv(int n, const std::vector<double>& A, const std::vector<double>& M,
                std::vector<double>& lam, std::vector<double>& X);
+// Row visiting orders (order.cpp): the vertices along a Morton curve through
+// xyz ([n][3]), a permutation of 0..n-1; and the same over 16-row chunks placed
+// at their centroids (a permutation of the chunk indices).
+std::vector<int32_t> morton_order(const std::vector<double>& xyz);
+std::vector<int32_t> chunk_morton_order(const HostLevel& H);
 
 // ----------------------------------------------------------- device level --
 struct DevLevel {

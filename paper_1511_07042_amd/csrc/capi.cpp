@@ -7,11 +7,16 @@
 
 #include "bmg_internal.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 namespace bmg {
 
 namespace {
 thread_local std::string g_err;
 }
+
+TraceRange::TraceRange(const char* name) { roctxRangePushA(name); }
+TraceRange::~TraceRange() { roctxRangePop(); }
 
 void set_error(const char* fmt, ...) {
   char buf[1024];
@@ -94,6 +99,7 @@ static int build_impl(const bmg_surface_desc* desc, int32_t n_refine, void* stre
                       bmg_hierarchy** out, bool to_device) {
   BMG_CHECK(out != nullptr, "out must be non-NULL");
   *out = nullptr;
+  TraceRange trace("bmg_build_hierarchy");
   bmg_hierarchy* h = new (std::nothrow) bmg_hierarchy();
   if (!h) return BMG_ENOMEM;
   int st = build_host_levels(desc, n_refine, h->host);

@@ -938,6 +938,7 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   std::vector<double> ramp_rows;
   int ramp_l0 = -1;
   if (ramp) {
+    TraceRange trace("bmg_solve: level ramp");
     ramp_l0 = lre->level;
     ramp_rows.assign(size_t(nl) * k, std::nan(""));
     const int warm_saved = ra.warm;
@@ -1020,6 +1021,7 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     BMG_TRY(ritz_step());
     ra.warm = warm_saved;
   } else if (shifted && !o.initial_block) {
+    TraceRange trace("bmg_solve: start");
     BMG_TRY(start(0.0));
     if (l_c < L) {
       BMG_TRY(adapt_shifts());
@@ -1109,6 +1111,7 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     BMG_HIP(hipGraphLaunch(w->gexec, s));
     return BMG_OK;
   };
+  TraceRange trace_cycles("bmg_solve: cycles");
   BMG_TRY(residual_step());
   for (;;) {
     // theta, rho2 and the Ritz status words: written to the pinned host buffer
@@ -1230,6 +1233,7 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
 int solve(bmg_hierarchy* h, int k, double sigma, double tol, const bmg_solve_opts* opts,
           double* evals, double* evecs, int64_t ld, int evecs_on_device, void* stream,
           bmg_solve_stats* stats) {
+  TraceRange trace("bmg_solve");
   BMG_CHECK(h != nullptr && evals != nullptr, "hierarchy and evals must be non-NULL");
   bmg_solve_opts o;
   bmg_solve_opts_default(&o);
