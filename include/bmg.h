@@ -123,8 +123,10 @@ typedef enum {
   BMG_EXPORT_ELL_M = 5,    /* double [N][W] values of M_l (padding 0)              */
   BMG_EXPORT_COLOURS = 6,  /* int32  [N] colour of each vertex                      */
   BMG_EXPORT_LUMPED = 7,   /* double [N] row sums of M_l                            */
-  BMG_EXPORT_COARSE_EIG = 8 /* level 0 only: double [N_0] eigenvalues then [N_0][N_0]
+  BMG_EXPORT_COARSE_EIG = 8, /* level 0 only: double [N_0] eigenvalues then [N_0][N_0]
                                row-major M_0-orthonormal eigenvectors (column j = pair j) */
+  BMG_EXPORT_COLOURS2 = 9   /* int32  [N] colour of each vertex in the distance-2
+                               colouring of the Kaczmarz smoother                    */
 } bmg_export_what;
 
 /* Copy one host-side array of a level into `host_out` (capacity in bytes).
@@ -136,7 +138,18 @@ int bmg_hierarchy_export(const bmg_hierarchy* h, int32_t level, int32_t what, vo
 
 /* ---------------------------------------------------------------- solve --- */
 
-typedef enum { BMG_SMOOTH_GS = 0, BMG_SMOOTH_JACOBI = 1 } bmg_smoother;
+/* Smoothers of the correction cycle, on S_l = A_l - sigma_l M_l.
+ * GS: multicolour symmetric Gauss-Seidel (greedy colouring, colours up then
+ *   down).  JACOBI: weighted Jacobi with opts.omega.
+ * KACZMARZ: multicolour symmetric Kaczmarz relaxation (Sec. 5.3, the paper's
+ *   smoother for the shifted, indefinite source problems): for each row i,
+ *   x <- x + ((f_i - s_i^T x) / |s_i|^2) s_i, the projection onto row i's
+ *   hyperplane (weight 1; opts.omega is not used).  Rows of one colour of a
+ *   greedy distance-2 colouring (no two rows of a colour share a column) are
+ *   projected at once; colours up, then down.  It converges for any
+ *   nonsingular S (it is Gauss-Seidel on S S^T) but damps more slowly than
+ *   GS where GS converges. */
+typedef enum { BMG_SMOOTH_GS = 0, BMG_SMOOTH_JACOBI = 1, BMG_SMOOTH_KACZMARZ = 2 } bmg_smoother;
 typedef enum { BMG_FP64 = 0, BMG_MIXED = 1 } bmg_precision;
 
 /* Iteration schemes.

@@ -21,9 +21,11 @@ What is computed (paper Sec. 4, Alg. 2 and Alg. 3, with Remark 3.2):
     V(nu1, nu2) cycle for the rediscretised operators A_l - sigma M_l on
     levels L down to l_c, with P^T as restriction and P as prolongation
     (Sec. 3), smoothing by multicolour symmetric Gauss-Seidel (Sec. 5.3,
-    method 4; Remark 4.2) or weighted Jacobi (weight 0.85 unless given).
- 4. M-orthonormalisation of Z = [W_c, U'] (Alg. 2 step 3, "orthogonalize with
-    respect to b_h") by SVQB, then the Ritz eigenproblem of the enriched
+    method 4; Remark 4.2), weighted Jacobi (weight 0.85 unless given) or
+    multicolour symmetric Kaczmarz (Sec. 5.3, methods 2 and 6; see Smoother).
+    All colourings are of the mesh graph (the pattern of M, which S shares).
+ 4. M-orthonormalisation of Z = [W_c, U'] (Alg. 2 step 3: orthogonalisation
+    in the b_h inner product) by SVQB, then the Ritz eigenproblem of the enriched
     pencil (eq. pb-c-aux-mat) shifted by sigma; the m Ritz pairs nearest sigma
     are kept (Alg. 2 step 2 choice of the index set Lambda, Remark 4.1).
  5. Stop when every returned pair carries a residual certificate: with
@@ -120,12 +122,23 @@ class LevelOps:
         self.A, self.M = fem.assemble(lv.xyz, lv.tri)
         self.D = fem.lumped_mass(self.M)
         self.P = P  # prolongation from the previous level to this one
-        self.colours = colour.greedy_colouring(self.A)
+        # colourings of the mesh graph: the pattern of M holds every edge, and
+        # S = A - sigma M couples every edge for sigma != 0 (A alone can have
+        # exact zeros, on edges opposite two right angles of the torus grid)
+        self.colours = colour.greedy_colouring(self.M)
         self.n = self.A.shape[0]
         self.area = float(fem.triangle_areas(lv.xyz, lv.tri).sum())
         e = np.concatenate([lv.xyz[lv.tri[:, a]] - lv.xyz[lv.tri[:, b]]
                             for a, b in ((0, 1), (1, 2), (2, 0))])
         self.hmax = float(np.sqrt((e * e).sum(axis=1)).max())  # longest edge
+        self._colours2 = None
+
+    @property
+    def colours2(self):
+        """Distance-2 colouring (Kaczmarz smoother), computed on first use."""
+        if self._colours2 is None:
+            self._colours2 = colour.distance2_colouring(self.M)
+        return self._colours2
 
 
 def build_levels(kind, n_refine, axes=(1.0, 1.0, 1.0)):
@@ -155,15 +168,30 @@ def coarsest_level(levels, sigma):
 
 
 class Smoother:
-    """Gauss-Seidel (multicolour, symmetric) or weighted Jacobi on A_l - sigma M_l."""
+    """Gauss-Seidel (multicolour, symmetric), weighted Jacobi or Kaczmarz
+    (multicolour, symmetric; Sec. 5.3) on A_l - sigma M_l.
+
+    Kaczmarz projects the iterate onto the hyperplane of one equation at a
+    time: x <- x + ((f_i - s_i^T x) / |s_i|^2) s_i with s_i row i of S (weight
+    1).  The rows of one colour of the distance-2 colouring have disjoint
+    patterns, so projecting them one after another equals projecting them at
+    once, which is what a colour step here does."""
 
     def __init__(self, lv, sigma, kind, omega):
-        self.S = (lv.A - sigma * lv.M).tocsr()
-        self.d = self.S.diagonal()
         self.kind = kind
         self.omega = omega
-        nc = int(lv.colours.max()) + 1
-        self.rows = [np.flatnonzero(lv.colours == c) for c in range(nc)]
+        colours = lv.colours2 if kind == "kaczmarz" else lv.colours
+        nc = int(colours.max()) + 1
+        self.rows = [np.flatnonzero(colours == c) for c in range(nc)]
+        self.set_shift(lv, sigma)
+
+    def set_shift(self, lv, sigma):
+        """S = A_l - sigma M_l and what the sweeps derive from it."""
+        self.S = (lv.A - sigma * lv.M).tocsr()
+        self.d = self.S.diagonal()
+        if self.kind == "kaczmarz":
+            self.q = np.asarray(self.S.multiply(self.S).sum(axis=1)).ravel()  # |s_i|^2
+            self.Sc = [self.S[r] for r in self.rows]  # the rows of each colour
 
     def sweep(self, x, f, forward=True):
         if self.kind == "jacobi":
@@ -172,7 +200,12 @@ class Smoother:
         x = x.copy()
         for c in order:
             r = self.rows[c]
-            x[r] += (f[r] - self.S[r] @ x) / self.d[r][:, None]
+            if self.kind == "kaczmarz":
+                Sr = self.Sc[c]
+                t = (f[r] - Sr @ x) / self.q[r][:, None]
+                x += Sr.T @ t
+            else:
+                x[r] += (f[r] - self.S[r] @ x) / self.d[r][:, None]
         return x
 
 
@@ -463,9 +496,7 @@ class ShiftedBMG:
             if l not in self.smoothers:
                 self.smoothers[l] = Smoother(lv, sig, self.kind, self.omega)
             else:
-                sm = self.smoothers[l]
-                sm.S = (lv.A - sig * lv.M).tocsr()
-                sm.d = sm.S.diagonal()
+                self.smoothers[l].set_shift(lv, sig)
         x = self.lam - (self.sigma + self.off[self.l_c])
         keep = np.abs(x) >= 1e-2 * max(1.0, abs(self.sigma))
         self.g = np.where(keep, 1.0 / np.where(keep, x, 1.0), 0.0)

@@ -19,11 +19,11 @@ _lib = C.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EBUSY, ECANCELED = 0, -1, -2, -3, -4, -5, -6
 KINDS = {"sphere": 0, "ellipsoid": 1, "torus": 2, "custom": 3}
-SMOOTHERS = {"gs": 0, "jacobi": 1}
+SMOOTHERS = {"gs": 0, "jacobi": 1, "kaczmarz": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 SCHEMES = {"auto": 0, "enriched": 1, "shifted": 2}
 EXPORTS = {"xyz": 0, "tri": 1, "parents": 2, "ell_cols": 3, "ell_a": 4, "ell_m": 5, "colours": 6,
-           "lumped": 7, "coarse_eig": 8}
+           "lumped": 7, "coarse_eig": 8, "colours2": 9}
 KERNEL_CLASSES = {"eigres": 0, "spmm_am": 1, "smooth": 2, "residual": 3, "restrict": 4,
                   "prolong": 5, "gram": 6, "update": 7, "ritz": 8, "smooth_pair": 9,
                   "restrict_res": 10, "prolong_smooth": 11, "smooth_add": 12}
@@ -208,7 +208,7 @@ class Hierarchy:
             arr = np.empty((n, W), np.int32)
         elif what in ("ell_a", "ell_m"):
             arr = np.empty((n, W), np.float64)
-        elif what == "colours":
+        elif what in ("colours", "colours2"):
             arr = np.empty(n, np.int32)
         elif what == "lumped":
             arr = np.empty(n, np.float64)

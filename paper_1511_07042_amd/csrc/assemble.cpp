@@ -1,6 +1,6 @@
 // P1 surface-FEM matrices of one level, stored in ELL form, plus the vertex
-// colouring used by the multicolour Gauss-Seidel smoother and the gather table
-// of the restriction.
+// colourings used by the multicolour Gauss-Seidel and Kaczmarz smoothers and
+// the gather table of the restriction.
 //
 // Paper Sec. 2.1 (eq. bl-dis) and Sec. 2.2 (eq. sp-fe, pb-eig-fea): a_h and
 // b_h integrate over flat triangles.  For a triangle with vertices x0, x1, x2
@@ -118,6 +118,44 @@ int assemble_level(HostLevel& lv, const HostLevel* coarser) {
   {
     std::vector<int32_t> pos(lv.colour_ptr.begin(), lv.colour_ptr.end() - 1);
     for (int64_t i = 0; i < n; ++i) lv.colour_rows[pos[lv.colour[i]]++] = int32_t(i);
+  }
+  // distance-2 colouring for the Kaczmarz smoother: greedy in increasing
+  // vertex index, each vertex taking the smallest colour not used by a
+  // lower-numbered vertex within two edges (so the rows of a colour share no
+  // column of S)
+  lv.colour2.assign(n, -1);
+  int32_t nc2 = 0;
+  {
+    std::vector<int64_t> seen;
+    std::vector<int32_t> mark2;
+    for (int64_t i = 0; i < n; ++i) {
+      for (int32_t j : nb[i]) {
+        if (j < i) {
+          const int32_t cj = lv.colour2[j];
+          if (cj >= int32_t(mark2.size())) mark2.resize(cj + 1, -1);
+          mark2[cj] = int32_t(i);
+        }
+        for (int32_t k : nb[j])
+          if (k < i) {
+            const int32_t ck = lv.colour2[k];
+            if (ck >= int32_t(mark2.size())) mark2.resize(ck + 1, -1);
+            mark2[ck] = int32_t(i);
+          }
+      }
+      int32_t c = 0;
+      while (c < int32_t(mark2.size()) && mark2[c] == int32_t(i)) ++c;
+      lv.colour2[i] = c;
+      nc2 = std::max(nc2, c + 1);
+    }
+  }
+  lv.n_colours2 = nc2;
+  lv.colour2_ptr.assign(nc2 + 1, 0);
+  for (int64_t i = 0; i < n; ++i) lv.colour2_ptr[lv.colour2[i] + 1]++;
+  for (int c = 0; c < nc2; ++c) lv.colour2_ptr[c + 1] += lv.colour2_ptr[c];
+  lv.colour2_rows.assign(n, 0);
+  {
+    std::vector<int32_t> pos(lv.colour2_ptr.begin(), lv.colour2_ptr.end() - 1);
+    for (int64_t i = 0; i < n; ++i) lv.colour2_rows[pos[lv.colour2[i]]++] = int32_t(i);
   }
   // restriction gather table: new vertices adjacent to each coarse vertex
   lv.RW = 0;

@@ -70,6 +70,11 @@ struct HostLevel {
   int32_t n_colours = 0;
   std::vector<int32_t> colour_ptr;   // [n_colours + 1]
   std::vector<int32_t> colour_rows;  // [n] rows grouped by colour, ascending inside
+  // distance-2 colouring (Kaczmarz): no two vertices within two edges share a colour
+  std::vector<int32_t> colour2;
+  int32_t n_colours2 = 0;
+  std::vector<int32_t> colour2_ptr;   // [n_colours2 + 1]
+  std::vector<int32_t> colour2_rows;  // [n]
   int32_t RW = 0;                    // children per coarse vertex (restriction gather width)
   std::vector<int32_t> rtab;         // [n_prev][RW] new vertices adjacent to coarse vertex i, -1 pad
   double area = 0.0;
@@ -107,7 +112,10 @@ struct DevLevel {
   int32_t* colour_rows = nullptr; // [n]
   int32_t* row_order = nullptr;   // [n] rows by Morton code of their vertex (large levels), else null
   int32_t* chunk_order = nullptr; // [ceil(n / 16)] 16-row chunks by Morton code of their centroid (large levels), else null
+  int32_t* colour2_rows = nullptr; // [n] rows grouped by distance-2 colour
   std::vector<int32_t> colour_ptr;
+  int32_t n_colours2 = 0;
+  std::vector<int32_t> colour2_ptr;
   int64_t bytes = 0;
 };
 
@@ -236,6 +244,10 @@ int launch_jacobi(const DevLevel& L, const T* S, double omega, const T* x, const
 template <typename T>
 int launch_gs_colour(const DevLevel& L, const T* S, int colour, T* x, const T* f, int m,
                      hipStream_t s);
+// Kaczmarz projections of the rows of one distance-2 colour, in place.
+template <typename T>
+int launch_kaczmarz_colour(const DevLevel& L, const T* S, int colour, T* x, const T* f, int m,
+                           hipStream_t s);
 // Fused cycle kernels (identical results to the unfused sequences):
 // two Jacobi sweeps from zero; residual + restriction; prolongation + one
 // Jacobi sweep.

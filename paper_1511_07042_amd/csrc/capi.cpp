@@ -201,6 +201,7 @@ int bmg_hierarchy_export(const bmg_hierarchy* h, int32_t level, int32_t what, vo
     case BMG_EXPORT_ELL_M: src = H.mm.data(); bytes = 8 * int64_t(H.mm.size()); break;
     case BMG_EXPORT_COLOURS: src = H.colour.data(); bytes = 4 * int64_t(H.colour.size()); break;
     case BMG_EXPORT_LUMPED: src = H.lumped.data(); bytes = 8 * int64_t(H.lumped.size()); break;
+    case BMG_EXPORT_COLOURS2: src = H.colour2.data(); bytes = 4 * int64_t(H.colour2.size()); break;
     case BMG_EXPORT_COARSE_EIG:
       BMG_CHECK(level == 0, "the coarse eigendecomposition exists on level 0 only");
       tmp = h->lam0;
@@ -284,6 +285,18 @@ int bmg_apply(const bmg_hierarchy* hc, const bmg_apply_args* a, const void* x, c
                                              (const double*)f, (double*)y, false, m, s);
         });
       }
+      if (a->smoother == BMG_SMOOTH_KACZMARZ) {
+        return with_shift(D, a->sigma, f32, s, [&](const void* S) -> int {
+          for (int k = 0; k < D.n_colours2; ++k) {
+            const int c = fwd ? k : D.n_colours2 - 1 - k;
+            if (f32)
+              BMG_TRY(launch_kaczmarz_colour<float>(D, (const float*)S, c, (float*)y, (const float*)f, m, s));
+            else
+              BMG_TRY(launch_kaczmarz_colour<double>(D, (const double*)S, c, (double*)y, (const double*)f, m, s));
+          }
+          return BMG_OK;
+        });
+      }
       BMG_CHECK(a->smoother == BMG_SMOOTH_GS, "unknown smoother");
       return with_shift(D, a->sigma, f32, s, [&](const void* S) -> int {
         for (int k = 0; k < D.n_colours; ++k) {
@@ -310,7 +323,9 @@ int bmg_apply(const bmg_hierarchy* hc, const bmg_apply_args* a, const void* x, c
     case BMG_OP_VCYCLE: {
       BMG_TRY(need_m(4));
       BMG_CHECK(x != nullptr, "x required");
-      BMG_CHECK(a->smoother == BMG_SMOOTH_GS || a->smoother == BMG_SMOOTH_JACOBI, "unknown smoother");
+      BMG_CHECK(a->smoother == BMG_SMOOTH_GS || a->smoother == BMG_SMOOTH_JACOBI ||
+                    a->smoother == BMG_SMOOTH_KACZMARZ,
+                "unknown smoother");
       BMG_CHECK(a->nu1 >= 0 && a->nu2 >= 0 && a->nu1 <= 64 && a->nu2 <= 64, "nu out of range");
       BMG_CHECK(a->omega > 0 && a->omega < 2, "omega must be in (0, 2)");
       return apply_vcycle(h, l, a->dtype, m, a->sigma, a->smoother, a->nu1, a->nu2, a->l_c,

@@ -69,6 +69,9 @@ int upload_hierarchy(bmg_hierarchy* h, hipStream_t s) {
     BMG_TRY(upload(&D.parents, H.parents.data(), H.parents.size(), s, D.bytes));
     BMG_TRY(upload(&D.rtab, H.rtab.data(), H.rtab.size(), s, D.bytes));
     BMG_TRY(upload(&D.colour_rows, H.colour_rows.data(), H.colour_rows.size(), s, D.bytes));
+    BMG_TRY(upload(&D.colour2_rows, H.colour2_rows.data(), H.colour2_rows.size(), s, D.bytes));
+    D.n_colours2 = H.n_colours2;
+    D.colour2_ptr = H.colour2_ptr;
     std::vector<int32_t> ord;
     if (H.n >= min_ordered) {
       ord = morton_order(H.xyz);
@@ -167,7 +170,7 @@ void free_level_eigs(bmg_hierarchy* h) {
 void free_device(bmg_hierarchy* h) {
   free_level_eigs(h);
   for (auto& D : h->dev) {
-    void* ptrs[] = {D.cols, D.a64, D.m64, D.a32, D.m32, D.dinv, D.parents, D.rtab, D.colour_rows, D.row_order, D.chunk_order};
+    void* ptrs[] = {D.cols, D.a64, D.m64, D.a32, D.m32, D.dinv, D.parents, D.rtab, D.colour_rows, D.row_order, D.chunk_order, D.colour2_rows};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     D = DevLevel();

@@ -161,6 +161,46 @@ __global__ void __launch_bounds__(256) k_gs(int64_t cnt, const int* __restrict__
   }
 }
 
+// Kaczmarz projection of the rows of one colour of a distance-2 colouring, in
+// place (Sec. 5.3): with t = (f_r - (S x)_r) / sum_k S_rk^2,
+// x_j <- x_j + t S_rj for every column j of row r (r included).  Rows of one
+// colour share no column, so the rows of a pass read and write disjoint
+// entries of x; each thread owns VW columns of the block.  ELL padding
+// entries (value 0, column r) add nothing.
+template <typename T, int WT>
+__global__ void __launch_bounds__(256) k_kaczmarz(int64_t cnt, const int* __restrict__ rows, int W,
+                                                  int m, int cpr, int rpb,
+                                                  const int* __restrict__ cols,
+                                                  const T* __restrict__ S, T* x,
+                                                  const T* __restrict__ f) {
+  constexpr int VW = Vec<T>::N;
+  const int rloc = threadIdx.x / cpr;
+  const int ch = threadIdx.x - rloc * cpr;
+  if (rloc >= rpb) return;
+  for (int64_t i = int64_t(blockIdx.x) * rpb + rloc; i < cnt; i += int64_t(gridDim.x) * rpb) {
+    const int64_t r = rows[i];
+    const int64_t base = r * W;
+    Vec<T> acc, xr;
+    const Vec<T> fv = ld(f + r * m + ch * VW);
+    row_gather<T, WT>(cols, S, base, W, x, m, ch * VW, acc, xr);
+    T q = T(0);
+    const int w = WT > 0 ? WT : W;
+    for (int k = 0; k < w; ++k) {
+      const T sv = S[base + k];
+      q += sv * sv;
+    }
+    Vec<T> t;
+    for (int c = 0; c < VW; ++c) t.v[c] = (fv.v[c] - acc.v[c]) / q;
+    for (int k = 0; k < w; ++k) {
+      const T sv = S[base + k];
+      T* xj = x + int64_t(cols[base + k]) * m + ch * VW;
+      Vec<T> v = ld(xj);
+      for (int c = 0; c < VW; ++c) v.v[c] += t.v[c] * sv;
+      st(xj, v);
+    }
+  }
+}
+
 // ---------------------------------------------------- fused cycle kernels --
 // Each computes, row by row, what a sequence of the kernels above computes,
 // with the same operations in the same order (so the results are identical
@@ -757,6 +797,21 @@ int launch_gs_colour(const DevLevel& L, const T* S, int colour, T* x, const T* f
 }
 
 template <typename T>
+int launch_kaczmarz_colour(const DevLevel& L, const T* S, int colour, T* x, const T* f, int m,
+                           hipStream_t s) {
+  if (colour < 0 || colour >= L.n_colours2) {
+    set_error("Kaczmarz colour %d out of range [0, %d)", colour, L.n_colours2);
+    return BMG_EINVAL;
+  }
+  const int64_t b = L.colour2_ptr[colour], e = L.colour2_ptr[colour + 1];
+  if (e <= b) return BMG_OK;
+  Geom g = row_geom<T>(e - b, m);
+  BMG_BY_WIDTH(L.W, (k_kaczmarz<T, 7>), (k_kaczmarz<T, 0>), g.grid, g.block, 0, s, e - b,
+               L.colour2_rows + b, L.W, m, g.cpr, g.rpb, L.cols, S, x, f);
+  return check_launch();
+}
+
+template <typename T>
 int launch_jacobi2z(const DevLevel& L, const T* S, double omega, const T* f, T* y, int m,
                     hipStream_t s) {
   Geom g = row_geom<T>(L.n, m);
@@ -879,6 +934,8 @@ int launch_write_evecs(int64_t n, const double* U, int m, const int* sel, const 
   template int launch_jacobi<T>(const DevLevel&, const T*, double, const T*, const T*, T*, bool, \
                                 int, hipStream_t, double*);                                               \
   template int launch_gs_colour<T>(const DevLevel&, const T*, int, T*, const T*, int, hipStream_t); \
+  template int launch_kaczmarz_colour<T>(const DevLevel&, const T*, int, T*, const T*, int,      \
+                                         hipStream_t);                                           \
   template int launch_eigres<T>(const DevLevel&, const double*, const double*, double, T*,       \
                                 double*, int, int, hipStream_t);                                 \
   template int launch_restrict<T>(const DevLevel&, const T*, T*, int, hipStream_t);              \

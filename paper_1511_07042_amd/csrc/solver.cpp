@@ -367,6 +367,7 @@ struct Cycle {
                  const std::vector<double>& phi0, const std::vector<double>& gh, int top) {
     tail_hi = -1;
     if (std::getenv("BMG_NO_TAIL")) return BMG_OK;
+    if (c.smoother == BMG_SMOOTH_KACZMARZ) return BMG_OK;  // the LDS tail runs Jacobi and GS
     const int nl = top + 1;
     if (nl > kTailMaxLevels) return BMG_OK;
     auto al = [](size_t x) { return (x + 15) / 16 * 16; };
@@ -513,6 +514,19 @@ struct Cycle {
     }
     if (from_zero) BMG_TRY(launch_fill<T>(e[l], D.n * c.m, T(0), s));
     const int kc = kclass(BMG_K_SMOOTH, l);
+    if (c.smoother == BMG_SMOOTH_KACZMARZ) {
+      for (int k = 0; k < D.n_colours2; ++k) {
+        const int col = forward ? k : D.n_colours2 - 1 - k;
+        const double nk = double(H.colour2_ptr[col + 1] - H.colour2_ptr[col]);
+        // ELL row (index + value) of each row of the colour, f and the gathered
+        // neighbour rows of x, and the neighbour rows written back
+        if (kt) kt->add(kc, (4 + b) * H.W * nk + b * c.m * nk * (1 + 2 * H.W), 1);
+        if (kt) BMG_TRY(kt->begin(kc));
+        BMG_TRY(launch_kaczmarz_colour<T>(D, S[l], col, e[l], f[l], c.m, s));
+        if (kt) BMG_TRY(kt->end(kc));
+      }
+      return BMG_OK;
+    }
     for (int k = 0; k < D.n_colours; ++k) {
       const int col = forward ? k : D.n_colours - 1 - k;
       const double nk = double(H.colour_ptr[col + 1] - H.colour_ptr[col]);
@@ -1262,7 +1276,9 @@ int solve(bmg_hierarchy* h, int k, double sigma, double tol, const bmg_solve_opt
     BMG_CHECK(o.n_c % 2 == 0 && o.n_c >= 2 && o.n_c <= h->n0, "n_c must be even and in [2, N_0]");
   BMG_CHECK(o.n_c + o.m <= 96, "n_c + m = %d exceeds 96", o.n_c + o.m);
   BMG_CHECK(o.nu1 >= 0 && o.nu2 >= 0 && o.nu1 <= 64 && o.nu2 <= 64, "nu1, nu2 must be in [0, 64]");
-  BMG_CHECK(o.smoother == BMG_SMOOTH_GS || o.smoother == BMG_SMOOTH_JACOBI, "unknown smoother");
+  BMG_CHECK(o.smoother == BMG_SMOOTH_GS || o.smoother == BMG_SMOOTH_JACOBI ||
+                o.smoother == BMG_SMOOTH_KACZMARZ,
+            "unknown smoother");
   BMG_CHECK(o.precision == BMG_FP64 || o.precision == BMG_MIXED, "unknown precision");
   BMG_CHECK(o.max_cycles >= 0, "max_cycles must be >= 0");
   BMG_CHECK(o.omega > 0 && o.omega < 2, "omega must be in (0, 2)");

@@ -1,6 +1,7 @@
 """Parity at the full C4 size (sphere refined 8 times: 655362 vertices).
 
 Kernels at levels 7 (163842 rows) and 8 with the solve's block width m = 80
+(Jacobi, Gauss-Seidel and Kaczmarz sweeps among them)
 (and 12 coarse columns where the solve has them), element by element against
 the oracle's own pencil and transfers.  At these sizes the row kernels wrap
 their grids (more than 8192 row groups), the Gram kernel visits row chunks in
@@ -117,6 +118,15 @@ def test_sweeps_and_transfers(c4, level):
                 sigma=2.0, smoother="gs")
         torch.cuda.synchronize()
         assert np.max(np.abs(_host(y) - ref)) < 1e-11 * max(1.0, np.max(np.abs(ref))), forward
+    kz = ob.Smoother(L, 2.0, "kaczmarz", 1.0)
+    for forward in (True, False):
+        ref = kz.sweep(e, f, forward=forward)
+        for dt, tol in ((torch.float64, 1e-11), (torch.float32, 1e-4)):
+            y = _dev(torch, e, dt)
+            h.apply("smooth_fwd" if forward else "smooth_bwd", f=_dev(torch, f, dt), y=y, level=level,
+                    sigma=2.0, smoother="kaczmarz")
+            torch.cuda.synchronize()
+            assert np.max(np.abs(_host(y) - ref)) < tol * max(1.0, np.max(np.abs(ref))), ("kaczmarz", dt)
     P = L.P
     nf, nc = P.shape
     for dt, tol in ((torch.float64, 1e-15), (torch.float32, 1e-6)):

@@ -64,7 +64,8 @@ def test_host_hierarchy_matches_oracle(lib, kind, nref, kw):
         assert np.all(cols[:, 0] == np.arange(len(cols)))  # diagonal first
         assert abs(Ah - A).max() <= 1e-13 * abs(A).max()
         assert abs(Mh - M).max() <= 1e-14 * abs(M).max()  # summation order only
-        assert np.array_equal(h.export(l, "colours"), colour.greedy_colouring(A))
+        assert np.array_equal(h.export(l, "colours"), colour.greedy_colouring(M))
+        assert np.array_equal(h.export(l, "colours2"), colour.distance2_colouring(M))
         assert np.allclose(h.export(l, "lumped"), fem.lumped_mass(M), rtol=1e-14)
         inf = h.info(l)
         # structural nonzeros: diagonal + both directions of every edge

@@ -83,13 +83,16 @@ def test_compare_cut_cluster_uses_the_full_reference_group(sphere3):
 def test_colouring_is_proper_on_every_level(kind, nref):
     axes = (1.0, 1.5, 2.0) if kind == "ellipsoid" else (1.0, 1.0, 1.0)
     for lv in bmg.build_levels(kind, nref, axes=axes):
-        col = colour.greedy_colouring(lv.A)
-        A = lv.A.tocoo()
+        # the smoothers' operator S = A - sigma M couples every mesh edge: its
+        # pattern is that of M (A alone has exact zeros on the torus grid)
+        col = lv.colours
+        assert np.array_equal(col, colour.greedy_colouring(lv.M))
+        A = (lv.A - 0.7 * lv.M).tocoo()
         off = A.row != A.col
         assert np.all(col[A.row[off]] != col[A.col[off]])
         # greedy in index order: each vertex has a lower-index neighbour of
         # every smaller colour (otherwise it would have taken that colour)
-        Acsr = lv.A.tocsr()
+        Acsr = lv.M.tocsr()
         for i in range(0, lv.n, max(1, lv.n // 200)):
             nb = Acsr.indices[Acsr.indptr[i]:Acsr.indptr[i + 1]]
             lower = set(col[nb[nb < i]])
