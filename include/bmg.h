@@ -320,6 +320,33 @@ int bmg_solve(bmg_hierarchy* h, int32_t k, double sigma, double tol, const bmg_s
               double* evals, double* evecs, int64_t ld, int32_t evecs_on_device, void* stream,
               bmg_solve_stats* stats);
 
+/* ------------------------------------------------------------ two-grid --- */
+
+/* The two-grid eigensolver with a spectral shift (Alg. 1) applied in a cascade
+ * between neighbouring levels (Remark 3.1), the fine source problem of
+ * eq. (pb-f-s) relaxed by Kaczmarz sweeps (Sec. 5.3; the remark after Alg. 1).
+ * All eigenpairs of (A_H, M_H) on level_H are computed (at most 12288
+ * vertices; kept with the hierarchy); the pairs idx (host [n], indices into
+ * that ascending spectrum) are followed.  On each level k = level_H + 1..top,
+ * for every pair c: u = P u_c, then nu multicolour Kaczmarz sweeps
+ * (alternating directions, forward first; FP64) on
+ *   (A_k - theta_c M_k) x = M_k u   from x = u,
+ * theta_c the pair's value on level k - 1 (on level_H its coarse eigenvalue;
+ * the fixed shift mu of Alg. 1 cancels, since the fine problem uses
+ * mu + lambda_H); theta_c <- x^T A_k x / x^T M_k x and u_c <- x / |x|_M.
+ * A coarse mesh too coarse for an eigenfunction's wavelength sends it to
+ * another eigenvalue (the loss of spectra of Sec. 5.1).
+ *   level_H in [0, L]; top in [level_H, L] or -1 for L; n in [1, 512];
+ *   nu in [0, 64] (the paper uses 5).
+ *   evals: host [L + 1][n]; row l (level_H <= l <= top) receives the values
+ *     on level l in the order of idx; other rows are not written.
+ *   evecs: NULL, or host column-major [n][N_top] (column c = pair c), unit
+ *     M_top-norm.
+ * Blocks until done; allocates its work buffers per call (4 N_top n doubles).
+ * BMG_EINVAL on a bad argument, BMG_ENOMEM, BMG_EDEVICE. */
+int bmg_two_grid(bmg_hierarchy* h, int32_t level_H, int32_t n, const int32_t* idx, int32_t top,
+                 int32_t nu, double* evals, double* evecs, void* stream);
+
 /* ------------------------------------------------ single-operator hook --- */
 
 typedef enum {

@@ -18,7 +18,9 @@ fem        P1 surface-FEM stiffness and mass matrices (Sec. 2, eqs. bl-dis, pb-e
 transfer   geometric prolongation P_h and restriction P_h^T (Sec. 3, eq. proj-1)
 colour     greedy vertex colouring for the multicolour Gauss-Seidel smoother
 rng        counter-based Gaussian test vectors (SplitMix64 + Box-Muller)
-bmg        the BMG cycle iterated to a residual certificate (Alg. 2/3, Remark 3.2)
+bmg        the BMG cycle iterated to a residual certificate (Alg. 2/3, Remark 3.2),
+           the level ramp (Alg. 4) and the smoothers (Jacobi, GS, Kaczmarz)
+twogrid    the two-grid Alg. 1 applied in a cascade (Remark 3.1)
 reference  the plain definition of the result: library generalized eigensolves
 
 Parity status: every function here is pinned by the ``-m "not gpu"`` tests in

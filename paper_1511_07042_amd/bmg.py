@@ -89,6 +89,8 @@ _sig = {
                             C.POINTER(C.c_double), C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
                             C.POINTER(SolveStats)]),
     "bmg_apply": (C.c_int, [_H, C.POINTER(ApplyArgs), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "bmg_two_grid": (C.c_int, [_H, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.c_int32,
+                               C.POINTER(C.c_double), C.c_void_p, C.c_void_p]),
     "bmg_gram_am_noalloc": (C.c_int, [_H, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32,
                                       C.c_void_p, C.c_void_p]),
     "bmg_server_create": (C.c_int, [C.c_int64, C.c_int32, C.POINTER(C.c_void_p)]),
@@ -276,6 +278,22 @@ class Hierarchy:
         stats.update(rho=rho, delta=delta, status=status, ramp_evals=ramp)
         V = None if out is None else out.T
         return evals, V, stats
+
+    def two_grid(self, level_H, idx, top=-1, nu=5, evecs=True, stream=None):
+        """Cascade of the two-grid Alg. 1 from level_H (see bmg_two_grid).
+
+        Returns (rows [n_levels, n] with NaN outside level_H..top, vectors
+        [N_top, n] or None)."""
+        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        n = len(idx)
+        rows = np.full((self.n_levels, n), np.nan)
+        top_l = self.n_levels - 1 if top < 0 else int(top)
+        V = np.zeros((n, self.info(top_l)["n_vert"])) if evecs else None
+        _check(_lib.bmg_two_grid(self._h, int(level_H), n, idx.ctypes.data_as(C.POINTER(C.c_int32)),
+                                 int(top), int(nu), rows.ctypes.data_as(C.POINTER(C.c_double)),
+                                 None if V is None else V.ctypes.data, _stream_ptr(stream)),
+               "bmg_two_grid")
+        return rows, (None if V is None else V.T)
 
     def apply(self, op, x=None, f=None, y=None, level=None, m=None, m2=0, dtype=None, sigma=0.0,
               smoother="gs", nu1=2, nu2=2, l_c=-1, omega=0.85, seed=0, stream=None):

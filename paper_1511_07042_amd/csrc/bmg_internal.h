@@ -185,6 +185,9 @@ int default_coarse_vectors(const bmg_hierarchy* h);
 int solve(bmg_hierarchy* h, int k, double sigma, double tol, const bmg_solve_opts* opts,
           double* evals, double* evecs, int64_t ld, int evecs_on_device, void* stream,
           bmg_solve_stats* stats);
+// Two-grid cascade of Alg. 1 (twogrid.cpp); see bmg_two_grid in bmg.h.
+int two_grid(bmg_hierarchy* h, int level_H, int n, const int32_t* idx, int top, int nu, double* evals,
+             double* evecs, hipStream_t s);
 
 // ------------------------------------------------------------- launchers --
 // Kernel timing: a caller that wants the next launch timed sets `start` and
@@ -248,6 +251,14 @@ int launch_gs_colour(const DevLevel& L, const T* S, int colour, T* x, const T* f
 template <typename T>
 int launch_kaczmarz_colour(const DevLevel& L, const T* S, int colour, T* x, const T* f, int m,
                            hipStream_t s);
+// The same in FP64 with a shift per column: column c relaxes
+// (A - shifts[c] M) x_c = f_c (shifts: device [m]; m even).
+int launch_kaczmarz_shifts_colour(const DevLevel& L, int colour, const double* shifts, double* x,
+                                  const double* f, int m, hipStream_t s);
+// Per column: rq[c] = u_c^T A u_c / u_c^T M u_c over the level's rows, then
+// u_c scaled in place to unit M-norm (a zero column stays zero, rq[c] = 0).
+// part: [kRqBlocks][2m] doubles; rq: device [2m] (rq, then 1 / M-norms).
+int launch_rq_normalise(const DevLevel& L, double* U, int m, double* part, double* rq, hipStream_t s);
 // Fused cycle kernels (identical results to the unfused sequences):
 // two Jacobi sweeps from zero; residual + restriction; prolongation + one
 // Jacobi sweep.

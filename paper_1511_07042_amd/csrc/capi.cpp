@@ -225,6 +225,12 @@ int bmg_solve(bmg_hierarchy* h, int32_t k, double sigma, double tol, const bmg_s
   return bmg::solve(h, k, sigma, tol, opts, evals, evecs, ld, evecs_on_device, stream, stats);
 }
 
+int bmg_two_grid(bmg_hierarchy* h, int32_t level_H, int32_t n, const int32_t* idx, int32_t top,
+                 int32_t nu, double* evals, double* evecs, void* stream) {
+  BMG_CHECK(h != nullptr && !h->dev.empty(), "hierarchy has no device data");
+  return bmg::two_grid(h, level_H, n, idx, top, nu, evals, evecs, static_cast<hipStream_t>(stream));
+}
+
 int bmg_apply(const bmg_hierarchy* hc, const bmg_apply_args* a, const void* x, const void* f,
               void* y, void* stream) {
   BMG_CHECK(hc && a, "NULL argument");

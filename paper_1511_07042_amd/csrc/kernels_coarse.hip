@@ -245,7 +245,47 @@ __global__ void __launch_bounds__(256) k_offsets(int lo, int top, int m, int nbl
   if (threadIdx.x == 0) shifts[top] = sigma;
 }
 
+// rq[c] = qA_c / qM_c and rq[m + c] = 1 / sqrt(qM_c) from the partial sums
+// part[b][2m] (zero columns: both 0).  One workgroup; blocks added in order.
+__global__ void __launch_bounds__(256) k_rq_final(int m, int nblk, const double* __restrict__ part,
+                                                  double* __restrict__ rq) {
+  for (int c = threadIdx.x; c < m; c += blockDim.x) {
+    double qa = 0, qm = 0;
+    for (int b = 0; b < nblk; ++b) {
+      qa += part[int64_t(b) * 2 * m + c];
+      qm += part[int64_t(b) * 2 * m + m + c];
+    }
+    rq[c] = qm > 0 ? qa / qm : 0.0;
+    rq[m + c] = qm > 0 ? 1.0 / sqrt(qm) : 0.0;
+  }
+}
+
+// U[i][c] *= scale[c]
+__global__ void __launch_bounds__(256) k_scale_cols(int64_t n, int m, double* __restrict__ U,
+                                                    const double* __restrict__ scale) {
+  const int64_t total = n * m;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x)
+    U[e] *= scale[e % m];
+}
+
 }  // namespace
+
+int launch_rq_normalise(const DevLevel& L, double* U, int m, double* part, double* rq, hipStream_t s) {
+  if (m % 2 != 0 || m < 2 || m > 512) {
+    set_error("Rayleigh quotients: m = %d must be even and at most 512", m);
+    return BMG_EINVAL;
+  }
+  const int nblk = kRqBlocks;
+  if (L.W == 7)
+    k_rq_part<7><<<nblk, 256, 0, s>>>(L.n, L.W, m, L.cols, L.a64, L.m64, U, part);
+  else
+    k_rq_part<0><<<nblk, 256, 0, s>>>(L.n, L.W, m, L.cols, L.a64, L.m64, U, part);
+  k_rq_final<<<1, 256, 0, s>>>(m, nblk, part, rq);
+  const int64_t total = L.n * m;
+  k_scale_cols<<<int(std::min<int64_t>((total + 255) / 256, 4096)), 256, 0, s>>>(L.n, m, U, rq + m);
+  return check_launch_c();
+}
 
 int spec_slices(int n) {
   const int tiles = (n + kTile - 1) / kTile;

@@ -201,6 +201,49 @@ __global__ void __launch_bounds__(256) k_kaczmarz(int64_t cnt, const int* __rest
   }
 }
 
+// The same projections with a shift per column (FP64): column c relaxes
+// (A - shifts[c] M) x_c = f_c, the operator formed on the fly from A and M.
+// A thread owns two columns of one row (m even).
+template <int WT>
+__global__ void __launch_bounds__(256) k_kaczmarz_shifts(int64_t cnt, const int* __restrict__ rows,
+                                                         int W, int m, const int* __restrict__ cols,
+                                                         const double* __restrict__ a,
+                                                         const double* __restrict__ mm,
+                                                         const double* __restrict__ shifts, double* x,
+                                                         const double* __restrict__ f) {
+  const int cpr = m >> 1;
+  const int rpb = 256 / cpr;
+  const int rloc = threadIdx.x / cpr;
+  const int ch = threadIdx.x - rloc * cpr;
+  if (rloc >= rpb) return;
+  const double s0 = shifts[2 * ch], s1 = shifts[2 * ch + 1];
+  const int w = WT > 0 ? WT : W;
+  for (int64_t i = int64_t(blockIdx.x) * rpb + rloc; i < cnt; i += int64_t(gridDim.x) * rpb) {
+    const int64_t r = rows[i];
+    const int64_t base = r * W;
+    double acc0 = 0, acc1 = 0, q0 = 0, q1 = 0;
+    for (int k = 0; k < w; ++k) {
+      const double av = a[base + k], mv = mm[base + k];
+      const double v0 = av - s0 * mv, v1 = av - s1 * mv;
+      const double2 xv = *reinterpret_cast<const double2*>(x + int64_t(cols[base + k]) * m + 2 * ch);
+      acc0 += v0 * xv.x;
+      acc1 += v1 * xv.y;
+      q0 += v0 * v0;
+      q1 += v1 * v1;
+    }
+    const double2 fv = *reinterpret_cast<const double2*>(f + r * m + 2 * ch);
+    const double t0 = (fv.x - acc0) / q0, t1 = (fv.y - acc1) / q1;
+    for (int k = 0; k < w; ++k) {
+      const double av = a[base + k], mv = mm[base + k];
+      double2* xj = reinterpret_cast<double2*>(x + int64_t(cols[base + k]) * m + 2 * ch);
+      double2 v = *xj;
+      v.x += t0 * (av - s0 * mv);
+      v.y += t1 * (av - s1 * mv);
+      *xj = v;
+    }
+  }
+}
+
 // ---------------------------------------------------- fused cycle kernels --
 // Each computes, row by row, what a sequence of the kernels above computes,
 // with the same operations in the same order (so the results are identical
@@ -808,6 +851,22 @@ int launch_kaczmarz_colour(const DevLevel& L, const T* S, int colour, T* x, cons
   Geom g = row_geom<T>(e - b, m);
   BMG_BY_WIDTH(L.W, (k_kaczmarz<T, 7>), (k_kaczmarz<T, 0>), g.grid, g.block, 0, s, e - b,
                L.colour2_rows + b, L.W, m, g.cpr, g.rpb, L.cols, S, x, f);
+  return check_launch();
+}
+
+int launch_kaczmarz_shifts_colour(const DevLevel& L, int colour, const double* shifts, double* x,
+                                  const double* f, int m, hipStream_t s) {
+  if (colour < 0 || colour >= L.n_colours2 || m < 2 || m % 2 != 0 || m > 512) {
+    set_error("Kaczmarz (per-column shifts): colour %d of %d, m = %d (even, at most 512)", colour,
+              L.n_colours2, m);
+    return BMG_EINVAL;
+  }
+  const int64_t b = L.colour2_ptr[colour], e = L.colour2_ptr[colour + 1];
+  if (e <= b) return BMG_OK;
+  const int rpb = 256 / (m / 2);
+  const int grid = int(std::min<int64_t>((e - b + rpb - 1) / rpb, 8192));
+  BMG_BY_WIDTH(L.W, k_kaczmarz_shifts<7>, k_kaczmarz_shifts<0>, grid, 256, 0, s, e - b,
+               L.colour2_rows + b, L.W, m, L.cols, L.a64, L.m64, shifts, x, f);
   return check_launch();
 }
 
