@@ -320,6 +320,29 @@ int bmg_solve(bmg_hierarchy* h, int32_t k, double sigma, double tol, const bmg_s
               double* evals, double* evecs, int64_t ld, int32_t evecs_on_device, void* stream,
               bmg_solve_stats* stats);
 
+/* ----------------------------------------------------------- estimator --- */
+
+/* The a posteriori error estimator of eq. est-res (Sec. 5) for k eigenpairs
+ * (evals[j], column j of evecs) of level `level`: per triangle T
+ *   eta_T^2 = h_T^2 lambda^2 |u|^2_{L2(T)}
+ *           + 1/2 sum_{e in dT} |e| |[grad u . mu_e]|^2_{L2(e)}
+ *           + |B_h grad u|^2_{L2(T)},
+ * eta(u) = (sum_T eta_T^2)^(1/2).  h_T: longest edge of T; the jump is the
+ * sum of the two outward conormal derivatives across e (mu_e in the plane of
+ * each triangle, normal to e); B_h = A_h - P_h, the geometric error of the
+ * Dirichlet form under the lift onto the exact surface, is taken for the
+ * sphere (radial lift: A_h = c P_h + t t^T / c with nu = x/|x|, c = nu . n_T,
+ * t = nu - c n_T; edge-midpoint rule) and is 0 for other surfaces.
+ *   evals: host [k];  evecs: device, column-major [k][ld] (the layout
+ *     bmg_solve writes with evecs_on_device = 1), ld >= N_level.
+ *   eta: host [k];  parts: nullable host [3][k] (the sums of the three terms);
+ *   eta2_T: nullable device [F_level], sum over the k pairs of eta_T^2.
+ * The level's triangles are uploaded on first use and kept with the
+ * hierarchy.  Blocks until eta is on the host.  BMG_EINVAL, BMG_ENOMEM,
+ * BMG_EDEVICE. */
+int bmg_estimate(bmg_hierarchy* h, int32_t level, int32_t k, const double* evals, const double* evecs,
+                 int64_t ld, double* eta, double* parts, double* eta2_T, void* stream);
+
 /* ------------------------------------------------------------ two-grid --- */
 
 /* The two-grid eigensolver with a spectral shift (Alg. 1) applied in a cascade

@@ -21,6 +21,7 @@ rng        counter-based Gaussian test vectors (SplitMix64 + Box-Muller)
 bmg        the BMG cycle iterated to a residual certificate (Alg. 2/3, Remark 3.2),
            the level ramp (Alg. 4) and the smoothers (Jacobi, GS, Kaczmarz)
 twogrid    the two-grid Alg. 1 applied in a cascade (Remark 3.1)
+estimator  the a posteriori error estimator eta_T (Sec. 5, eq. est-res)
 reference  the plain definition of the result: library generalized eigensolves
 
 Parity status: every function here is pinned by the ``-m "not gpu"`` tests in

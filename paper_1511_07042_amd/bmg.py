@@ -89,6 +89,8 @@ _sig = {
                             C.POINTER(C.c_double), C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
                             C.POINTER(SolveStats)]),
     "bmg_apply": (C.c_int, [_H, C.POINTER(ApplyArgs), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "bmg_estimate": (C.c_int, [_H, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_void_p, C.c_int64,
+                               C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p, C.c_void_p]),
     "bmg_two_grid": (C.c_int, [_H, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.c_int32,
                                C.POINTER(C.c_double), C.c_void_p, C.c_void_p]),
     "bmg_gram_am_noalloc": (C.c_int, [_H, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32,
@@ -278,6 +280,30 @@ class Hierarchy:
         stats.update(rho=rho, delta=delta, status=status, ramp_evals=ramp)
         V = None if out is None else out.T
         return evals, V, stats
+
+    def estimate(self, evals, evecs, level=None, per_triangle=False, stream=None):
+        """bmg_estimate on a torch.cuda FP64 tensor evecs [N, k] (columns
+        contiguous, as solve(evecs="device") returns).  Returns (eta [k],
+        parts [3, k], eta2_T [F] torch tensor or None)."""
+        import torch
+        lvl = self.n_levels - 1 if level is None else int(level)
+        evals = np.ascontiguousarray(evals, dtype=np.float64)
+        k = len(evals)
+        V = evecs.T
+        assert V.is_cuda and V.dtype == torch.float64 and V.is_contiguous(), \
+            "evecs must be an [N, k] view of a contiguous [k, N] FP64 CUDA tensor"
+        ld = V.shape[1]
+        eta = np.zeros(k)
+        parts = np.zeros((3, k))
+        e2 = None
+        if per_triangle:
+            e2 = torch.zeros(self.info(lvl)["n_tri"], dtype=torch.float64, device=V.device)
+        _check(_lib.bmg_estimate(self._h, lvl, k, evals.ctypes.data_as(C.POINTER(C.c_double)),
+                                 C.c_void_p(V.data_ptr()), int(ld), eta.ctypes.data_as(C.POINTER(C.c_double)),
+                                 parts.ctypes.data_as(C.POINTER(C.c_double)),
+                                 None if e2 is None else C.c_void_p(e2.data_ptr()), _stream_ptr(stream)),
+               "bmg_estimate")
+        return eta, parts, e2
 
     def two_grid(self, level_H, idx, top=-1, nu=5, evecs=True, stream=None):
         """Cascade of the two-grid Alg. 1 from level_H (see bmg_two_grid).

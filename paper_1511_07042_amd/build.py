@@ -15,9 +15,9 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libbmg.so")
 
-SOURCES = ["mesh.cpp", "assemble.cpp", "dense_host.cpp", "order.cpp", "hierarchy.cpp", "twogrid.cpp", "solver.cpp",
+SOURCES = ["mesh.cpp", "assemble.cpp", "dense_host.cpp", "order.cpp", "hierarchy.cpp", "twogrid.cpp", "estimate.cpp", "solver.cpp",
            "capi.cpp", "server.cpp", "dense_device.cpp", "kernels_sparse.hip", "kernels_gram.hip",
-           "kernels_dense.hip", "kernels_tail.hip", "kernels_coarse.hip"]
+           "kernels_dense.hip", "kernels_tail.hip", "kernels_coarse.hip", "kernels_estimate.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

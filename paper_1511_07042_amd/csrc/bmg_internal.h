@@ -119,6 +119,18 @@ struct DevLevel {
   int64_t bytes = 0;
 };
 
+// Triangles of one level on the device for the a posteriori estimator:
+// tri [F][3], nbr [F][3] = 4 t' + j for the neighbour t' across edge i
+// (opposite vertex i) and that edge's index j in t', xyz [N][3].
+struct EstLevel {
+  int level = -1;
+  int64_t F = 0;
+  int32_t* tri = nullptr;
+  int32_t* nbr = nullptr;
+  double* xyz = nullptr;
+  int64_t bytes = 0;
+};
+
 // All generalized eigenpairs of one level (Alg. 2 step 1 taken at a finer
 // coarse level; the interior-shift scheme's coarse solve and start block).
 // Built on first use and kept with the hierarchy: it does not depend on the
@@ -153,6 +165,11 @@ struct bmg_hierarchy {
   // per-level eigendecompositions of the interior-shift scheme (by level)
   std::mutex eig_mutex;
   std::vector<std::unique_ptr<bmg::LevelEig>> level_eig;
+  // the surface (bmg_surface_kind) the hierarchy was built for
+  int kind = -1;
+  // per-level triangle data of the a posteriori estimator (by level)
+  std::mutex est_mutex;
+  std::vector<std::unique_ptr<bmg::EstLevel>> est;
 };
 
 namespace bmg {
@@ -185,6 +202,15 @@ int default_coarse_vectors(const bmg_hierarchy* h);
 int solve(bmg_hierarchy* h, int k, double sigma, double tol, const bmg_solve_opts* opts,
           double* evals, double* evecs, int64_t ld, int evecs_on_device, void* stream,
           bmg_solve_stats* stats);
+// A posteriori estimator of eq. est-res (estimate.cpp); see bmg_estimate in bmg.h.
+int estimate(bmg_hierarchy* h, int level, int k, const double* evals, const double* evecs, int64_t ld,
+             double* eta, double* parts, double* eta2_T, hipStream_t s);
+void free_est_levels(bmg_hierarchy* h);
+// Per-triangle kernel and the fixed-order reduction of its per-block sums
+// (kernels_estimate.hip): part [nblk][k][3], out [3][k].
+int est_blocks(int64_t F);
+int launch_estimate(const EstLevel& E, int k, const double* U, int64_t ld, const double* lam,
+                    int sphere, double* eta2_T, double* part, double* out, hipStream_t s);
 // Two-grid cascade of Alg. 1 (twogrid.cpp); see bmg_two_grid in bmg.h.
 int two_grid(bmg_hierarchy* h, int level_H, int n, const int32_t* idx, int top, int nu, double* evals,
              double* evecs, hipStream_t s);

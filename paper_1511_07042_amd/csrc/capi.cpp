@@ -102,6 +102,7 @@ static int build_impl(const bmg_surface_desc* desc, int32_t n_refine, void* stre
   TraceRange trace("bmg_build_hierarchy");
   bmg_hierarchy* h = new (std::nothrow) bmg_hierarchy();
   if (!h) return BMG_ENOMEM;
+  if (desc) h->kind = desc->kind;
   int st = build_host_levels(desc, n_refine, h->host);
   for (size_t l = 0; st == BMG_OK && l < h->host.size(); ++l)
     st = assemble_level(h->host[l], l ? &h->host[l - 1] : nullptr);
@@ -223,6 +224,12 @@ int bmg_solve(bmg_hierarchy* h, int32_t k, double sigma, double tol, const bmg_s
               bmg_solve_stats* stats) {
   BMG_CHECK(h != nullptr && !h->dev.empty(), "hierarchy has no device data");
   return bmg::solve(h, k, sigma, tol, opts, evals, evecs, ld, evecs_on_device, stream, stats);
+}
+
+int bmg_estimate(bmg_hierarchy* h, int32_t level, int32_t k, const double* evals, const double* evecs,
+                 int64_t ld, double* eta, double* parts, double* eta2_T, void* stream) {
+  BMG_CHECK(h != nullptr && !h->dev.empty(), "hierarchy has no device data");
+  return bmg::estimate(h, level, k, evals, evecs, ld, eta, parts, eta2_T, static_cast<hipStream_t>(stream));
 }
 
 int bmg_two_grid(bmg_hierarchy* h, int32_t level_H, int32_t n, const int32_t* idx, int32_t top,

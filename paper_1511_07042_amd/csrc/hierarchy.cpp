@@ -169,6 +169,7 @@ void free_level_eigs(bmg_hierarchy* h) {
 
 void free_device(bmg_hierarchy* h) {
   free_level_eigs(h);
+  free_est_levels(h);
   for (auto& D : h->dev) {
     void* ptrs[] = {D.cols, D.a64, D.m64, D.a32, D.m32, D.dinv, D.parents, D.rtab, D.colour_rows, D.row_order, D.chunk_order, D.colour2_rows};
     for (void* p : ptrs)
