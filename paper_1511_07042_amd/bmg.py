@@ -27,6 +27,9 @@ EXPORTS = {"xyz": 0, "tri": 1, "parents": 2, "ell_cols": 3, "ell_a": 4, "ell_m":
 KERNEL_CLASSES = {"eigres": 0, "spmm_am": 1, "smooth": 2, "residual": 3, "restrict": 4,
                   "prolong": 5, "gram": 6, "update": 7, "ritz": 8, "smooth_pair": 9,
                   "restrict_res": 10, "prolong_smooth": 11, "smooth_add": 12}
+# operators whose output y is in the operator's precision (dtype 0: FP64, 1: FP32)
+T_OUT_OPS = {"A", "M", "shifted", "residual", "smooth_fwd", "smooth_bwd", "restrict", "prolong_add",
+             "vcycle", "eigres", "coarse_solve"}
 OPS = {"A": 0, "M": 1, "shifted": 2, "residual": 3, "smooth_fwd": 4, "smooth_bwd": 5,
        "restrict": 6, "prolong_add": 7, "vcycle": 8, "gaussian": 9, "gram": 10, "syev": 11,
        "eigres": 12, "update": 13, "gram_am": 14, "coarse_solve": 15, "shift_offsets": 16}
@@ -330,7 +333,13 @@ class Hierarchy:
         a.op = OPS[op]
         ref = x if x is not None else y
         if dtype is None:
+            if op in T_OUT_OPS and x is not None and y is not None and x.dtype != y.dtype:
+                raise ValueError(f"{op}: x is {x.dtype} and y is {y.dtype}; pass dtype explicitly")
             dtype = 1 if ref.dtype == torch.float32 else 0
+        if op in T_OUT_OPS and y is not None and y.dtype != (torch.float32 if dtype else torch.float64):
+            # the library writes y in the operator's precision and cannot see its size
+            raise ValueError(f"{op}: y is {y.dtype} but the operator writes "
+                             f"{'float32' if dtype else 'float64'}")
         a.dtype = int(dtype)
         a.m = int(m if m is not None else ref.shape[-1])
         a.m2 = int(m2)

@@ -140,3 +140,21 @@ def test_server_arguments_and_missing_device(lib):
 def test_finest_vertex_formula(lib, kind, nref, kw):
     h = lib.Hierarchy(kind, nref, device=False, **kw)
     assert lib.finest_vertices(kind, nref, **{k: v for k, v in kw.items() if k in ("nu", "nv")}) == h.N
+
+
+def test_apply_rejects_an_output_of_the_wrong_precision(lib):
+    # the library writes y in the operator's precision without knowing its
+    # size, so the binding refuses a y of the other precision before any call
+    import torch
+
+    class _H:
+        n_levels = 3
+    x64 = torch.zeros((8, 4), dtype=torch.float64)
+    y32 = torch.zeros((8, 4), dtype=torch.float32)
+    with pytest.raises(ValueError):
+        lib.Hierarchy.apply(_H(), "eigres", x=x64, f=torch.zeros(4, dtype=torch.float64), y=y32)
+    with pytest.raises(ValueError):
+        lib.Hierarchy.apply(_H(), "eigres", x=x64, f=torch.zeros(4, dtype=torch.float64), y=x64.clone(),
+                            dtype=1)
+    with pytest.raises(ValueError):
+        lib.Hierarchy.apply(_H(), "A", x=y32, y=x64.clone())
