@@ -107,11 +107,24 @@ struct DevLevel {
   float* a32 = nullptr;
   float* m32 = nullptr;
   double* dinv = nullptr;         // 1 / lumped mass
-  int32_t* parents = nullptr;     // [n - n_prev][2]
-  int32_t* rtab = nullptr;        // [n_prev][RW]
+  // Storage order: large levels keep their rows permuted along a Morton curve
+  // (storage row r is vertex perm[r], vertex i is storage row iperm[i]); both
+  // null when the level is stored in vertex order.  Row blocks on the device
+  // use the storage order; the API converts at its boundary.
+  int32_t* perm = nullptr;        // [n]
+  int32_t* iperm = nullptr;       // [n]
+  std::vector<int32_t> perm_h;    // host copy of perm (empty when null)
+  // Transfers to and from the level below, in both levels' storage rows.
+  // Nested form (par_nc = n_prev, rself null): fine row i < n_prev is coarse
+  // vertex i, parents [n - n_prev][2] are those of the new vertices.  General
+  // form (par_nc = 0): parents [n][2] for every fine row (a coarse vertex's
+  // copy names it twice), rself [n_prev] the fine row of each coarse vertex.
+  int64_t par_nc = 0;
+  int32_t* parents = nullptr;
+  int32_t* rself = nullptr;
+  int32_t* rtab = nullptr;        // [n_prev][RW] fine rows of the new vertices adjacent to coarse row i, -1 pad
   int32_t* colour_rows = nullptr; // [n]
-  int32_t* row_order = nullptr;   // [n] rows by Morton code of their vertex (large levels), else null
-  int32_t* chunk_order = nullptr; // [ceil(n / 16)] 16-row chunks by Morton code of their centroid (large levels), else null
+  int32_t* chunk_order = nullptr; // [ceil(n / 16)] 16-row chunks by Morton code of their centroid (large levels stored in vertex order), else null
   int32_t* colour2_rows = nullptr; // [n] rows grouped by distance-2 colour
   std::vector<int32_t> colour_ptr;
   int32_t n_colours2 = 0;
@@ -310,18 +323,23 @@ template <typename T>
 int launch_add_to(double* u, const T* e, int64_t count, hipStream_t s);
 template <typename T>
 int launch_convert(const double* x, T* y, int64_t count, hipStream_t s);
-int launch_gaussian(double* y, int64_t n, int m, uint64_t seed, hipStream_t s);
+// element (r, j) from counter perm[r] m + j (perm null: r m + j), so the block
+// in a permuted storage order holds the same numbers per vertex
+int launch_gaussian(double* y, int64_t n, int m, uint64_t seed, hipStream_t s, const int* perm = nullptr);
 
 // Gram: G[nz][ny] = Z^T Y with Z = [z1 (w1 cols) | z2 (w2 cols)], Y = [y1 | y2]
 // (v1, v2 cols), all FP64 [n][w] blocks.  part: [nblk][nzp][nyp].
 struct GramPlan {
   int nz, ny, nzp, nyp, nblk;
+  int64_t per_block;  // doubles of partial sums per block (the larger of the two layouts)
 };
 GramPlan gram_plan(int64_t n, int nz, int ny);
+int64_t sym_tile_doubles(int w1, int m);
 // G = [w | u]^T [A_L u | M_L u] with the products formed in LDS (fused SpMM
 // and Gram; w1 columns of w, m of u; plan for nz = w1 + m, ny = 2 m).
+// uperm (nullable): w and u are in vertex order and storage row r reads row uperm[r]
 int launch_gram_am(const GramPlan& p, const DevLevel& L, const double* w, int w1, const double* u,
-                   int m, double* part, double* G, hipStream_t s);
+                   int m, double* part, double* G, hipStream_t s, const int* uperm = nullptr);
 int launch_gram(const GramPlan& p, int64_t n, const double* z1, int w1, const double* z2, int w2,
                 const double* y1, int v1, const double* y2, int v2, double* part, double* G,
                 hipStream_t s);
@@ -401,9 +419,14 @@ int launch_offsets(const std::vector<DevLevel>& dev, int lo, int top, const doub
                    double sigma, const double* theta, double* part, double* shifts, hipStream_t s);
 
 // column-wise argmax |U[:, sel_j]| (lowest row on ties) and output writer
-int launch_signs(int64_t n, const double* U, int m, const int* sel, int k, double* sign_out,
+// signs and output of the selected columns in vertex order (iperm: the
+// storage row of each vertex, null when the storage is in vertex order)
+int launch_signs(int64_t n, const double* U, int m, const int* sel, int k, const int* iperm, double* sign_out,
                  double* part_val, int* part_idx, int nblk, hipStream_t s);
 int launch_write_evecs(int64_t n, const double* U, int m, const int* sel, const double* sign,
-                       int k, double* out, int64_t ld, hipStream_t s);
+                       int k, const int* iperm, double* out, int64_t ld, hipStream_t s);
+// y[r] = x[map[r]] for an [n][m] block
+template <typename T>
+int launch_permute_rows(int64_t n, int m, const int* map, const T* x, T* y, hipStream_t s);
 
 }  // namespace bmg

@@ -238,20 +238,18 @@ int bmg_two_grid(bmg_hierarchy* h, int32_t level_H, int32_t n, const int32_t* id
   return bmg::two_grid(h, level_H, n, idx, top, nu, evals, evecs, static_cast<hipStream_t>(stream));
 }
 
-int bmg_apply(const bmg_hierarchy* hc, const bmg_apply_args* a, const void* x, const void* f,
-              void* y, void* stream) {
-  BMG_CHECK(hc && a, "NULL argument");
-  bmg_hierarchy* h = const_cast<bmg_hierarchy*>(hc);
-  BMG_CHECK(!h->dev.empty(), "hierarchy has no device data");
-  const int nl = int(h->dev.size());
+}  // extern "C"
+
+namespace {
+
+using namespace bmg;
+
+// One operator on row blocks in the levels' storage order.
+int apply_stored(bmg_hierarchy* h, const bmg_apply_args* a, const void* x, const void* f, void* y,
+                 hipStream_t s) {
   const int l = a->level;
-  BMG_CHECK(l >= 0 && l < nl, "level %d out of range", l);
-  BMG_CHECK(a->dtype == 0 || a->dtype == 1, "dtype must be 0 (FP64) or 1 (FP32)");
   const int m = a->m;
   const DevLevel& D = h->dev[l];
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  BMG_CHECK(y != nullptr, "y must be non-NULL");
-  BMG_HIP(hipSetDevice(h->device));
   const bool f32 = a->dtype == 1;
   auto need_m = [&](int mult) -> int {
     BMG_CHECK(m >= mult && m % mult == 0 && m <= 4096, "m = %d must be a positive multiple of %d", m, mult);
@@ -352,7 +350,7 @@ int bmg_apply(const bmg_hierarchy* hc, const bmg_apply_args* a, const void* x, c
       BMG_CHECK(m >= 1 && m <= 96 && a->m2 >= 1 && a->m2 <= 192, "GRAM needs m <= 96, m2 <= 192");
       GramPlan p = gram_plan(D.n, m, a->m2);
       double* part = nullptr;
-      BMG_HIP(hipMalloc(&part, sizeof(double) * p.nblk * p.nzp * p.nyp));
+      BMG_HIP(hipMalloc(&part, sizeof(double) * p.nblk * p.per_block));
       int st = launch_gram(p, D.n, (const double*)x, m, nullptr, 0, (const double*)f, a->m2, nullptr,
                            0, part, (double*)y, s);
       (void)hipStreamSynchronize(s);
@@ -389,7 +387,7 @@ int bmg_apply(const bmg_hierarchy* hc, const bmg_apply_args* a, const void* x, c
                 "GRAM_AM needs even m, 0 <= m2, m2 + m <= 96, and x when m2 > 0");
       GramPlan p = gram_plan(D.n, a->m2 + m, 2 * m);
       double* part = nullptr;
-      BMG_HIP(hipMalloc(&part, sizeof(double) * p.nblk * p.nzp * p.nyp));
+      BMG_HIP(hipMalloc(&part, sizeof(double) * p.nblk * p.per_block));
       int st = launch_gram_am(p, D, (const double*)x, a->m2, (const double*)f, m, part, (double*)y, s);
       (void)hipStreamSynchronize(s);
       (void)hipFree(part);
@@ -454,6 +452,108 @@ int bmg_apply(const bmg_hierarchy* hc, const bmg_apply_args* a, const void* x, c
     default:
       BMG_CHECK(false, "unknown op %d", a->op);
   }
+}
+
+// The row blocks an operator reads or writes: which argument (0 x, 1 f, 2 y),
+// the level (0: the op's level, -1: the one below), direction, columns, and
+// whether the block is FP64 whatever the op's precision.
+struct RowBlock {
+  int arg, dl;
+  bool in, out;
+  int cols;
+  bool f64;
+};
+
+std::vector<RowBlock> row_blocks(const bmg_apply_args* a, const void* x) {
+  const int m = a->m;
+  switch (a->op) {
+    case BMG_OP_A:
+    case BMG_OP_M: return {{0, 0, true, false, m, true}, {2, 0, false, true, m, true}};
+    case BMG_OP_SHIFTED: return {{0, 0, true, false, m, false}, {2, 0, false, true, m, false}};
+    case BMG_OP_RESIDUAL:
+      return {{0, 0, true, false, m, false}, {1, 0, true, false, m, false}, {2, 0, false, true, m, false}};
+    case BMG_OP_SMOOTH_FWD:
+    case BMG_OP_SMOOTH_BWD: {
+      std::vector<RowBlock> b{{1, 0, true, false, m, false}, {2, 0, true, true, m, false}};
+      if (x) b.push_back({0, 0, true, false, m, false});
+      return b;
+    }
+    case BMG_OP_RESTRICT: return {{0, 0, true, false, m, false}, {2, -1, false, true, m, false}};
+    case BMG_OP_PROLONG_ADD: return {{0, -1, true, false, m, false}, {2, 0, true, true, m, false}};
+    case BMG_OP_VCYCLE: return {{0, 0, true, false, m, false}, {2, 0, false, true, m, false}};
+    case BMG_OP_EIGRES: return {{0, 0, true, false, m, true}, {2, 0, false, true, m, false}};
+    case BMG_OP_GRAM_AM: {
+      std::vector<RowBlock> b{{1, 0, true, false, m, true}};
+      if (x) b.push_back({0, 0, true, false, a->m2, true});
+      return b;
+    }
+    case BMG_OP_SHIFT_OFFSETS: return {{0, 0, true, false, m, true}};
+    default: return {};  // no row blocks, or row-local / order-free ops (Gaussian in vertex order, Gram, update)
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int bmg_apply(const bmg_hierarchy* hc, const bmg_apply_args* a, const void* x, const void* f,
+              void* y, void* stream) {
+  using namespace bmg;
+  BMG_CHECK(hc && a, "NULL argument");
+  bmg_hierarchy* h = const_cast<bmg_hierarchy*>(hc);
+  BMG_CHECK(!h->dev.empty(), "hierarchy has no device data");
+  const int nl = int(h->dev.size());
+  const int l = a->level;
+  BMG_CHECK(l >= 0 && l < nl, "level %d out of range", l);
+  BMG_CHECK(a->dtype == 0 || a->dtype == 1, "dtype must be 0 (FP64) or 1 (FP32)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  BMG_CHECK(y != nullptr, "y must be non-NULL");
+  BMG_HIP(hipSetDevice(h->device));
+  // Blocks cross this boundary in vertex order; a level stored in another
+  // order gets its blocks permuted into temporaries and back.
+  std::vector<RowBlock> blocks = row_blocks(a, x);
+  bool permuted = false;
+  for (const RowBlock& b : blocks) {
+    const int lv = l + b.dl;
+    if (lv >= 0 && h->dev[lv].perm != nullptr) permuted = true;
+  }
+  if (!permuted) return apply_stored(h, a, x, f, y, s);
+  BMG_CHECK(a->m >= 1 && a->m <= 4096 && a->m2 >= 0 && a->m2 <= 4096, "m out of range");
+  const void* args[3] = {x, f, y};
+  void* tmp[3] = {nullptr, nullptr, nullptr};
+  int st = BMG_OK;
+  auto permute = [&](const RowBlock& b, const int* map, const void* src, void* dst) -> int {
+    const int64_t n = h->dev[l + b.dl].n;
+    if (b.f64 || a->dtype == 0)
+      return launch_permute_rows<double>(n, b.cols, map, static_cast<const double*>(src), static_cast<double*>(dst), s);
+    return launch_permute_rows<float>(n, b.cols, map, static_cast<const float*>(src), static_cast<float*>(dst), s);
+  };
+  for (const RowBlock& b : blocks) {
+    if (l + b.dl < 0) continue;
+    const DevLevel& D = h->dev[l + b.dl];
+    if (D.perm == nullptr || args[b.arg] == nullptr) continue;
+    const size_t eb = (b.f64 || a->dtype == 0) ? sizeof(double) : sizeof(float);
+    if (hipMalloc(&tmp[b.arg], eb * size_t(D.n) * b.cols) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("hipMalloc of a storage-order temporary failed");
+      st = BMG_ENOMEM;
+      break;
+    }
+    if (b.in && (st = permute(b, D.perm, args[b.arg], tmp[b.arg])) != BMG_OK) break;  // storage row r <- vertex perm[r]
+  }
+  if (st == BMG_OK)
+    st = apply_stored(h, a, tmp[0] ? tmp[0] : x, tmp[1] ? tmp[1] : f, tmp[2] ? tmp[2] : y, s);
+  if (st == BMG_OK)
+    for (const RowBlock& b : blocks) {
+      if (l + b.dl < 0) continue;
+      const DevLevel& D = h->dev[l + b.dl];
+      if (!b.out || tmp[b.arg] == nullptr) continue;
+      if ((st = permute(b, D.iperm, tmp[b.arg], y)) != BMG_OK) break;  // vertex i <- storage row iperm[i]
+    }
+  (void)hipStreamSynchronize(s);
+  for (void* p : tmp)
+    if (p) (void)hipFree(p);
+  return st;
 }
 
 }  // extern "C"

@@ -31,8 +31,11 @@ int upload(T** dst, const T* src, size_t count, hipStream_t s, int64_t& bytes) {
 // cover (and so their rounding): it is used on levels this large only.
 constexpr int64_t kChunkOrderMinRows = 131072;
 
-// Levels with at least this many rows get a row order (smaller levels stay in
-// the caches in any order); BMG_ROW_ORDER_MIN_ROWS overrides it.
+// Levels with at least this many rows are stored in a Morton order of their
+// vertices (smaller levels stay in the caches in any order);
+// BMG_ROW_ORDER_MIN_ROWS overrides it, down to kStorageOrderFloor.
+constexpr int64_t kStorageOrderFloor = 16384;
+static_assert(kStorageOrderFloor > kLevelEigMax, "levels with dense eigendecompositions stay in vertex order");
 int64_t row_order_min_rows() {
   if (const char* e = std::getenv("BMG_ROW_ORDER_MIN_ROWS")) return std::atoll(e);
   return 131072;
@@ -40,11 +43,25 @@ int64_t row_order_min_rows() {
 
 }  // namespace
 
+// Device copy of a level.  A large level is stored with its rows permuted
+// along a Morton curve through the vertex positions: storage row r holds
+// vertex perm[r] (iperm is the inverse), the ELL column indices, colour lists
+// and transfer tables are renumbered to match, and every row keeps its slots
+// in the same order, so each row's arithmetic is unchanged.  A row and its
+// neighbours then sit close together in memory, and the neighbour rows a
+// kernel gathers are still in the caches from the rows just before.  The
+// transfer tables of a stored-permuted level take a general form: parents
+// [n][2] gives both parents of every fine row in the coarse level's storage
+// (a vertex of the coarse level names its copy twice: (x + x) / 2 = x
+// exactly), with par_nc = 0; rself [n_prev] gives the storage row of each
+// coarse vertex's own copy.  Other levels keep the nested numbering (fine
+// rows below n_prev are the coarse vertices, par_nc = n_prev, rself null).
 int upload_hierarchy(bmg_hierarchy* h, hipStream_t s) {
   const int nl = int(h->host.size());
   h->dev.resize(nl);
   std::vector<std::vector<float>> keep32;  // host staging must live until the stream syncs
   const int64_t min_ordered = row_order_min_rows();
+  std::vector<int32_t> iperm_prev;  // storage row of each vertex of the level below (empty: identity)
   for (int l = 0; l < nl; ++l) {
     const HostLevel& H = h->host[l];
     DevLevel& D = h->dev[l];
@@ -56,33 +73,96 @@ int upload_hierarchy(bmg_hierarchy* h, hipStream_t s) {
     D.colour_ptr = H.colour_ptr;
     D.bytes = 0;
     const size_t nw = size_t(H.n) * H.W;
-    BMG_TRY(upload(&D.cols, H.cols.data(), nw, s, D.bytes));
-    BMG_TRY(upload(&D.a64, H.a.data(), nw, s, D.bytes));
-    BMG_TRY(upload(&D.m64, H.mm.data(), nw, s, D.bytes));
-    keep32.emplace_back(H.a.begin(), H.a.end());
+    // never a level small enough for the LDS tail or a dense level
+    // eigendecomposition: those read the host tables in vertex order
+    const bool permuted = H.n >= min_ordered && H.n >= kStorageOrderFloor;
+    std::vector<int32_t> perm, iperm;
+    if (permuted) {
+      perm = morton_order(H.xyz);
+      iperm.assign(size_t(H.n), 0);
+      for (int64_t r = 0; r < H.n; ++r) iperm[size_t(perm[size_t(r)])] = int32_t(r);
+    }
+    auto snew = [&](int32_t q) { return permuted ? iperm[size_t(q)] : q; };        // this level
+    auto cnew = [&](int32_t q) { return iperm_prev.empty() ? q : iperm_prev[size_t(q)]; };  // level below
+    auto nat = [&](int64_t r) { return permuted ? int64_t(perm[size_t(r)]) : r; };
+    std::vector<int32_t> cols(nw);
+    std::vector<double> a(nw), mm(nw);
+    for (int64_t r = 0; r < H.n; ++r) {
+      const size_t q = size_t(nat(r));
+      for (int k = 0; k < H.W; ++k) {
+        cols[size_t(r) * H.W + k] = snew(H.cols[q * H.W + k]);
+        a[size_t(r) * H.W + k] = H.a[q * H.W + k];
+        mm[size_t(r) * H.W + k] = H.mm[q * H.W + k];
+      }
+    }
+    BMG_TRY(upload(&D.cols, cols.data(), nw, s, D.bytes));
+    BMG_TRY(upload(&D.a64, a.data(), nw, s, D.bytes));
+    BMG_TRY(upload(&D.m64, mm.data(), nw, s, D.bytes));
+    keep32.emplace_back(a.begin(), a.end());
     BMG_TRY(upload(&D.a32, keep32.back().data(), nw, s, D.bytes));
-    keep32.emplace_back(H.mm.begin(), H.mm.end());
+    keep32.emplace_back(mm.begin(), mm.end());
     BMG_TRY(upload(&D.m32, keep32.back().data(), nw, s, D.bytes));
     std::vector<double> dinv(H.n);
-    for (int64_t i = 0; i < H.n; ++i) dinv[i] = 1.0 / H.lumped[i];
+    for (int64_t r = 0; r < H.n; ++r) dinv[r] = 1.0 / H.lumped[size_t(nat(r))];
     BMG_TRY(upload(&D.dinv, dinv.data(), size_t(H.n), s, D.bytes));
-    BMG_TRY(upload(&D.parents, H.parents.data(), H.parents.size(), s, D.bytes));
-    BMG_TRY(upload(&D.rtab, H.rtab.data(), H.rtab.size(), s, D.bytes));
-    BMG_TRY(upload(&D.colour_rows, H.colour_rows.data(), H.colour_rows.size(), s, D.bytes));
-    BMG_TRY(upload(&D.colour2_rows, H.colour2_rows.data(), H.colour2_rows.size(), s, D.bytes));
+    // transfer tables between this level and the one below
+    std::vector<int32_t> par, rtab(H.rtab.size()), rself;
+    if (l > 0) {
+      if (permuted) {
+        par.resize(size_t(H.n) * 2);
+        for (int64_t r = 0; r < H.n; ++r) {
+          const int64_t q = nat(r);
+          if (q < H.n_prev) {
+            par[2 * r] = par[2 * r + 1] = cnew(int32_t(q));
+          } else {
+            par[2 * r] = cnew(H.parents[size_t(2 * (q - H.n_prev))]);
+            par[2 * r + 1] = cnew(H.parents[size_t(2 * (q - H.n_prev) + 1)]);
+          }
+        }
+        // coarse storage row i is vertex c of the level below; its own copy
+        // and its adjacent new vertices in this level's storage
+        rself.resize(size_t(H.n_prev));
+        std::vector<int32_t> cnat(size_t(H.n_prev));  // coarse storage row -> vertex
+        for (int64_t c = 0; c < H.n_prev; ++c) cnat[size_t(cnew(int32_t(c)))] = int32_t(c);
+        for (int64_t i = 0; i < H.n_prev; ++i) {
+          const int32_t c = cnat[size_t(i)];
+          rself[size_t(i)] = snew(c);
+          for (int k = 0; k < H.RW; ++k) {
+            const int32_t j = H.rtab[size_t(c) * H.RW + k];
+            rtab[size_t(i) * H.RW + k] = j < 0 ? -1 : snew(j);
+          }
+        }
+        D.par_nc = 0;
+      } else {
+        // nested numbering (the level below is then not permuted either)
+        par = H.parents;
+        rtab = H.rtab;
+        D.par_nc = H.n_prev;
+      }
+    }
+    BMG_TRY(upload(&D.parents, par.data(), par.size(), s, D.bytes));
+    BMG_TRY(upload(&D.rtab, rtab.data(), rtab.size(), s, D.bytes));
+    BMG_TRY(upload(&D.rself, rself.data(), rself.size(), s, D.bytes));
+    std::vector<int32_t> crows(H.colour_rows.size()), c2rows(H.colour2_rows.size());
+    for (size_t i = 0; i < crows.size(); ++i) crows[i] = snew(H.colour_rows[i]);
+    for (size_t i = 0; i < c2rows.size(); ++i) c2rows[i] = snew(H.colour2_rows[i]);
+    BMG_TRY(upload(&D.colour_rows, crows.data(), crows.size(), s, D.bytes));
+    BMG_TRY(upload(&D.colour2_rows, c2rows.data(), c2rows.size(), s, D.bytes));
     D.n_colours2 = H.n_colours2;
     D.colour2_ptr = H.colour2_ptr;
-    std::vector<int32_t> ord;
-    if (H.n >= min_ordered) {
-      ord = morton_order(H.xyz);
-      BMG_TRY(upload(&D.row_order, ord.data(), ord.size(), s, D.bytes));
+    if (permuted) {
+      BMG_TRY(upload(&D.perm, perm.data(), perm.size(), s, D.bytes));
+      BMG_TRY(upload(&D.iperm, iperm.data(), iperm.size(), s, D.bytes));
+      D.perm_h = perm;
     }
+    // the fused Gram's chunk order: only where the storage is in index order
     std::vector<int32_t> cord;
-    if (H.n >= kChunkOrderMinRows) {
+    if (!permuted && H.n >= kChunkOrderMinRows) {
       cord = chunk_morton_order(H);
       BMG_TRY(upload(&D.chunk_order, cord.data(), cord.size(), s, D.bytes));
     }
-    BMG_HIP(hipStreamSynchronize(s));  // dinv, ord and cord are locals
+    BMG_HIP(hipStreamSynchronize(s));  // the staging vectors are locals
+    iperm_prev = std::move(iperm);
   }
   // level-0 eigendecomposition on the device (FP64 and FP32, with transposes)
   const int64_t n0 = h->n0;
@@ -171,7 +251,8 @@ void free_device(bmg_hierarchy* h) {
   free_level_eigs(h);
   free_est_levels(h);
   for (auto& D : h->dev) {
-    void* ptrs[] = {D.cols, D.a64, D.m64, D.a32, D.m32, D.dinv, D.parents, D.rtab, D.colour_rows, D.row_order, D.chunk_order, D.colour2_rows};
+    void* ptrs[] = {D.cols, D.a64, D.m64, D.a32, D.m32, D.dinv, D.parents, D.rtab, D.rself, D.colour_rows,
+                     D.chunk_order, D.colour2_rows, D.perm, D.iperm};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     D = DevLevel();

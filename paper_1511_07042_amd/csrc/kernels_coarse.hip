@@ -159,15 +159,32 @@ __global__ void k_gather_rows(int n, int m, const double* __restrict__ phi, cons
   }
 }
 
-// Per-block partial sums of u^T A u and u^T M u over the first n rows of the
-// FP64 block U [*][m]: part[b][c] (A) and part[b][m + c] (M).  A thread owns
-// two columns of one row at a time (rows grid-stride); the block's rows are
-// added in a fixed order.
+// Injection of a coarse level's rows into a finer level's block: storage row
+// r of level l is row rs[n-1][...rs[0][r]] of the finer block, rs[t] the
+// general restriction tables (rself) of the stored-permuted levels between
+// (each maps a row of the level below to its copy); with n = 0 it is row r
+// (nested numbering: the coarse vertices come first).
+constexpr int kInjMax = 4;
+struct InjChain {
+  const int* rs[kInjMax];
+  int n;
+};
+
+__device__ __forceinline__ int64_t inject(const InjChain& c, int64_t r) {
+  for (int t = 0; t < c.n; ++t) r = c.rs[t][r];
+  return r;
+}
+
+// Per-block partial sums of u^T A u and u^T M u for u the injection of the
+// FP64 block U [*][m] into a level of n rows: part[b][c] (A) and part[b][m + c]
+// (M).  A thread owns two columns of one row at a time (rows grid-stride);
+// the block's rows are added in a fixed order.
 template <int WT>
 __global__ void __launch_bounds__(256) k_rq_part(int64_t n, int W, int m, const int* __restrict__ cols,
                                                  const double* __restrict__ a,
                                                  const double* __restrict__ mm,
-                                                 const double* __restrict__ U, double* __restrict__ part) {
+                                                 const double* __restrict__ U, double* __restrict__ part,
+                                                 InjChain inj) {
   __shared__ double red[256][4];
   const int cpr = m >> 1;
   const int rpb = 256 / cpr;
@@ -180,7 +197,7 @@ __global__ void __launch_bounds__(256) k_rq_part(int64_t n, int W, int m, const 
       double ax0 = 0, ax1 = 0, mx0 = 0, mx1 = 0;
       const int width = WT > 0 ? WT : W;
       for (int k = 0; k < width; ++k) {
-        const int64_t j = cols[base + k];
+        const int64_t j = inject(inj, cols[base + k]);
         const double av = a[base + k], mv = mm[base + k];
         const double2 xv = *reinterpret_cast<const double2*>(U + j * m + 2 * ch);
         ax0 += av * xv.x;
@@ -188,7 +205,7 @@ __global__ void __launch_bounds__(256) k_rq_part(int64_t n, int W, int m, const 
         mx0 += mv * xv.x;
         mx1 += mv * xv.y;
       }
-      const double2 ui = *reinterpret_cast<const double2*>(U + i * m + 2 * ch);
+      const double2 ui = *reinterpret_cast<const double2*>(U + inject(inj, i) * m + 2 * ch);
       qa0 += ui.x * ax0;
       qa1 += ui.y * ax1;
       qm0 += ui.x * mx0;
@@ -278,9 +295,9 @@ int launch_rq_normalise(const DevLevel& L, double* U, int m, double* part, doubl
   }
   const int nblk = kRqBlocks;
   if (L.W == 7)
-    k_rq_part<7><<<nblk, 256, 0, s>>>(L.n, L.W, m, L.cols, L.a64, L.m64, U, part);
+    k_rq_part<7><<<nblk, 256, 0, s>>>(L.n, L.W, m, L.cols, L.a64, L.m64, U, part, InjChain{});
   else
-    k_rq_part<0><<<nblk, 256, 0, s>>>(L.n, L.W, m, L.cols, L.a64, L.m64, U, part);
+    k_rq_part<0><<<nblk, 256, 0, s>>>(L.n, L.W, m, L.cols, L.a64, L.m64, U, part, InjChain{});
   k_rq_final<<<1, 256, 0, s>>>(m, nblk, part, rq);
   const int64_t total = L.n * m;
   k_scale_cols<<<int(std::min<int64_t>((total + 255) / 256, 4096)), 256, 0, s>>>(L.n, m, U, rq + m);
@@ -347,10 +364,19 @@ int launch_offsets(const std::vector<DevLevel>& dev, int lo, int top, const doub
   for (int l = lo; l < top; ++l) {
     const DevLevel& L = dev[l];
     double* p = part + int64_t(l) * nblk * 2 * m;
+    InjChain inj{};
+    for (int q = l + 1; q <= top; ++q) {
+      if (dev[q].rself == nullptr) continue;
+      if (inj.n == kInjMax) {
+        set_error("adaptive shifts: more than %d stored-permuted levels above level %d", kInjMax, l);
+        return BMG_EINVAL;
+      }
+      inj.rs[inj.n++] = dev[q].rself;
+    }
     if (L.W == 7)
-      k_rq_part<7><<<nblk, 256, 0, s>>>(L.n, L.W, m, L.cols, L.a64, L.m64, U, p);
+      k_rq_part<7><<<nblk, 256, 0, s>>>(L.n, L.W, m, L.cols, L.a64, L.m64, U, p, inj);
     else
-      k_rq_part<0><<<nblk, 256, 0, s>>>(L.n, L.W, m, L.cols, L.a64, L.m64, U, p);
+      k_rq_part<0><<<nblk, 256, 0, s>>>(L.n, L.W, m, L.cols, L.a64, L.m64, U, p, inj);
   }
   k_offsets<<<1, 256, 0, s>>>(lo, top, m, nblk, sigma, part, theta, shifts);
   return check_launch_c();

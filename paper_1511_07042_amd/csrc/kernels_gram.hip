@@ -13,6 +13,7 @@
 //
 // Update: U = Z Y for a small Y (the new Ritz vectors U <- [W_c, U'] Y).
 #include <algorithm>
+#include <cstdlib>
 
 #include <mutex>
 #include <vector>
@@ -105,7 +106,8 @@ static_assert(kGramAmChunk == 16, "the levels' chunk order (DevLevel::chunk_orde
 template <int WT>
 __device__ __forceinline__ double4 am_item(int64_t r, bool valid, int W, const int* __restrict__ cols,
                                            const double* __restrict__ a, const double* __restrict__ mm,
-                                           const double* __restrict__ u, int m, int ch) {
+                                           const double* __restrict__ u, int m, int ch,
+                                           double2* diag = nullptr, const int* __restrict__ uperm = nullptr) {
   double a0 = 0.0, a1 = 0.0, m0 = 0.0, m1 = 0.0;
   const int64_t base = r * W;
   if (WT > 0) {
@@ -118,6 +120,9 @@ __device__ __forceinline__ double4 am_item(int64_t r, bool valid, int W, const i
       av[k] = a[base + k];
       mv[k] = mm[base + k];
     }
+    if (uperm != nullptr)
+#pragma unroll
+      for (int k = 0; k < WT; ++k) j[k] = uperm[j[k]];
 #pragma unroll
     for (int k = 0; k < WT; ++k) xv[k] = *reinterpret_cast<const double2*>(u + int64_t(j[k]) * m + 2 * ch);
 #pragma unroll
@@ -127,11 +132,13 @@ __device__ __forceinline__ double4 am_item(int64_t r, bool valid, int W, const i
       m0 += mv[k] * xv[k].x;
       m1 += mv[k] * xv[k].y;
     }
+    if (diag) *diag = valid ? xv[0] : double2{0.0, 0.0};
   } else {
     for (int k = 0; k < W; ++k) {
-      const int jj = cols[base + k];
+      const int jj = uperm != nullptr ? uperm[cols[base + k]] : cols[base + k];
       const double av = a[base + k], mv = mm[base + k];
       const double2 xv = *reinterpret_cast<const double2*>(u + int64_t(jj) * m + 2 * ch);
+      if (k == 0 && diag) *diag = valid ? xv : double2{0.0, 0.0};
       a0 += av * xv.x;
       a1 += av * xv.y;
       m0 += mv * xv.x;
@@ -249,6 +256,187 @@ __global__ void __launch_bounds__(256) k_gram_am(int64_t n, int64_t rows_per_blo
     if (tj >= TJ) break;
     for (int i = 0; i < TI; ++i)
       for (int v = 0; v < 4; ++v) out[(16 * i + lk + 4 * v) * nyp + 16 * tj + li] = acc[i][t][v];
+  }
+}
+
+// Fused SpMM and Gram with the symmetric blocks computed once.  The Gram
+// blocks of Z = [W | U] are W^T [A U | M U] and the symmetric U^T A U, U^T M U;
+// the kernel computes W^T [A U | M U] and only the upper tiles of the two
+// symmetric blocks.  Columns are laid out in 16-wide tiles: the chunk's rows of
+// Z as [W padded to 16 TW | U padded to 16 TU] and of Y = [A U | M U] as
+// [A U padded to 16 TU | M U padded to 16 TU], both staged in LDS.  The tile
+// list (host-built) is split evenly over the four wavefronts, so each
+// wavefront holds few accumulators; two LDS buffers alternate between chunks,
+// so one barrier per chunk separates the products of a chunk from the MFMAs
+// that read it, and the registers leave room for two blocks per CU (the
+// gathers of one overlap the MFMAs of the other).  Partial sums per block, by
+// tile, reduced in a fixed order by k_gram_sym_reduce.  uperm (nullable):
+// the blocks W and U are in vertex order while the level is stored permuted;
+// storage row r then reads row uperm[r].
+constexpr int kSymMaxTiles = 72;
+struct SymTiles {
+  int T;                                         // tiles in the list
+  unsigned char ti[kSymMaxTiles], tj[kSymMaxTiles];  // Z tile, Y tile
+};
+
+// LDS row strides (doubles): an odd number of 16-double groups, so the four
+// rows a fragment load touches fall on alternating halves of the banks.
+__host__ __device__ constexpr int sym_zp(int TW, int TU) { return 16 * ((TW + TU) | 1); }
+__host__ __device__ constexpr int sym_yp(int TU) { return 16 * (2 * TU + 1); }
+
+template <int TPW, int NB, int WT>
+__global__ void __launch_bounds__(256) k_gram_sym(int64_t n, int64_t rows_per_block, SymTiles tl, int TW,
+                                                  int TU, const int* __restrict__ cols,
+                                                  const double* __restrict__ a,
+                                                  const double* __restrict__ mm, int W,
+                                                  const double* __restrict__ z1, int w1,
+                                                  const double* __restrict__ u, int m,
+                                                  double* __restrict__ part,
+                                                  const int* __restrict__ corder,
+                                                  const int* __restrict__ uperm) {
+  constexpr int CH = kGramAmChunk;
+  extern __shared__ double lds[];
+  const int ZP = sym_zp(TW, TU), YP = sym_yp(TU);
+  double* const zs0 = lds;                 // [2][CH][ZP]
+  double* const ys0 = lds + 2 * CH * ZP;   // [2][CH][YP]
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 15;
+  const int lk = lane >> 4;
+  const int cpr = m / 2;
+  const int items = CH * cpr;
+  const int uoff = 16 * TW;   // first U column of a Z row
+  const int moff = 16 * TU;   // first M U column of a Y row
+  d4 acc[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  // padding columns stay zero for the whole kernel
+  for (int e = threadIdx.x; e < 2 * CH * (ZP + YP); e += blockDim.x) lds[e] = 0.0;
+  __syncthreads();
+  const int64_t rb = int64_t(blockIdx.x) * rows_per_block;
+  const int64_t re = rb + rows_per_block < n ? rb + rows_per_block : n;
+  int buf = 0;
+  for (int64_t c0 = rb; c0 < re; c0 += CH, buf ^= 1) {
+    const int64_t r0 = corder != nullptr ? int64_t(corder[c0 / CH]) * CH : c0;
+    const int64_t r1 = r0 + CH < n ? r0 + CH : n;
+    double* const zs = zs0 + buf * CH * ZP;
+    double* const ys = ys0 + buf * CH * YP;
+    // rows of W (rows past the end are zero)
+    for (int e = threadIdx.x; e < CH * w1; e += blockDim.x) {
+      const int rl = e / w1, c = e - (e / w1) * w1;
+      const int64_t r = r0 + rl;
+      const int64_t rz = uperm != nullptr && r < r1 ? int64_t(uperm[r]) : r;
+      zs[rl * ZP + c] = r < r1 ? z1[rz * w1 + c] : 0.0;
+    }
+    // rows of A U and M U; the U row itself is the gather of the diagonal
+    // slot (slot 0 of every ELL row is the row)
+    for (int e0 = threadIdx.x; e0 < items; e0 += NB * 256) {
+      double4 y[NB];
+      double2 d[NB];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        const int e = e0 + k * 256;
+        const int rl = e / cpr, ch = e - (e / cpr) * cpr;
+        const int64_t r = r0 + rl;
+        const bool valid = e < items && r < r1;
+        y[k] = am_item<WT>(valid ? r : r0, valid, W, cols, a, mm, u, m, ch, &d[k], uperm);
+      }
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        const int e = e0 + k * 256;
+        if (e < items) {
+          const int rl = e / cpr, ch = e - (e / cpr) * cpr;
+          double* yr = ys + rl * YP;
+          yr[2 * ch] = y[k].x;
+          yr[2 * ch + 1] = y[k].y;
+          yr[moff + 2 * ch] = y[k].z;
+          yr[moff + 2 * ch + 1] = y[k].w;
+          double* zr = zs + rl * ZP + uoff;
+          zr[2 * ch] = d[k].x;
+          zr[2 * ch + 1] = d[k].y;
+        }
+      }
+    }
+    __syncthreads();  // this buffer's rows are complete (and the other buffer is free)
+#pragma unroll
+    for (int q = 0; q < CH / 4; ++q) {
+      const double* zq = zs + (4 * q + lk) * ZP + li;
+      const double* yq = ys + (4 * q + lk) * YP + li;
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        const int tile = wave * TPW + t;
+        if (tile < tl.T)
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(zq[16 * tl.ti[tile]], yq[16 * tl.tj[tile]], acc[t],
+                                                        0, 0, 0);
+      }
+    }
+  }
+  double* out = part + int64_t(blockIdx.x) * tl.T * 256;
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int tile = wave * TPW + t;
+    if (tile < tl.T)
+      for (int v = 0; v < 4; ++v) out[tile * 256 + (lk + 4 * v) * 16 + li] = acc[t][v];
+  }
+}
+
+// G from the tile partials of k_gram_sym: each output element summed over the
+// blocks in the same fixed order as k_gram_reduce, then placed in G [nz][2 m]
+// (rows [W | U], columns [A U | M U]).  An element (a, b) of a symmetric block
+// is computed for a <= b only and written to (a, b) and (b, a).
+__global__ void __launch_bounds__(1024) k_gram_sym_reduce(const double* __restrict__ part, int nblk,
+                                                          SymTiles tl, int TW, int TU, int w1, int m,
+                                                          double* __restrict__ G) {
+  constexpr int kOut = 16, kSeg = 64;
+  __shared__ double red[kSeg][kOut];
+  const int el = threadIdx.x & (kOut - 1), seg = threadIdx.x / kOut;
+  const int e = blockIdx.x * kOut + el;
+  const int tot = tl.T * 256;
+  double s = 0.0;
+  if (e < tot) {
+    const int64_t stride = int64_t(tot);
+    constexpr int kU = 8;
+    for (int b0 = seg; b0 < nblk; b0 += kSeg * kU) {
+      double v[kU];
+#pragma unroll
+      for (int q = 0; q < kU; ++q) {
+        const int b = b0 + kSeg * q;
+        v[q] = b < nblk ? part[b * stride + e] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < kU; ++q)
+        if (b0 + kSeg * q < nblk) s += v[q];
+    }
+  }
+  red[seg][el] = s;
+  __syncthreads();
+  double g = 0.0;
+  if (threadIdx.x < kOut * (kSeg / 4)) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) g += red[4 * seg + q][el];
+  }
+  __syncthreads();
+  if (threadIdx.x < kOut * (kSeg / 4)) red[seg][el] = g;
+  __syncthreads();
+  if (threadIdx.x < kOut && e < tot) {
+    double t = 0.0;
+    for (int q = 0; q < kSeg / 4; ++q) t += red[q][el];
+    const int tile = e / 256, rr = (e / 16) & 15, cc = e & 15;
+    const int ti = tl.ti[tile], tj = tl.tj[tile];
+    const int ny = 2 * m;
+    const int yj = 16 * tj + cc;
+    const int b = tj < TU ? yj : yj - 16 * TU;   // column of U
+    const int off = tj < TU ? 0 : m;             // A U or M U
+    if (b >= m) return;
+    if (ti < TW) {
+      const int zi = 16 * ti + rr;
+      if (zi < w1) G[zi * ny + off + b] = t;
+    } else {
+      const int ua = 16 * (ti - TW) + rr;
+      if (ua >= m || ua > b) return;
+      G[(w1 + ua) * ny + off + b] = t;
+      if (ua != b) G[(w1 + b) * ny + off + ua] = t;
+    }
   }
 }
 
@@ -421,6 +609,10 @@ GramPlan gram_plan(int64_t n, int nz, int ny) {
   const int64_t cap = int64_t(0.5 * double(n) * (nz + ny) / (double(p.nzp) * p.nyp));
   blocks = std::min<int64_t>(blocks, std::max<int64_t>(cap, 1));
   p.nblk = int(std::max<int64_t>(1, std::min<int64_t>(blocks, 1024)));
+  // partial sums per block: the dense tile layout, or the symmetric one of
+  // the fused kernel when nz = w1 + m and ny = 2 m
+  p.per_block = int64_t(p.nzp) * p.nyp;
+  if (ny % 2 == 0 && nz >= ny / 2) p.per_block = std::max(p.per_block, sym_tile_doubles(nz - ny / 2, ny / 2));
   return p;
 }
 
@@ -466,8 +658,128 @@ int launch_gram(const GramPlan& p, int64_t n, const double* z1, int w1, const do
   return check_launch();
 }
 
+namespace {
+
+// Tiles of the symmetric fused Gram: W rows against every Y tile, then the
+// upper tiles (ti <= tj) of U^T A U and of U^T M U.
+SymTiles sym_tiles(int w1, int m) {
+  SymTiles tl{};
+  const int TW = (w1 + 15) / 16, TU = (m + 15) / 16;
+  int T = 0;
+  for (int ti = 0; ti < TW; ++ti)
+    for (int tj = 0; tj < 2 * TU; ++tj) {
+      tl.ti[T] = (unsigned char)ti;
+      tl.tj[T] = (unsigned char)tj;
+      ++T;
+    }
+  for (int half = 0; half < 2; ++half)
+    for (int i = 0; i < TU; ++i)
+      for (int j = i; j < TU; ++j) {
+        tl.ti[T] = (unsigned char)(TW + i);
+        tl.tj[T] = (unsigned char)(half * TU + j);
+        ++T;
+      }
+  tl.T = T;
+  return tl;
+}
+
+template <int TPW, int NB, int WT>
+void sym_attr() {
+  (void)hipFuncSetAttribute((const void*)k_gram_sym<TPW, NB, WT>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+template <int TPW>
+void sym_attr_all() {
+  sym_attr<TPW, 1, 7>();
+  sym_attr<TPW, 1, 0>();
+  sym_attr<TPW, 2, 7>();
+  sym_attr<TPW, 2, 0>();
+  sym_attr<TPW, 3, 7>();
+  sym_attr<TPW, 3, 0>();
+}
+
+template <int TPW>
+void sym_launch(const GramPlan& p, const DevLevel& L, const SymTiles& tl, int TW, int TU, const double* w,
+                int w1, const double* u, int m, int64_t rpb, size_t shm, double* part, hipStream_t s,
+                const int* uperm) {
+  const int64_t n = L.n;
+  static const int nbenv = std::getenv("BMG_GRAM_NB") ? std::atoi(std::getenv("BMG_GRAM_NB")) : 0;
+  const int nb = nbenv ? nbenv : (kGramAmChunk * (m / 2) > 256 ? 2 : 1);
+#define GS(nb_, wt_)                                                                              \
+  BMG_LAUNCH((k_gram_sym<TPW, nb_, wt_>), p.nblk, 256, shm, s, n, rpb, tl, TW, TU, L.cols, L.a64, \
+             L.m64, L.W, w, w1, u, m, part, L.chunk_order, uperm)
+  if (L.W == 7) {
+    if (nb == 3) GS(3, 7);
+    else if (nb == 2) GS(2, 7);
+    else GS(1, 7);
+  } else {
+    if (nb == 3) GS(3, 0);
+    else if (nb == 2) GS(2, 0);
+    else GS(1, 0);
+  }
+#undef GS
+}
+
+}  // namespace
+
+int64_t sym_tile_doubles(int w1, int m) { return int64_t(sym_tiles(w1, m).T) * 256; }
+
 int launch_gram_am(const GramPlan& p, const DevLevel& L, const double* w, int w1, const double* u,
-                   int m, double* part, double* G, hipStream_t s) {
+                   int m, double* part, double* G, hipStream_t s, const int* uperm) {
+  static const bool dense = std::getenv("BMG_GRAM_DENSE") != nullptr;
+  if (!dense || uperm != nullptr) {
+    const int TW = (w1 + 15) / 16, TU = (m + 15) / 16;
+    if (TW > 2 || TU > 6 || p.ny != 2 * m || p.nz != w1 + m || m % 2 != 0 || m < 2) {
+      set_error("gram_am: unsupported shape w1=%d m=%d", w1, m);
+      return BMG_EINVAL;
+    }
+    const SymTiles tl = sym_tiles(w1, m);
+    if (int64_t(tl.T) * 256 > p.per_block) {
+      set_error("gram_am: partial buffer of %lld doubles per block is too small", (long long)p.per_block);
+      return BMG_EINVAL;
+    }
+    static std::once_flag once;
+    std::call_once(once, [] {
+      sym_attr_all<1>();
+      sym_attr_all<2>();
+      sym_attr_all<3>();
+      sym_attr_all<4>();
+      sym_attr_all<6>();
+      sym_attr_all<8>();
+      sym_attr_all<10>();
+      sym_attr_all<12>();
+      sym_attr_all<17>();
+    });
+    const int64_t n = L.n;
+    // at most two blocks per CU (one round of blocks)
+    static const int cap = std::getenv("BMG_GRAM_BLOCKS") ? std::atoi(std::getenv("BMG_GRAM_BLOCKS")) : 512;
+    GramPlan q = p;
+    q.nblk = std::max(1, std::min(p.nblk, cap));
+    int64_t rpb = (n + q.nblk - 1) / q.nblk;
+    rpb = (rpb + kGramAmChunk - 1) / kGramAmChunk * kGramAmChunk;
+    q.nblk = int((n + rpb - 1) / rpb);
+    const size_t shm = size_t(2) * kGramAmChunk * (sym_zp(TW, TU) + sym_yp(TU)) * sizeof(double);
+    const int tpw = (tl.T + 3) / 4;
+    {
+      const LaunchEvents ev = g_launch_events;
+      g_launch_events = LaunchEvents{ev.start, nullptr};
+      if (tpw <= 1) sym_launch<1>(q, L, tl, TW, TU, w, w1, u, m, rpb, shm, part, s, uperm);
+      else if (tpw <= 2) sym_launch<2>(q, L, tl, TW, TU, w, w1, u, m, rpb, shm, part, s, uperm);
+      else if (tpw <= 3) sym_launch<3>(q, L, tl, TW, TU, w, w1, u, m, rpb, shm, part, s, uperm);
+      else if (tpw <= 4) sym_launch<4>(q, L, tl, TW, TU, w, w1, u, m, rpb, shm, part, s, uperm);
+      else if (tpw <= 6) sym_launch<6>(q, L, tl, TW, TU, w, w1, u, m, rpb, shm, part, s, uperm);
+      else if (tpw <= 8) sym_launch<8>(q, L, tl, TW, TU, w, w1, u, m, rpb, shm, part, s, uperm);
+      else if (tpw <= 10) sym_launch<10>(q, L, tl, TW, TU, w, w1, u, m, rpb, shm, part, s, uperm);
+      else if (tpw <= 12) sym_launch<12>(q, L, tl, TW, TU, w, w1, u, m, rpb, shm, part, s, uperm);
+      else sym_launch<17>(q, L, tl, TW, TU, w, w1, u, m, rpb, shm, part, s, uperm);
+      g_launch_events = LaunchEvents{nullptr, ev.stop};
+    }
+    int st = check_launch();
+    if (st != BMG_OK) return st;
+    BMG_LAUNCH((k_gram_sym_reduce), (tl.T * 256 + 15) / 16, 1024, 0, s, part, q.nblk, tl, TW, TU, w1, m, G);
+    return check_launch();
+  }
   const int TI = p.nzp / 16;
   const int TJ = p.nyp / 16;
   const int TJW = (TJ + 3) / 4;
@@ -611,12 +923,13 @@ extern "C" int bmg_gram_am_noalloc(const bmg_hierarchy* h, int32_t level, const 
   const DevLevel& D = h->dev[level];
   GramPlan p = gram_plan(D.n, m2 + m, 2 * m);
   // as many row blocks as the planner asks for, while their partial sums fit
-  const size_t per_block = size_t(p.nzp) * p.nyp;
+  const size_t per_block = size_t(p.per_block);
   if (per_block > kNoallocScratchDoubles) {
     set_error("gram_am_noalloc: one block's partial sums (%zu doubles) exceed the %zu-double scratch",
               per_block, kNoallocScratchDoubles);
     return BMG_EINVAL;
   }
   p.nblk = int(std::min<size_t>(size_t(p.nblk), kNoallocScratchDoubles / per_block));
-  return launch_gram_am(p, D, w, m2, u, m, part, G, static_cast<hipStream_t>(stream));
+  // the blocks come in vertex order; a permuted level reads them through perm
+  return launch_gram_am(p, D, w, m2, u, m, part, G, static_cast<hipStream_t>(stream), D.perm);
 }

@@ -95,23 +95,20 @@ enum { K_SHIFTED = 0, K_RESIDUAL = 1, K_JACOBI = 2, K_JACOBI0 = 3, K_JACOBI_ADD 
 // MODE K_SHIFTED: y = S x; K_RESIDUAL: y = f - S x;
 // K_JACOBI: y = x + omega (f - S x) / d; K_JACOBI0: y = omega f / d  (x = 0),
 // with S = A - sigma M (precomputed once per solve) and d = S_ii.
-// WT: ELL width when it is the built-in 7, else 0 (runtime W).  ord (or
-// null: rows in index order) is the order the rows are visited in: a
-// space-filling-curve order keeps the neighbour rows a pass gathers in cache
-// (every row's result is the same in any order).
+// WT: ELL width when it is the built-in 7, else 0 (runtime W).
 template <typename T, int MODE, int WT>
 __global__ void __launch_bounds__(256) k_rowop(int64_t n, int W, int m, int cpr, int rpb,
                                                const int* __restrict__ cols,
                                                const T* __restrict__ S, T omega,
                                                const T* __restrict__ x,
                                                const T* __restrict__ f, T* __restrict__ y,
-                                               double* __restrict__ u, const int* __restrict__ ord) {
+                                               double* __restrict__ u) {
   constexpr int VW = Vec<T>::N;
   const int rloc = threadIdx.x / cpr;
   const int ch = threadIdx.x - rloc * cpr;
   if (rloc >= rpb) return;
   for (int64_t i = int64_t(blockIdx.x) * rpb + rloc; i < n; i += int64_t(gridDim.x) * rpb) {
-    const int64_t r = ord != nullptr ? int64_t(ord[i]) : i;
+    const int64_t r = i;
     const int64_t base = r * W;
     Vec<T> acc, xr;
     const T d = S[base];
@@ -328,6 +325,7 @@ __global__ void __launch_bounds__(256) k_resrestrict(int64_t nc, int W, int RW, 
                                                      int rpb, const int* __restrict__ cols,
                                                      const T* __restrict__ S,
                                                      const int* __restrict__ rtab,
+                                                     const int* __restrict__ rself,
                                                      const T* __restrict__ e,
                                                      const T* __restrict__ f,
                                                      T* __restrict__ fc) {
@@ -337,7 +335,8 @@ __global__ void __launch_bounds__(256) k_resrestrict(int64_t nc, int W, int RW, 
   if (rloc >= rpb) return;
   const int off = ch * VW;
   for (int64_t i = int64_t(blockIdx.x) * rpb + rloc; i < nc; i += int64_t(gridDim.x) * rpb) {
-    Vec<T> acc = residual_row<T, WT>(cols, S, i, W, e, f, m, off);
+    const int64_t self = rself != nullptr ? int64_t(rself[i]) : i;
+    Vec<T> acc = residual_row<T, WT>(cols, S, self, W, e, f, m, off);
     Vec<T> h;
     for (int c = 0; c < VW; ++c) h.v[c] = T(0);
     for (int k = 0; k < RW; ++k) {
@@ -585,12 +584,14 @@ __global__ void __launch_bounds__(256) k_colsum(const double* __restrict__ part,
 template <typename T>
 __global__ void __launch_bounds__(256) k_restrict(int64_t nc, int RW, int m, int cpr, int rpb,
                                                   const int* __restrict__ rtab,
+                                                  const int* __restrict__ rself,
                                                   const T* __restrict__ x, T* __restrict__ y) {
   constexpr int VW = Vec<T>::N;
   const int rloc = threadIdx.x / cpr;
   const int ch = threadIdx.x - rloc * cpr;
   for (int64_t i = int64_t(blockIdx.x) * rpb + rloc; i < nc; i += int64_t(gridDim.x) * rpb) {
-    Vec<T> acc = ld(x + i * m + ch * VW);
+    const int64_t self = rself != nullptr ? int64_t(rself[i]) : i;
+    Vec<T> acc = ld(x + self * m + ch * VW);
     Vec<T> h;
     for (int c = 0; c < VW; ++c) h.v[c] = T(0);
     for (int k = 0; k < RW; ++k) {
@@ -604,7 +605,9 @@ __global__ void __launch_bounds__(256) k_restrict(int64_t nc, int RW, int m, int
   }
 }
 
-// y[i] += x[i] (i < nc);  y[nc + e] += (x[a_e] + x[b_e]) / 2   (P, eq. proj-1)
+// y[i] += x[i] (i < nc);  y[nc + e] += (x[a_e] + x[b_e]) / 2   (P, eq. proj-1).
+// With nc = 0 (general tables) every row takes its two parents, equal for a
+// vertex of the coarse level.
 template <typename T>
 __global__ void __launch_bounds__(256) k_prolong_add(int64_t n, int64_t nc, int m, int cpr, int rpb,
                                                      const int* __restrict__ parents,
@@ -682,11 +685,14 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
 
 // Element (i, j), counter c = i m + j: u1, u2 in (0, 1] from counters 2c and
 // 2c + 1; z = sqrt(-2 ln u1) cos(2 pi u2)  (Box-Muller).
-__global__ void k_gaussian(double* y, int64_t cnt, uint64_t seed) {
+__global__ void k_gaussian(double* y, int64_t cnt, int m, uint64_t seed, const int* __restrict__ perm) {
   const double two53 = 1.0 / 9007199254740992.0;
   for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < cnt;
        c += int64_t(gridDim.x) * blockDim.x) {
-    const uint64_t cc = uint64_t(c);
+    // the counter is the element's place in vertex order (storage row r holds
+    // vertex perm[r])
+    const int64_t r = c / m;
+    const uint64_t cc = perm != nullptr ? uint64_t(int64_t(perm[r]) * m + (c - r * m)) : uint64_t(c);
     const double u1 = (double(splitmix64(seed ^ (2 * cc)) >> 11) + 1.0) * two53;
     const double u2 = (double(splitmix64(seed ^ (2 * cc + 1)) >> 11) + 1.0) * two53;
     y[c] = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
@@ -694,21 +700,24 @@ __global__ void k_gaussian(double* y, int64_t cnt, uint64_t seed) {
 }
 
 // ---------------------------------------------------------------- output --
-// Per block and selected column j: (max |U[r][sel_j]|, lowest r attaining it).
+// Per block and selected column j: (max |U[i][sel_j]|, lowest vertex i
+// attaining it); vertex i is storage row iperm[i] (iperm null: row i).
 __global__ void k_argmax(int64_t n, const double* __restrict__ U, int m,
-                         const int* __restrict__ sel, int k, double* pv, int* pi) {
+                         const int* __restrict__ sel, int k, const int* __restrict__ iperm, double* pv,
+                         int* pi) {
   __shared__ double sv[256];
   __shared__ int si[256];
   for (int j = 0; j < k; ++j) {
     const int col = sel[j];
     double best = -1.0;
     int bi = 0x7fffffff;
-    for (int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < n;
-         r += int64_t(gridDim.x) * blockDim.x) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+      const int64_t r = iperm != nullptr ? int64_t(iperm[i]) : i;
       const double v = fabs(U[r * m + col]);
       if (v > best) {
         best = v;
-        bi = int(r);
+        bi = int(i);
       }
     }
     sv[threadIdx.x] = best;
@@ -734,8 +743,8 @@ __global__ void k_argmax(int64_t n, const double* __restrict__ U, int m,
 }
 
 __global__ void k_sign_final(const double* __restrict__ U, int m, const int* __restrict__ sel, int k,
-                             const double* __restrict__ pv, const int* __restrict__ pi, int nblk,
-                             double* sign_out) {
+                             const int* __restrict__ iperm, const double* __restrict__ pv,
+                             const int* __restrict__ pi, int nblk, double* sign_out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= k) return;
   double best = -1.0;
@@ -748,18 +757,33 @@ __global__ void k_sign_final(const double* __restrict__ U, int m, const int* __r
       bi = i;
     }
   }
-  sign_out[j] = (U[int64_t(bi) * m + sel[j]] < 0) ? -1.0 : 1.0;
+  const int64_t r = iperm != nullptr ? int64_t(iperm[bi]) : int64_t(bi);
+  sign_out[j] = (U[r * m + sel[j]] < 0) ? -1.0 : 1.0;
 }
 
+// out[j][i] = sign_j U[iperm[i]][sel_j]: column-major, vertex order.
 __global__ void k_write_evecs(int64_t n, const double* __restrict__ U, int m,
                               const int* __restrict__ sel, const double* __restrict__ sign, int k,
-                              double* out, int64_t ld) {
+                              const int* __restrict__ iperm, double* out, int64_t ld) {
   const int64_t total = n * k;
   for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
        t += int64_t(gridDim.x) * blockDim.x) {
     const int j = int(t / n);
-    const int64_t r = t - int64_t(j) * n;
-    out[int64_t(j) * ld + r] = sign[j] * U[r * m + sel[j]];
+    const int64_t i = t - int64_t(j) * n;
+    const int64_t r = iperm != nullptr ? int64_t(iperm[i]) : i;
+    out[int64_t(j) * ld + i] = sign[j] * U[r * m + sel[j]];
+  }
+}
+
+// Row permutation of an [n][m] block: y[r] = x[map[r]] (vector loads of 16 bytes).
+template <typename T>
+__global__ void k_permute_rows(int64_t n, int m, const int* __restrict__ map, const T* __restrict__ x,
+                               T* __restrict__ y) {
+  const int64_t total = n * m;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t r = t / m;
+    y[t] = x[int64_t(map[r]) * m + (t - r * m)];
   }
 }
 
@@ -805,10 +829,10 @@ int launch_shifted(const DevLevel& L, const T* S, int mode, const T* x, const T*
   Geom g = row_geom<T>(L.n, m);
   if (mode == ROW_SHIFTED)
     BMG_BY_WIDTH(L.W, (k_rowop<T, K_SHIFTED, 7>), (k_rowop<T, K_SHIFTED, 0>), g.grid, g.block, 0, s,
-                 L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(0), x, f, y, nullptr, L.row_order);
+                 L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(0), x, f, y, nullptr);
   else
     BMG_BY_WIDTH(L.W, (k_rowop<T, K_RESIDUAL, 7>), (k_rowop<T, K_RESIDUAL, 0>), g.grid, g.block, 0, s,
-                 L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(0), x, f, y, nullptr, L.row_order);
+                 L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(0), x, f, y, nullptr);
   return check_launch();
 }
 
@@ -818,13 +842,13 @@ int launch_jacobi(const DevLevel& L, const T* S, double omega, const T* x, const
   Geom g = row_geom<T>(L.n, m);
   if (x_is_zero)
     BMG_LAUNCH((k_rowop<T, K_JACOBI0, 0>), g.grid, g.block, 0, s, L.n, L.W, m, g.cpr, g.rpb, L.cols,
-               S, T(omega), x, f, y, nullptr, L.row_order);
+               S, T(omega), x, f, y, nullptr);
   else if (u_add != nullptr)
     BMG_BY_WIDTH(L.W, (k_rowop<T, K_JACOBI_ADD, 7>), (k_rowop<T, K_JACOBI_ADD, 0>), g.grid, g.block, 0,
-                 s, L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(omega), x, f, y, u_add, L.row_order);
+                 s, L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(omega), x, f, y, u_add);
   else
     BMG_BY_WIDTH(L.W, (k_rowop<T, K_JACOBI, 7>), (k_rowop<T, K_JACOBI, 0>), g.grid, g.block, 0, s,
-                 L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(omega), x, f, y, nullptr, L.row_order);
+                 L.n, L.W, m, g.cpr, g.rpb, L.cols, S, T(omega), x, f, y, nullptr);
   return check_launch();
 }
 
@@ -884,7 +908,7 @@ int launch_resrestrict(const DevLevel& fine, const T* S, const T* e, const T* f,
                        hipStream_t s) {
   Geom g = row_geom<T>(fine.n_prev, m);
   BMG_BY_WIDTH(fine.W, (k_resrestrict<T, 7>), (k_resrestrict<T, 0>), g.grid, g.block, 0, s,
-               fine.n_prev, fine.W, fine.RW, m, g.cpr, g.rpb, fine.cols, S, fine.rtab, e, f, fc);
+               fine.n_prev, fine.W, fine.RW, m, g.cpr, g.rpb, fine.cols, S, fine.rtab, fine.rself, e, f, fc);
   return check_launch();
 }
 
@@ -893,7 +917,7 @@ int launch_prolong_jacobi(const DevLevel& fine, const T* S, double omega, const 
                           const T* f, T* y, int m, hipStream_t s) {
   Geom g = row_geom<T>(fine.n, m);
   BMG_BY_WIDTH(fine.W, (k_prolong_jacobi<T, 7>), (k_prolong_jacobi<T, 0>), g.grid, g.block, 0, s,
-               fine.n, fine.n_prev, fine.W, m, g.cpr, g.rpb, fine.cols, S, fine.parents, T(omega),
+               fine.n, fine.par_nc, fine.W, m, g.cpr, g.rpb, fine.cols, S, fine.parents, T(omega),
                e, ec, f, y);
   return check_launch();
 }
@@ -931,15 +955,15 @@ int launch_colsum(const double* part, int nblk, int m, double* out, hipStream_t 
 template <typename T>
 int launch_restrict(const DevLevel& fine, const T* x, T* y, int m, hipStream_t s) {
   Geom g = row_geom<T>(fine.n_prev, m);
-  BMG_LAUNCH((k_restrict<T>), g.grid, g.block, 0, s, fine.n_prev, fine.RW, m, g.cpr, g.rpb, fine.rtab, x, y);
+  BMG_LAUNCH((k_restrict<T>), g.grid, g.block, 0, s, fine.n_prev, fine.RW, m, g.cpr, g.rpb, fine.rtab, fine.rself,
+             x, y);
   return check_launch();
 }
 
 template <typename T>
 int launch_prolong_add(const DevLevel& fine, const T* x, T* y, int m, hipStream_t s) {
   Geom g = row_geom<T>(fine.n, m);
-  BMG_LAUNCH((k_prolong_add<T>), g.grid, g.block, 0, s, fine.n, fine.n_prev, m, g.cpr, g.rpb, fine.parents, x,
-                                              y);
+  BMG_LAUNCH((k_prolong_add<T>), g.grid, g.block, 0, s, fine.n, fine.par_nc, m, g.cpr, g.rpb, fine.parents, x, y);
   return check_launch();
 }
 
@@ -968,23 +992,31 @@ int launch_convert(const double* x, T* y, int64_t count, hipStream_t s) {
   return check_launch();
 }
 
-int launch_gaussian(double* y, int64_t n, int m, uint64_t seed, hipStream_t s) {
-  k_gaussian<<<grid1d(n * m), 256, 0, s>>>(y, n * m, seed);
+int launch_gaussian(double* y, int64_t n, int m, uint64_t seed, hipStream_t s, const int* perm) {
+  k_gaussian<<<grid1d(n * m), 256, 0, s>>>(y, n * m, m, seed, perm);
   return check_launch();
 }
 
-int launch_signs(int64_t n, const double* U, int m, const int* sel, int k, double* sign_out,
+int launch_signs(int64_t n, const double* U, int m, const int* sel, int k, const int* iperm, double* sign_out,
                  double* part_val, int* part_idx, int nblk, hipStream_t s) {
-  k_argmax<<<nblk, 256, 0, s>>>(n, U, m, sel, k, part_val, part_idx);
-  k_sign_final<<<(k + 63) / 64, 64, 0, s>>>(U, m, sel, k, part_val, part_idx, nblk, sign_out);
+  k_argmax<<<nblk, 256, 0, s>>>(n, U, m, sel, k, iperm, part_val, part_idx);
+  k_sign_final<<<(k + 63) / 64, 64, 0, s>>>(U, m, sel, k, iperm, part_val, part_idx, nblk, sign_out);
   return check_launch();
 }
 
 int launch_write_evecs(int64_t n, const double* U, int m, const int* sel, const double* sign,
-                       int k, double* out, int64_t ld, hipStream_t s) {
-  k_write_evecs<<<grid1d(n * k), 256, 0, s>>>(n, U, m, sel, sign, k, out, ld);
+                       int k, const int* iperm, double* out, int64_t ld, hipStream_t s) {
+  k_write_evecs<<<grid1d(n * k), 256, 0, s>>>(n, U, m, sel, sign, k, iperm, out, ld);
   return check_launch();
 }
+
+template <typename T>
+int launch_permute_rows(int64_t n, int m, const int* map, const T* x, T* y, hipStream_t s) {
+  k_permute_rows<T><<<grid1d(n * m), 256, 0, s>>>(n, m, map, x, y);
+  return check_launch();
+}
+template int launch_permute_rows<double>(int64_t, int, const int*, const double*, double*, hipStream_t);
+template int launch_permute_rows<float>(int64_t, int, const int*, const float*, float*, hipStream_t);
 
 #define BMG_INST(T)                                                                              \
   template int launch_shift<T>(const DevLevel&, double, T*, hipStream_t);                        \

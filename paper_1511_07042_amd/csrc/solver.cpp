@@ -143,8 +143,7 @@ int make_workspace(bmg_hierarchy* h, int m, int n_c, int prec, bmg_workspace** o
   const int nz = n_c + m;
   w->gp = gram_plan(N, nz, 2 * m);
   w->gpw = gram_plan(N, n_c, 2 * n_c);
-  const size_t gpb = std::max(size_t(w->gp.nblk) * w->gp.nzp * w->gp.nyp,
-                              size_t(w->gpw.nblk) * w->gpw.nzp * w->gpw.nyp);
+  const size_t gpb = std::max(size_t(w->gp.nblk) * w->gp.per_block, size_t(w->gpw.nblk) * w->gpw.per_block);
   AL(w->gpart, sizeof(double) * gpb);
   AL(w->G, sizeof(double) * nz * 2 * m);
   AL(w->GW, sizeof(double) * n_c * 2 * n_c);
@@ -831,9 +830,12 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   if (ramp) {
     // the ramp below fills U
   } else if (o.initial_block) {
-    BMG_HIP(hipMemcpyAsync(w->U, o.initial_block, sizeof(double) * N * m, hipMemcpyHostToDevice, s));
+    // the caller's block is in vertex order; the level's storage may not be
+    double* dst = DL.perm != nullptr ? w->AU : w->U;
+    BMG_HIP(hipMemcpyAsync(dst, o.initial_block, sizeof(double) * N * m, hipMemcpyHostToDevice, s));
+    if (DL.perm != nullptr) BMG_TRY(launch_permute_rows<double>(N, m, DL.perm, w->AU, w->U, s));
   } else if (!shifted) {
-    BMG_TRY(launch_gaussian(w->U, N, m, o.seed, s));
+    BMG_TRY(launch_gaussian(w->U, N, m, o.seed, s, DL.perm));
   }
 
   KTimer kt;
@@ -864,7 +866,9 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   ra.status = w->status;
   auto ritz_step = [&]() -> int {
     // H4: A U', M U' and the Gram blocks of Z = [W_c, U'] in one fused pass
-    kt.add(BMG_K_GRAM, 4.0 * Nd * nz * m, 1);
+    // flops of the needed outputs: W^T [A U', M U'] and one triangle of each
+    // symmetric block (U'^T A U', U'^T M U')
+    kt.add(BMG_K_GRAM, 2.0 * Nd * (2.0 * n_c * m + double(m) * (m + 1)), 1);
     BMG_TRY(kt.begin(BMG_K_GRAM));
     BMG_TRY(launch_gram_am(w->gp, DL, w->W, n_c, w->U, m, w->gpart, w->G, s));
     BMG_TRY(kt.end(BMG_K_GRAM));
@@ -1186,11 +1190,11 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     for (int j = 0; j < k; ++j) evals[j] = theta[sel[j]];
   if (evecs && have_pairs) {
     BMG_HIP(hipMemcpyAsync(w->sel, sel.data(), sizeof(int) * k, hipMemcpyHostToDevice, s));
-    BMG_TRY(launch_signs(N, w->U, m, w->sel, k, w->sign, w->argv, w->argi, w->nblk_arg, s));
+    BMG_TRY(launch_signs(N, w->U, m, w->sel, k, DL.iperm, w->sign, w->argv, w->argi, w->nblk_arg, s));
     if (evecs_on_device) {
-      BMG_TRY(launch_write_evecs(N, w->U, m, w->sel, w->sign, k, evecs, ld, s));
+      BMG_TRY(launch_write_evecs(N, w->U, m, w->sel, w->sign, k, DL.iperm, evecs, ld, s));
     } else {
-      BMG_TRY(launch_write_evecs(N, w->U, m, w->sel, w->sign, k, w->AU, N, s));
+      BMG_TRY(launch_write_evecs(N, w->U, m, w->sel, w->sign, k, DL.iperm, w->AU, N, s));
       BMG_HIP(hipMemcpy2DAsync(evecs, sizeof(double) * ld, w->AU, sizeof(double) * N,
                                sizeof(double) * N, k, hipMemcpyDeviceToHost, s));
     }

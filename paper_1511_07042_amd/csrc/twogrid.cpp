@@ -102,8 +102,11 @@ int two_grid(bmg_hierarchy* h, int level_H, int n, const int32_t* idx, int top, 
       std::vector<double> hb(size_t(N) * m);
       BMG_HIP(hipMemcpyAsync(hb.data(), U, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, s));
       BMG_HIP(hipStreamSynchronize(s));
+      // storage row r of the top level is vertex perm[r]
+      const std::vector<int32_t>& perm = h->dev[top].perm_h;
       for (int c = 0; c < n; ++c)
-        for (int64_t i = 0; i < N; ++i) evecs[size_t(c) * N + i] = hb[size_t(i) * m + c];
+        for (int64_t r = 0; r < N; ++r)
+          evecs[size_t(c) * N + (perm.empty() ? r : perm[size_t(r)])] = hb[size_t(r) * m + c];
     }
     return BMG_OK;
   };

@@ -294,6 +294,9 @@ def test_gram_fused_products(env, level, m2, m):
     scale = np.abs(Z).T @ np.hstack([abs(L.A) @ np.abs(U), abs(L.M) @ np.abs(U)])
     err = _rel(_host(y), Z.T @ Y, scale)
     assert err < 1e-14, err
+    # the symmetric blocks U^T A U and U^T M U come out exactly symmetric
+    g = _host(y)[m2:]
+    assert np.array_equal(g[:, :m], g[:, :m].T) and np.array_equal(g[:, m:], g[:, m:].T)
 
 
 def test_gram_fused_runtime_width(env):

@@ -25,11 +25,15 @@ def _case(p, h, level, m2, m, seed):
     return W, U, g0, g1
 
 
-def test_noalloc_gram_equals_allocating_entry_point():
+@pytest.mark.parametrize("storage", ["vertex", "morton"])
+def test_noalloc_gram_equals_allocating_entry_point(storage, monkeypatch):
+    # storage "morton": level 6 is stored with its rows permuted (threshold 0),
+    # so the entry point reads the vertex-order blocks through the permutation
     import torch
     import paper_1511_07042_amd as p
     from oracle import bmg as ob
     lv = ob.build_levels("sphere", 6)
+    monkeypatch.setenv("BMG_ROW_ORDER_MIN_ROWS", "0" if storage == "morton" else "1000000000")
     with p.Hierarchy("sphere", 6) as h:
         # a large call first (many row blocks, the partial sums fill most of the
         # scratch), then a smaller one on another level
