@@ -55,7 +55,7 @@ KSYMBOL = {"smooth": "k_rowop<{T}, 2, 7>", "residual": "k_rowop<{T}, 1, 7>",
            "restrict": "k_restrict<{T}>", "prolong": "k_prolong_add<{T}>",
            "smooth_pair": "k_jacobi2z<{T}, 7>", "restrict_res": "k_resrestrict<{T}, 7>",
            "prolong_smooth": "k_prolong_jacobi<{T}, 7>", "eigres": "k_eigres<{T}, 7>",
-           "spmm_am": "k_spmm_am<7>", "gram": "k_gram_sym + k_gram_sym_reduce", "update": "k_update_zy",
+           "spmm_am": "k_spmm_am<7>", "gram": "k_gram_sym1 + k_gram_sym_reduce", "update": "k_update_zy",
            "ritz": "k_ritz", "smooth_add": "k_rowop<{T}, 4, 7>"}
 
 # Committed HBM-traffic summaries (two rocprofv3 --pmc passes each).

@@ -380,6 +380,175 @@ __global__ void __launch_bounds__(256) k_gram_sym(int64_t n, int64_t rows_per_bl
   }
 }
 
+// The same products and tiles with one (row, column pair) item per thread:
+// a block is 16 rows x m/2 column pairs rounded up to whole wavefronts, so
+// each thread forms one item per chunk with all seven gathers in flight at
+// once, and the tiles are split over all of the block's wavefronts (few
+// accumulators each).  The chunk's ELL rows (columns and both value arrays)
+// are staged in LDS one chunk ahead: their loads are issued at the start of
+// the previous chunk and stored before its barrier, so a chunk costs one
+// round trip to memory (the gathers) plus its MFMAs.  The MFMA fragment
+// offsets are kept in registers for the whole kernel.  Needs 16 W <= the
+// block size.  Partial sums as in k_gram_sym (same tiles, same order).
+template <int TPW, int WT>
+__global__ void __launch_bounds__(1024) k_gram_sym1(int64_t n, int64_t rows_per_block, SymTiles tl, int TW,
+                                                   int TU, const int* __restrict__ cols,
+                                                   const double* __restrict__ a,
+                                                   const double* __restrict__ mm, int W,
+                                                   const double* __restrict__ z1, int w1,
+                                                   const double* __restrict__ u, int m,
+                                                   double* __restrict__ part,
+                                                   const int* __restrict__ corder,
+                                                   const int* __restrict__ uperm) {
+  constexpr int CH = kGramAmChunk;
+  extern __shared__ double lds[];
+  const int ZP = sym_zp(TW, TU), YP = sym_yp(TU);
+  const int CW = CH * W;
+  double* const zs0 = lds;                                     // [2][CH][ZP]
+  double* const ys0 = zs0 + 2 * CH * ZP;                       // [2][CH][YP]
+  double* const ma0 = ys0 + 2 * CH * YP;                       // [2][CH W] values of A
+  double* const mm0 = ma0 + 2 * CW;                            // [2][CH W] values of M
+  int* const mc0 = reinterpret_cast<int*>(mm0 + 2 * CW);       // [2][CH W] columns
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const int cpr = m / 2, items = CH * cpr;
+  const int uoff = 16 * TW, moff = 16 * TU;
+  d4 acc[TPW];
+  int zo[TPW], yo[TPW];
+  bool live[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    const int tile = wave * TPW + t;
+    live[t] = tile < tl.T;
+    zo[t] = live[t] ? 16 * tl.ti[tile] : 0;
+    yo[t] = live[t] ? 16 * tl.tj[tile] : 0;
+  }
+  for (int e = tid; e < 2 * CH * (ZP + YP); e += nthr) lds[e] = 0.0;  // padding stays zero
+  const int64_t rb = int64_t(blockIdx.x) * rows_per_block;
+  const int64_t re = rb + rows_per_block < n ? rb + rows_per_block : n;
+  auto first_row = [&](int64_t c0) -> int64_t {
+    return corder != nullptr ? int64_t(corder[c0 / CH]) * CH : c0;
+  };
+  // one entry (row r0 + tid / W, slot tid % W) of a chunk's ELL rows
+  auto mload = [&](int64_t r0, int& pc, double& pa, double& pm) {
+    const int64_t g = r0 * W + tid;
+    const bool ok = g < n * W;
+    pc = ok ? cols[g] : int(r0);
+    pa = ok ? a[g] : 0.0;
+    pm = ok ? mm[g] : 0.0;
+  };
+  const bool mt = tid < CW;
+  if (rb < re && mt) {
+    int pc;
+    double pa, pm;
+    mload(first_row(rb), pc, pa, pm);
+    mc0[tid] = pc;
+    ma0[tid] = pa;
+    mm0[tid] = pm;
+  }
+  __syncthreads();
+  const int rl = tid / cpr, ch = tid - (tid / cpr) * cpr;
+  const bool wl = tid < CH * w1;
+  const int wrl = wl ? tid / w1 : 0, wc = wl ? tid - (tid / w1) * w1 : 0;
+  int buf = 0;
+  for (int64_t c0 = rb; c0 < re; c0 += CH, buf ^= 1) {
+    const int64_t r0 = first_row(c0);
+    const int64_t r1 = r0 + CH < n ? r0 + CH : n;
+    double* const zs = zs0 + buf * CH * ZP;
+    double* const ys = ys0 + buf * CH * YP;
+    // the next chunk's ELL rows: loads in flight during this chunk
+    const bool more = c0 + CH < re;
+    int pc = 0;
+    double pa = 0.0, pm = 0.0;
+    if (more && mt) mload(first_row(c0 + CH), pc, pa, pm);
+    double wv = 0.0;
+    if (wl) {
+      const int64_t r = r0 + wrl;
+      if (r < r1) wv = z1[(uperm != nullptr ? int64_t(uperm[r]) : r) * w1 + wc];
+    }
+    if (tid < items) {
+      const int* mc = mc0 + buf * CW + rl * W;
+      const double* ma = ma0 + buf * CW + rl * W;
+      const double* mv = mm0 + buf * CW + rl * W;
+      double a0 = 0.0, a1 = 0.0, m0 = 0.0, m1 = 0.0;
+      double2 x0;
+      if (WT > 0) {
+        int j[WT > 0 ? WT : 1];
+        double2 xv[WT > 0 ? WT : 1];
+#pragma unroll
+        for (int k = 0; k < WT; ++k) j[k] = uperm != nullptr ? uperm[mc[k]] : mc[k];
+#pragma unroll
+        for (int k = 0; k < WT; ++k) xv[k] = *reinterpret_cast<const double2*>(u + int64_t(j[k]) * m + 2 * ch);
+#pragma unroll
+        for (int k = 0; k < WT; ++k) {
+          const double av = ma[k], mw = mv[k];
+          a0 += av * xv[k].x;
+          a1 += av * xv[k].y;
+          m0 += mw * xv[k].x;
+          m1 += mw * xv[k].y;
+        }
+        x0 = xv[0];
+      } else {
+        x0 = double2{0.0, 0.0};
+        for (int k = 0; k < W; ++k) {
+          const int jj = uperm != nullptr ? uperm[mc[k]] : mc[k];
+          const double2 xv = *reinterpret_cast<const double2*>(u + int64_t(jj) * m + 2 * ch);
+          if (k == 0) x0 = xv;  // slot 0 of every ELL row is the row itself
+          a0 += ma[k] * xv.x;
+          a1 += ma[k] * xv.y;
+          m0 += mv[k] * xv.x;
+          m1 += mv[k] * xv.y;
+        }
+      }
+      const bool valid = r0 + rl < r1;
+      double* yr = ys + rl * YP;
+      double* zr = zs + rl * ZP + uoff;
+      yr[2 * ch] = valid ? a0 : 0.0;
+      yr[2 * ch + 1] = valid ? a1 : 0.0;
+      yr[moff + 2 * ch] = valid ? m0 : 0.0;
+      yr[moff + 2 * ch + 1] = valid ? m1 : 0.0;
+      zr[2 * ch] = valid ? x0.x : 0.0;
+      zr[2 * ch + 1] = valid ? x0.y : 0.0;
+    }
+    if (wl) zs[wrl * ZP + wc] = wv;
+    for (int e = tid + nthr; e < CH * w1; e += nthr) {  // W wider than the block covers at once
+      const int rw = e / w1, cw = e - (e / w1) * w1;
+      const int64_t r = r0 + rw;
+      zs[rw * ZP + cw] = r < r1 ? z1[(uperm != nullptr ? int64_t(uperm[r]) : r) * w1 + cw] : 0.0;
+    }
+    if (more && mt) {
+      mc0[(buf ^ 1) * CW + tid] = pc;
+      ma0[(buf ^ 1) * CW + tid] = pa;
+      mm0[(buf ^ 1) * CW + tid] = pm;
+    }
+    __syncthreads();  // this chunk's rows and the next chunk's ELL rows are in LDS
+#pragma unroll
+    for (int q = 0; q < CH / 4; ++q) {
+      const double* zq = zs + (4 * q + lk) * ZP + li;
+      const double* yq = ys + (4 * q + lk) * YP + li;
+      double af[TPW], bf[TPW];
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        af[t] = zq[zo[t]];
+        bf[t] = yq[yo[t]];
+      }
+#pragma unroll
+      for (int t = 0; t < TPW; ++t)
+        if (live[t]) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[t], bf[t], acc[t], 0, 0, 0);
+    }
+  }
+  double* out = part + int64_t(blockIdx.x) * tl.T * 256;
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int tile = wave * TPW + t;
+    if (live[t])
+      for (int v = 0; v < 4; ++v) out[tile * 256 + (lk + 4 * v) * 16 + li] = acc[t][v];
+  }
+}
+
 // G from the tile partials of k_gram_sym: each output element summed over the
 // blocks in the same fixed order as k_gram_reduce, then placed in G [nz][2 m]
 // (rows [W | U], columns [A U | M U]).  An element (a, b) of a symmetric block
@@ -721,6 +890,26 @@ void sym_launch(const GramPlan& p, const DevLevel& L, const SymTiles& tl, int TW
 #undef GS
 }
 
+template <int TPW>
+void sym1_attr() {
+  (void)hipFuncSetAttribute((const void*)k_gram_sym1<TPW, 7>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  (void)hipFuncSetAttribute((const void*)k_gram_sym1<TPW, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+}
+
+template <int TPW>
+void sym1_launch(const GramPlan& p, const DevLevel& L, const SymTiles& tl, int TW, int TU, const double* w,
+                 int w1, const double* u, int m, int64_t rpb, int nthr, size_t shm, double* part, hipStream_t s,
+                 const int* uperm) {
+  if (L.W == 7)
+    BMG_LAUNCH((k_gram_sym1<TPW, 7>), p.nblk, nthr, shm, s, L.n, rpb, tl, TW, TU, L.cols, L.a64, L.m64, L.W, w,
+               w1, u, m, part, L.chunk_order, uperm);
+  else
+    BMG_LAUNCH((k_gram_sym1<TPW, 0>), p.nblk, nthr, shm, s, L.n, rpb, tl, TW, TU, L.cols, L.a64, L.m64, L.W, w,
+               w1, u, m, part, L.chunk_order, uperm);
+}
+
 }  // namespace
 
 int64_t sym_tile_doubles(int w1, int m) { return int64_t(sym_tiles(w1, m).T) * 256; }
@@ -760,6 +949,39 @@ int launch_gram_am(const GramPlan& p, const DevLevel& L, const double* w, int w1
     rpb = (rpb + kGramAmChunk - 1) / kGramAmChunk * kGramAmChunk;
     q.nblk = int((n + rpb - 1) / rpb);
     const size_t shm = size_t(2) * kGramAmChunk * (sym_zp(TW, TU) + sym_yp(TU)) * sizeof(double);
+    // one item per thread when the block (16 rows x m/2 column pairs, whole
+    // wavefronts) can stage a chunk's ELL rows
+    const int nthr = (kGramAmChunk * (m / 2) + 63) / 64 * 64;
+    const int tpw1 = (tl.T + nthr / 64 - 1) / (nthr / 64);
+    if (kGramAmChunk * L.W <= nthr && nthr <= 1024 && tpw1 <= 8) {
+      static std::once_flag once1;
+      std::call_once(once1, [] {
+        sym1_attr<1>();
+        sym1_attr<2>();
+        sym1_attr<3>();
+        sym1_attr<4>();
+        sym1_attr<5>();
+        sym1_attr<6>();
+        sym1_attr<8>();
+      });
+      const size_t shm1 = shm + size_t(2) * kGramAmChunk * L.W * (2 * sizeof(double) + sizeof(int));
+      const LaunchEvents ev = g_launch_events;
+      g_launch_events = LaunchEvents{ev.start, nullptr};
+#define G1(t_) sym1_launch<t_>(q, L, tl, TW, TU, w, w1, u, m, rpb, nthr, shm1, part, s, uperm)
+      if (tpw1 <= 1) G1(1);
+      else if (tpw1 <= 2) G1(2);
+      else if (tpw1 <= 3) G1(3);
+      else if (tpw1 <= 4) G1(4);
+      else if (tpw1 <= 5) G1(5);
+      else if (tpw1 <= 6) G1(6);
+      else G1(8);
+#undef G1
+      g_launch_events = LaunchEvents{nullptr, ev.stop};
+      int st = check_launch();
+      if (st != BMG_OK) return st;
+      BMG_LAUNCH((k_gram_sym_reduce), (tl.T * 256 + 15) / 16, 1024, 0, s, part, q.nblk, tl, TW, TU, w1, m, G);
+      return check_launch();
+    }
     const int tpw = (tl.T + 3) / 4;
     {
       const LaunchEvents ev = g_launch_events;
