@@ -269,7 +269,8 @@ typedef struct {
   int32_t cycles;      /* correction + Ritz cycles performed */
   int32_t converged;   /* 1 if every returned pair met the certificate */
   int32_t m, n_c, l_c; /* values actually used */
-  int32_t reserved;
+  int32_t group_size;  /* requests solved together in the solve that produced this
+                          result (bmg_solve_group; 1 for bmg_solve) */
   double t_solve_ms;   /* HIP-event time on `stream` from entry to output */
   double max_rho_over_delta; /* final max over returned pairs of rho_i / delta_i */
   double max_kato_temple;    /* final max of rho_i^2 / (delta_i max(|theta_i|, 1)) */
@@ -319,6 +320,42 @@ typedef struct {
 int bmg_solve(bmg_hierarchy* h, int32_t k, double sigma, double tol, const bmg_solve_opts* opts,
               double* evals, double* evecs, int64_t ld, int32_t evecs_on_device, void* stream,
               bmg_solve_stats* stats);
+
+/* One request of a grouped solve (bmg_solve_group): the arguments of one
+ * bmg_solve call and its result. */
+typedef struct {
+  int32_t k;                  /* pairs wanted */
+  double tol;                 /* as in bmg_solve */
+  const bmg_solve_opts* opts; /* NULL: defaults; see bmg_solve_group for what must agree */
+  double* evals;              /* out: host [k] */
+  double* evecs;              /* out: NULL or column-major [k][ld], host or device memory */
+  int64_t ld;
+  int32_t evecs_on_device;
+  int32_t status;             /* out: this request's bmg_status */
+  bmg_solve_stats* stats;     /* nullable, as in bmg_solve (ramp_evals not written) */
+} bmg_group_request;
+
+/* Serving (growth pattern 5 of the hot path): n requests for eigenpairs of
+ * the same hierarchy nearest the same sigma, solved together.  Their test
+ * blocks are concatenated column-wise into one [N_L][sum m_i] block, so every
+ * launch of the correction cycle (sweeps, residuals, transfers, the coarse
+ * end) and of the eigen-residual runs once for all of them, and the whole
+ * cycle is replayed as one HIP graph; the Gram, Rayleigh-Ritz and update steps
+ * run per request on its column slice.  A request is certified, and its
+ * output written, at the first cycle where its own pairs meet its tolerance,
+ * exactly as in bmg_solve; the others continue.  Every column's arithmetic in
+ * the cycle is the same as in a solo solve; the residual norms are summed in a
+ * different grouping of rows, so a request's result equals its bmg_solve
+ * result to rounding (and may take one cycle more or less).
+ * Must agree across the group: the scheme (ENRICHED: sigma <= 0, or scheme
+ * BMG_SCHEME_ENRICHED), precision, smoother, nu1, nu2, omega, n_c, l_c; no
+ * initial_block or level ramp.  Per request: k, tol, m (sum of m at most 512),
+ * seed, max_cycles, angle_tol.  Returns BMG_OK when every request converged,
+ * else the first failing request's status (each request's own status is in
+ * reqs[i].status); BMG_EINVAL (nothing run) when the group breaks the rules
+ * above or a request is invalid for bmg_solve. */
+int bmg_solve_group(bmg_hierarchy* h, double sigma, int32_t n, bmg_group_request* reqs,
+                    const void* hip_stream);
 
 /* ----------------------------------------------------------- estimator --- */
 

@@ -61,7 +61,7 @@ class SolveOpts(C.Structure):
 
 class SolveStats(C.Structure):
     _fields_ = [("cycles", C.c_int32), ("converged", C.c_int32), ("m", C.c_int32),
-                ("n_c", C.c_int32), ("l_c", C.c_int32), ("reserved", C.c_int32),
+                ("n_c", C.c_int32), ("l_c", C.c_int32), ("group_size", C.c_int32),
                 ("t_solve_ms", C.c_double), ("max_rho_over_delta", C.c_double),
                 ("max_kato_temple", C.c_double), ("rho", C.POINTER(C.c_double)),
                 ("delta", C.POINTER(C.c_double)), ("timed_kernel_ms", C.c_double),
@@ -70,6 +70,12 @@ class SolveStats(C.Structure):
                 ("scheme", C.c_int32), ("reserved2", C.c_int32), ("coarse_eig_ms", C.c_double),
                 ("lc_shift", C.c_double), ("ramp_evals", C.POINTER(C.c_double)),
                 ("ramp_start", C.c_int32), ("reserved3", C.c_int32)]
+
+
+class GroupRequest(C.Structure):
+    _fields_ = [("k", C.c_int32), ("tol", C.c_double), ("opts", C.POINTER(SolveOpts)),
+                ("evals", C.POINTER(C.c_double)), ("evecs", C.c_void_p), ("ld", C.c_int64),
+                ("evecs_on_device", C.c_int32), ("status", C.c_int32), ("stats", C.POINTER(SolveStats))]
 
 
 class ApplyArgs(C.Structure):
@@ -91,6 +97,7 @@ _sig = {
     "bmg_solve": (C.c_int, [_H, C.c_int32, C.c_double, C.c_double, C.POINTER(SolveOpts),
                             C.POINTER(C.c_double), C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
                             C.POINTER(SolveStats)]),
+    "bmg_solve_group": (C.c_int, [_H, C.c_double, C.c_int32, C.POINTER(GroupRequest), C.c_void_p]),
     "bmg_apply": (C.c_int, [_H, C.POINTER(ApplyArgs), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "bmg_estimate": (C.c_int, [_H, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_void_p, C.c_int64,
                                C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p, C.c_void_p]),
@@ -283,6 +290,53 @@ class Hierarchy:
         stats.update(rho=rho, delta=delta, status=status, ramp_evals=ramp)
         V = None if out is None else out.T
         return evals, V, stats
+
+    def solve_group(self, requests, sigma=0.0, nu1=2, nu2=2, smoother="jacobi", precision="mixed",
+                    n_c=0, l_c=-1, omega=0.85, evecs="host", stream=None, allow_noconv=False,
+                    scheme="auto"):
+        """bmg_solve_group: requests is a list of dicts with k and optionally m,
+        seed, tol (1e-8), max_cycles (200), angle_tol (1e-7).  Returns a list of
+        (evals [k], evecs [N, k] or None, stats dict), one per request."""
+        n = len(requests)
+        arr = (GroupRequest * n)()
+        keep = []
+        for i, q in enumerate(requests):
+            o = SolveOpts()
+            _lib.bmg_solve_opts_default(C.byref(o))
+            o.m, o.nu1, o.nu2 = int(q.get("m", 0)), int(nu1), int(nu2)
+            o.smoother, o.precision = SMOOTHERS[smoother], PRECISIONS[precision]
+            o.max_cycles, o.n_c, o.l_c = int(q.get("max_cycles", 200)), int(n_c), int(l_c)
+            o.omega, o.angle_tol, o.seed = float(omega), float(q.get("angle_tol", 1e-7)), int(q.get("seed", 0))
+            o.timed_kernel = -1
+            o.scheme = SCHEMES[scheme]
+            k = int(q["k"])
+            ev = np.zeros(k, np.float64)
+            rho, delta = np.zeros(k, np.float64), np.zeros(k, np.float64)
+            st = SolveStats()
+            st.rho = rho.ctypes.data_as(C.POINTER(C.c_double))
+            st.delta = delta.ctypes.data_as(C.POINTER(C.c_double))
+            out, ptr, on_dev = None, None, 0
+            if evecs == "host":
+                out = np.zeros((k, self.N), np.float64)
+                ptr = out.ctypes.data
+            elif evecs == "device":
+                import torch
+                out = torch.empty((k, self.N), dtype=torch.float64, device="cuda")
+                ptr, on_dev = out.data_ptr(), 1
+            keep.append((o, ev, rho, delta, st, out))
+            arr[i].k, arr[i].tol = k, float(q.get("tol", 1e-8))
+            arr[i].opts = C.pointer(o)
+            arr[i].evals = ev.ctypes.data_as(C.POINTER(C.c_double))
+            arr[i].evecs, arr[i].ld, arr[i].evecs_on_device = ptr, int(self.N), on_dev
+            arr[i].stats = C.pointer(st)
+        status = _lib.bmg_solve_group(self._h, float(sigma), n, arr, _stream_ptr(stream))
+        _check(status, "bmg_solve_group", allow=(ENOCONV,) if allow_noconv else ())
+        res = []
+        for i, (o, ev, rho, delta, st, out) in enumerate(keep):
+            stats = {f: getattr(st, f) for f, _ in SolveStats._fields_ if f not in ("rho", "delta", "ramp_evals")}
+            stats.update(rho=rho, delta=delta, status=arr[i].status)
+            res.append((ev, None if out is None else out.T, stats))
+        return res
 
     def estimate(self, evals, evecs, level=None, per_triangle=False, stream=None):
         """bmg_estimate on a torch.cuda FP64 tensor evecs [N, k] (columns

@@ -215,6 +215,11 @@ int default_coarse_vectors(const bmg_hierarchy* h);
 int solve(bmg_hierarchy* h, int k, double sigma, double tol, const bmg_solve_opts* opts,
           double* evals, double* evecs, int64_t ld, int evecs_on_device, void* stream,
           bmg_solve_stats* stats);
+// Grouped solve (solver.cpp); see bmg_solve_group in bmg.h.  cancel: nullable
+// per-request flags (a request whose flag reads nonzero stops with
+// BMG_ECANCELED at the end of the current cycle).
+int solve_group(bmg_hierarchy* h, double sigma, int n, bmg_group_request* reqs, void* stream,
+                const std::atomic<int>* const* cancel = nullptr);
 // A posteriori estimator of eq. est-res (estimate.cpp); see bmg_estimate in bmg.h.
 int estimate(bmg_hierarchy* h, int level, int k, const double* evals, const double* evecs, int64_t ld,
              double* eta, double* parts, double* eta2_T, hipStream_t s);
@@ -337,15 +342,17 @@ GramPlan gram_plan(int64_t n, int nz, int ny);
 int64_t sym_tile_doubles(int w1, int m);
 // G = [w | u]^T [A_L u | M_L u] with the products formed in LDS (fused SpMM
 // and Gram; w1 columns of w, m of u; plan for nz = w1 + m, ny = 2 m).
-// uperm (nullable): w and u are in vertex order and storage row r reads row uperm[r]
+// uperm (nullable): w and u are in vertex order and storage row r reads row uperm[r];
+// ldu: row stride of u (0: m), so u may be a column slice of a wider block
 int launch_gram_am(const GramPlan& p, const DevLevel& L, const double* w, int w1, const double* u,
-                   int m, double* part, double* G, hipStream_t s, const int* uperm = nullptr);
+                   int m, double* part, double* G, hipStream_t s, const int* uperm = nullptr, int ldu = 0);
 int launch_gram(const GramPlan& p, int64_t n, const double* z1, int w1, const double* z2, int w2,
                 const double* y1, int v1, const double* y2, int v2, double* part, double* G,
                 hipStream_t s);
-// U[n][m] = Z Y, Z = [z1 (w1) | z2 (w2)], Y [w1+w2][m] device
+// U[n][m] = Z Y, Z = [z1 (w1) | z2 (w2)], Y [w1+w2][m] device; ldz2, ldu: row
+// strides of z2 and U (0: w2 and m), so both may be column slices of a wider block
 int launch_update_zy(int64_t n, const double* z1, int w1, const double* z2, int w2,
-                     const double* Y, double* U, int m, hipStream_t s);
+                     const double* Y, double* U, int m, hipStream_t s, int ldz2 = 0, int ldu = 0);
 
 // Coarse end of the correction cycle in one workgroup, in LDS (kernels_tail.hip).
 constexpr int kTailMaxLevels = 12;

@@ -226,6 +226,11 @@ int bmg_solve(bmg_hierarchy* h, int32_t k, double sigma, double tol, const bmg_s
   return bmg::solve(h, k, sigma, tol, opts, evals, evecs, ld, evecs_on_device, stream, stats);
 }
 
+int bmg_solve_group(bmg_hierarchy* h, double sigma, int32_t n, bmg_group_request* reqs, const void* hip_stream) {
+  BMG_CHECK(h != nullptr && !h->dev.empty(), "hierarchy has no device data");
+  return bmg::solve_group(h, sigma, n, reqs, const_cast<void*>(hip_stream));
+}
+
 int bmg_estimate(bmg_hierarchy* h, int32_t level, int32_t k, const double* evals, const double* evecs,
                  int64_t ld, double* eta, double* parts, double* eta2_T, void* stream) {
   BMG_CHECK(h != nullptr && !h->dev.empty(), "hierarchy has no device data");

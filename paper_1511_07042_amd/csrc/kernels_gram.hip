@@ -106,7 +106,7 @@ static_assert(kGramAmChunk == 16, "the levels' chunk order (DevLevel::chunk_orde
 template <int WT>
 __device__ __forceinline__ double4 am_item(int64_t r, bool valid, int W, const int* __restrict__ cols,
                                            const double* __restrict__ a, const double* __restrict__ mm,
-                                           const double* __restrict__ u, int m, int ch,
+                                           const double* __restrict__ u, int ldu, int ch,
                                            double2* diag = nullptr, const int* __restrict__ uperm = nullptr) {
   double a0 = 0.0, a1 = 0.0, m0 = 0.0, m1 = 0.0;
   const int64_t base = r * W;
@@ -124,7 +124,7 @@ __device__ __forceinline__ double4 am_item(int64_t r, bool valid, int W, const i
 #pragma unroll
       for (int k = 0; k < WT; ++k) j[k] = uperm[j[k]];
 #pragma unroll
-    for (int k = 0; k < WT; ++k) xv[k] = *reinterpret_cast<const double2*>(u + int64_t(j[k]) * m + 2 * ch);
+    for (int k = 0; k < WT; ++k) xv[k] = *reinterpret_cast<const double2*>(u + int64_t(j[k]) * ldu + 2 * ch);
 #pragma unroll
     for (int k = 0; k < WT; ++k) {
       a0 += av[k] * xv[k].x;
@@ -137,7 +137,7 @@ __device__ __forceinline__ double4 am_item(int64_t r, bool valid, int W, const i
     for (int k = 0; k < W; ++k) {
       const int jj = uperm != nullptr ? uperm[cols[base + k]] : cols[base + k];
       const double av = a[base + k], mv = mm[base + k];
-      const double2 xv = *reinterpret_cast<const double2*>(u + int64_t(jj) * m + 2 * ch);
+      const double2 xv = *reinterpret_cast<const double2*>(u + int64_t(jj) * ldu + 2 * ch);
       if (k == 0 && diag) *diag = valid ? xv : double2{0.0, 0.0};
       a0 += av * xv.x;
       a1 += av * xv.y;
@@ -146,117 +146,6 @@ __device__ __forceinline__ double4 am_item(int64_t r, bool valid, int W, const i
     }
   }
   return valid ? double4{a0, a1, m0, m1} : double4{0.0, 0.0, 0.0, 0.0};
-}
-
-// Fused SpMM and Gram: G = Z^T [A U, M U] with Z = [W | U] (W: w1 columns,
-// U: m columns), the products A U and M U formed row chunk by row chunk in LDS
-// and contracted at once, so they never travel to or from HBM.  For each
-// 16-row chunk of its range a block (256 threads) first computes the chunk's
-// rows of A U and M U (FP64, one thread per row and column pair, the ELL row
-// gathered against U), then its four wavefronts run the chunk's MFMAs exactly
-// as k_gram does, with the B fragments read from LDS.  Partial sums per block
-// as in k_gram (reduced by k_gram_reduce in a fixed order).  A chunk is
-// kGramAmChunk rows: its products are formed in one pass (more gathers in
-// flight per barrier; with m > 32 a thread takes three items at once) and
-// contracted 16 rows at a time.
-template <int TI, int TJW, int WT>
-__global__ void __launch_bounds__(256) k_gram_am(int64_t n, int64_t rows_per_block, int nzp, int nyp,
-                                                 const int* __restrict__ cols,
-                                                 const double* __restrict__ a,
-                                                 const double* __restrict__ mm, int W,
-                                                 const double* __restrict__ z1, int w1,
-                                                 const double* __restrict__ u, int m,
-                                                 double* __restrict__ part,
-                                                 const int* __restrict__ corder) {
-  constexpr int CH = kGramAmChunk;
-  extern __shared__ double ys[];  // [CH][nyp]: rows of [A U | M U] (zero padded)
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int TJ = nyp / 16;
-  const int li = lane & 15;
-  const int lk = lane >> 4;
-  const int cpr = m / 2;          // column pairs of U
-  const int items = CH * cpr;     // (row, pair) items of a chunk
-  d4 acc[TI][TJW];
-  for (int i = 0; i < TI; ++i)
-    for (int t = 0; t < TJW; ++t) acc[i][t] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int e = threadIdx.x; e < CH * nyp; e += blockDim.x) ys[e] = 0.0;
-  const int64_t rb = int64_t(blockIdx.x) * rows_per_block;
-  const int64_t re = rb + rows_per_block < n ? rb + rows_per_block : n;
-  for (int64_t c0 = rb; c0 < re; c0 += CH) {
-    // logical chunk c0 / CH is the matrix rows [r0, r1): in index order the
-    // same rows, else the chunk the level's chunk order puts there (16
-    // consecutive rows, so the rows of Z are still read as one piece, while
-    // the gathers of consecutive chunks stay close on the surface)
-    const int64_t r0 = corder != nullptr ? int64_t(corder[c0 / CH]) * CH : c0;
-    const int64_t r1 = r0 + CH < n ? r0 + CH : n;
-    // A fragments of the chunk's first 16 rows (global), issued before the products
-    double af[4][TI];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t r = r0 + 4 * q + lk;
-      const bool ok = r < r1;
-#pragma unroll
-      for (int i = 0; i < TI; ++i) af[q][i] = ok ? zcol(z1, w1, u, m, r, 16 * i + li) : 0.0;
-    }
-    __syncthreads();  // the previous chunk's B fragments have been read
-    // with more than one item per thread (m > 32), three per pass with their
-    // loads in flight together
-    constexpr int NB = TJW > 1 ? 3 : 1;
-    for (int e0 = threadIdx.x; e0 < items; e0 += NB * 256) {
-      double4 y[NB];
-#pragma unroll
-      for (int k = 0; k < NB; ++k) {
-        const int e = e0 + k * 256;
-        const int rl = e / cpr, ch = e - (e / cpr) * cpr;
-        const int64_t r = r0 + rl;
-        const bool valid = e < items && r < r1;
-        y[k] = am_item<WT>(valid ? r : r0, valid, W, cols, a, mm, u, m, ch);
-      }
-#pragma unroll
-      for (int k = 0; k < NB; ++k) {
-        const int e = e0 + k * 256;
-        if (e < items) {
-          const int rl = e / cpr, ch = e - (e / cpr) * cpr;
-          double* yr = ys + rl * nyp;
-          yr[2 * ch] = y[k].x;
-          yr[2 * ch + 1] = y[k].y;
-          yr[m + 2 * ch] = y[k].z;
-          yr[m + 2 * ch + 1] = y[k].w;
-        }
-      }
-    }
-    __syncthreads();
-    for (int h = 0; h < CH / 16; ++h) {
-      if (h > 0) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int64_t r = r0 + 16 * h + 4 * q + lk;
-          const bool ok = r < r1;
-#pragma unroll
-          for (int i = 0; i < TI; ++i) af[q][i] = ok ? zcol(z1, w1, u, m, r, 16 * i + li) : 0.0;
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int t = 0; t < TJW; ++t) {
-          const int tj = wave + 4 * t;
-          if (tj >= TJ) continue;
-          const double b = ys[(16 * h + 4 * q + lk) * nyp + 16 * tj + li];
-#pragma unroll
-          for (int i = 0; i < TI; ++i)
-            acc[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[q][i], b, acc[i][t], 0, 0, 0);
-        }
-    }
-  }
-  double* out = part + int64_t(blockIdx.x) * nzp * nyp;
-  for (int t = 0; t < TJW; ++t) {
-    const int tj = wave + 4 * t;
-    if (tj >= TJ) break;
-    for (int i = 0; i < TI; ++i)
-      for (int v = 0; v < 4; ++v) out[(16 * i + lk + 4 * v) * nyp + 16 * tj + li] = acc[i][t][v];
-  }
 }
 
 // Fused SpMM and Gram with the symmetric blocks computed once.  The Gram
@@ -290,7 +179,7 @@ __global__ void __launch_bounds__(256) k_gram_sym(int64_t n, int64_t rows_per_bl
                                                   const double* __restrict__ a,
                                                   const double* __restrict__ mm, int W,
                                                   const double* __restrict__ z1, int w1,
-                                                  const double* __restrict__ u, int m,
+                                                  const double* __restrict__ u, int m, int ldu,
                                                   double* __restrict__ part,
                                                   const int* __restrict__ corder,
                                                   const int* __restrict__ uperm) {
@@ -339,7 +228,7 @@ __global__ void __launch_bounds__(256) k_gram_sym(int64_t n, int64_t rows_per_bl
         const int rl = e / cpr, ch = e - (e / cpr) * cpr;
         const int64_t r = r0 + rl;
         const bool valid = e < items && r < r1;
-        y[k] = am_item<WT>(valid ? r : r0, valid, W, cols, a, mm, u, m, ch, &d[k], uperm);
+        y[k] = am_item<WT>(valid ? r : r0, valid, W, cols, a, mm, u, ldu, ch, &d[k], uperm);
       }
 #pragma unroll
       for (int k = 0; k < NB; ++k) {
@@ -396,7 +285,7 @@ __global__ void __launch_bounds__(1024) k_gram_sym1(int64_t n, int64_t rows_per_
                                                    const double* __restrict__ a,
                                                    const double* __restrict__ mm, int W,
                                                    const double* __restrict__ z1, int w1,
-                                                   const double* __restrict__ u, int m,
+                                                   const double* __restrict__ u, int m, int ldu,
                                                    double* __restrict__ part,
                                                    const int* __restrict__ corder,
                                                    const int* __restrict__ uperm) {
@@ -481,7 +370,7 @@ __global__ void __launch_bounds__(1024) k_gram_sym1(int64_t n, int64_t rows_per_
 #pragma unroll
         for (int k = 0; k < WT; ++k) j[k] = uperm != nullptr ? uperm[mc[k]] : mc[k];
 #pragma unroll
-        for (int k = 0; k < WT; ++k) xv[k] = *reinterpret_cast<const double2*>(u + int64_t(j[k]) * m + 2 * ch);
+        for (int k = 0; k < WT; ++k) xv[k] = *reinterpret_cast<const double2*>(u + int64_t(j[k]) * ldu + 2 * ch);
 #pragma unroll
         for (int k = 0; k < WT; ++k) {
           const double av = ma[k], mw = mv[k];
@@ -495,7 +384,7 @@ __global__ void __launch_bounds__(1024) k_gram_sym1(int64_t n, int64_t rows_per_
         x0 = double2{0.0, 0.0};
         for (int k = 0; k < W; ++k) {
           const int jj = uperm != nullptr ? uperm[mc[k]] : mc[k];
-          const double2 xv = *reinterpret_cast<const double2*>(u + int64_t(jj) * m + 2 * ch);
+          const double2 xv = *reinterpret_cast<const double2*>(u + int64_t(jj) * ldu + 2 * ch);
           if (k == 0) x0 = xv;  // slot 0 of every ELL row is the row itself
           a0 += ma[k] * xv.x;
           a1 += ma[k] * xv.y;
@@ -674,9 +563,9 @@ constexpr int kUpdKMax = 24;  // k steps of 4: nz <= 96
 
 template <int TJ, int KM>
 __global__ void __launch_bounds__(256) k_update_zy(int64_t n, const double* z1, int w1,
-                                                   const double* z2, int w2,
+                                                   const double* z2, int w2, int ldz2,
                                                    const double* __restrict__ Y, int m, int ks,
-                                                   double* U) {
+                                                   double* U, int ldu) {
   extern __shared__ double ys[];  // [ks * 4][TJ * 16]
   constexpr int MP = TJ * 16;
   const int nz = w1 + w2;
@@ -692,7 +581,7 @@ __global__ void __launch_bounds__(256) k_update_zy(int64_t n, const double* z1, 
     const int64_t r = tile * 16 + li;
     const bool live = tile < tiles && r < n;
     const double* p1 = z1 + (live ? r : 0) * w1;
-    const double* p2 = z2 + (live ? r : 0) * w2 - w1;
+    const double* p2 = z2 + (live ? r : 0) * ldz2 - w1;
     if ((w1 & 1) == 0) {
 #pragma unroll
       for (int s2 = 0; s2 < KM / 2; ++s2) {
@@ -743,7 +632,7 @@ __global__ void __launch_bounds__(256) k_update_zy(int64_t n, const double* z1, 
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t row = tile * 16 + lk + 4 * v;
-        if (row < n) U[row * m + c] = acc[t][v];
+        if (row < n) U[row * ldu + c] = acc[t][v];
       }
     }
 #pragma unroll
@@ -870,14 +759,14 @@ void sym_attr_all() {
 
 template <int TPW>
 void sym_launch(const GramPlan& p, const DevLevel& L, const SymTiles& tl, int TW, int TU, const double* w,
-                int w1, const double* u, int m, int64_t rpb, size_t shm, double* part, hipStream_t s,
+                int w1, const double* u, int m, int ldu, int64_t rpb, size_t shm, double* part, hipStream_t s,
                 const int* uperm) {
   const int64_t n = L.n;
   static const int nbenv = std::getenv("BMG_GRAM_NB") ? std::atoi(std::getenv("BMG_GRAM_NB")) : 0;
   const int nb = nbenv ? nbenv : (kGramAmChunk * (m / 2) > 256 ? 2 : 1);
 #define GS(nb_, wt_)                                                                              \
   BMG_LAUNCH((k_gram_sym<TPW, nb_, wt_>), p.nblk, 256, shm, s, n, rpb, tl, TW, TU, L.cols, L.a64, \
-             L.m64, L.W, w, w1, u, m, part, L.chunk_order, uperm)
+             L.m64, L.W, w, w1, u, m, ldu, part, L.chunk_order, uperm)
   if (L.W == 7) {
     if (nb == 3) GS(3, 7);
     else if (nb == 2) GS(2, 7);
@@ -900,14 +789,14 @@ void sym1_attr() {
 
 template <int TPW>
 void sym1_launch(const GramPlan& p, const DevLevel& L, const SymTiles& tl, int TW, int TU, const double* w,
-                 int w1, const double* u, int m, int64_t rpb, int nthr, size_t shm, double* part, hipStream_t s,
-                 const int* uperm) {
+                 int w1, const double* u, int m, int ldu, int64_t rpb, int nthr, size_t shm, double* part,
+                 hipStream_t s, const int* uperm) {
   if (L.W == 7)
     BMG_LAUNCH((k_gram_sym1<TPW, 7>), p.nblk, nthr, shm, s, L.n, rpb, tl, TW, TU, L.cols, L.a64, L.m64, L.W, w,
-               w1, u, m, part, L.chunk_order, uperm);
+               w1, u, m, ldu, part, L.chunk_order, uperm);
   else
     BMG_LAUNCH((k_gram_sym1<TPW, 0>), p.nblk, nthr, shm, s, L.n, rpb, tl, TW, TU, L.cols, L.a64, L.m64, L.W, w,
-               w1, u, m, part, L.chunk_order, uperm);
+               w1, u, m, ldu, part, L.chunk_order, uperm);
 }
 
 }  // namespace
@@ -915,9 +804,13 @@ void sym1_launch(const GramPlan& p, const DevLevel& L, const SymTiles& tl, int T
 int64_t sym_tile_doubles(int w1, int m) { return int64_t(sym_tiles(w1, m).T) * 256; }
 
 int launch_gram_am(const GramPlan& p, const DevLevel& L, const double* w, int w1, const double* u,
-                   int m, double* part, double* G, hipStream_t s, const int* uperm) {
-  static const bool dense = std::getenv("BMG_GRAM_DENSE") != nullptr;
-  if (!dense || uperm != nullptr) {
+                   int m, double* part, double* G, hipStream_t s, const int* uperm, int ldu) {
+  if (ldu <= 0) ldu = m;
+  if (ldu < m || (ldu & 1) != 0) {
+    set_error("gram_am: row stride %d of u must be even and at least m = %d", ldu, m);
+    return BMG_EINVAL;
+  }
+  {
     const int TW = (w1 + 15) / 16, TU = (m + 15) / 16;
     if (TW > 2 || TU > 6 || p.ny != 2 * m || p.nz != w1 + m || m % 2 != 0 || m < 2) {
       set_error("gram_am: unsupported shape w1=%d m=%d", w1, m);
@@ -967,7 +860,7 @@ int launch_gram_am(const GramPlan& p, const DevLevel& L, const double* w, int w1
       const size_t shm1 = shm + size_t(2) * kGramAmChunk * L.W * (2 * sizeof(double) + sizeof(int));
       const LaunchEvents ev = g_launch_events;
       g_launch_events = LaunchEvents{ev.start, nullptr};
-#define G1(t_) sym1_launch<t_>(q, L, tl, TW, TU, w, w1, u, m, rpb, nthr, shm1, part, s, uperm)
+#define G1(t_) sym1_launch<t_>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, nthr, shm1, part, s, uperm)
       if (tpw1 <= 1) G1(1);
       else if (tpw1 <= 2) G1(2);
       else if (tpw1 <= 3) G1(3);
@@ -986,15 +879,15 @@ int launch_gram_am(const GramPlan& p, const DevLevel& L, const double* w, int w1
     {
       const LaunchEvents ev = g_launch_events;
       g_launch_events = LaunchEvents{ev.start, nullptr};
-      if (tpw <= 1) sym_launch<1>(q, L, tl, TW, TU, w, w1, u, m, rpb, shm, part, s, uperm);
-      else if (tpw <= 2) sym_launch<2>(q, L, tl, TW, TU, w, w1, u, m, rpb, shm, part, s, uperm);
-      else if (tpw <= 3) sym_launch<3>(q, L, tl, TW, TU, w, w1, u, m, rpb, shm, part, s, uperm);
-      else if (tpw <= 4) sym_launch<4>(q, L, tl, TW, TU, w, w1, u, m, rpb, shm, part, s, uperm);
-      else if (tpw <= 6) sym_launch<6>(q, L, tl, TW, TU, w, w1, u, m, rpb, shm, part, s, uperm);
-      else if (tpw <= 8) sym_launch<8>(q, L, tl, TW, TU, w, w1, u, m, rpb, shm, part, s, uperm);
-      else if (tpw <= 10) sym_launch<10>(q, L, tl, TW, TU, w, w1, u, m, rpb, shm, part, s, uperm);
-      else if (tpw <= 12) sym_launch<12>(q, L, tl, TW, TU, w, w1, u, m, rpb, shm, part, s, uperm);
-      else sym_launch<17>(q, L, tl, TW, TU, w, w1, u, m, rpb, shm, part, s, uperm);
+      if (tpw <= 1) sym_launch<1>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm);
+      else if (tpw <= 2) sym_launch<2>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm);
+      else if (tpw <= 3) sym_launch<3>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm);
+      else if (tpw <= 4) sym_launch<4>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm);
+      else if (tpw <= 6) sym_launch<6>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm);
+      else if (tpw <= 8) sym_launch<8>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm);
+      else if (tpw <= 10) sym_launch<10>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm);
+      else if (tpw <= 12) sym_launch<12>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm);
+      else sym_launch<17>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm);
       g_launch_events = LaunchEvents{nullptr, ev.stop};
     }
     int st = check_launch();
@@ -1002,57 +895,6 @@ int launch_gram_am(const GramPlan& p, const DevLevel& L, const double* w, int w1
     BMG_LAUNCH((k_gram_sym_reduce), (tl.T * 256 + 15) / 16, 1024, 0, s, part, q.nblk, tl, TW, TU, w1, m, G);
     return check_launch();
   }
-  const int TI = p.nzp / 16;
-  const int TJ = p.nyp / 16;
-  const int TJW = (TJ + 3) / 4;
-  if (TI < 1 || TI > 6 || TJW < 1 || TJW > 3 || p.ny != 2 * m || p.nz != w1 + m || m % 2 != 0) {
-    set_error("gram_am: unsupported shape nz=%d ny=%d m=%d", p.nz, p.ny, m);
-    return BMG_EINVAL;
-  }
-  const int64_t n = L.n;
-  int64_t rpb = (n + p.nblk - 1) / p.nblk;
-  rpb = (rpb + kGramAmChunk - 1) / kGramAmChunk * kGramAmChunk;
-  const size_t shm = size_t(kGramAmChunk) * p.nyp * sizeof(double);
-  {
-    const LaunchEvents ev = g_launch_events;
-    g_launch_events = LaunchEvents{ev.start, nullptr};
-#define GA(a_, b_)                                                                                 \
-  do {                                                                                             \
-    if (L.W == 7)                                                                                  \
-      BMG_LAUNCH((k_gram_am<a_, b_, 7>), p.nblk, 256, shm, s, n, rpb, p.nzp, p.nyp, L.cols, L.a64, \
-                 L.m64, L.W, w, w1, u, m, part, L.chunk_order);                                     \
-    else                                                                                           \
-      BMG_LAUNCH((k_gram_am<a_, b_, 0>), p.nblk, 256, shm, s, n, rpb, p.nzp, p.nyp, L.cols, L.a64, \
-                 L.m64, L.W, w, w1, u, m, part, L.chunk_order);                                     \
-  } while (0)
-    switch (TI * 4 + TJW) {
-      case 1 * 4 + 1: GA(1, 1); break;
-      case 1 * 4 + 2: GA(1, 2); break;
-      case 1 * 4 + 3: GA(1, 3); break;
-      case 2 * 4 + 1: GA(2, 1); break;
-      case 2 * 4 + 2: GA(2, 2); break;
-      case 2 * 4 + 3: GA(2, 3); break;
-      case 3 * 4 + 1: GA(3, 1); break;
-      case 3 * 4 + 2: GA(3, 2); break;
-      case 3 * 4 + 3: GA(3, 3); break;
-      case 4 * 4 + 1: GA(4, 1); break;
-      case 4 * 4 + 2: GA(4, 2); break;
-      case 4 * 4 + 3: GA(4, 3); break;
-      case 5 * 4 + 1: GA(5, 1); break;
-      case 5 * 4 + 2: GA(5, 2); break;
-      case 5 * 4 + 3: GA(5, 3); break;
-      case 6 * 4 + 1: GA(6, 1); break;
-      case 6 * 4 + 2: GA(6, 2); break;
-      case 6 * 4 + 3: GA(6, 3); break;
-    }
-#undef GA
-    g_launch_events = LaunchEvents{nullptr, ev.stop};
-  }
-  int st = check_launch();
-  if (st != BMG_OK) return st;
-  const int tot = p.nz * p.ny;
-  BMG_LAUNCH((k_gram_reduce), (tot + 15) / 16, 1024, 0, s, part, p.nblk, p.nzp, p.nyp, p.nz, p.ny, G);
-  return check_launch();
 }
 
 // ------------------------------------------- allocation-free fused Gram --
@@ -1090,8 +932,14 @@ int noalloc_scratch(int dev, double** out) {
 }  // namespace
 
 int launch_update_zy(int64_t n, const double* z1, int w1, const double* z2, int w2,
-                     const double* Y, double* U, int m, hipStream_t s) {
+                     const double* Y, double* U, int m, hipStream_t s, int ldz2, int ldu) {
   const int nz = w1 + w2;
+  if (ldz2 <= 0) ldz2 = w2;
+  if (ldu <= 0) ldu = m;
+  if (ldz2 < w2 || ldu < m || (ldz2 & 1) != 0) {
+    set_error("update: row strides %d, %d too small for w2 = %d, m = %d (or odd)", ldz2, ldu, w2, m);
+    return BMG_EINVAL;
+  }
   const int ks = (nz + 7) / 8 * 2;  // k steps of 4, in pairs (see the kernel's A fragments)
   const int TJ = (m + 15) / 16;
   if (ks < 1 || ks > kUpdKMax || TJ < 1 || TJ > 6 || m % 4 != 0) {
@@ -1113,9 +961,9 @@ int launch_update_zy(int64_t n, const double* z1, int w1, const double* z2, int 
 #define UL(tj)                                                                                    \
   do {                                                                                            \
     if (ks <= 12)                                                                                 \
-      BMG_LAUNCH((k_update_zy<tj, 12>), grid, 256, shm, s, n, z1, w1, z2, w2, Y, m, ks, U);       \
-    else                                                                                          \
-      BMG_LAUNCH((k_update_zy<tj, 24>), grid, 256, shm, s, n, z1, w1, z2, w2, Y, m, ks, U);       \
+      BMG_LAUNCH((k_update_zy<tj, 12>), grid, 256, shm, s, n, z1, w1, z2, w2, ldz2, Y, m, ks, U, ldu); \
+    else                                                                                              \
+      BMG_LAUNCH((k_update_zy<tj, 24>), grid, 256, shm, s, n, z1, w1, z2, w2, ldz2, Y, m, ks, U, ldu); \
   } while (0)
   switch (TJ) {
     case 1: UL(1); break;

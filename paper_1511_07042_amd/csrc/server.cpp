@@ -10,9 +10,14 @@
 // the active requests; smaller requests may pass a waiting larger one, a
 // bounded number of times.
 //
-// A request's result is the result of bmg_solve with the same arguments, bit
-// for bit: the kernels are deterministic and solves share only read-only
-// hierarchy data.  Hierarchies are built on first use and cached by surface
+// Requests for the same surface, level and shift that run the enriched scheme
+// with the same cycle options are grouped: a worker that starts one takes the
+// compatible requests waiting behind it (up to kMaxGroup, 512 columns) and runs
+// them as one grouped solve (bmg_solve_group), whose correction cycle is a
+// single set of launches over their concatenated blocks.  A grouped request's
+// result equals its bmg_solve result to rounding; any other request's result
+// is the result of bmg_solve with the same arguments, bit for bit: the kernels
+// are deterministic and solves share only read-only hierarchy data.  Hierarchies are built on first use and cached by surface
 // and level; idle workspaces and then idle hierarchies (least recently used
 // first) are freed when the budget needs their memory.
 #include <algorithm>
@@ -46,6 +51,8 @@ struct Request {
   double sigma = 0.0, tol = 0.0;
   bmg_solve_opts opts{};
   std::string key;
+  bool groupable = false;  // enriched scheme, no ramp: may share a grouped solve
+  int m_est = 0;           // block width the solver will use
   int64_t n_est = 0;   // finest-level vertices
   int64_t need = 0;    // workspace bytes reserved while running
   int64_t hier = 0;    // hierarchy bytes if it must be built
@@ -180,6 +187,18 @@ std::string surface_key(const Request& r) {
   return k.str();
 }
 
+constexpr int kMaxGroup = 8;
+constexpr int kMaxGroupColumns = 512;
+
+// Whether b may join a grouped solve led by a: same hierarchy and shift, and
+// the options a grouped solve requires to agree (bmg_solve_group).
+bool group_compatible(const Request& a, const Request& b) {
+  const bmg_solve_opts &x = a.opts, &y = b.opts;
+  return a.groupable && b.groupable && a.key == b.key && a.sigma == b.sigma && x.precision == y.precision &&
+         x.smoother == y.smoother && x.nu1 == y.nu1 && x.nu2 == y.nu2 && x.omega == y.omega &&
+         x.n_c == y.n_c && x.l_c == y.l_c;
+}
+
 // Sets the calling thread's cancel flag for the duration of a solve.
 struct CancelScope {
   explicit CancelScope(const std::atomic<int>* f) { bmg::g_cancel = f; }
@@ -201,6 +220,7 @@ struct bmg_server {
   int running = 0;
   uint64_t next_id = 1, tick = 0;
   bool stopping = false;
+  bool grouping = std::getenv("BMG_NO_GROUP") == nullptr;
   std::vector<std::thread> workers;
 
   // ---- everything below runs with mu held
@@ -252,6 +272,28 @@ struct bmg_server {
       if (head_only) break;
     }
     return nullptr;
+  }
+
+  // Compatible requests waiting behind the leader that fit the budget: taken
+  // off the queue and reserved (their workspaces' bytes) for one grouped solve.
+  std::vector<Request*> take_group(Request* lead) {
+    std::vector<Request*> g{lead};
+    if (!grouping || !lead->groupable) return g;
+    int cols = lead->m_est;
+    for (size_t i = 0; i < queue.size() && int(g.size()) < kMaxGroup;) {
+      Request& r = *reqs.at(queue[i]);
+      if (group_compatible(*lead, r) && cols + r.m_est <= kMaxGroupColumns &&
+          resident() + r.need <= budget) {
+        cols += r.m_est;
+        active_bytes += r.need;
+        r.state = RUNNING;
+        g.push_back(&r);
+        queue.erase(queue.begin() + i);
+      } else {
+        ++i;
+      }
+    }
+    return g;
   }
 
   void finish(Request* r, int st) {
@@ -321,25 +363,45 @@ struct bmg_server {
       r->state = RUNNING;
       active_bytes += r->need;
       ++running;
+      const std::vector<Request*> group = take_group(r);
       bmg_hierarchy* h = nullptr;
       int st = acquire_hierarchy(r, stream, lk, &h);
+      std::vector<int> sts(group.size(), st);
       if (st == BMG_OK) {
         lk.unlock();
         int64_t nf = 0, hb = 0;
         hierarchy_totals(h, &nf, &hb);
-        r->N = nf;
-        r->evals.assign(r->k, 0.0);
-        r->evecs.assign(size_t(r->N) * r->k, 0.0);
-        r->rho.assign(r->k, 0.0);
-        r->delta.assign(r->k, 0.0);
-        r->stats.rho = r->rho.data();
-        r->stats.delta = r->delta.data();
-        {
+        for (Request* q : group) {
+          q->N = nf;
+          q->evals.assign(q->k, 0.0);
+          q->evecs.assign(size_t(q->N) * q->k, 0.0);
+          q->rho.assign(q->k, 0.0);
+          q->delta.assign(q->k, 0.0);
+          q->stats.rho = q->rho.data();
+          q->stats.delta = q->delta.data();
+        }
+        if (group.size() == 1) {
           CancelScope scope(&r->cancel);
           st = bmg::solve(h, r->k, r->sigma, r->tol, &r->opts, r->evals.data(), r->evecs.data(),
                           r->N, 0, stream, &r->stats);
+          sts[0] = st;
+          if (st != BMG_OK) r->error = bmg_last_error();
+        } else {
+          std::vector<bmg_group_request> gr(group.size());
+          std::vector<const std::atomic<int>*> flags(group.size());
+          for (size_t i = 0; i < group.size(); ++i) {
+            Request* q = group[i];
+            gr[i] = bmg_group_request{q->k, q->tol, &q->opts, q->evals.data(), q->evecs.data(), q->N, 0,
+                                      BMG_OK, &q->stats};
+            flags[i] = &q->cancel;
+          }
+          st = bmg::solve_group(h, r->sigma, int(group.size()), gr.data(), stream, flags.data());
+          const std::string err = st == BMG_OK ? "" : bmg_last_error();
+          for (size_t i = 0; i < group.size(); ++i) {
+            sts[i] = gr[i].status;
+            if (sts[i] != BMG_OK) group[i]->error = sts[i] == BMG_ECANCELED ? "canceled" : err;
+          }
         }
-        if (st != BMG_OK) r->error = bmg_last_error();
         lk.lock();
         auto it = cache.find(r->key);
         if (it != cache.end()) {
@@ -347,9 +409,12 @@ struct bmg_server {
           it->second.last_use = ++tick;
         }
       }
-      active_bytes -= r->need;
       --running;
-      finish(r, st);
+      for (size_t i = 0; i < group.size(); ++i) {
+        active_bytes -= group[i]->need;
+        if (st != BMG_OK && group[i]->error.empty()) group[i]->error = r->error;
+        finish(group[i], sts[i]);
+      }
     }
     lk.unlock();
     if (stream) (void)hipStreamDestroy(stream);
@@ -422,6 +487,8 @@ int bmg_server_submit(bmg_server* s, const bmg_surface_desc* desc, int32_t n_ref
   if (shifted)
     extra = shifted_estimate(r->desc, n_refine, m_est, r->opts.m > 0, r->opts.precision, &m_est);
   r->need = workspace_estimate(r->desc, n_refine, m_est, n_c, r->opts.precision) + extra;
+  r->groupable = !shifted && r->opts.ramp_cycles == 0;
+  r->m_est = m_est;
   BMG_CHECK(m_est >= k && int64_t(m_est) <= r->n_est / 2, "m must be in [k, N_L / 2]");
   std::lock_guard<std::mutex> g(s->mu);
   BMG_CHECK(!s->stopping, "the server is shutting down");

@@ -14,6 +14,7 @@
 //   H5  SVQB M-orthonormalisation and the shifted Ritz problem (one workgroup).
 //   H6  U <- Z Y.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <cstdio>
@@ -26,6 +27,7 @@
 struct bmg_workspace {
   int64_t N = 0;
   int m = 0, n_c = 0, prec = 0, nl = 0;
+  int gram_m = 0;  // widest block the Gram / Ritz buffers serve (m, or less in a grouped solve)
   bool busy = false;
   double *W = nullptr, *AW = nullptr, *MW = nullptr;
   double *U = nullptr, *AU = nullptr, *MU = nullptr;
@@ -100,8 +102,10 @@ void free_workspace(bmg_workspace* w) {
   delete w;
 }
 
-int make_workspace(bmg_hierarchy* h, int m, int n_c, int prec, bmg_workspace** out) {
+int make_workspace(bmg_hierarchy* h, int m, int n_c, int prec, bmg_workspace** out, int gram_m = 0) {
   auto* w = new bmg_workspace();
+  if (gram_m <= 0) gram_m = m;
+  w->gram_m = gram_m;
   const int nl = int(h->dev.size());
   const int64_t N = h->dev[nl - 1].n;
   w->N = N;
@@ -140,14 +144,20 @@ int make_workspace(bmg_hierarchy* h, int m, int n_c, int prec, bmg_workspace** o
   AL(w->tail_img, size_t(kTailLdsBudget));
   AL(w->ctmp, vb * h->n0 * m);
   AL(w->gco, vb * h->n0);
-  const int nz = n_c + m;
-  w->gp = gram_plan(N, nz, 2 * m);
+  // Gram and Ritz buffers for blocks up to gram_m wide: every plan of a width
+  // w <= gram_m fits the partial-sum buffer
+  const int nz = n_c + gram_m;
+  w->gp = gram_plan(N, nz, 2 * gram_m);
   w->gpw = gram_plan(N, n_c, 2 * n_c);
-  const size_t gpb = std::max(size_t(w->gp.nblk) * w->gp.per_block, size_t(w->gpw.nblk) * w->gpw.per_block);
+  size_t gpb = std::max(size_t(w->gp.nblk) * w->gp.per_block, size_t(w->gpw.nblk) * w->gpw.per_block);
+  for (int gw = 2; gw < gram_m; gw += 2) {
+    const GramPlan q = gram_plan(N, n_c + gw, 2 * gw);
+    gpb = std::max(gpb, size_t(q.nblk) * q.per_block);
+  }
   AL(w->gpart, sizeof(double) * gpb);
-  AL(w->G, sizeof(double) * nz * 2 * m);
+  AL(w->G, sizeof(double) * nz * 2 * gram_m);
   AL(w->GW, sizeof(double) * n_c * 2 * n_c);
-  AL(w->Y, sizeof(double) * nz * m);
+  AL(w->Y, sizeof(double) * nz * gram_m);
   // theta [m], rho2 [m] and the Ritz status words [16] are contiguous: one
   // device-to-host copy per cycle reads all three
   AL(w->theta, sizeof(double) * (2 * m + 8));
@@ -191,18 +201,19 @@ int make_workspace(bmg_hierarchy* h, int m, int n_c, int prec, bmg_workspace** o
   return BMG_OK;
 }
 
-int acquire_workspace(bmg_hierarchy* h, int m, int n_c, int prec, bmg_workspace** out) {
+int acquire_workspace(bmg_hierarchy* h, int m, int n_c, int prec, bmg_workspace** out, int gram_m = 0) {
+  if (gram_m <= 0) gram_m = m;
   {
     std::lock_guard<std::mutex> g(h->ws_mutex);
     for (auto* w : h->ws_pool)
-      if (!w->busy && w->m == m && w->n_c == n_c && w->prec == prec) {
+      if (!w->busy && w->m == m && w->n_c == n_c && w->prec == prec && w->gram_m == gram_m) {
         w->busy = true;
         *out = w;
         return BMG_OK;
       }
   }
   bmg_workspace* w = nullptr;
-  BMG_TRY(make_workspace(h, m, n_c, prec, &w));
+  BMG_TRY(make_workspace(h, m, n_c, prec, &w, gram_m));
   w->busy = true;
   std::lock_guard<std::mutex> g(h->ws_mutex);
   h->ws_pool.push_back(w);
@@ -1208,6 +1219,7 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   if (stats) {
     stats->cycles = cycles;
     stats->converged = cert.ok ? 1 : 0;
+    stats->group_size = 1;
     stats->m = m;
     stats->n_c = n_c;
     stats->l_c = l_c;
@@ -1244,6 +1256,247 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     }
   }
   return status;
+}
+
+// One request of a grouped solve: its slice of the concatenated block and
+// its own Ritz state.
+struct GroupItem {
+  bmg_group_request* r = nullptr;
+  bmg_solve_opts o{};
+  int m = 0, off = 0;
+  double* rscratch = nullptr;  // [ritz_scratch_doubles(n_c + m)], persists between Ritz steps
+  int* status = nullptr;       // [16] Ritz status words
+  const std::atomic<int>* cancel = nullptr;
+  bool done = false;
+  int cycles = 0;
+};
+
+// Grouped enriched solve (bmg_solve_group): the workspace w is M = sum m_i
+// columns wide; request i owns columns [off_i, off_i + m_i) of U, of the
+// correction blocks and of theta / rho2.
+template <typename T>
+int run_group(bmg_hierarchy* h, bmg_workspace* w, double sigma, std::vector<GroupItem>& items,
+              const bmg_solve_opts& o, int l_c, hipStream_t s) {
+  const int nl = int(h->dev.size());
+  const int L = nl - 1;
+  const DevLevel& DL = h->dev[L];
+  const int64_t N = DL.n;
+  const int M = w->m, n_c = o.n_c;
+  const int64_t n0 = h->n0;
+  const auto t0 = std::chrono::steady_clock::now();
+  // S2: W_c = P_{0->L} Phi_c (the n_c level-0 eigenvectors nearest sigma) and
+  // its Gram blocks, shared by the group
+  {
+    std::vector<int> idx = nearest(h->lam0, sigma, n_c);
+    std::sort(idx.begin(), idx.end());
+    std::vector<double> phic(size_t(n0) * n_c);
+    for (int64_t i = 0; i < n0; ++i)
+      for (int j = 0; j < n_c; ++j) phic[size_t(i) * n_c + j] = h->phi0[size_t(i) * n0 + idx[j]];
+    double* cur = (L % 2 == 0) ? w->W : w->AW;
+    BMG_HIP(hipMemcpyAsync(cur, phic.data(), sizeof(double) * phic.size(), hipMemcpyHostToDevice, s));
+    for (int l = 1; l <= L; ++l) {
+      double* nxt = (cur == w->W) ? w->AW : w->W;
+      BMG_TRY(launch_fill<double>(nxt, h->dev[l].n * n_c, 0.0, s));
+      BMG_TRY(launch_prolong_add<double>(h->dev[l], cur, nxt, n_c, s));
+      cur = nxt;
+    }
+    BMG_TRY(launch_spmm_am(DL, w->W, w->AW, w->MW, n_c, s));
+    BMG_TRY(launch_gram(w->gpw, N, w->W, n_c, nullptr, 0, w->AW, n_c, w->MW, n_c, w->gpart, w->GW, s));
+    BMG_HIP(hipStreamSynchronize(s));  // phic is a host local
+  }
+  // S3: each request's seeded block (the same numbers as its solo solve),
+  // drawn into scratch and copied into its columns
+  for (GroupItem& it : items) {
+    BMG_TRY(launch_gaussian(w->AU, N, it.m, it.o.seed, s, DL.perm));
+    BMG_HIP(hipMemcpy2DAsync(w->U + it.off, sizeof(double) * M, w->AU, sizeof(double) * it.m,
+                             sizeof(double) * it.m, size_t(N), hipMemcpyDeviceToDevice, s));
+  }
+  // H4-H6 per request on its slice: fused Gram, Ritz, update in place
+  auto ritz_steps = [&](int warm) -> int {
+    for (GroupItem& it : items) {
+      const int nz = n_c + it.m;
+      const GramPlan gp = gram_plan(N, nz, 2 * it.m);
+      double* u = w->U + it.off;
+      BMG_TRY(launch_gram_am(gp, DL, w->W, n_c, u, it.m, w->gpart, w->G, s, nullptr, M));
+      RitzArgs ra;
+      ra.n_c = n_c;
+      ra.m = it.m;
+      ra.nz = nz;
+      ra.sigma = sigma;
+      ra.rtol2 = kRitzRtol2;
+      ra.warm = warm;
+      ra.G = w->G;
+      ra.GW = w->GW;
+      ra.Y = w->Y;
+      ra.theta = w->theta + it.off;
+      ra.scratch = it.rscratch;
+      ra.status = it.status;
+      BMG_TRY(launch_ritz(ra, s));
+      BMG_TRY(launch_update_zy(N, w->W, n_c, u, it.m, w->Y, u, it.m, s, M, M));
+    }
+    return BMG_OK;
+  };
+  BMG_TRY(ritz_steps(0));
+  Cycle<T> cyc;
+  BMG_TRY(init_cycle<T>(cyc, h, w, CycleCfg{M, o.nu1, o.nu2, o.smoother, l_c, sigma, o.omega}, L, s));
+  cyc.L = L;
+  const bool fold_add = std::getenv("BMG_NO_FUSE") == nullptr;
+  // H1 over the whole block: -R and every column's rho^2
+  auto residual_step = [&]() -> int {
+    BMG_TRY(launch_eigres<T>(DL, w->U, w->theta, -1.0, cyc.f[L], w->rho2part, w->nblk_res, M, s));
+    BMG_TRY(launch_colsum(w->rho2part, w->nblk_res, M, w->rho2, s, nullptr, nullptr));
+    return BMG_OK;
+  };
+  auto cycle_body = [&]() -> int {
+    cyc.add_u = fold_add ? w->U : nullptr;
+    cyc.add_level = L;
+    cyc.added = false;
+    BMG_TRY(cyc.vcycle(L));
+    if (!cyc.added) BMG_TRY(launch_add_to<T>(w->U, cyc.e[L], N * M, s));
+    BMG_TRY(ritz_steps(1));
+    BMG_TRY(residual_step());
+    return BMG_OK;
+  };
+  // the cycle is replayed as a graph when it can be captured
+  bool use_graph = !std::getenv("BMG_NO_GRAPH");
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  auto launch_body = [&]() -> int {
+    if (!use_graph) return cycle_body();
+    if (!gexec) {
+      const std::vector<T*> e0 = cyc.e, t0v = cyc.t;
+      BMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      const int cst = cycle_body();
+      hipGraph_t g = nullptr;
+      const hipError_t ce = hipStreamEndCapture(s, &g);
+      const bool swapped = cyc.e != e0 || cyc.t != t0v;
+      if (cst != BMG_OK || ce != hipSuccess || swapped) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        cyc.e = e0;
+        cyc.t = t0v;
+        use_graph = false;
+        return cycle_body();
+      }
+      if (hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        set_error("graph instantiation failed");
+        return BMG_EDEVICE;
+      }
+      graph = g;
+    }
+    BMG_HIP(hipGraphLaunch(gexec, s));
+    return BMG_OK;
+  };
+  struct GraphGuard {
+    hipGraph_t& g;
+    hipGraphExec_t& e;
+    ~GraphGuard() {
+      if (e) (void)hipGraphExecDestroy(e);
+      if (g) (void)hipGraphDestroy(g);
+    }
+  } guard{graph, gexec};
+  BMG_TRY(residual_step());
+  const int n = int(items.size());
+  int left = n, cycles = 0;
+  std::vector<double> hb(2 * size_t(M));
+  std::vector<int> hs(16 * size_t(n));
+  // the requests' status words are contiguous (see solve_group)
+  const int* status_base = items[0].status;
+  for (;;) {
+    BMG_HIP(hipMemcpyAsync(hb.data(), w->theta, sizeof(double) * 2 * M, hipMemcpyDeviceToHost, s));
+    BMG_HIP(hipMemcpyAsync(hs.data(), status_base, sizeof(int) * hs.size(), hipMemcpyDeviceToHost, s));
+    BMG_HIP(hipStreamSynchronize(s));
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (int q = 0; q < n; ++q) {
+      GroupItem& it = items[q];
+      if (it.done) continue;
+      bmg_group_request& r = *it.r;
+      std::vector<double> theta(hb.begin() + it.off, hb.begin() + it.off + it.m);
+      std::vector<double> rho2(hb.begin() + M + it.off, hb.begin() + M + it.off + it.m);
+      const int rstat = hs[16 * q];
+      int st = BMG_OK;
+      Cert cert;
+      bool finish = false;
+      if (rstat == 1) {
+        st = BMG_ENOCONV;
+        finish = true;
+      } else {
+        bool finite = true;
+        for (int j = 0; j < it.m; ++j) finite = finite && std::isfinite(theta[j]) && std::isfinite(rho2[j]);
+        cert = certify(theta, rho2, sigma, r.k, r.tol, it.o.angle_tol);
+        if (!finite) {
+          st = BMG_ENOCONV;
+          finish = true;
+        } else if (cert.ok) {
+          finish = true;
+        } else if (it.cancel && it.cancel->load(std::memory_order_relaxed)) {
+          st = BMG_ECANCELED;
+          finish = true;
+        } else if (cycles >= it.o.max_cycles) {
+          st = BMG_ENOCONV;
+          finish = true;
+        }
+      }
+      if (!finish) continue;
+      // output as in bmg_solve, from this request's columns of the block
+      std::vector<int> sel = cert.ret;
+      std::sort(sel.begin(), sel.end());
+      const bool have_pairs = rstat != 1 && int(sel.size()) == r.k;
+      if (have_pairs) {
+        for (int j = 0; j < r.k; ++j) r.evals[j] = theta[sel[j]];
+        if (r.evecs) {
+          std::vector<int> gsel(sel);
+          for (int& c : gsel) c += it.off;
+          BMG_HIP(hipMemcpyAsync(w->sel, gsel.data(), sizeof(int) * r.k, hipMemcpyHostToDevice, s));
+          BMG_TRY(launch_signs(N, w->U, M, w->sel, r.k, DL.iperm, w->sign, w->argv, w->argi, w->nblk_arg, s));
+          if (r.evecs_on_device) {
+            BMG_TRY(launch_write_evecs(N, w->U, M, w->sel, w->sign, r.k, DL.iperm, r.evecs, r.ld, s));
+          } else {
+            BMG_TRY(launch_write_evecs(N, w->U, M, w->sel, w->sign, r.k, DL.iperm, w->AU, N, s));
+            BMG_HIP(hipMemcpy2DAsync(r.evecs, sizeof(double) * r.ld, w->AU, sizeof(double) * N,
+                                     sizeof(double) * N, r.k, hipMemcpyDeviceToHost, s));
+          }
+          BMG_HIP(hipStreamSynchronize(s));  // gsel is a local
+        }
+      }
+      if (r.stats) {
+        bmg_solve_stats& t = *r.stats;
+        t.cycles = cycles;
+        t.converged = cert.ok && st == BMG_OK ? 1 : 0;
+        t.group_size = n;
+        t.m = it.m;
+        t.n_c = n_c;
+        t.l_c = l_c;
+        t.t_solve_ms = ms;
+        t.max_rho_over_delta = cert.max_dk;
+        t.max_kato_temple = cert.max_kt;
+        t.timed_kernel_ms = 0.0;
+        t.timed_kernel_bytes = 0.0;
+        t.timed_kernel_units = 0;
+        t.ritz_sweeps_max = 0;
+        t.ritz_fallbacks = 0;
+        t.scheme = BMG_SCHEME_ENRICHED;
+        t.coarse_eig_ms = 0.0;
+        t.lc_shift = sigma;
+        t.ramp_start = -1;
+        for (int j = 0; j < r.k && have_pairs; ++j) {
+          const int pos = int(std::find(cert.ret.begin(), cert.ret.end(), sel[j]) - cert.ret.begin());
+          if (t.rho) t.rho[j] = cert.rho[pos];
+          if (t.delta) t.delta[j] = cert.delta[pos];
+        }
+      }
+      r.status = st;
+      it.done = true;
+      it.cycles = cycles;
+      --left;
+    }
+    if (left == 0) break;
+    BMG_TRY(launch_body());
+    ++cycles;
+  }
+  return BMG_OK;
 }
 
 }  // namespace
@@ -1333,6 +1586,110 @@ int solve(bmg_hierarchy* h, int k, double sigma, double tol, const bmg_solve_opt
   if (hipEventRecord(w->ev_out, s) == hipSuccess) (void)hipStreamWaitEvent(cs, w->ev_out, 0);
   release_workspace(h, w);
   return st;
+}
+
+int solve_group(bmg_hierarchy* h, double sigma, int n, bmg_group_request* reqs, void* stream,
+                const std::atomic<int>* const* cancel) {
+  TraceRange trace("bmg_solve_group");
+  BMG_CHECK(h != nullptr && !h->dev.empty(), "hierarchy with device data required");
+  BMG_CHECK(n >= 1 && reqs != nullptr, "n >= 1 requests required");
+  BMG_CHECK(std::isfinite(sigma), "sigma must be finite");
+  const int nl = int(h->dev.size());
+  const int64_t N = h->dev[nl - 1].n;
+  std::vector<GroupItem> items(n);
+  int M = 0;
+  for (int i = 0; i < n; ++i) {
+    bmg_group_request& r = reqs[i];
+    GroupItem& it = items[i];
+    it.r = &r;
+    bmg_solve_opts_default(&it.o);
+    if (r.opts) it.o = *r.opts;
+    bmg_solve_opts& o = it.o;
+    BMG_CHECK(r.k >= 1 && r.evals != nullptr, "request %d: k >= 1 and evals required", i);
+    BMG_CHECK(r.tol > 0 && std::isfinite(r.tol), "request %d: tol must be positive and finite", i);
+    BMG_CHECK(o.scheme == BMG_SCHEME_ENRICHED || (o.scheme == BMG_SCHEME_AUTO && sigma <= 0.0),
+              "request %d: a grouped solve runs the enriched scheme (sigma <= 0 or scheme ENRICHED)", i);
+    BMG_CHECK(o.initial_block == nullptr && o.ramp_cycles == 0, "request %d: no initial block or ramp in a group", i);
+    if (o.m <= 0) o.m = default_block_width(r.k, sigma);
+    if (o.n_c <= 0) o.n_c = default_coarse_vectors(h);
+    if (o.l_c < 0) o.l_c = weyl_coarsest(h, sigma);
+    BMG_CHECK(o.m % 4 == 0 && o.m >= r.k && int64_t(o.m) <= N / 2, "request %d: m = %d invalid", i, o.m);
+    BMG_CHECK(o.n_c % 2 == 0 && o.n_c >= 2 && o.n_c <= h->n0 && o.n_c + o.m <= 96,
+              "request %d: n_c = %d invalid", i, o.n_c);
+    BMG_CHECK(o.max_cycles >= 0 && o.angle_tol > 0, "request %d: max_cycles / angle_tol invalid", i);
+    BMG_CHECK(r.evecs == nullptr || r.ld >= N, "request %d: ld must be >= N_L", i);
+    const bmg_solve_opts& f = items[0].o;
+    BMG_CHECK(o.precision == f.precision && o.smoother == f.smoother && o.nu1 == f.nu1 && o.nu2 == f.nu2 &&
+                  o.omega == f.omega && o.n_c == f.n_c && o.l_c == f.l_c,
+              "request %d: precision, smoother, nu1, nu2, omega, n_c and l_c must agree across the group", i);
+    it.m = o.m;
+    it.off = M;
+    it.cancel = cancel ? cancel[i] : nullptr;
+    M += o.m;
+    r.status = BMG_EINVAL;
+  }
+  const bmg_solve_opts& o = items[0].o;
+  BMG_CHECK(M <= 512, "the group's blocks are %d columns wide; at most 512", M);
+  BMG_CHECK(o.nu1 >= 0 && o.nu2 >= 0 && o.nu1 <= 64 && o.nu2 <= 64, "nu1, nu2 must be in [0, 64]");
+  BMG_CHECK(o.smoother == BMG_SMOOTH_GS || o.smoother == BMG_SMOOTH_JACOBI || o.smoother == BMG_SMOOTH_KACZMARZ,
+            "unknown smoother");
+  BMG_CHECK(o.precision == BMG_FP64 || o.precision == BMG_MIXED, "unknown precision");
+  BMG_CHECK(o.omega > 0 && o.omega < 2, "omega must be in (0, 2)");
+  BMG_CHECK(o.l_c >= 0 && o.l_c < nl, "l_c out of range");
+  BMG_HIP(hipSetDevice(h->device));
+  int max_m = 0;
+  for (const GroupItem& it : items) max_m = std::max(max_m, it.m);
+  bmg_workspace* w = nullptr;
+  BMG_TRY(acquire_workspace(h, M, o.n_c, o.precision, &w, max_m));
+  hipStream_t cs = static_cast<hipStream_t>(stream);
+  hipStream_t s = w->stream;
+  // per-request Ritz scratch and status words (contiguous: one readback)
+  std::vector<void*> bufs;
+  int st = BMG_OK;
+  auto dalloc_local = [&](void** p, size_t bytes) -> int {
+    if (hipMalloc(p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("hipMalloc of %zu bytes failed", bytes);
+      return BMG_ENOMEM;
+    }
+    bufs.push_back(*p);
+    return BMG_OK;
+  };
+  int* status_all = nullptr;
+  st = dalloc_local(reinterpret_cast<void**>(&status_all), sizeof(int) * 16 * n);
+  for (int i = 0; i < n && st == BMG_OK; ++i) {
+    items[i].status = status_all + 16 * i;
+    st = dalloc_local(reinterpret_cast<void**>(&items[i].rscratch),
+                      sizeof(double) * ritz_scratch_doubles(o.n_c + items[i].m));
+  }
+  if (st == BMG_OK && hipMemsetAsync(status_all, 0, sizeof(int) * 16 * n, s) != hipSuccess) {
+    set_error("status clear failed");
+    st = BMG_EDEVICE;
+  }
+  if (st == BMG_OK) {
+    if (hipEventRecord(w->ev_in, cs) != hipSuccess || hipStreamWaitEvent(s, w->ev_in, 0) != hipSuccess) {
+      set_error("stream join failed");
+      st = BMG_EDEVICE;
+    } else {
+      st = (o.precision == BMG_MIXED) ? run_group<float>(h, w, sigma, items, o, o.l_c, s)
+                                      : run_group<double>(h, w, sigma, items, o, o.l_c, s);
+    }
+  }
+  (void)hipStreamSynchronize(s);
+  if (hipEventRecord(w->ev_out, s) == hipSuccess) (void)hipStreamWaitEvent(cs, w->ev_out, 0);
+  for (void* p : bufs) (void)hipFree(p);
+  release_workspace(h, w);
+  if (st != BMG_OK) {
+    for (int i = 0; i < n; ++i)
+      if (!items[i].done) reqs[i].status = st;
+    return st;
+  }
+  for (int i = 0; i < n; ++i)
+    if (reqs[i].status != BMG_OK) {
+      set_error("request %d of the group ended with status %d", i, reqs[i].status);
+      return reqs[i].status;
+    }
+  return BMG_OK;
 }
 
 // V-cycle for bmg_apply: uses a temporary workspace.
