@@ -373,16 +373,24 @@ def serving(a, bmg):
         "makespan_s": round(span, 3), "slots": a.serving_slots, "budget_gib": a.serving_budget_gib,
         "seed": 0, "data": "synthetic",
         "cycles_p50": float(np.percentile([r["stats"]["cycles"] for r in res], 50)),
+        "grouped_requests": int(sum(r["stats"]["group_size"] > 1 for r in res)),
+        "max_group_size": int(max(r["stats"]["group_size"] for r in res)),
         "config": {"workload": "c5_serving_stream", "kinds": sorted(kinds),
                    "shifts": not a.serving_no_shift, "smoother": a.smoother},
     }
 
 
-def concurrent(bmg, cfg, smoother, n_req=16, slots=8):
-    """Independent solves of the headline workload (seeds 0..n_req-1) through the
-    server at once: whole-device throughput when the one-workgroup Ritz steps of
-    several solves run side by side.  Reported beside `value`, not as it."""
+def concurrent(bmg, cfg, smoother, n_req=16, slots=8, grouping=True):
+    """Independent solves of one workload (seeds 0..n_req-1) through the server
+    at once: whole-device throughput when several solves share the device, as
+    grouped solves (compatible requests waiting together run as one
+    concatenated block) or, with grouping off, side by side on their own
+    streams.  Reported beside `value`, not as it."""
     kw = dict(m=cfg["m"], nu1=cfg["nu1"], nu2=cfg["nu2"], smoother=smoother, precision="mixed")
+    if grouping:
+        os.environ.pop("BMG_NO_GROUP", None)
+    else:
+        os.environ["BMG_NO_GROUP"] = "1"  # read when the server is created
     with bmg.Server(64 << 30, max_slots=slots) as srv:
         srv.wait(srv.submit(cfg["kind"], cfg["n_refine"], cfg["k"], cfg["sigma"], cfg["tol"],
                             axes=cfg["axes"], seed=999, **kw), evecs=False)  # builds the hierarchy
@@ -391,11 +399,13 @@ def concurrent(bmg, cfg, smoother, n_req=16, slots=8):
                           axes=cfg["axes"], seed=s, **kw) for s in range(n_req)]
         res = [srv.wait(i, evecs=False) for i in ids]
         dt = time.perf_counter() - t0
+    os.environ.pop("BMG_NO_GROUP", None)
     ok = sum(r["status"] == 0 for r in res)
     return {"value": round(ok * cfg["k"] / dt, 3), "unit": "eigenpairs/s", "solves": n_req,
-            "converged": ok, "slots": slots, "seconds": round(dt, 4),
-            "note": "independent solves of the headline workload run concurrently through the "
-                    "serving API (one stream per slot); not the single-solve `value`"}
+            "converged": ok, "slots": slots, "seconds": round(dt, 4), "grouping": grouping,
+            "group_sizes": sorted((r["stats"]["group_size"] for r in res), reverse=True),
+            "note": "independent solves run concurrently through the serving API; not the "
+                    "single-solve `value`"}
 
 
 def section(bmg, name, precs, steps, warmup, smoother, with_breakdown=False):
@@ -463,6 +473,8 @@ def main():
         out["c2"] = section(bmg, "c2_sphere_ref6", precs, a.steps, 1, a.smoother)
         if a.only in ("both", "mixed") and not a.no_concurrent:
             out["c2"]["concurrent"] = concurrent(bmg, CONFIGS["c2_sphere_ref6"], a.smoother)
+            out["c2"]["concurrent_ungrouped"] = concurrent(bmg, CONFIGS["c2_sphere_ref6"], a.smoother,
+                                                           grouping=False)
     if a.serving > 0:
         out["serving"] = serving(a, bmg)
     if not a.no_cpu_baseline:

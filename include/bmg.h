@@ -252,8 +252,9 @@ typedef struct {
  *   SMOOTH_ADD      (4 + b) nnz + 2 b n m + 16 n m   (the cycle's last Jacobi
  *                   sweep on the finest level: x, f read; its result added to
  *                   the FP64 iterate U, read and written);
- *   GRAM      fused A U, M U and Z^T [A U | M U]: 4 N nz m flops (the products'
- *             20 nnz + 8 N nz bytes read);
+ *   GRAM      fused A U, M U and Z^T [A U | M U]: 2 N (2 n_c m + m (m + 1))
+ *             flops, the outputs the Ritz step needs (one triangle of each
+ *             symmetric m x m block); the products' 20 nnz + 8 N nz bytes read;
  *   UPDATE    8 N nz + 8 N m bytes, 2 N nz m flops;   RITZ  one workgroup. */
 typedef enum {
   BMG_K_EIGRES = 0, BMG_K_SPMM_AM = 1, BMG_K_SMOOTH = 2, BMG_K_RESIDUAL = 3,
@@ -504,9 +505,15 @@ typedef struct bmg_server bmg_server;
  * device.  Hierarchies are built on first use and cached per surface and
  * level; idle workspaces, then idle hierarchies (least recently used first),
  * are freed when the budget needs their memory.
- * Each request's result is bit-for-bit the result of bmg_solve with the same
- * arguments (the kernels are deterministic and requests share only read-only
- * hierarchy data).  Uses the current device; BMG_EDEVICE if there is none.
+ * Requests on the same surface and level, at the same shift, that run the
+ * enriched scheme with the same precision, smoother, nu1, nu2, omega, n_c and
+ * l_c, and wait together, run as one grouped solve (bmg_solve_group; up to 8
+ * requests and 512 block columns) in one slot.  A request that ran alone gets
+ * bit-for-bit the result of bmg_solve with the same arguments (the kernels
+ * are deterministic and requests share only read-only hierarchy data); a
+ * grouped one gets it to rounding (stats.group_size > 1).  A server created
+ * while the environment variable BMG_NO_GROUP is set groups nothing.
+ * Uses the current device; BMG_EDEVICE if there is none.
  * BMG_EINVAL if hbm_budget_bytes <= 0 or max_slots is outside [1, 64].
  * Ownership: *out belongs to the caller until bmg_server_destroy. */
 int bmg_server_create(int64_t hbm_budget_bytes, int32_t max_slots, bmg_server** out);

@@ -343,16 +343,23 @@ int64_t sym_tile_doubles(int w1, int m);
 // G = [w | u]^T [A_L u | M_L u] with the products formed in LDS (fused SpMM
 // and Gram; w1 columns of w, m of u; plan for nz = w1 + m, ny = 2 m).
 // uperm (nullable): w and u are in vertex order and storage row r reads row uperm[r];
-// ldu: row stride of u (0: m), so u may be a column slice of a wider block
+// ldu: row stride of u (0: m), so u may be a column slice of a wider block;
+// nreq > 1: that many equal-width requests side by side in u (request r's
+// columns start r m further), partials and G of request r at r part_stride
+// and r g_stride, in one launch
 int launch_gram_am(const GramPlan& p, const DevLevel& L, const double* w, int w1, const double* u,
-                   int m, double* part, double* G, hipStream_t s, const int* uperm = nullptr, int ldu = 0);
+                   int m, double* part, double* G, hipStream_t s, const int* uperm = nullptr, int ldu = 0,
+                   int nreq = 1, int64_t part_stride = 0, int64_t g_stride = 0);
 int launch_gram(const GramPlan& p, int64_t n, const double* z1, int w1, const double* z2, int w2,
                 const double* y1, int v1, const double* y2, int v2, double* part, double* G,
                 hipStream_t s);
 // U[n][m] = Z Y, Z = [z1 (w1) | z2 (w2)], Y [w1+w2][m] device; ldz2, ldu: row
 // strides of z2 and U (0: w2 and m), so both may be column slices of a wider block
+// nreq > 1: that many equal-width requests side by side (request r's columns
+// of z2 and U start r w2 and r m further, its Y at r (w1 + w2) m), one launch
 int launch_update_zy(int64_t n, const double* z1, int w1, const double* z2, int w2,
-                     const double* Y, double* U, int m, hipStream_t s, int ldz2 = 0, int ldu = 0);
+                     const double* Y, double* U, int m, hipStream_t s, int ldz2 = 0, int ldu = 0,
+                     int nreq = 1);
 
 // Coarse end of the correction cycle in one workgroup, in LDS (kernels_tail.hip).
 constexpr int kTailMaxLevels = 12;
@@ -391,6 +398,20 @@ struct RitzArgs {
   int* status;           // out: 0 ok, 1 rank loss below m, 2 Jacobi did not converge
 };
 int launch_ritz(const RitzArgs& a, hipStream_t s);
+// The Ritz steps of several requests in one launch (one workgroup each).
+constexpr int kRitzBatchMax = 16;
+struct RitzBatch {
+  int n, n_c;
+  double sigma, rtol2;
+  const double* GW;
+  int m[kRitzBatchMax];
+  const double* G[kRitzBatchMax];
+  double* Y[kRitzBatchMax];
+  double* theta[kRitzBatchMax];
+  double* scratch[kRitzBatchMax];
+  int* status[kRitzBatchMax];
+};
+int launch_ritz_batch(const RitzBatch& b, int warm, hipStream_t s);
 // Significance threshold (squared) of a rotation in the Ritz step.  An
 // off-diagonal a_pq left below 1e-11 of the diagonal scale moves a Ritz vector
 // by ~1e-11 relative and adds ~1e-11 ||C|| to its residual: far below what the

@@ -435,11 +435,9 @@ __device__ void select_nearest_zero(const double* X, int r, int mm, RitzShared& 
 // an unused nz^2 slot, Lg (packed inverse Cholesky factor, or the SVQB basis
 // T), W1 (SVQB only).  The scaled shifted matrix S (GA - sigma GM) S stays in
 // LDS (packed, in R0) until the products.
-__global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma, double rtol2, int warm,
-                                                   const double* __restrict__ G,
-                                                   const double* __restrict__ GW, double* Y,
-                                                   double* theta, double* scratch, int* status) {
-  extern __shared__ double lds[];
+__device__ __forceinline__ void ritz_body(double* lds, int n_c, int m, double sigma, double rtol2, int warm,
+                                          const double* __restrict__ G, const double* __restrict__ GW,
+                                          double* Y, double* theta, double* scratch, int* status) {
   RitzShared& sh = *reinterpret_cast<RitzShared*>(lds);
   const int nz = n_c + m;
   const int n = nz;
@@ -898,6 +896,24 @@ __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma,
   }
 }
 
+__global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma, double rtol2, int warm,
+                                                   const double* __restrict__ G,
+                                                   const double* __restrict__ GW, double* Y,
+                                                   double* theta, double* scratch, int* status) {
+  extern __shared__ double lds[];
+  ritz_body(lds, n_c, m, sigma, rtol2, warm, G, GW, Y, theta, scratch, status);
+}
+
+// The Ritz steps of a grouped solve in one launch: workgroup i runs request
+// i's step (its own Gram, Y, theta, scratch and status), each on a CU of its
+// own, so the group's steps run side by side.
+__global__ void __launch_bounds__(kThreads) k_ritz_batch(RitzBatch b, int warm) {
+  extern __shared__ double lds[];
+  const int i = blockIdx.x;
+  ritz_body(lds, b.n_c, b.m[i], b.sigma, b.rtol2, warm, b.G[i], b.GW, b.Y[i], b.theta[i], b.scratch[i],
+            b.status[i]);
+}
+
 // Symmetric eigendecomposition of one n x n matrix (n <= 96), ascending.
 __global__ void __launch_bounds__(kThreads) k_syev(int n, const double* __restrict__ A, double* w,
                                                    double* Vout, int* status) {
@@ -949,7 +965,7 @@ int set_lds_attr() {
   static std::once_flag once;
   static hipError_t err = hipSuccess;
   std::call_once(once, [] {
-    for (const void* f : {(const void*)k_ritz, (const void*)k_syev}) {
+    for (const void* f : {(const void*)k_ritz, (const void*)k_ritz_batch, (const void*)k_syev}) {
       const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -979,6 +995,18 @@ int launch_ritz(const RitzArgs& a, hipStream_t s) {
   BMG_TRY(set_lds_attr());
   BMG_LAUNCH((k_ritz), 1, kThreads, lds_bytes(a.nz), s, a.n_c, a.m, a.sigma, a.rtol2, a.warm, a.G, a.GW, a.Y,
                                               a.theta, a.scratch, a.status);
+  return check_launch();
+}
+
+int launch_ritz_batch(const RitzBatch& b, int warm, hipStream_t s) {
+  int nz = 0;
+  for (int i = 0; i < b.n; ++i) nz = std::max(nz, b.n_c + b.m[i]);
+  if (b.n < 1 || b.n > kRitzBatchMax || nz > kMaxN) {
+    set_error("ritz batch: %d requests (at most %d), nz = %d (at most %d)", b.n, kRitzBatchMax, nz, kMaxN);
+    return BMG_EINVAL;
+  }
+  BMG_TRY(set_lds_attr());
+  BMG_LAUNCH((k_ritz_batch), b.n, kThreads, lds_bytes(nz), s, b, warm);
   return check_launch();
 }
 

@@ -182,9 +182,13 @@ __global__ void __launch_bounds__(256) k_gram_sym(int64_t n, int64_t rows_per_bl
                                                   const double* __restrict__ u, int m, int ldu,
                                                   double* __restrict__ part,
                                                   const int* __restrict__ corder,
-                                                  const int* __restrict__ uperm) {
+                                                  const int* __restrict__ uperm, int64_t part_stride) {
   constexpr int CH = kGramAmChunk;
   extern __shared__ double lds[];
+  // a batch of equal-width requests: blockIdx.y picks the request, whose
+  // columns start m further along each row and whose partials follow the last
+  u += int64_t(blockIdx.y) * m;
+  part += int64_t(blockIdx.y) * part_stride;
   const int ZP = sym_zp(TW, TU), YP = sym_yp(TU);
   double* const zs0 = lds;                 // [2][CH][ZP]
   double* const ys0 = lds + 2 * CH * ZP;   // [2][CH][YP]
@@ -288,9 +292,11 @@ __global__ void __launch_bounds__(1024) k_gram_sym1(int64_t n, int64_t rows_per_
                                                    const double* __restrict__ u, int m, int ldu,
                                                    double* __restrict__ part,
                                                    const int* __restrict__ corder,
-                                                   const int* __restrict__ uperm) {
+                                                   const int* __restrict__ uperm, int64_t part_stride) {
   constexpr int CH = kGramAmChunk;
   extern __shared__ double lds[];
+  u += int64_t(blockIdx.y) * m;  // batch of equal-width requests, as in k_gram_sym
+  part += int64_t(blockIdx.y) * part_stride;
   const int ZP = sym_zp(TW, TU), YP = sym_yp(TU);
   const int CW = CH * W;
   double* const zs0 = lds;                                     // [2][CH][ZP]
@@ -444,8 +450,11 @@ __global__ void __launch_bounds__(1024) k_gram_sym1(int64_t n, int64_t rows_per_
 // is computed for a <= b only and written to (a, b) and (b, a).
 __global__ void __launch_bounds__(1024) k_gram_sym_reduce(const double* __restrict__ part, int nblk,
                                                           SymTiles tl, int TW, int TU, int w1, int m,
-                                                          double* __restrict__ G) {
+                                                          double* __restrict__ G, int64_t part_stride,
+                                                          int64_t g_stride) {
   constexpr int kOut = 16, kSeg = 64;
+  part += int64_t(blockIdx.y) * part_stride;  // request blockIdx.y of a batch
+  G += int64_t(blockIdx.y) * g_stride;
   __shared__ double red[kSeg][kOut];
   const int el = threadIdx.x & (kOut - 1), seg = threadIdx.x / kOut;
   const int e = blockIdx.x * kOut + el;
@@ -565,7 +574,12 @@ template <int TJ, int KM>
 __global__ void __launch_bounds__(256) k_update_zy(int64_t n, const double* z1, int w1,
                                                    const double* z2, int w2, int ldz2,
                                                    const double* __restrict__ Y, int m, int ks,
-                                                   double* U, int ldu) {
+                                                   double* U, int ldu, int64_t y_stride) {
+  // a batch of equal-width requests: blockIdx.y picks the request (its
+  // columns m further along each row, its Y after the previous one's)
+  z2 += int64_t(blockIdx.y) * w2;
+  U += int64_t(blockIdx.y) * m;
+  Y += int64_t(blockIdx.y) * y_stride;
   extern __shared__ double ys[];  // [ks * 4][TJ * 16]
   constexpr int MP = TJ * 16;
   const int nz = w1 + w2;
@@ -760,13 +774,13 @@ void sym_attr_all() {
 template <int TPW>
 void sym_launch(const GramPlan& p, const DevLevel& L, const SymTiles& tl, int TW, int TU, const double* w,
                 int w1, const double* u, int m, int ldu, int64_t rpb, size_t shm, double* part, hipStream_t s,
-                const int* uperm) {
+                const int* uperm, int nreq, int64_t part_stride) {
   const int64_t n = L.n;
   static const int nbenv = std::getenv("BMG_GRAM_NB") ? std::atoi(std::getenv("BMG_GRAM_NB")) : 0;
   const int nb = nbenv ? nbenv : (kGramAmChunk * (m / 2) > 256 ? 2 : 1);
-#define GS(nb_, wt_)                                                                              \
-  BMG_LAUNCH((k_gram_sym<TPW, nb_, wt_>), p.nblk, 256, shm, s, n, rpb, tl, TW, TU, L.cols, L.a64, \
-             L.m64, L.W, w, w1, u, m, ldu, part, L.chunk_order, uperm)
+#define GS(nb_, wt_)                                                                                   \
+  BMG_LAUNCH((k_gram_sym<TPW, nb_, wt_>), dim3(p.nblk, nreq), 256, shm, s, n, rpb, tl, TW, TU, L.cols,  \
+             L.a64, L.m64, L.W, w, w1, u, m, ldu, part, L.chunk_order, uperm, part_stride)
   if (L.W == 7) {
     if (nb == 3) GS(3, 7);
     else if (nb == 2) GS(2, 7);
@@ -790,13 +804,13 @@ void sym1_attr() {
 template <int TPW>
 void sym1_launch(const GramPlan& p, const DevLevel& L, const SymTiles& tl, int TW, int TU, const double* w,
                  int w1, const double* u, int m, int ldu, int64_t rpb, int nthr, size_t shm, double* part,
-                 hipStream_t s, const int* uperm) {
+                 hipStream_t s, const int* uperm, int nreq, int64_t part_stride) {
   if (L.W == 7)
-    BMG_LAUNCH((k_gram_sym1<TPW, 7>), p.nblk, nthr, shm, s, L.n, rpb, tl, TW, TU, L.cols, L.a64, L.m64, L.W, w,
-               w1, u, m, ldu, part, L.chunk_order, uperm);
+    BMG_LAUNCH((k_gram_sym1<TPW, 7>), dim3(p.nblk, nreq), nthr, shm, s, L.n, rpb, tl, TW, TU, L.cols, L.a64,
+               L.m64, L.W, w, w1, u, m, ldu, part, L.chunk_order, uperm, part_stride);
   else
-    BMG_LAUNCH((k_gram_sym1<TPW, 0>), p.nblk, nthr, shm, s, L.n, rpb, tl, TW, TU, L.cols, L.a64, L.m64, L.W, w,
-               w1, u, m, ldu, part, L.chunk_order, uperm);
+    BMG_LAUNCH((k_gram_sym1<TPW, 0>), dim3(p.nblk, nreq), nthr, shm, s, L.n, rpb, tl, TW, TU, L.cols, L.a64,
+               L.m64, L.W, w, w1, u, m, ldu, part, L.chunk_order, uperm, part_stride);
 }
 
 }  // namespace
@@ -804,8 +818,13 @@ void sym1_launch(const GramPlan& p, const DevLevel& L, const SymTiles& tl, int T
 int64_t sym_tile_doubles(int w1, int m) { return int64_t(sym_tiles(w1, m).T) * 256; }
 
 int launch_gram_am(const GramPlan& p, const DevLevel& L, const double* w, int w1, const double* u,
-                   int m, double* part, double* G, hipStream_t s, const int* uperm, int ldu) {
+                   int m, double* part, double* G, hipStream_t s, const int* uperm, int ldu, int nreq,
+                   int64_t part_stride, int64_t g_stride) {
   if (ldu <= 0) ldu = m;
+  if (nreq < 1 || nreq > 65535 || (nreq > 1 && (uperm != nullptr || int64_t(nreq) * m > ldu))) {
+    set_error("gram_am: batch of %d requests of width %d in rows of %d", nreq, m, ldu);
+    return BMG_EINVAL;
+  }
   if (ldu < m || (ldu & 1) != 0) {
     set_error("gram_am: row stride %d of u must be even and at least m = %d", ldu, m);
     return BMG_EINVAL;
@@ -860,7 +879,7 @@ int launch_gram_am(const GramPlan& p, const DevLevel& L, const double* w, int w1
       const size_t shm1 = shm + size_t(2) * kGramAmChunk * L.W * (2 * sizeof(double) + sizeof(int));
       const LaunchEvents ev = g_launch_events;
       g_launch_events = LaunchEvents{ev.start, nullptr};
-#define G1(t_) sym1_launch<t_>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, nthr, shm1, part, s, uperm)
+#define G1(t_) sym1_launch<t_>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, nthr, shm1, part, s, uperm, nreq, part_stride)
       if (tpw1 <= 1) G1(1);
       else if (tpw1 <= 2) G1(2);
       else if (tpw1 <= 3) G1(3);
@@ -872,27 +891,29 @@ int launch_gram_am(const GramPlan& p, const DevLevel& L, const double* w, int w1
       g_launch_events = LaunchEvents{nullptr, ev.stop};
       int st = check_launch();
       if (st != BMG_OK) return st;
-      BMG_LAUNCH((k_gram_sym_reduce), (tl.T * 256 + 15) / 16, 1024, 0, s, part, q.nblk, tl, TW, TU, w1, m, G);
+      BMG_LAUNCH((k_gram_sym_reduce), dim3((tl.T * 256 + 15) / 16, nreq), 1024, 0, s, part, q.nblk, tl, TW,
+               TU, w1, m, G, part_stride, g_stride);
       return check_launch();
     }
     const int tpw = (tl.T + 3) / 4;
     {
       const LaunchEvents ev = g_launch_events;
       g_launch_events = LaunchEvents{ev.start, nullptr};
-      if (tpw <= 1) sym_launch<1>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm);
-      else if (tpw <= 2) sym_launch<2>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm);
-      else if (tpw <= 3) sym_launch<3>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm);
-      else if (tpw <= 4) sym_launch<4>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm);
-      else if (tpw <= 6) sym_launch<6>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm);
-      else if (tpw <= 8) sym_launch<8>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm);
-      else if (tpw <= 10) sym_launch<10>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm);
-      else if (tpw <= 12) sym_launch<12>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm);
-      else sym_launch<17>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm);
+      if (tpw <= 1) sym_launch<1>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm, nreq, part_stride);
+      else if (tpw <= 2) sym_launch<2>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm, nreq, part_stride);
+      else if (tpw <= 3) sym_launch<3>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm, nreq, part_stride);
+      else if (tpw <= 4) sym_launch<4>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm, nreq, part_stride);
+      else if (tpw <= 6) sym_launch<6>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm, nreq, part_stride);
+      else if (tpw <= 8) sym_launch<8>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm, nreq, part_stride);
+      else if (tpw <= 10) sym_launch<10>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm, nreq, part_stride);
+      else if (tpw <= 12) sym_launch<12>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm, nreq, part_stride);
+      else sym_launch<17>(q, L, tl, TW, TU, w, w1, u, m, ldu, rpb, shm, part, s, uperm, nreq, part_stride);
       g_launch_events = LaunchEvents{nullptr, ev.stop};
     }
     int st = check_launch();
     if (st != BMG_OK) return st;
-    BMG_LAUNCH((k_gram_sym_reduce), (tl.T * 256 + 15) / 16, 1024, 0, s, part, q.nblk, tl, TW, TU, w1, m, G);
+    BMG_LAUNCH((k_gram_sym_reduce), dim3((tl.T * 256 + 15) / 16, nreq), 1024, 0, s, part, q.nblk, tl, TW,
+               TU, w1, m, G, part_stride, g_stride);
     return check_launch();
   }
 }
@@ -932,10 +953,15 @@ int noalloc_scratch(int dev, double** out) {
 }  // namespace
 
 int launch_update_zy(int64_t n, const double* z1, int w1, const double* z2, int w2,
-                     const double* Y, double* U, int m, hipStream_t s, int ldz2, int ldu) {
+                     const double* Y, double* U, int m, hipStream_t s, int ldz2, int ldu, int nreq) {
   const int nz = w1 + w2;
   if (ldz2 <= 0) ldz2 = w2;
   if (ldu <= 0) ldu = m;
+  if (nreq < 1 || nreq > 65535 || (nreq > 1 && (int64_t(nreq) * w2 > ldz2 || int64_t(nreq) * m > ldu))) {
+    set_error("update: batch of %d requests too wide for rows of %d / %d", nreq, ldz2, ldu);
+    return BMG_EINVAL;
+  }
+  const int64_t y_stride = int64_t(nz) * m;
   if (ldz2 < w2 || ldu < m || (ldz2 & 1) != 0) {
     set_error("update: row strides %d, %d too small for w2 = %d, m = %d (or odd)", ldz2, ldu, w2, m);
     return BMG_EINVAL;
@@ -961,9 +987,11 @@ int launch_update_zy(int64_t n, const double* z1, int w1, const double* z2, int 
 #define UL(tj)                                                                                    \
   do {                                                                                            \
     if (ks <= 12)                                                                                 \
-      BMG_LAUNCH((k_update_zy<tj, 12>), grid, 256, shm, s, n, z1, w1, z2, w2, ldz2, Y, m, ks, U, ldu); \
-    else                                                                                              \
-      BMG_LAUNCH((k_update_zy<tj, 24>), grid, 256, shm, s, n, z1, w1, z2, w2, ldz2, Y, m, ks, U, ldu); \
+      BMG_LAUNCH((k_update_zy<tj, 12>), dim3(grid, nreq), 256, shm, s, n, z1, w1, z2, w2, ldz2, Y, m, ks, U, \
+                 ldu, y_stride);                                                                         \
+    else                                                                                                 \
+      BMG_LAUNCH((k_update_zy<tj, 24>), dim3(grid, nreq), 256, shm, s, n, z1, w1, z2, w2, ldz2, Y, m, ks, U, \
+                 ldu, y_stride);                                                                         \
   } while (0)
   switch (TJ) {
     case 1: UL(1); break;

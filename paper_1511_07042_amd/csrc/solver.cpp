@@ -1266,6 +1266,8 @@ struct GroupItem {
   int m = 0, off = 0;
   double* rscratch = nullptr;  // [ritz_scratch_doubles(n_c + m)], persists between Ritz steps
   int* status = nullptr;       // [16] Ritz status words
+  double *gpart = nullptr, *G = nullptr, *Y = nullptr;  // this request's Gram partials, Gram, Ritz Y
+  GramPlan gp{};
   const std::atomic<int>* cancel = nullptr;
   bool done = false;
   int cycles = 0;
@@ -1311,28 +1313,47 @@ int run_group(bmg_hierarchy* h, bmg_workspace* w, double sigma, std::vector<Grou
     BMG_HIP(hipMemcpy2DAsync(w->U + it.off, sizeof(double) * M, w->AU, sizeof(double) * it.m,
                              sizeof(double) * it.m, size_t(N), hipMemcpyDeviceToDevice, s));
   }
-  // H4-H6 per request on its slice: fused Gram, Ritz, update in place
+  // H4-H6 per request on its slice: the fused Gram and the update per
+  // request (own Gram, Y and partial buffers), the Ritz steps of all requests
+  // in one launch (one workgroup each, side by side on different CUs)
+  // equal widths: one Gram launch and one update launch for the whole group
+  // (their buffers are contiguous, see solve_group)
+  bool equal = items.size() > 1;
+  for (const GroupItem& it : items) equal = equal && it.m == items[0].m;
   auto ritz_steps = [&](int warm) -> int {
-    for (GroupItem& it : items) {
-      const int nz = n_c + it.m;
-      const GramPlan gp = gram_plan(N, nz, 2 * it.m);
-      double* u = w->U + it.off;
-      BMG_TRY(launch_gram_am(gp, DL, w->W, n_c, u, it.m, w->gpart, w->G, s, nullptr, M));
-      RitzArgs ra;
-      ra.n_c = n_c;
-      ra.m = it.m;
-      ra.nz = nz;
-      ra.sigma = sigma;
-      ra.rtol2 = kRitzRtol2;
-      ra.warm = warm;
-      ra.G = w->G;
-      ra.GW = w->GW;
-      ra.Y = w->Y;
-      ra.theta = w->theta + it.off;
-      ra.scratch = it.rscratch;
-      ra.status = it.status;
-      BMG_TRY(launch_ritz(ra, s));
-      BMG_TRY(launch_update_zy(N, w->W, n_c, u, it.m, w->Y, u, it.m, s, M, M));
+    const int nq = int(items.size());
+    const int m0 = items[0].m, nz0 = n_c + m0;
+    if (equal)
+      BMG_TRY(launch_gram_am(items[0].gp, DL, w->W, n_c, w->U, m0, items[0].gpart, items[0].G, s, nullptr, M, nq,
+                             int64_t(items[0].gp.nblk) * items[0].gp.per_block, int64_t(nz0) * 2 * m0));
+    else
+      for (GroupItem& it : items)
+        BMG_TRY(launch_gram_am(it.gp, DL, w->W, n_c, w->U + it.off, it.m, it.gpart, it.G, s, nullptr, M));
+    for (size_t b0 = 0; b0 < items.size(); b0 += kRitzBatchMax) {
+      RitzBatch rb{};
+      rb.n = int(std::min<size_t>(kRitzBatchMax, items.size() - b0));
+      rb.n_c = n_c;
+      rb.sigma = sigma;
+      rb.rtol2 = kRitzRtol2;
+      rb.GW = w->GW;
+      for (int q = 0; q < rb.n; ++q) {
+        GroupItem& it = items[b0 + q];
+        rb.m[q] = it.m;
+        rb.G[q] = it.G;
+        rb.Y[q] = it.Y;
+        rb.theta[q] = w->theta + it.off;
+        rb.scratch[q] = it.rscratch;
+        rb.status[q] = it.status;
+      }
+      BMG_TRY(launch_ritz_batch(rb, warm, s));
+    }
+    if (equal) {
+      BMG_TRY(launch_update_zy(N, w->W, n_c, w->U, m0, items[0].Y, w->U, m0, s, M, M, nq));
+    } else {
+      for (GroupItem& it : items) {
+        double* u = w->U + it.off;
+        BMG_TRY(launch_update_zy(N, w->W, n_c, u, it.m, it.Y, u, it.m, s, M, M));
+      }
     }
     return BMG_OK;
   };
@@ -1400,21 +1421,30 @@ int run_group(bmg_hierarchy* h, bmg_workspace* w, double sigma, std::vector<Grou
   BMG_TRY(residual_step());
   const int n = int(items.size());
   int left = n, cycles = 0;
-  std::vector<double> hb(2 * size_t(M));
-  std::vector<int> hs(16 * size_t(n));
-  // the requests' status words are contiguous (see solve_group)
+  // per-cycle readback into pinned memory (a copy to pageable memory can wait
+  // for other streams' work): theta and rho2 of every column, then every
+  // request's status words (contiguous, see solve_group)
+  double* pin = nullptr;
+  const size_t pin_bytes = sizeof(double) * 2 * M + sizeof(int) * 16 * size_t(n);
+  BMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&pin), pin_bytes));
+  struct PinGuard {
+    double* p;
+    ~PinGuard() { (void)hipHostFree(p); }
+  } pin_guard{pin};
+  const double* hb = pin;
+  const int* hs = reinterpret_cast<const int*>(pin + 2 * M);
   const int* status_base = items[0].status;
   for (;;) {
-    BMG_HIP(hipMemcpyAsync(hb.data(), w->theta, sizeof(double) * 2 * M, hipMemcpyDeviceToHost, s));
-    BMG_HIP(hipMemcpyAsync(hs.data(), status_base, sizeof(int) * hs.size(), hipMemcpyDeviceToHost, s));
+    BMG_HIP(hipMemcpyAsync(pin, w->theta, sizeof(double) * 2 * M, hipMemcpyDeviceToHost, s));
+    BMG_HIP(hipMemcpyAsync(pin + 2 * M, status_base, sizeof(int) * 16 * n, hipMemcpyDeviceToHost, s));
     BMG_HIP(hipStreamSynchronize(s));
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     for (int q = 0; q < n; ++q) {
       GroupItem& it = items[q];
       if (it.done) continue;
       bmg_group_request& r = *it.r;
-      std::vector<double> theta(hb.begin() + it.off, hb.begin() + it.off + it.m);
-      std::vector<double> rho2(hb.begin() + M + it.off, hb.begin() + M + it.off + it.m);
+      std::vector<double> theta(hb + it.off, hb + it.off + it.m);
+      std::vector<double> rho2(hb + M + it.off, hb + M + it.off + it.m);
       const int rstat = hs[16 * q];
       int st = BMG_OK;
       Cert cert;
@@ -1637,10 +1667,10 @@ int solve_group(bmg_hierarchy* h, double sigma, int n, bmg_group_request* reqs, 
   BMG_CHECK(o.omega > 0 && o.omega < 2, "omega must be in (0, 2)");
   BMG_CHECK(o.l_c >= 0 && o.l_c < nl, "l_c out of range");
   BMG_HIP(hipSetDevice(h->device));
-  int max_m = 0;
-  for (const GroupItem& it : items) max_m = std::max(max_m, it.m);
+  // the requests' Gram and Ritz buffers are their own (below): the
+  // workspace's serve only the shared W_c block
   bmg_workspace* w = nullptr;
-  BMG_TRY(acquire_workspace(h, M, o.n_c, o.precision, &w, max_m));
+  BMG_TRY(acquire_workspace(h, M, o.n_c, o.precision, &w, 2));
   hipStream_t cs = static_cast<hipStream_t>(stream);
   hipStream_t s = w->stream;
   // per-request Ritz scratch and status words (contiguous: one readback)
@@ -1657,10 +1687,31 @@ int solve_group(bmg_hierarchy* h, double sigma, int n, bmg_group_request* reqs, 
   };
   int* status_all = nullptr;
   st = dalloc_local(reinterpret_cast<void**>(&status_all), sizeof(int) * 16 * n);
+  // per-request Gram partials, Gram and Y, one contiguous array each (the
+  // layout the equal-width batched launches need)
+  size_t n_part = 0, n_g = 0, n_y = 0;
+  for (GroupItem& it : items) {
+    const int nz = o.n_c + it.m;
+    it.gp = gram_plan(N, nz, 2 * it.m);
+    n_part += size_t(it.gp.nblk) * it.gp.per_block;
+    n_g += size_t(nz) * 2 * it.m;
+    n_y += size_t(nz) * it.m;
+  }
+  double *part_all = nullptr, *g_all = nullptr, *y_all = nullptr;
+  if (st == BMG_OK) st = dalloc_local(reinterpret_cast<void**>(&part_all), sizeof(double) * n_part);
+  if (st == BMG_OK) st = dalloc_local(reinterpret_cast<void**>(&g_all), sizeof(double) * n_g);
+  if (st == BMG_OK) st = dalloc_local(reinterpret_cast<void**>(&y_all), sizeof(double) * n_y);
   for (int i = 0; i < n && st == BMG_OK; ++i) {
-    items[i].status = status_all + 16 * i;
-    st = dalloc_local(reinterpret_cast<void**>(&items[i].rscratch),
-                      sizeof(double) * ritz_scratch_doubles(o.n_c + items[i].m));
+    GroupItem& it = items[i];
+    const int nz = o.n_c + it.m;
+    it.status = status_all + 16 * i;
+    it.gpart = part_all;
+    it.G = g_all;
+    it.Y = y_all;
+    part_all += size_t(it.gp.nblk) * it.gp.per_block;
+    g_all += size_t(nz) * 2 * it.m;
+    y_all += size_t(nz) * it.m;
+    st = dalloc_local(reinterpret_cast<void**>(&it.rscratch), sizeof(double) * ritz_scratch_doubles(nz));
   }
   if (st == BMG_OK && hipMemsetAsync(status_all, 0, sizeof(int) * 16 * n, s) != hipSuccess) {
     set_error("status clear failed");
