@@ -62,7 +62,9 @@ KSYMBOL = {"smooth": "k_rowop<{T}, 2, 7>", "residual": "k_rowop<{T}, 1, 7>",
 TRAFFIC_FILES = {
     ("restrict_res", "c2_sphere_ref6", "mixed"): "profiles/resrestrict_c2_sphere_ref6_traffic.txt",
     ("smooth", "c4_sphere_ref8", "mixed"): "profiles/jacobi_sweep_c4_sphere_ref8_traffic.txt",
+    ("gram", "c4_sphere_ref8", "mixed"): "profiles/gram_c4_sphere_ref8_traffic.txt",
 }
+ROW_KERNELS = "paper_1511_07042_amd/csrc/kernels_sparse.hip"
 
 # Stored eigenvalues of each workload's pencil (written from the oracle by
 # tests/golden/make_reference_eigs.py): the per-pair error of the timed solves.
@@ -114,10 +116,10 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4, "launches": 5}))
 
 
-def kernel_source_hash():
-    """sha256 of the row-kernel source file: traffic summaries taken with other
+def kernel_source_hash(rel=ROW_KERNELS):
+    """sha256 of a kernel source file: traffic summaries taken with other
     kernel code are not reported."""
-    src = open(os.path.join(ROOT, "paper_1511_07042_amd", "csrc", "kernels_sparse.hip"), "rb").read()
+    src = open(os.path.join(ROOT, rel), "rb").read()
     return hashlib.sha256(src).hexdigest()
 
 
@@ -134,9 +136,10 @@ def measured_traffic(kclass, workload, prec, per_unit):
         if "=" in line and not line.startswith("#"):
             key, val = line.split("=", 1)
             kv[key.strip()] = val.strip()
-    if kv.get("kernel_source_sha256") != kernel_source_hash():
+    if kv.get("kernel_source_sha256") != kernel_source_hash(kv.get("kernel_source", ROW_KERNELS)):
         return None
-    algo = float(kv.get("algorithmic_bytes_per_launch", "nan"))
+    # the amount the roofline counts per launch (bytes, or flops for a matrix-core class)
+    algo = float(kv.get("algorithmic_per_launch", kv.get("algorithmic_bytes_per_launch", "nan")))
     if not abs(algo - per_unit) <= 0.5:
         return None
     return float(kv["traffic_bytes_per_launch"])

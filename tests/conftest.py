@@ -14,6 +14,13 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
+    # Oracle solves marked slow (minutes each on the CPU) run only with
+    # BMG_SLOW_TESTS=1, so that the default CPU suite takes a few minutes.
+    if not os.environ.get("BMG_SLOW_TESTS"):
+        skip_slow = pytest.mark.skip(reason="slow oracle solve; set BMG_SLOW_TESTS=1 to run")
+        for it in items:
+            if "slow" in it.keywords:
+                it.add_marker(skip_slow)
     # GPU tests are skipped (not failed) when no GPU is visible, so that the
     # CPU suite stays green; on a machine with a GPU they run and must pass.
     try:

@@ -47,6 +47,7 @@ def test_committed_traffic_records_are_well_formed():
                 k, v = line.split("=", 1)
                 kv[k.strip()] = v.strip()
         assert kclass in b.KCLASS and len(kv["kernel_source_sha256"]) == 64
+        assert os.path.exists(os.path.join(ROOT, kv.get("kernel_source", b.ROW_KERNELS)))
         algo, traffic = float(kv["algorithmic_bytes_per_launch"]), float(kv["traffic_bytes_per_launch"])
         # HBM traffic is at least the algorithmic bytes, and the two counter
         # passes were scaled by a copy calibration

@@ -75,6 +75,7 @@ def test_exact_coarse_level_is_the_fine_eigensolve():
     assert np.max(np.abs(ev - ref_ev) / ref_ev) < 1e-12
 
 
+@pytest.mark.slow
 def test_torus_interior_shift():
     levels = bmg.build_levels("torus", 1)
     lv = levels[-1]
