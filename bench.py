@@ -60,7 +60,6 @@ KSYMBOL = {"smooth": "k_rowop<{T}, 2, 7>", "residual": "k_rowop<{T}, 1, 7>",
 
 # Committed HBM-traffic summaries (two rocprofv3 --pmc passes each).
 TRAFFIC_FILES = {
-    ("restrict_res", "c2_sphere_ref6", "mixed"): "profiles/resrestrict_c2_sphere_ref6_traffic.txt",
     ("smooth", "c4_sphere_ref8", "mixed"): "profiles/jacobi_sweep_c4_sphere_ref8_traffic.txt",
     ("gram", "c4_sphere_ref8", "mixed"): "profiles/gram_c4_sphere_ref8_traffic.txt",
 }
