@@ -396,6 +396,8 @@ struct RitzArgs {
   double* theta;         // out [m] ascending
   double* scratch;       // [ritz_scratch_doubles(nz)]; its tail persists between calls
   int* status;           // out: 0 ok, 1 rank loss below m, 2 Jacobi did not converge
+  const double* rho2 = nullptr;  // [m] residual norms of the previous block (with theta on
+                                 // entry): the Jacobi threshold follows them; null: rtol2
 };
 int launch_ritz(const RitzArgs& a, hipStream_t s);
 // The Ritz steps of several requests in one launch (one workgroup each).
@@ -410,6 +412,7 @@ struct RitzBatch {
   double* theta[kRitzBatchMax];
   double* scratch[kRitzBatchMax];
   int* status[kRitzBatchMax];
+  const double* rho2[kRitzBatchMax];  // as RitzArgs::rho2
 };
 int launch_ritz_batch(const RitzBatch& b, int warm, hipStream_t s);
 // Significance threshold (squared) of a rotation in the Ritz step.  An

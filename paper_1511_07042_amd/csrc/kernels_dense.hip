@@ -437,8 +437,32 @@ __device__ void select_nearest_zero(const double* X, int r, int mm, RitzShared& 
 // LDS (packed, in R0) until the products.
 __device__ __forceinline__ void ritz_body(double* lds, int n_c, int m, double sigma, double rtol2, int warm,
                                           const double* __restrict__ G, const double* __restrict__ GW,
-                                          double* Y, double* theta, double* scratch, int* status) {
+                                          double* Y, double* theta, double* scratch, int* status,
+                                          const double* __restrict__ rho2) {
   RitzShared& sh = *reinterpret_cast<RitzShared*>(lds);
+  // Jacobi's significance threshold follows the block's accuracy: with the
+  // previous Ritz values theta and residual norms rho2 (both [m], read before
+  // theta is overwritten), eps = the geometric mean over the columns of
+  // sqrt(rho2_j) / max(|theta_j|, 1) (a column already exact, such as the
+  // constant mode inside the coarse space, does not pin it at rounding), and
+  // rotations below tau = 1e-3 eps (at most 1e-4, at least sqrt(rtol2)) are
+  // skipped.  A skipped rotation moves a Ritz vector by about tau times
+  // ||C|| over the gap to the other values, three orders below the block's
+  // typical error, so it does not slow the iteration; the certificate is
+  // computed from true residuals either way.  rho2 null: rtol2 as given.
+  if (rho2 != nullptr) {
+    if (threadIdx.x < 64) {
+      double e = 0.0;
+      for (int j = threadIdx.x; j < m; j += 64)
+        e += log(fmax(sqrt(fmax(rho2[j], 0.0)) / fmax(fabs(theta[j]), 1.0), 1e-30));
+      for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+      if (threadIdx.x == 0) sh.j.bcast[0] = exp(e / m);
+    }
+    __syncthreads();
+    const double tau = fmin(1e-4, 1e-3 * sh.j.bcast[0]);
+    rtol2 = fmax(rtol2, tau * tau);
+    __syncthreads();  // bcast is reused below
+  }
   const int nz = n_c + m;
   const int n = nz;
   double* R0 = lds + shared_doubles();  // [nz][nz] (eigenvectors: rows of even length)
@@ -899,9 +923,10 @@ __device__ __forceinline__ void ritz_body(double* lds, int n_c, int m, double si
 __global__ void __launch_bounds__(kThreads) k_ritz(int n_c, int m, double sigma, double rtol2, int warm,
                                                    const double* __restrict__ G,
                                                    const double* __restrict__ GW, double* Y,
-                                                   double* theta, double* scratch, int* status) {
+                                                   double* theta, double* scratch, int* status,
+                                                   const double* __restrict__ rho2) {
   extern __shared__ double lds[];
-  ritz_body(lds, n_c, m, sigma, rtol2, warm, G, GW, Y, theta, scratch, status);
+  ritz_body(lds, n_c, m, sigma, rtol2, warm, G, GW, Y, theta, scratch, status, rho2);
 }
 
 // The Ritz steps of a grouped solve in one launch: workgroup i runs request
@@ -911,7 +936,7 @@ __global__ void __launch_bounds__(kThreads) k_ritz_batch(RitzBatch b, int warm) 
   extern __shared__ double lds[];
   const int i = blockIdx.x;
   ritz_body(lds, b.n_c, b.m[i], b.sigma, b.rtol2, warm, b.G[i], b.GW, b.Y[i], b.theta[i], b.scratch[i],
-            b.status[i]);
+            b.status[i], b.rho2[i]);
 }
 
 // Symmetric eigendecomposition of one n x n matrix (n <= 96), ascending.
@@ -994,7 +1019,7 @@ int launch_ritz(const RitzArgs& a, hipStream_t s) {
   }
   BMG_TRY(set_lds_attr());
   BMG_LAUNCH((k_ritz), 1, kThreads, lds_bytes(a.nz), s, a.n_c, a.m, a.sigma, a.rtol2, a.warm, a.G, a.GW, a.Y,
-                                              a.theta, a.scratch, a.status);
+             a.theta, a.scratch, a.status, a.rho2);
   return check_launch();
 }
 

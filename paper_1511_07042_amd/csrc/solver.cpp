@@ -1142,6 +1142,11 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
   };
   TraceRange trace_cycles("bmg_solve: cycles");
   BMG_TRY(residual_step());
+  // from here on every Ritz step finds the previous block's residual norms
+  // in w->rho2 and its Jacobi threshold follows them; a level ramp (the
+  // paper's fixed-cycle runs, whose values are compared level by level) keeps
+  // the exact threshold
+  ra.rho2 = ramp ? nullptr : w->rho2;
   for (;;) {
     // theta, rho2 and the Ritz status words: written to the pinned host buffer
     // by the cycle's last kernel (k_colsum), else copied back here
@@ -1344,6 +1349,7 @@ int run_group(bmg_hierarchy* h, bmg_workspace* w, double sigma, std::vector<Grou
         rb.theta[q] = w->theta + it.off;
         rb.scratch[q] = it.rscratch;
         rb.status[q] = it.status;
+        rb.rho2[q] = warm ? w->rho2 + it.off : nullptr;  // the residuals exist from the first cycle on
       }
       BMG_TRY(launch_ritz_batch(rb, warm, s));
     }
