@@ -578,27 +578,41 @@ __device__ __forceinline__ void ritz_body(double* lds, int n_c, int m, double si
       for (int t = 0; t < kB; ++t)
         if (kept[t]) sh.kk[sh.r++] = j + t;
     }
-    // trailing rows i > j + 3
+    // trailing rows i > j + 3, on the matrix cores: every entry (i, c), c <= i,
+    // subtracts sum_t f_t(i) y_t(c), a rank-4 product, one
+    // v_mfma_f64_16x16x4f64 per 16 x 16 tile.  A lane of the A fragment holds
+    // -f_k(i) of row i (k = lane / 16), a lane of the B fragment y_k(c) of
+    // column c; the result lane holds column c of four rows.  A tile reads and
+    // writes only its own entries, and the pivot rows (read by every tile) and
+    // the rows' block columns of X (the f sources; those entries of Z are
+    // written instead) are not written in this step.
     const int jl = j + kB - 1;
     const int w = n - 1 - jl;
-    for (int idx = tid; idx < w * kCW; idx += nt) {
-      const int i = jl + 1 + idx / kCW, cl = idx % kCW;
-      double f[kB];
+    {
+      const int lane = tid & 63, wv = tid >> 6, nwv = nt >> 6;
+      const int li = lane & 15, lk = lane >> 4;
+      const int tm = (w + 15) / 16, tn = (n + 15) / 16;
+      for (int id = wv; id < tm * tn; id += nwv) {
+        const int ti = id / tn, tj = id - (id / tn) * tn;
+        const int i0 = jl + 1 + 16 * ti, c0 = 16 * tj;
+        if (c0 > i0 + 15) continue;  // above the diagonal
+        double fa = 0.0, fb = 0.0;
+        const int i = i0 + li;
+        if (i < n) {
+          double f[kB];
 #pragma unroll
-      for (int t = 0; t < kB; ++t) {
-        double x = Ra[tri(i, j + t)];
+          for (int t = 0; t < kB; ++t) {
+            double x = Ra[tri(i, j + t)];
 #pragma unroll
-        for (int r = 0; r < t; ++r) x -= f[r] * a[t][r];  // a[t][r]: pivot row r at column t, step r
-        f[t] = x * ip[t];
-      }
-      double out[kCE];
-#pragma unroll
-      for (int u = 0; u < kCE; ++u) {
-        const int c = cl + kCW * u;
-        out[u] = 0.0;
-        if (c <= i) {
+            for (int r = 0; r < t; ++r) x -= f[r] * a[t][r];  // a[t][r]: pivot row r at column t, step r
+            f[t] = x * ip[t];
+          }
+          fa = -(lk == 0 ? f[0] : lk == 1 ? f[1] : lk == 2 ? f[2] : f[3]);
+        }
+        const int c = c0 + li;
+        const bool zpart = c <= jl;
+        if (c < n) {
           double y[kB];
-          const bool zpart = c <= jl;
 #pragma unroll
           for (int t = 0; t < kB; ++t) {
             double v = zpart ? (c <= j + t ? Rb[tri(j + t, c)] : 0.0) : Ra[tri(c, j + t)];
@@ -606,20 +620,19 @@ __device__ __forceinline__ void ritz_body(double* lds, int n_c, int m, double si
             for (int r = 0; r < t; ++r) v -= l[t][r] * y[r];
             y[t] = v;
           }
-          double acc = zpart ? (c < j ? Rb[tri(i, c)] : 0.0) : Ra[tri(i, c)];
-#pragma unroll
-          for (int t = 0; t < kB; ++t) acc -= f[t] * y[t];
-          out[u] = acc;
+          fb = lk == 0 ? y[0] : lk == 1 ? y[1] : lk == 2 ? y[2] : y[3];
         }
-      }
+        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, fb, acc, 0, 0, 0);
 #pragma unroll
-      for (int u = 0; u < kCE; ++u) {
-        const int c = cl + kCW * u;
-        if (c <= i) {
-          if (c <= jl)
-            Rb[tri(i, c)] = out[u];
-          else
-            Ra[tri(i, c)] = out[u];
+        for (int v = 0; v < 4; ++v) {
+          const int row = i0 + lk + 4 * v;
+          if (row < n && c <= row) {
+            if (zpart)
+              Rb[tri(row, c)] = (c < j ? Rb[tri(row, c)] : 0.0) + acc[v];
+            else
+              Ra[tri(row, c)] += acc[v];
+          }
         }
       }
     }
