@@ -89,7 +89,7 @@ def parse():
     ap.add_argument("--no-concurrent", action="store_true",
                     help="skip the 16 concurrent C2 solves through the serving API")
     ap.add_argument("--no-breakdown", action="store_true", help="skip the per-class breakdown")
-    ap.add_argument("--serving", type=int, default=32, metavar="N",
+    ap.add_argument("--serving", type=int, default=256, metavar="N",
                     help="requests in the serving section (0: skip it)")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the serving stream and print its JSON line")
@@ -328,6 +328,10 @@ def _serve(bmg, reqs, slots, budget, timed, smoother):
                 res = srv.poll(rid, evecs=False)
                 if res is not None:
                     out[ids.pop(rid)] = res
+                    done = sum(o is not None for o in out)
+                    if done % 32 == 0 or done == len(reqs):
+                        print(f"# serving ({'timed' if timed else 'capacity'}): {done}/{len(reqs)} requests "
+                              f"done at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
             time.sleep(0.0005)
         makespan = time.perf_counter() - t0
     return out, makespan

@@ -180,7 +180,12 @@ typedef enum { BMG_SCHEME_AUTO = 0, BMG_SCHEME_ENRICHED = 1, BMG_SCHEME_SHIFTED 
 typedef struct {
   int32_t m;          /* test vectors; 0 -> 4 ceil(1.25 k / 4) (sigma = 0) or
                          4 ceil(1.5 k / 4) (sigma != 0), raised by the
-                         shifted scheme's coarse-level cap; a multiple of 4 */
+                         shifted scheme's coarse-level cap, then (bmg_solve
+                         only) widened to whole clusters: until the first
+                         eigenvalue of a coarse level left out of the block
+                         is 1.25 times as far from sigma as the k-th (Sec. 4,
+                         the choice of Lambda), at most 96 - n_c and half the
+                         finest level's rows; a multiple of 4 */
   int32_t nu1, nu2;   /* pre- and post-smoothing sweeps per level (2, 2) */
   int32_t smoother;   /* bmg_smoother: multicolour symmetric Gauss-Seidel (colours
                          ascending before, descending after the coarse correction)

@@ -199,6 +199,27 @@ int device_sygv_keep(int n, const std::vector<double>& A, const std::vector<doub
                      std::vector<double>& lam, double** vecs, hipStream_t s);
 // Largest level the interior-shift scheme eigendecomposes densely.
 constexpr int kLevelEigMax = 12288;
+
+// A device-wide synchronisation (hipFree, hipDeviceSynchronize, the dense
+// eigensolver's set-up and teardown) on one thread while another thread's
+// stream is capturing a graph fails and leaves a sticky error on the calling
+// thread, which then fails its next launch.  Graph captures therefore hold a
+// process-wide lock shared and such calls hold it exclusively; the exclusive
+// side is re-entrant on one thread.  Captures only enqueue kernels.
+struct DeviceSyncGuard {
+  DeviceSyncGuard();
+  ~DeviceSyncGuard();
+  DeviceSyncGuard(const DeviceSyncGuard&) = delete;
+  DeviceSyncGuard& operator=(const DeviceSyncGuard&) = delete;
+};
+struct CaptureGuard {
+  CaptureGuard();
+  ~CaptureGuard();
+  CaptureGuard(const CaptureGuard&) = delete;
+  CaptureGuard& operator=(const CaptureGuard&) = delete;
+};
+// hipFree under DeviceSyncGuard (null is ignored)
+void dev_free(void* p);
 // The eigendecomposition of level l (built on first use; thread-safe).
 int level_eig(bmg_hierarchy* h, int l, hipStream_t s, const LevelEig** out);
 void free_level_eigs(bmg_hierarchy* h);
@@ -211,6 +232,10 @@ int64_t idle_workspace_bytes(bmg_hierarchy* h);
 void trim_idle_workspaces(bmg_hierarchy* h);
 // Defaults shared by the solver and the server's footprint estimates.
 int default_block_width(int k, double sigma);
+// The widest block the solver gives a request that names no width: at most
+// 96 - n_c columns, half the finest level's rows and (interior scheme) half
+// of level l_c's.
+int block_width_cap(const bmg_hierarchy* h, int n_c, bool shifted, int l_c);
 int default_coarse_vectors(const bmg_hierarchy* h);
 int solve(bmg_hierarchy* h, int k, double sigma, double tol, const bmg_solve_opts* opts,
           double* evals, double* evecs, int64_t ld, int evecs_on_device, void* stream,

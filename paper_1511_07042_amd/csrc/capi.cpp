@@ -49,7 +49,7 @@ int with_shift(const DevLevel& D, double sigma, bool f32, hipStream_t s, F&& fn)
                : launch_shift<double>(D, sigma, static_cast<double*>(S), s);
   if (st == BMG_OK) st = fn(static_cast<const void*>(S));
   (void)hipStreamSynchronize(s);
-  (void)hipFree(S);
+  dev_free(S);
   return st;
 }
 }  // namespace
@@ -163,6 +163,7 @@ int bmg_build_hierarchy_host(const bmg_surface_desc* desc, int32_t n_refine, bmg
 
 void bmg_free_hierarchy(bmg_hierarchy* h) {
   if (!h) return;
+  bmg::DeviceSyncGuard sync;
   if (!h->dev.empty()) (void)hipDeviceSynchronize();
   free_workspaces(h);
   free_device(h);
@@ -271,7 +272,7 @@ int apply_stored(bmg_hierarchy* h, const bmg_apply_args* a, const void* x, const
       int st = a->op == BMG_OP_A ? launch_spmm_am(D, (const double*)x, (double*)y, other, m, s)
                                  : launch_spmm_am(D, (const double*)x, other, (double*)y, m, s);
       (void)hipStreamSynchronize(s);
-      (void)hipFree(other);
+      dev_free(other);
       return st;
     }
     case BMG_OP_SHIFTED:
@@ -359,7 +360,7 @@ int apply_stored(bmg_hierarchy* h, const bmg_apply_args* a, const void* x, const
       int st = launch_gram(p, D.n, (const double*)x, m, nullptr, 0, (const double*)f, a->m2, nullptr,
                            0, part, (double*)y, s);
       (void)hipStreamSynchronize(s);
-      (void)hipFree(part);
+      dev_free(part);
       return st;
     }
     case BMG_OP_SYEV: {
@@ -372,7 +373,7 @@ int apply_stored(bmg_hierarchy* h, const bmg_apply_args* a, const void* x, const
       int hs = 0;
       (void)hipMemcpyAsync(&hs, st_d, sizeof(int), hipMemcpyDeviceToHost, s);
       (void)hipStreamSynchronize(s);
-      (void)hipFree(st_d);
+      dev_free(st_d);
       if (st == BMG_OK && hs != 0) {
         set_error("Jacobi sweep limit reached");
         return BMG_ENOCONV;
@@ -395,7 +396,7 @@ int apply_stored(bmg_hierarchy* h, const bmg_apply_args* a, const void* x, const
       BMG_HIP(hipMalloc(&part, sizeof(double) * p.nblk * p.per_block));
       int st = launch_gram_am(p, D, (const double*)x, a->m2, (const double*)f, m, part, (double*)y, s);
       (void)hipStreamSynchronize(s);
-      (void)hipFree(part);
+      dev_free(part);
       return st;
     }
     case BMG_OP_UPDATE: {
@@ -439,7 +440,7 @@ int apply_stored(bmg_hierarchy* h, const bmg_apply_args* a, const void* x, const
                                              (double*)t, (double*)part, (double*)y, m, s);
       (void)hipStreamSynchronize(s);
       for (void* p : {g, t, part, (void*)sh})
-        if (p) (void)hipFree(p);
+        if (p) dev_free(p);
       return st;
     }
     case BMG_OP_SHIFT_OFFSETS: {
@@ -451,7 +452,7 @@ int apply_stored(bmg_hierarchy* h, const bmg_apply_args* a, const void* x, const
       int st = launch_offsets(h->dev, a->l_c, l, (const double*)x, m, a->sigma, (const double*)f, part,
                               (double*)y, s);
       (void)hipStreamSynchronize(s);
-      (void)hipFree(part);
+      dev_free(part);
       return st;
     }
     default:
@@ -557,7 +558,7 @@ int bmg_apply(const bmg_hierarchy* hc, const bmg_apply_args* a, const void* x, c
     }
   (void)hipStreamSynchronize(s);
   for (void* p : tmp)
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p);
   return st;
 }
 

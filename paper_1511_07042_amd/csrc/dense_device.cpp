@@ -88,7 +88,10 @@ int device_sygv_keep(int n, const std::vector<double>& A, const std::vector<doub
   if (st == BMG_OK && (hipMemcpyAsync(dA, A.data(), nn * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
                        hipMemcpyAsync(dB, M.data(), nn * 8, hipMemcpyHostToDevice, s) != hipSuccess))
     fail("upload");
-  if (st == BMG_OK && so.create(&hdl) != rocblas_status_success) fail("rocblas_create_handle");
+  if (st == BMG_OK) {
+    DeviceSyncGuard sync;  // the handle's set-up may synchronise the device
+    if (so.create(&hdl) != rocblas_status_success) fail("rocblas_create_handle");
+  }
   if (st == BMG_OK && so.set_stream(hdl, s) != rocblas_status_success) fail("rocblas_set_stream");
   if (st == BMG_OK && so.sygvd(hdl, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_lower, n,
                                dA, n, dB, n, dD, dE, dinfo) != rocblas_status_success)
@@ -100,16 +103,19 @@ int device_sygv_keep(int n, const std::vector<double>& A, const std::vector<doub
         hipStreamSynchronize(s) != hipSuccess)
       fail("download");
   }
-  if (hdl) (void)so.destroy(hdl);
+  if (hdl) {
+    DeviceSyncGuard sync;  // and so may its teardown
+    (void)so.destroy(hdl);
+  }
   (void)hipStreamSynchronize(s);
   for (void* p : {(void*)dB, (void*)dD, (void*)dE, (void*)dinfo})
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p);
   if (st == BMG_OK && info != 0) {
     set_error("coarse eigensolve: dsygvd info = %d (mass matrix not positive definite?)", info);
     st = BMG_EINVAL;
   }
   if (st != BMG_OK) {
-    if (dA) (void)hipFree(dA);
+    if (dA) dev_free(dA);
     return st;
   }
   *vecs = dA;
@@ -126,7 +132,7 @@ int device_sygv(int n, const std::vector<double>& A, const std::vector<double>& 
   std::vector<double> rows(nn);
   const hipError_t e1 = hipMemcpyAsync(rows.data(), d, nn * 8, hipMemcpyDeviceToHost, s);
   const hipError_t e2 = hipStreamSynchronize(s);
-  (void)hipFree(d);
+  dev_free(d);
   if (e1 != hipSuccess || e2 != hipSuccess) {
     (void)hipGetLastError();
     set_error("coarse eigensolve: download failed");

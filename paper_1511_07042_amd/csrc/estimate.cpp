@@ -62,7 +62,7 @@ int est_level(bmg_hierarchy* h, int l, hipStream_t s, const EstLevel** out) {
   if (st == BMG_OK && hipStreamSynchronize(s) != hipSuccess) st = BMG_EDEVICE;  // nbr is a local
   if (st != BMG_OK) {
     for (void* p : {static_cast<void*>(e->tri), static_cast<void*>(e->nbr), static_cast<void*>(e->xyz)})
-      if (p) (void)hipFree(p);
+      if (p) dev_free(p);
     return st;
   }
   *out = e.get();
@@ -77,7 +77,7 @@ void free_est_levels(bmg_hierarchy* h) {
   for (auto& e : h->est) {
     if (!e) continue;
     for (void* p : {static_cast<void*>(e->tri), static_cast<void*>(e->nbr), static_cast<void*>(e->xyz)})
-      if (p) (void)hipFree(p);
+      if (p) dev_free(p);
     e.reset();
   }
   h->est.clear();
@@ -122,7 +122,7 @@ int estimate(bmg_hierarchy* h, int level, int k, const double* evals, const doub
   };
   const int st = run();
   (void)hipStreamSynchronize(s);
-  for (void* p : bufs) (void)hipFree(p);
+  for (void* p : bufs) dev_free(p);
   return st;
 }
 

@@ -10,6 +10,8 @@
 
 #include "bmg_internal.h"
 
+#include <shared_mutex>
+
 namespace bmg {
 
 namespace {
@@ -180,6 +182,26 @@ int upload_hierarchy(bmg_hierarchy* h, hipStream_t s) {
   return BMG_OK;
 }
 
+namespace {
+std::shared_mutex g_capture_mu;
+thread_local int t_sync_depth = 0;
+}  // namespace
+
+DeviceSyncGuard::DeviceSyncGuard() {
+  if (t_sync_depth++ == 0) g_capture_mu.lock();
+}
+DeviceSyncGuard::~DeviceSyncGuard() {
+  if (--t_sync_depth == 0) g_capture_mu.unlock();
+}
+CaptureGuard::CaptureGuard() { g_capture_mu.lock_shared(); }
+CaptureGuard::~CaptureGuard() { g_capture_mu.unlock_shared(); }
+
+void dev_free(void* p) {
+  if (p == nullptr) return;
+  DeviceSyncGuard g;
+  (void)hipFree(p);
+}
+
 int level_eig(bmg_hierarchy* h, int l, hipStream_t s, const LevelEig** out) {
   TraceRange trace("bmg_level_eig");
   std::lock_guard<std::mutex> g(h->eig_mutex);
@@ -222,8 +244,8 @@ int level_eig(bmg_hierarchy* h, int l, hipStream_t s, const LevelEig** out) {
   BMG_TRY(upload(&e->d_lam, e->lam.data(), size_t(n), s, e->bytes));
   if (hipMalloc(reinterpret_cast<void**>(&e->d_phi32), nn * sizeof(float)) != hipSuccess) {
     (void)hipGetLastError();
-    (void)hipFree(e->d_phi64);
-    (void)hipFree(e->d_lam);
+    dev_free(e->d_phi64);
+    dev_free(e->d_lam);
     set_error("hipMalloc of %zu bytes failed", nn * sizeof(float));
     return BMG_ENOMEM;
   }
@@ -241,7 +263,7 @@ void free_level_eigs(bmg_hierarchy* h) {
   for (auto& e : h->level_eig) {
     if (!e) continue;
     for (void* p : {(void*)e->d_lam, (void*)e->d_phi64, (void*)e->d_phi32})
-      if (p) (void)hipFree(p);
+      if (p) dev_free(p);
     e.reset();
   }
   h->level_eig.clear();
@@ -254,12 +276,12 @@ void free_device(bmg_hierarchy* h) {
     void* ptrs[] = {D.cols, D.a64, D.m64, D.a32, D.m32, D.dinv, D.parents, D.rtab, D.rself, D.colour_rows,
                      D.chunk_order, D.colour2_rows, D.perm, D.iperm};
     for (void* p : ptrs)
-      if (p) (void)hipFree(p);
+      if (p) dev_free(p);
     D = DevLevel();
   }
   void* ptrs[] = {h->d_phi0_64, h->d_phi0t_64, h->d_phi0_32, h->d_phi0t_32};
   for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p);
   h->d_phi0_64 = h->d_phi0t_64 = nullptr;
   h->d_phi0_32 = h->d_phi0t_32 = nullptr;
 }

@@ -350,10 +350,13 @@ struct bmg_server {
 
   void worker_main() {
     hipStream_t stream = nullptr;
-    if (hipSetDevice(device) != hipSuccess ||
-        hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) {
-      (void)hipGetLastError();
-      stream = nullptr;
+    {
+      bmg::DeviceSyncGuard sync;
+      if (hipSetDevice(device) != hipSuccess ||
+          hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        stream = nullptr;
+      }
     }
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
@@ -417,7 +420,10 @@ struct bmg_server {
       }
     }
     lk.unlock();
-    if (stream) (void)hipStreamDestroy(stream);
+    if (stream) {
+      bmg::DeviceSyncGuard sync;
+      (void)hipStreamDestroy(stream);
+    }
   }
 };
 
@@ -483,10 +489,17 @@ int bmg_server_submit(bmg_server* s, const bmg_surface_desc* desc, int32_t n_ref
   r->key = surface_key(*r);
   r->n_est = level_vertices(r->desc, n_refine).back();
   r->hier = hierarchy_estimate(r->desc, n_refine);
+  // a request that names no width may run wider than the default when it runs
+  // alone (the solver widens the block to whole clusters of the spectrum), so
+  // its footprint takes the widest block the solver can choose; grouping
+  // keeps the default width (a grouped solve does not widen)
+  int m_foot = m_est;
+  if (r->opts.m <= 0)
+    m_foot = std::max(m_est, int(std::min<int64_t>(96 - n_c, r->n_est / 2) / 4 * 4));
   int64_t extra = 0;
   if (shifted)
-    extra = shifted_estimate(r->desc, n_refine, m_est, r->opts.m > 0, r->opts.precision, &m_est);
-  r->need = workspace_estimate(r->desc, n_refine, m_est, n_c, r->opts.precision) + extra;
+    extra = shifted_estimate(r->desc, n_refine, m_foot, r->opts.m > 0, r->opts.precision, &m_foot);
+  r->need = workspace_estimate(r->desc, n_refine, m_foot, n_c, r->opts.precision) + extra;
   r->groupable = !shifted && r->opts.ramp_cycles == 0;
   r->m_est = m_est;
   BMG_CHECK(m_est >= k && int64_t(m_est) <= r->n_est / 2, "m must be in [k, N_L / 2]");

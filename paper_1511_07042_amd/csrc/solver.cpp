@@ -91,12 +91,13 @@ int dalloc(bmg_workspace* w, void** p, size_t bytes) {
 }
 
 void free_workspace(bmg_workspace* w) {
+  DeviceSyncGuard sync;  // stream, graph and pinned-memory teardown synchronise
   if (w->gexec) (void)hipGraphExecDestroy(w->gexec);
   if (w->graph) (void)hipGraphDestroy(w->graph);
   if (w->ev_in) (void)hipEventDestroy(w->ev_in);
   if (w->ev_out) (void)hipEventDestroy(w->ev_out);
   if (w->stream) (void)hipStreamDestroy(w->stream);
-  for (void* p : w->allocs) (void)hipFree(p);
+  for (void* p : w->allocs) dev_free(p);
   if (w->hbuf) (void)hipHostFree(w->hbuf);
   if (w->tail_h) (void)hipHostFree(w->tail_h);
   delete w;
@@ -173,6 +174,7 @@ int make_workspace(bmg_hierarchy* h, int m, int n_c, int prec, bmg_workspace** o
   AL(w->argi, sizeof(int) * w->nblk_arg * m);
   AL(w->tail_d, sizeof(TailArgs));
 #undef AL
+  DeviceSyncGuard sync;  // stream, events and pinned memory
   if (hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&w->ev_in, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&w->ev_out, hipEventDisableTiming) != hipSuccess) {
@@ -677,6 +679,60 @@ int default_block_width(int k, double sigma) {
 
 int default_coarse_vectors(const bmg_hierarchy* h) { return int(std::min<int64_t>(h->n0, 32)) & ~1; }
 
+// The block must hold whole clusters of the spectrum plus overlap (Sec. 4,
+// the choice of Lambda: multiplicities and the gap between clusters).  Given
+// a coarse level's eigenvalues lam, which place the clusters near sigma, the
+// default width m is widened until the first eigenvalue left out lies at
+// least 1.25 times as far from sigma as the k-th nearest: the block then
+// converges the k-th pair at a ratio of at most 0.8 per cycle even when k
+// cuts a cluster (the sphere's multiplets, a nearly round ellipsoid's split
+// ones), where a block ending inside the cluster barely converges at all.
+// A multiple of 4, at most m_cap; unchanged if the coarse spectrum does not
+// reach past the window.
+int widen_block_width(const std::vector<double>& lam, int k, double sigma, int m, int m_cap) {
+  if (k < 1 || int(lam.size()) <= k) return m;
+  std::vector<double> d(lam.size());
+  for (size_t i = 0; i < lam.size(); ++i) d[i] = std::fabs(lam[i] - sigma);
+  std::sort(d.begin(), d.end());
+  const double dk = d[size_t(k) - 1];
+  size_t c = 0;
+  while (c < d.size() && d[c] < 1.25 * dk) ++c;
+  if (c >= d.size()) return m;
+  const int want = 4 * ((int(c) + 3) / 4);
+  return std::max(m, std::min(want, m_cap));
+}
+
+int block_width_cap(const bmg_hierarchy* h, int n_c, bool shifted, int l_c) {
+  int64_t cap = std::min<int64_t>(96 - n_c, h->host.back().n / 2);
+  if (shifted) cap = std::min<int64_t>(cap, h->host[l_c].n / 2);
+  return int(cap / 4 * 4);
+}
+
+// The default width widened by widen_block_width on the spectrum of level l_c
+// (interior scheme: the level it eigendecomposes anyway) or of the coarsest
+// level with at least max(4 m, 96) vertices (enriched scheme: it places the
+// clusters up to a few times the default width, and a new hierarchy pays for
+// only a small dense eigensolve); kept as it is if no such level fits the
+// dense eigensolve.
+int widened_default_width(bmg_hierarchy* h, int k, double sigma, bool shifted, int l_c, int n_c,
+                          hipStream_t s, int* m) {
+  const int nl = int(h->host.size());
+  int g = -1;
+  if (shifted) {
+    g = l_c;
+  } else {
+    const int64_t need = std::max(4 * int64_t(*m), int64_t(96));
+    for (int l = 0; l < nl && g < 0; ++l)
+      if (h->host[l].n >= need && h->host[l].n <= kLevelEigMax) g = l;
+  }
+  const int cap = block_width_cap(h, n_c, shifted, l_c);
+  if (g < 0 || cap <= *m) return BMG_OK;
+  const LevelEig* le = nullptr;
+  BMG_TRY(level_eig(h, g, s, &le));
+  *m = widen_block_width(le->lam, k, sigma, *m, cap);
+  return BMG_OK;
+}
+
 // Coarse level of the interior-shift scheme.  The P1 eigenvalue error of an
 // eigenfunction near sigma on level l is O(sigma^2 h^2) (the a priori estimate
 // of Sec. 2.2, Lemma 2.2) with h the mesh size along it, and a block of m vectors spans a
@@ -1107,10 +1163,15 @@ int run_solve(bmg_hierarchy* h, bmg_workspace* w, int k, double sigma, double to
     if (!w->gexec) {
       const std::vector<T*> e0 = cyc.e, t0 = cyc.t;
       const size_t kt_used = kt.used;
-      BMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      const int cst = cycle_body();
+      int cst = BMG_OK;
       hipGraph_t g = nullptr;
-      const hipError_t ce = hipStreamEndCapture(s, &g);
+      hipError_t ce = hipSuccess;
+      {
+        CaptureGuard cg;  // no device-wide synchronisation meanwhile
+        BMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        cst = cycle_body();
+        ce = hipStreamEndCapture(s, &g);
+      }
       const bool swapped = cyc.e != e0 || cyc.t != t0;  // odd number of Jacobi swaps
       if (cst != BMG_OK || ce != hipSuccess || swapped) {
         // capture impossible here: run this and later cycles as plain launches
@@ -1392,10 +1453,15 @@ int run_group(bmg_hierarchy* h, bmg_workspace* w, double sigma, std::vector<Grou
     if (!use_graph) return cycle_body();
     if (!gexec) {
       const std::vector<T*> e0 = cyc.e, t0v = cyc.t;
-      BMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      const int cst = cycle_body();
+      int cst = BMG_OK;
       hipGraph_t g = nullptr;
-      const hipError_t ce = hipStreamEndCapture(s, &g);
+      hipError_t ce = hipSuccess;
+      {
+        CaptureGuard cg;  // no device-wide synchronisation meanwhile
+        BMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        cst = cycle_body();
+        ce = hipStreamEndCapture(s, &g);
+      }
       const bool swapped = cyc.e != e0 || cyc.t != t0v;
       if (cst != BMG_OK || ce != hipSuccess || swapped) {
         if (g) (void)hipGraphDestroy(g);
@@ -1432,10 +1498,16 @@ int run_group(bmg_hierarchy* h, bmg_workspace* w, double sigma, std::vector<Grou
   // request's status words (contiguous, see solve_group)
   double* pin = nullptr;
   const size_t pin_bytes = sizeof(double) * 2 * M + sizeof(int) * 16 * size_t(n);
-  BMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&pin), pin_bytes));
+  {
+    DeviceSyncGuard sync;
+    BMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&pin), pin_bytes));
+  }
   struct PinGuard {
     double* p;
-    ~PinGuard() { (void)hipHostFree(p); }
+    ~PinGuard() {
+      DeviceSyncGuard sync;
+      (void)hipHostFree(p);
+    }
   } pin_guard{pin};
   const double* hb = pin;
   const int* hs = reinterpret_cast<const int*>(pin + 2 * M);
@@ -1583,6 +1655,10 @@ int solve(bmg_hierarchy* h, int k, double sigma, double tol, const bmg_solve_opt
               "eigensolve takes at most %d", l_c, (long long)h->host[l_c].n, kLevelEigMax);
     BMG_CHECK(h->host[l_c].n >= o.m, "l_c = %d has %lld vertices, fewer than the m = %d start vectors",
               l_c, (long long)h->host[l_c].n, o.m);
+  }
+  if (!m_given) {
+    BMG_HIP(hipSetDevice(h->device));
+    BMG_TRY(widened_default_width(h, k, sigma, shifted, l_c, o.n_c, static_cast<hipStream_t>(stream), &o.m));
   }
   BMG_CHECK(o.ramp_cycles >= 0 && o.ramp_cycles <= 64, "ramp_cycles must be in [0, 64]");
   int ramp_l0 = -1;
@@ -1734,7 +1810,7 @@ int solve_group(bmg_hierarchy* h, double sigma, int n, bmg_group_request* reqs, 
   }
   (void)hipStreamSynchronize(s);
   if (hipEventRecord(w->ev_out, s) == hipSuccess) (void)hipStreamWaitEvent(cs, w->ev_out, 0);
-  for (void* p : bufs) (void)hipFree(p);
+  for (void* p : bufs) dev_free(p);
   release_workspace(h, w);
   if (st != BMG_OK) {
     for (int i = 0; i < n; ++i)

@@ -112,7 +112,7 @@ int two_grid(bmg_hierarchy* h, int level_H, int n, const int32_t* idx, int top, 
   };
   const int st = run();
   (void)hipStreamSynchronize(s);
-  for (void* p : bufs) (void)hipFree(p);
+  for (void* p : bufs) dev_free(p);
   return st;
 }
 

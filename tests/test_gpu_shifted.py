@@ -204,3 +204,36 @@ def test_rank_loss_reports_noconv_without_output(lib):
                             scheme="enriched")
         assert st["status"] == -4 and np.all(ev == 0.0) and np.all(U == 0.0)
         del evals
+
+
+# ---------------------------------------------------- default block width --
+
+def test_default_width_covers_a_cut_multiplet(lib):
+    # sigma = 101.6 with k = 7: the seven eigenvalues nearest sigma lie in the
+    # 21-fold multiplet l = 10 (lambda ~ 110).  The default width (12) ends
+    # inside it and the block barely converges; the width taken from the
+    # coarse level's spectrum holds the whole multiplet.
+    from oracle import bmg as ob, reference
+    lv = ob.build_levels("sphere", 5)
+    ref_ev, ref_U = reference.discrete_eigs(lv[-1].A, lv[-1].M, 40, 101.6)
+    with lib.Hierarchy("sphere", 5) as h:
+        ev, U, st = h.solve(7, 101.6, 1e-8, precision="mixed", smoother="jacobi")
+        assert st["converged"] == 1 and st["m"] >= 24, (st["m"], st["cycles"])
+        _check_pairs(ev, U, lv[-1].M, ref_ev, ref_U, 101.6, 7)
+        # an explicit width is kept as given
+        ev2, U2, st2 = h.solve(7, 101.6, 1e-8, m=28, precision="mixed", smoother="jacobi")
+        assert st2["m"] == 28
+
+
+def test_default_width_covers_a_split_cluster_at_zero(lib):
+    # a nearly round ellipsoid: its l = 4 group (nine eigenvalues, split by
+    # under 7%) starts at index 16, so k = 17 cuts it, and the default width
+    # (24) ends inside the group as well; the widened block reaches past it
+    from oracle import bmg as ob, reference
+    axes = (1.961, 1.8452, 1.8167)
+    lv = ob.build_levels("ellipsoid", 5, axes=axes)
+    ref_ev, ref_U = reference.discrete_eigs(lv[-1].A, lv[-1].M, 40, 0.0)
+    with lib.Hierarchy("ellipsoid", 5, axes=axes) as h:
+        ev, U, st = h.solve(17, 0.0, 1e-8, precision="mixed", smoother="jacobi")
+        assert st["converged"] == 1 and st["m"] >= 28, (st["m"], st["cycles"])
+        _check_pairs(ev, U, lv[-1].M, ref_ev, ref_U, 0.0, 17)
