@@ -163,3 +163,26 @@ def test_poll_busy_then_done(lib):
         assert srv.poll(rid) is None  # still queued or running right after submit
         r = srv.wait(rid)
         assert r["status"] == lib.OK and r["evecs"].shape == (10 * 4 ** 5 + 2, 25)
+
+
+def test_new_hierarchies_under_eviction_all_succeed(lib):
+    # 24 requests, each on a hierarchy of its own (random ellipsoid axes),
+    # both schemes and widths the solver chooses, on 8 slots under a budget
+    # that holds only a few at a time: workers free hierarchies, workspaces
+    # and eigendecompositions (device-wide synchronisations) while others
+    # capture their cycle graphs.  Every request must succeed, and a few are
+    # checked against their solo solves.
+    rs = np.random.default_rng(5)
+    reqs = []
+    for i in range(24):
+        axes = tuple(float(x) for x in rs.uniform(1.0, 2.0, 3))
+        sigma = 0.0 if i % 2 == 0 else float(rs.uniform(15.0, 60.0))
+        reqs.append(dict(kind="ellipsoid", n_refine=3 + i % 2, k=int(rs.integers(4, 13)), sigma=sigma,
+                         axes=axes, precision="mixed", smoother="jacobi", seed=100 + i))
+    with lib.Server(512 << 20, max_slots=8) as srv:
+        ids = [_submit(lib, srv, r) for r in reqs]
+        res = [srv.wait(i) for i in ids]
+    for i, r in enumerate(res):
+        assert r["status"] == 0, (i, reqs[i], r["error"])
+    for i in (0, 1, 7):
+        _same(res[i], _alone(lib, reqs[i]), i, reqs[i])
